@@ -1,0 +1,156 @@
+"""Python access to the FP64 SimNet oracle (``simnet_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product package.  It shares
+no code with the HIP library; both only consume inputs made by ``synth``.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "simnet_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+PREDICT, INJECT = 0, 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (plain C, IEEE double, no contraction)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-ffp-contract=off",
+                               "-fno-fast-math", "-fPIC", "-shared", "-o", tmp, SRC,
+                               "-lpthread", "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C")
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
+        L.ol_model_new.restype = P
+        L.ol_model_new.argtypes = [C.c_int, i32p, f32p, C.c_int, C.c_int]
+        L.ol_model_free.argtypes = [P]
+        L.ol_model_nout.restype = C.c_int
+        L.ol_model_nout.argtypes = [P]
+        L.ol_forward.restype = C.c_int
+        L.ol_forward.argtypes = [P, C.c_int64, f64p, f64p]
+        L.ol_round.restype = C.c_int32
+        L.ol_round.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_int32)]
+        L.ol_partition.restype = C.c_int
+        L.ol_partition.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i64p, i32p]
+        L.ol_simulate.restype = C.c_int
+        L.ol_simulate.argtypes = [P, i32p, P, C.c_int64, C.c_int32, i64p, i64p, i32p,
+                                  C.c_int32, P, i64p, i64p, i64p, i64p, P, P, i64p, C.c_int32]
+        _lib = L
+    return _lib
+
+
+def flat_params(ws: Sequence[np.ndarray], bs: Sequence[np.ndarray]) -> np.ndarray:
+    parts = []
+    for w, b in zip(ws, bs):
+        parts.append(np.asarray(w, np.float32).ravel())
+        parts.append(np.asarray(b, np.float32).ravel())
+    return np.ascontiguousarray(np.concatenate(parts), dtype=np.float32)
+
+
+class Model:
+    """The predictor with its parameters held in double precision."""
+
+    def __init__(self, layers, ws, bs, n_feat: int, n_slot: int):
+        desc = np.array([[ly.kind, ly.c_in, ly.c_out, ly.relu] for ly in layers],
+                        dtype=np.int32).ravel()
+        self._params = flat_params(ws, bs)
+        self.n_feat, self.n_slot = n_feat, n_slot
+        self.ptr = lib().ol_model_new(len(layers), desc, self._params, n_feat, n_slot)
+        if not self.ptr:
+            raise ValueError("layer list does not fit the window shape")
+        self.n_out = lib().ol_model_nout(self.ptr)
+
+    def __del__(self):
+        if getattr(self, "ptr", None) and _lib is not None:
+            _lib.ol_model_free(self.ptr)
+            self.ptr = None
+
+    def forward(self, x: np.ndarray) -> np.ndarray:
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.shape[1:] == (self.n_slot, self.n_feat)
+        out = np.zeros((x.shape[0], self.n_out), dtype=np.float64)
+        lib().ol_forward(self.ptr, x.shape[0], x, out)
+        return out
+
+
+def round_latency(v: float, lat_max: int = 65535):
+    fl = C.c_int32(0)
+    r = lib().ol_round(float(v), int(lat_max), C.byref(fl))
+    return int(r), int(fl.value)
+
+
+def partition(n_instr: int, n_sub: int, warm_max: int = 0):
+    start = np.zeros(n_sub, np.int64)
+    length = np.zeros(n_sub, np.int64)
+    warm = np.zeros(n_sub, np.int32)
+    if lib().ol_partition(n_instr, n_sub, warm_max, start, length, warm) != 0:
+        raise ValueError("cannot partition")
+    return start, length, warm
+
+
+def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=65535):
+    return np.array([n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max],
+                    dtype=np.int32)
+
+
+def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
+             model: Optional[Model] = None, mode: int = PREDICT,
+             lat_table: Optional[np.ndarray] = None, want_logits: bool = False,
+             want_lat: bool = False, n_instr: Optional[int] = None, threads: int = 0) -> dict:
+    """Run the oracle over every sub-trace; returns per-sub-trace int64 arrays
+    and optionally the per-prediction logits (float64) and latencies."""
+    start = np.ascontiguousarray(start, np.int64)
+    length = np.ascontiguousarray(length, np.int64)
+    warm = np.ascontiguousarray(warm, np.int32)
+    K = start.shape[0]
+    n_out = int(cfg[2])
+    n_pred = int(np.sum(warm.astype(np.int64) + length))
+    if feat is not None:
+        feat = np.ascontiguousarray(feat, np.float32)
+        n_instr = feat.shape[0]
+    elif n_instr is None:
+        n_instr = int(np.max(start + length))
+    res = {k: np.zeros(K, np.int64) for k in ("fetch", "drain", "final", "warm_tick")}
+    logits = np.zeros((n_pred, n_out), np.float64) if want_logits else None
+    lat = np.zeros((n_pred, n_out), np.int32) if want_lat else None
+    if lat_table is not None:
+        lat_table = np.ascontiguousarray(lat_table, np.int32)
+        assert lat_table.size >= n_pred * n_out
+    counters = np.zeros(2, np.int64)
+    rc = lib().ol_simulate(model.ptr if model else None, cfg,
+                           feat.ctypes.data if feat is not None else None, n_instr, K,
+                           start, length, warm, mode,
+                           lat_table.ctypes.data if lat_table is not None else None,
+                           res["fetch"], res["drain"], res["final"], res["warm_tick"],
+                           logits.ctypes.data if logits is not None else None,
+                           lat.ctypes.data if lat is not None else None,
+                           counters, threads)
+    if rc != 0:
+        raise ValueError("oracle rejected the arguments")
+    res["total"] = int(np.sum(res["final"] - res["warm_tick"]))
+    res["n_clamped"], res["n_nonfinite"] = int(counters[0]), int(counters[1])
+    res["logits"], res["lat"] = logits, lat
+    return res

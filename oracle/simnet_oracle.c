@@ -1,0 +1,395 @@
+/*
+ * SimNet oracle: a plain, slow, FP64 / exact-int64 CPU reference of the
+ * parallel simulation step loop (Li et al., "SimNet: Accurate and
+ * High-Performance Computer Architecture Simulation using Deep Learning").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header or table with the HIP
+ * library.
+ *
+ * What it follows:
+ *   - Sec. 2.2 (model input): each in-flight context instruction contributes
+ *     its features plus its residence and execution latency; the instruction
+ *     to be predicted carries zeros in those columns.
+ *   - Sec. 2.3 (CNN): instructions along one axis, features as channels;
+ *     every convolution has kernel 2 and stride 2 with no overlap; ReLU after
+ *     each convolution and after the hidden fully connected layer; the last
+ *     convolution output is flattened (PyTorch channel-major order) into two
+ *     fully connected layers.  Outputs are (fetch, execution) latency.
+ *   - Sec. 3.1, Eq. 1: program time = sum of fetch latencies + drain.
+ *   - Sec. 3.2 (context and clock management): processor queue is a FIFO;
+ *     a fetch latency F > 0 advances curTick by F and ages every queued
+ *     instruction; an instruction is ready to retire once its residence
+ *     exceeds its execution latency; retirement is in order and limited to
+ *     the retire width per cycle; after the last instruction the clock keeps
+ *     running until the queue is empty.  This file runs that rule literally,
+ *     one cycle at a time.
+ *   - Sec. 3.3 (parallel simulation): the trace is cut into equal contiguous
+ *     sub-traces that are simulated independently; the total is the sum of
+ *     their clocks.
+ *
+ * Readings where the paper is silent (each also listed in the design notes):
+ *   ready means residence strictly greater than execution latency; the
+ *   context snapshot for instruction i is the queue after instruction i-1 was
+ *   pushed; at most W retirements per cycle, greedy from the head, none
+ *   during a zero fetch latency; slot k >= 1 holds the k-th newest queued
+ *   instruction and only the newest n_slot-1 are shown; odd lengths follow
+ *   PyTorch Conv1d (floor, the unpaired last slot dropped); rounding is to
+ *   nearest, ties to even, clamped to [0, lat_max], non-finite -> 0;
+ *   sub-trace k additionally simulates the warm[k] instructions before its
+ *   start, whose fetch cycles are excluded from its count.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <unistd.h>
+
+enum { OL_CONV = 0, OL_FC = 1 };
+enum { OL_PREDICT = 0, OL_INJECT = 1 };
+
+/* cfg[] layout shared with the Python wrapper */
+enum { CF_NFEAT = 0, CF_NSLOT, CF_NOUT, CF_W, CF_COLRES, CF_COLEXE, CF_COLSTO, CF_LATMAX, CF_LEN };
+
+typedef struct {
+  int n_layers;
+  int32_t desc[16][4];      /* kind, c_in, c_out, relu */
+  double* w[16];
+  double* b[16];
+  int n_feat, n_slot, n_out, max_width;
+} ol_model;
+
+/* ------------------------------------------------------------- model --- */
+
+/* params: PyTorch order, concatenated: w0, b0, w1, b1, ...  conv weight is
+ * [c_out][c_in][2], fc weight is [out][in]. */
+void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
+                   int n_feat, int n_slot) {
+  if (n_layers < 1 || n_layers > 16) return NULL;
+  ol_model* m = (ol_model*)calloc(1, sizeof(ol_model));
+  m->n_layers = n_layers;
+  m->n_feat = n_feat;
+  m->n_slot = n_slot;
+  int ch = n_feat, len = n_slot, width = n_feat * n_slot;
+  size_t off = 0;
+  for (int l = 0; l < n_layers; ++l) {
+    for (int j = 0; j < 4; ++j) m->desc[l][j] = desc[4 * l + j];
+    int kind = desc[4 * l], ci = desc[4 * l + 1], co = desc[4 * l + 2];
+    size_t nw;
+    if (kind == OL_CONV) {
+      if (ci != ch || len < 2) { free(m); return NULL; }
+      nw = (size_t)co * ci * 2;
+      len = len / 2;
+    } else {
+      if (ci != ch * len) { free(m); return NULL; }
+      nw = (size_t)co * ci;
+      len = 1;
+    }
+    ch = co;
+    if (ch * len > width) width = ch * len;
+    m->w[l] = (double*)malloc(nw * sizeof(double));
+    m->b[l] = (double*)malloc((size_t)co * sizeof(double));
+    for (size_t i = 0; i < nw; ++i) m->w[l][i] = (double)params[off + i];
+    off += nw;
+    for (int i = 0; i < co; ++i) m->b[l][i] = (double)params[off + i];
+    off += co;
+  }
+  if (len != 1) { /* the network must end in a fully connected layer */
+    for (int l = 0; l < n_layers; ++l) { free(m->w[l]); free(m->b[l]); }
+    free(m);
+    return NULL;
+  }
+  m->n_out = ch;
+  m->max_width = width;
+  return m;
+}
+
+void ol_model_free(void* p) {
+  ol_model* m = (ol_model*)p;
+  if (!m) return;
+  for (int l = 0; l < m->n_layers; ++l) { free(m->w[l]); free(m->b[l]); }
+  free(m);
+}
+
+int ol_model_nout(const void* p) { return ((const ol_model*)p)->n_out; }
+
+/* Forward pass of one window x[n_slot][n_feat] by the layer definitions
+ * (Sec. 2.3).  a/b are scratch of at least max_width doubles.
+ * Activations are kept channel-major: act[c * len + pos]. */
+static void forward_one(const ol_model* m, const double* x, double* out,
+                        double* a, double* t) {
+  int ch = m->n_feat, len = m->n_slot;
+  for (int l = 0; l < len; ++l)
+    for (int c = 0; c < ch; ++c) a[c * len + l] = x[l * ch + c];
+  for (int li = 0; li < m->n_layers; ++li) {
+    const int32_t* d = m->desc[li];
+    const double* w = m->w[li];
+    const double* b = m->b[li];
+    int co = d[2];
+    if (d[0] == OL_CONV) {
+      int lout = len / 2;
+      for (int o = 0; o < co; ++o)
+        for (int p = 0; p < lout; ++p) {
+          double s = b[o];
+          for (int ci = 0; ci < ch; ++ci)
+            for (int k = 0; k < 2; ++k)
+              s += w[((size_t)o * ch + ci) * 2 + k] * a[ci * len + 2 * p + k];
+          t[o * lout + p] = (d[3] && s < 0.0) ? 0.0 : s;
+        }
+      len = lout;
+    } else {
+      int n_in = ch * len; /* flatten: index c*len + p, already the layout of a */
+      for (int o = 0; o < co; ++o) {
+        double s = b[o];
+        for (int j = 0; j < n_in; ++j) s += w[(size_t)o * n_in + j] * a[j];
+        t[o] = (d[3] && s < 0.0) ? 0.0 : s;
+      }
+      len = 1;
+    }
+    ch = co;
+    memcpy(a, t, sizeof(double) * (size_t)ch * len);
+  }
+  memcpy(out, a, sizeof(double) * (size_t)m->n_out);
+}
+
+/* Batched forward: x [B][n_slot][n_feat] (double) -> out [B][n_out]. */
+int ol_forward(const void* p, int64_t B, const double* x, double* out) {
+  const ol_model* m = (const ol_model*)p;
+  double* a = (double*)malloc(sizeof(double) * m->max_width);
+  double* t = (double*)malloc(sizeof(double) * m->max_width);
+  size_t win = (size_t)m->n_slot * m->n_feat;
+  for (int64_t i = 0; i < B; ++i) forward_one(m, x + i * win, out + i * m->n_out, a, t);
+  free(a);
+  free(t);
+  return 0;
+}
+
+/* ------------------------------------------------------------ rounding --- */
+
+/* Round a predicted latency to integer cycles: nearest, ties to even, clamp
+ * to [0, lat_max]; a non-finite value becomes 0.  flags: bit0 non-finite,
+ * bit1 clamped. */
+int32_t ol_round(double v, int32_t lat_max, int32_t* flags) {
+  *flags = 0;
+  if (!isfinite(v)) { *flags = 1; return 0; }
+  double r = nearbyint(v);
+  if (r < 0.0) { *flags = 2; return 0; }
+  if (r > (double)lat_max) { *flags = 2; return lat_max; }
+  return (int32_t)r;
+}
+
+/* ----------------------------------------------------------- partition --- */
+
+/* Equal contiguous sub-traces (Sec. 3.3): the first n mod k get one extra
+ * instruction; warm[k] = min(warm_max, start[k]). */
+int ol_partition(int64_t n_instr, int32_t n_sub, int32_t warm_max,
+                 int64_t* start, int64_t* len, int32_t* warm) {
+  if (n_sub <= 0 || n_instr < n_sub) return -1;
+  int64_t q = n_instr / n_sub, r = n_instr % n_sub, s = 0;
+  for (int32_t k = 0; k < n_sub; ++k) {
+    start[k] = s;
+    len[k] = q + (k < r ? 1 : 0);
+    warm[k] = (int32_t)(s < warm_max ? s : warm_max);
+    s += len[k];
+  }
+  return 0;
+}
+
+/* ------------------------------------------------- literal queue model --- */
+
+typedef struct { int64_t idx, res; int32_t e, s; } qentry;
+
+typedef struct {
+  qentry* q;
+  int64_t head, tail, cap;
+} queue;
+
+static void q_push(queue* Q, qentry e) {
+  if (Q->tail == Q->cap) {
+    if (Q->head > 0) {
+      memmove(Q->q, Q->q + Q->head, sizeof(qentry) * (size_t)(Q->tail - Q->head));
+      Q->tail -= Q->head;
+      Q->head = 0;
+    }
+    if (Q->tail == Q->cap) {
+      Q->cap = Q->cap ? 2 * Q->cap : 256;
+      Q->q = (qentry*)realloc(Q->q, sizeof(qentry) * (size_t)Q->cap);
+    }
+  }
+  Q->q[Q->tail++] = e;
+}
+
+/* One clock cycle of the processor queue: the clock moves by one, every
+ * queued instruction ages by one, then up to W ready instructions leave from
+ * the head in program order. */
+static void tick(queue* Q, int64_t* cur, int W) {
+  *cur += 1;
+  for (int64_t j = Q->head; j < Q->tail; ++j) Q->q[j].res += 1;
+  int n = 0;
+  while (n < W && Q->head < Q->tail && Q->q[Q->head].res > Q->q[Q->head].e) {
+    Q->head++;
+    n++;
+  }
+}
+
+typedef struct {
+  const ol_model* m;
+  const int32_t* cfg;
+  const float* feat;
+  int32_t n_sub;
+  const int64_t* start;
+  const int64_t* len;
+  const int32_t* warm;
+  const int64_t* pred_off;
+  int32_t mode;
+  const int32_t* lat_table;
+  int64_t *fetch, *drain, *final_tick, *warm_tick;
+  double* logits_out;
+  int32_t* lat_out;
+  int64_t counters[2]; /* clamped, non-finite (summed under the lock) */
+  int32_t next;
+  int32_t err;
+  pthread_mutex_t mu;
+} sim_job;
+
+static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* t,
+                         queue* Q, int64_t* cnt) {
+  const int32_t* cfg = J->cfg;
+  const int D = cfg[CF_NFEAT], L = cfg[CF_NSLOT], n_out = cfg[CF_NOUT], W = cfg[CF_W];
+  const int cr = cfg[CF_COLRES], ce = cfg[CF_COLEXE], cs = cfg[CF_COLSTO];
+  const int32_t lat_max = cfg[CF_LATMAX];
+  const int C = L - 1;
+  const int need_pred = (J->mode == OL_PREDICT) || (J->logits_out != NULL);
+  double out[8];
+
+  Q->head = Q->tail = 0;
+  int64_t cur = 0, t_w = 0;
+  const int64_t w = J->warm[k], n_pos = J->warm[k] + J->len[k];
+  const int64_t first = J->start[k] - w;
+  for (int64_t p = 0; p < n_pos; ++p) {
+    const int64_t i = first + p;
+    const int64_t g = J->pred_off[k] + p; /* global prediction index */
+    if (need_pred) {
+      /* Window (Sec. 2.2): slot 0 = this instruction with zero dynamic
+       * columns; slot j >= 1 = j-th newest queued instruction. */
+      memset(win, 0, sizeof(double) * (size_t)L * D);
+      for (int c = 0; c < D; ++c) win[c] = J->feat[i * D + c];
+      if (cr >= 0) win[cr] = 0.0;
+      if (ce >= 0) win[ce] = 0.0;
+      if (cs >= 0) win[cs] = 0.0;
+      int64_t inq = Q->tail - Q->head;
+      int shown = (int)(inq < C ? inq : C);
+      for (int j = 1; j <= shown; ++j) {
+        const qentry* e = &Q->q[Q->tail - j];
+        double* row = win + (size_t)j * D;
+        for (int c = 0; c < D; ++c) row[c] = J->feat[e->idx * D + c];
+        if (cr >= 0) row[cr] = (double)e->res;
+        if (ce >= 0) row[ce] = (double)e->e;
+        if (cs >= 0) row[cs] = (n_out >= 3) ? (double)e->s : 0.0;
+      }
+      forward_one(J->m, win, out, a, t);
+      if (J->logits_out)
+        for (int o = 0; o < n_out; ++o) J->logits_out[g * n_out + o] = out[o];
+    }
+    int32_t lat[8];
+    for (int o = 0; o < n_out; ++o) {
+      if (J->mode == OL_PREDICT) {
+        int32_t fl;
+        lat[o] = ol_round(out[o], lat_max, &fl);
+        if (fl & 2) cnt[0]++;
+        if (fl & 1) cnt[1]++;
+      } else {
+        lat[o] = J->lat_table[g * n_out + o];
+      }
+      if (J->lat_out) J->lat_out[g * n_out + o] = lat[o];
+    }
+    /* Clock management (Sec. 3.2): F cycles pass, one at a time. */
+    for (int32_t f = 0; f < lat[0]; ++f) tick(Q, &cur, W);
+    qentry e = {i, 0, lat[1], n_out >= 3 ? lat[2] : 0};
+    q_push(Q, e);
+    if (p == w - 1) t_w = cur;
+  }
+  const int64_t t_last = cur;
+  while (Q->tail > Q->head) tick(Q, &cur, W); /* drain */
+  J->fetch[k] = t_last - t_w;
+  J->drain[k] = cur - t_last;
+  J->final_tick[k] = cur;
+  J->warm_tick[k] = t_w;
+}
+
+static void* sim_worker(void* arg) {
+  sim_job* J = (sim_job*)arg;
+  const int D = J->cfg[CF_NFEAT], L = J->cfg[CF_NSLOT];
+  int width = J->m ? J->m->max_width : 1;
+  double* win = (double*)malloc(sizeof(double) * (size_t)L * D);
+  double* a = (double*)malloc(sizeof(double) * (size_t)width);
+  double* t = (double*)malloc(sizeof(double) * (size_t)width);
+  queue Q = {NULL, 0, 0, 0};
+  int64_t cnt[2] = {0, 0};
+  for (;;) {
+    pthread_mutex_lock(&J->mu);
+    int32_t k = J->next++;
+    pthread_mutex_unlock(&J->mu);
+    if (k >= J->n_sub) break;
+    simulate_one(J, k, win, a, t, &Q, cnt);
+  }
+  pthread_mutex_lock(&J->mu);
+  J->counters[0] += cnt[0];
+  J->counters[1] += cnt[1];
+  pthread_mutex_unlock(&J->mu);
+  free(Q.q);
+  free(win);
+  free(a);
+  free(t);
+  return NULL;
+}
+
+/* Simulate every sub-trace.  mode OL_PREDICT advances with the model's own
+ * rounded predictions; OL_INJECT advances with lat_table[(pred_off[k] + p) *
+ * n_out + o] (the model is then only run when logits_out is requested and
+ * may be NULL otherwise).  Per-sub-trace results: fetch = T_last - T_w,
+ * drain = final - T_last, final tick, T_w.  counters[0] = clamped, [1] =
+ * non-finite.  Returns 0, or -1 on invalid arguments. */
+int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_t n_instr,
+                int32_t n_sub, const int64_t* start, const int64_t* len, const int32_t* warm,
+                int32_t mode, const int32_t* lat_table,
+                int64_t* fetch, int64_t* drain, int64_t* final_tick, int64_t* warm_tick,
+                double* logits_out, int32_t* lat_out, int64_t* counters, int32_t n_threads) {
+  const ol_model* m = (const ol_model*)model;
+  if (cfg[CF_NOUT] < 2 || cfg[CF_NOUT] > 2) return -1; /* store latency not modelled */
+  if (cfg[CF_W] < 1 || cfg[CF_NSLOT] < 1) return -1;
+  if ((mode == OL_PREDICT || logits_out) && !m) return -1;
+  if (m && (m->n_feat != cfg[CF_NFEAT] || m->n_slot != cfg[CF_NSLOT] || m->n_out != cfg[CF_NOUT]))
+    return -1;
+  if (mode == OL_INJECT && !lat_table) return -1;
+  int64_t* pred_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_sub + 1));
+  pred_off[0] = 0;
+  for (int32_t k = 0; k < n_sub; ++k) {
+    if (len[k] < 1 || warm[k] < 0 || start[k] - warm[k] < 0 || start[k] + len[k] > n_instr) {
+      free(pred_off);
+      return -1;
+    }
+    pred_off[k + 1] = pred_off[k] + warm[k] + len[k];
+  }
+  sim_job J;
+  memset(&J, 0, sizeof(J));
+  J.m = m; J.cfg = cfg; J.feat = feat; J.n_sub = n_sub;
+  J.start = start; J.len = len; J.warm = warm; J.pred_off = pred_off;
+  J.mode = mode; J.lat_table = lat_table;
+  J.fetch = fetch; J.drain = drain; J.final_tick = final_tick; J.warm_tick = warm_tick;
+  J.logits_out = logits_out; J.lat_out = lat_out;
+  pthread_mutex_init(&J.mu, NULL);
+  if (n_threads <= 0) n_threads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
+  if (n_threads > n_sub) n_threads = n_sub;
+  if (n_threads < 1) n_threads = 1;
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)n_threads);
+  for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, sim_worker, &J);
+  for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+  free(th);
+  pthread_mutex_destroy(&J.mu);
+  if (counters) { counters[0] = J.counters[0]; counters[1] = J.counters[1]; }
+  free(pred_off);
+  return 0;
+}

@@ -1,0 +1,278 @@
+"""Seeded synthetic inputs shared by the oracle and the HIP path.
+
+This module holds input generation only: instruction-trace feature rows,
+random-init predictor weights, sub-trace length streams and injected latency
+tables.  None of the simulator's or the predictor's arithmetic lives here.
+
+Every draw comes from a counter-based SplitMix64 stream (Steele, Lea and
+Flood, "Fast splittable pseudorandom number generators", OOPSLA 2014): the
+value for (seed, stream, counter) is the SplitMix64 output mixer applied to
+``key(seed, stream) + (counter + 1) * GOLDEN``.  A trace row therefore depends
+only on its instruction index, never on how the trace is later partitioned
+or on how many threads generate it.
+
+Feature layout (the paper lists static-property, instruction-context and
+history-context features in its feature table, Sec. 2.2; its per-instruction
+counts do not add up, so a synthetic layout with the same roles is used):
+
+  D = 32:  [0,5)   op class one-hot (int-ALU, load, store, branch, FP)
+           [5,26)  3 register ids, each one-hot into 7 buckets, bucket = id*7//32
+           [26,29) data access level one-hot (L1, L2, DRAM)
+           [29]    branch-mispredict flag (drawn for branches only)
+           [30]    residence latency   (dynamic, written by the simulator)
+           [31]    execution latency   (dynamic, written by the simulator)
+  D = 50:  [0,30)  as above, [30,47) reserved zeros,
+           [47] residence, [48] execution, [49] store latency (dynamic)
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+GOLDEN = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+OP_PROBS = (0.40, 0.25, 0.10, 0.15, 0.10)  # int-ALU, load, store, branch, FP
+OP_INT, OP_LOAD, OP_STORE, OP_BRANCH, OP_FP = range(5)
+LEVEL_PROBS = (0.90, 0.07, 0.03)  # L1, L2, DRAM
+MISPREDICT_RATE = 0.05  # of branch instructions
+N_REG_IDS = 32
+N_REG_BUCKETS = 7
+
+
+def _mix(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> np.uint64(30))) * _M1
+        z = (z ^ (z >> np.uint64(27))) * _M2
+    return z ^ (z >> np.uint64(31))
+
+
+def stream_key(seed: int, stream: int) -> np.uint64:
+    base = np.array([(seed * 0x632BE59BD9B4E019 + stream * 0x85EBCA77C2B2AE63)
+                     & 0xFFFFFFFFFFFFFFFF], dtype=np.uint64)
+    return _mix(base)[0]
+
+
+def u64(seed: int, stream: int, counter) -> np.ndarray:
+    """Raw 64-bit SplitMix64 outputs for an array of counters."""
+    c = np.asarray(counter, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = stream_key(seed, stream) + (c + np.uint64(1)) * GOLDEN
+    return _mix(z)
+
+
+def uniform(seed: int, stream: int, counter) -> np.ndarray:
+    """Doubles in [0, 1) from the top 53 bits."""
+    return (u64(seed, stream, counter) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+def _categorical(u: np.ndarray, probs: Sequence[float]) -> np.ndarray:
+    edges = np.cumsum(np.asarray(probs, dtype=np.float64))
+    edges[-1] = 1.0 + 1e-12
+    return np.searchsorted(edges, u, side="right").astype(np.int64)
+
+
+# ---------------------------------------------------------------- traces ---
+
+TRACE_STREAM = 11
+N_FIELDS = 6  # op, reg0, reg1, reg2, level, mispredict
+
+
+def trace_fields(seed: int, lo: int, hi: int) -> dict:
+    """Categorical fields of instructions [lo, hi) of the trace."""
+    n = np.arange(lo, hi, dtype=np.uint64)
+    base = n * np.uint64(N_FIELDS)
+    op = _categorical(uniform(seed, TRACE_STREAM, base + np.uint64(0)), OP_PROBS)
+    regs = np.stack([(u64(seed, TRACE_STREAM, base + np.uint64(1 + r)) >> np.uint64(59)).astype(np.int64)
+                     for r in range(3)], axis=1)
+    level = _categorical(uniform(seed, TRACE_STREAM, base + np.uint64(4)), LEVEL_PROBS)
+    mis = (uniform(seed, TRACE_STREAM, base + np.uint64(5)) < MISPREDICT_RATE) & (op == OP_BRANCH)
+    return {"op": op, "regs": regs, "level": level, "mispredict": mis.astype(np.int64)}
+
+
+def pack_codes(fields: dict) -> np.ndarray:
+    """One uint32 per instruction: op | r0<<3 | r1<<8 | r2<<13 | level<<18 | mis<<20."""
+    r = fields["regs"]
+    code = (fields["op"] | (r[:, 0] << 3) | (r[:, 1] << 8) | (r[:, 2] << 13)
+            | (fields["level"] << 18) | (fields["mispredict"] << 20))
+    return code.astype(np.uint32)
+
+
+def expand_codes(codes: np.ndarray, n_feat: int) -> np.ndarray:
+    """Feature rows (float32, dynamic columns zero) from packed codes."""
+    if n_feat not in (32, 50):
+        raise ValueError("feature layouts exist for D=32 and D=50")
+    c = np.asarray(codes, dtype=np.int64)
+    n = c.shape[0]
+    x = np.zeros((n, n_feat), dtype=np.float32)
+    rows = np.arange(n)
+    x[rows, c & 7] = 1.0
+    for r in range(3):
+        rid = (c >> (3 + 5 * r)) & 31
+        x[rows, 5 + 7 * r + (rid * N_REG_BUCKETS) // N_REG_IDS] = 1.0
+    x[rows, 26 + ((c >> 18) & 3)] = 1.0
+    x[:, 29] = ((c >> 20) & 1).astype(np.float32)
+    return x
+
+
+def trace_codes(seed: int, n_instr: int, lo: int = 0, hi: Optional[int] = None,
+                chunk: int = 1 << 22) -> np.ndarray:
+    hi = n_instr if hi is None else hi
+    out = np.empty(hi - lo, dtype=np.uint32)
+    for a in range(lo, hi, chunk):
+        b = min(hi, a + chunk)
+        out[a - lo:b - lo] = pack_codes(trace_fields(seed, a, b))
+    return out
+
+
+def trace_features(seed: int, n_instr: int, n_feat: int, lo: int = 0,
+                   hi: Optional[int] = None) -> np.ndarray:
+    return expand_codes(trace_codes(seed, n_instr, lo, hi), n_feat)
+
+
+def dynamic_columns(n_feat: int) -> Tuple[int, int, int]:
+    """(residence, execution, store) column of each layout; -1 = absent."""
+    return (30, 31, -1) if n_feat == 32 else (47, 48, 49)
+
+
+# --------------------------------------------------------------- weights ---
+
+@dataclass(frozen=True)
+class Layer:
+    kind: int      # 0 = conv (kernel 2, stride 2), 1 = fully connected
+    c_in: int
+    c_out: int
+    relu: int
+
+
+CONV, FC = 0, 1
+
+
+def layer_param_shapes(layers: Sequence[Layer]) -> List[Tuple[Tuple[int, ...], Tuple[int]]]:
+    """PyTorch parameter shapes: conv weight [co][ci][2], fc weight [out][in]."""
+    out = []
+    for ly in layers:
+        if ly.kind == CONV:
+            out.append(((ly.c_out, ly.c_in, 2), (ly.c_out,)))
+        else:
+            out.append(((ly.c_out, ly.c_in), (ly.c_out,)))
+    return out
+
+
+WEIGHT_STREAM = 101
+OUT_GAIN = 8.0
+OUT_BIAS = (-6.0, 8.0)
+
+
+def init_weights(seed: int, layers: Sequence[Layer], out_bias: Optional[Sequence[float]] = OUT_BIAS,
+                 out_gain: float = OUT_GAIN):
+    """Random-init parameters, one SplitMix64 stream per tensor.
+
+    Hidden layers: weights U(+-sqrt(6/fan_in)) (He et al. 2015 uniform, which
+    keeps activation scale through ReLU), biases U(+-1/sqrt(fan_in)).
+    Output layer: weights U(+-out_gain/sqrt(fan_in)) and bias ``out_bias``
+    (fetch, execution), chosen so that rounded latencies are spread out
+    (fetch mostly 0-3, execution ~4-40 cycles) instead of all rounding to the
+    bias.  Returns lists of float32 arrays in PyTorch layouts."""
+    ws, bs = [], []
+    last = len(layers) - 1
+    for li, (ly, (wshape, bshape)) in enumerate(zip(layers, layer_param_shapes(layers))):
+        fan_in = ly.c_in * (2 if ly.kind == CONV else 1)
+        wbound = (out_gain if li == last else math.sqrt(6.0)) / math.sqrt(fan_in)
+        bbound = 1.0 / math.sqrt(fan_in)
+        nw = int(np.prod(wshape))
+        w = (2.0 * uniform(seed, WEIGHT_STREAM + 2 * li, np.arange(nw)) - 1.0) * wbound
+        b = (2.0 * uniform(seed, WEIGHT_STREAM + 2 * li + 1, np.arange(bshape[0])) - 1.0) * bbound
+        ws.append(w.astype(np.float32).reshape(wshape))
+        bs.append(b.astype(np.float32))
+    if out_bias is not None:
+        bs[-1] = np.asarray(out_bias, dtype=np.float32).copy()
+    return ws, bs
+
+
+# ------------------------------------------------------ latency injection ---
+
+LAT_STREAM = 201
+
+
+def latency_table(seed: int, n_pred: int, n_out: int, f_max: int = 12, e_max: int = 48,
+                  heavy: float = 0.0) -> np.ndarray:
+    """Injected integer latencies [n_pred][n_out] (int32): fetch mostly 0-2,
+    execution skewed towards small values; ``heavy`` is the probability of a
+    long-latency outlier (drawn up to 8*e_max)."""
+    idx = np.arange(n_pred * n_out, dtype=np.uint64)
+    u = uniform(seed, LAT_STREAM, idx).reshape(n_pred, n_out)
+    v = uniform(seed, LAT_STREAM + 1, idx).reshape(n_pred, n_out)
+    t = np.zeros((n_pred, n_out), dtype=np.int64)
+    f = _categorical(u[:, 0], (0.35, 0.45, 0.10, 0.10))
+    f = np.where(f == 3, 3 + np.floor(v[:, 0] * (f_max - 2)).astype(np.int64), f)
+    t[:, 0] = f
+    for o in range(1, n_out):
+        e = np.floor((u[:, o] ** 2) * (e_max + 1)).astype(np.int64)
+        if heavy > 0:
+            e = np.where(v[:, o] < heavy, np.floor(u[:, o] * 8 * e_max).astype(np.int64), e)
+        t[:, o] = e
+    return t.astype(np.int32)
+
+
+# ------------------------------------------------------------ sub-traces ---
+
+LEN_STREAM = 301
+
+
+def loguniform_lengths(seed: int, n_sub: int, lo: float, hi: float) -> np.ndarray:
+    """round(exp(U(ln lo, ln hi))) per sub-trace (int64)."""
+    u = uniform(seed, LEN_STREAM, np.arange(n_sub))
+    return np.rint(np.exp(math.log(lo) + u * (math.log(hi) - math.log(lo)))).astype(np.int64)
+
+
+# --------------------------------------------------------------- configs ---
+
+@dataclass
+class Workload:
+    name: str
+    n_instr: int
+    n_feat: int
+    n_slot: int
+    layers: List[Layer]
+    n_sub: int = 1
+    warmup: int = 0
+    retire_width: int = 8
+    lat_max: int = 65535
+    n_out: int = 2
+    trace_seed: int = 1
+    weight_seed: int = 2
+    length_seed: int = 3
+    lengths: Optional[str] = None   # None = one trace split equally
+    len_range: Tuple[float, float] = (1e3, 2e5)
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def cols(self) -> Tuple[int, int, int]:
+        return dynamic_columns(self.n_feat)
+
+
+def net_small() -> List[Layer]:
+    """32 -> conv 32 -> conv 64 -> FC 2 over 16 slots."""
+    return [Layer(CONV, 32, 32, 1), Layer(CONV, 32, 64, 1), Layer(FC, 256, 2, 0)]
+
+
+def net_c3() -> List[Layer]:
+    """50 -> conv 64 -> conv 128 -> conv 256 -> FC 512 -> FC 2 over 111 slots."""
+    return [Layer(CONV, 50, 64, 1), Layer(CONV, 64, 128, 1), Layer(CONV, 128, 256, 1),
+            Layer(FC, 256 * 13, 512, 1), Layer(FC, 512, 2, 0)]
+
+
+def workload(name: str) -> Workload:
+    if name == "tiny":        # 10k instructions, one sub-trace, 16 slots x 32 features
+        return Workload("tiny", 10_000, 32, 16, net_small())
+    if name == "c3_1m":       # 1M instructions, 4,096 sub-traces, 256 warm-up, 111 x 50
+        return Workload("c3_1m", 1_000_000, 50, 111, net_c3(), n_sub=4096, warmup=256)
+    if name == "c3_uneven":   # 20k independent streams, log-uniform lengths 1e3..2e5
+        return Workload("c3_uneven", 0, 50, 111, net_c3(), n_sub=20_000, lengths="loguniform")
+    raise KeyError(name)
