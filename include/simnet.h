@@ -1,0 +1,167 @@
+/*
+ * simnet.h - C ABI of libsimnet.so, an MI355X (gfx950) implementation of the
+ * parallel simulation step loop of SimNet (Li et al., "SimNet: Accurate and
+ * High-Performance Computer Architecture Simulation using Deep Learning").
+ *
+ * One step advances every active sub-trace by one instruction:
+ *   1. build the instruction's model input from the trace and the sub-trace's
+ *      processor queue (Sec. 2.2: the instruction plus its in-flight context
+ *      instructions, each with residence and execution latency);
+ *   2. run the CNN latency predictor on the whole batch (Sec. 2.3; batched
+ *      across sub-traces as in Sec. 3.3);
+ *   3. round the predicted latencies to cycles, advance the sub-trace's clock
+ *      by the fetch latency, retire ready instructions in order at the retire
+ *      width and enqueue the new one (Sec. 3.2, context and clock management).
+ * The simulated time of a sub-trace is the sum of its fetch latencies plus
+ * the drain after its last fetch (Sec. 3.1, Eq. 1); the total is the sum
+ * over sub-traces (Sec. 3.3).
+ *
+ * Conventions
+ *   - Every call returns a sim_status; no exception crosses the ABI.  The
+ *     text of the last error of a context is available from sim_last_error.
+ *   - Device pointers are HIP device memory of the current device; the
+ *     caller owns every buffer it passes and the library never frees it.
+ *     Host arrays are read during the call only.
+ *   - All work is enqueued on config.stream (a hipStream_t; NULL = the
+ *     legacy default stream).  sim_step and predictor_fwd are asynchronous;
+ *     sim_run synchronises the stream before it returns.
+ *   - A context is not thread-safe; separate contexts are independent.
+ *   - Instruction counts and clock ticks are int64.
+ */
+#ifndef SIMNET_H
+#define SIMNET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SIMNET_API __attribute__((visibility("default")))
+
+typedef struct sim_ctx sim_ctx; /* opaque, owned by the library */
+
+typedef enum {
+  SIM_OK = 0,
+  SIM_EINVAL = -1,        /* an argument or a combination of them is invalid */
+  SIM_ENOMEM = -2,        /* a device or host allocation failed */
+  SIM_EDEVICE = -3,       /* a HIP call failed (message in sim_last_error) */
+  SIM_ESTATE = -4,        /* call not valid in the context's current state */
+  SIM_ENONFINITE = -5,    /* weights contain NaN or Inf */
+  SIM_EUNSUPPORTED = -6   /* valid request with no kernel for it (network shape, precision) */
+} sim_status;
+
+typedef enum { SIM_FP32 = 0, SIM_BF16 = 1, SIM_FP8E4M3 = 2 } sim_precision;
+
+/* Where the latencies that advance the clock come from.
+ *   PREDICT: the predictor's own rounded outputs (the simulation proper).
+ *   INJECT : lat_table; the predictor is not run.
+ *   SHADOW : lat_table advances the state; the predictor still runs on the
+ *            same windows and every prediction whose rounded value differs
+ *            from the table is counted in n_shadow_mismatch. */
+typedef enum { SIM_LAT_PREDICT = 0, SIM_LAT_INJECT = 1, SIM_LAT_SHADOW = 2 } sim_lat_mode;
+
+typedef enum { SIM_FEAT_F32 = 0 } sim_feat_dtype;
+
+/* One predictor layer.  kind 0: 1-D convolution over instructions, kernel 2,
+ * stride 2, no padding, output length floor(L/2) (Sec. 2.3: non-overlapping
+ * kernel-2 convolutions; odd lengths drop the unpaired last slot);
+ * kind 1: fully connected on the channel-major flattening (index c*L + p).
+ * relu != 0 applies ReLU after the layer. */
+typedef struct {
+  int32_t kind, c_in, c_out, relu;
+} sim_layer;
+
+typedef struct {
+  int32_t n_feat;        /* D: features per instruction (window width) */
+  int32_t n_slot;        /* L: window slots = 1 + context capacity C */
+  int32_t n_out;         /* predicted latencies per instruction: 2 (fetch, execution) */
+  int32_t retire_width;  /* W: in-order retirements per cycle, 1..16 */
+  int32_t col_res;       /* feature column receiving residence latency, -1 = none */
+  int32_t col_exe;       /* feature column receiving execution latency, -1 = none */
+  int32_t col_sto;       /* feature column receiving store latency (written 0), -1 = none */
+  int32_t lat_max;       /* rounded latencies are clamped to [0, lat_max] */
+  int32_t prec;          /* sim_precision of the predictor */
+  int32_t reserved;      /* must be 0 */
+  void* stream;          /* hipStream_t borrowed from the caller */
+} sim_config;
+
+/* The trace and its partition into sub-traces.  Sub-trace k simulates trace
+ * rows [start[k] - warm[k], start[k] + len[k]) in order; the first warm[k]
+ * are warm-up (predicted and queued, their fetch cycles not counted). */
+typedef struct {
+  const void* feat;      /* DEVICE, [n_instr][n_feat] float32 row-major; the
+                            dynamic columns are ignored.  Borrowed: must stay
+                            valid and unchanged for the context's lifetime. */
+  int32_t feat_dtype;    /* sim_feat_dtype */
+  int32_t n_sub;         /* number of sub-traces K >= 1 */
+  int64_t n_instr;       /* rows in feat, < 2^31 */
+  const int64_t* start;  /* HOST [n_sub] */
+  const int64_t* len;    /* HOST [n_sub], each >= 1 */
+  const int32_t* warm;   /* HOST [n_sub], each >= 0 and <= start[k] */
+} sim_trace;
+
+/* Results of sim_run.  Scalars are always written; each per-sub-trace array
+ * is a HOST buffer of n_sub int64 owned by the caller, or NULL to skip. */
+typedef struct {
+  int64_t total_cycles;      /* sum over k of (final_tick[k] - warm_tick[k]) */
+  int64_t measured_instr;    /* sum of len */
+  int64_t predicted_instr;   /* sum of warm + len */
+  int64_t n_clamped;         /* rounded predictions outside [0, lat_max] */
+  int64_t n_nonfinite;       /* non-finite predictions (used as 0) */
+  int64_t n_shadow_mismatch; /* SHADOW mode: rounded prediction != table */
+  int64_t* fetch_cycles;     /* T_last - T_warm: sum of counted fetch latencies */
+  int64_t* drain_cycles;     /* final - T_last: Eq. 1's drain */
+  int64_t* final_tick;       /* curTick when the queue has emptied */
+  int64_t* warm_tick;        /* curTick after the last warm-up instruction (0 if none) */
+} sim_result;
+
+/* Pure host check of a configuration and trace description; touches no
+ * device memory (feat is only checked for non-NULL).  SIM_OK or SIM_EINVAL. */
+SIMNET_API int sim_validate_config(const sim_config* cfg, const sim_trace* trace);
+
+/* Create a context: validates, copies the sub-trace table to the device and
+ * allocates the per-sub-trace state (processor queue of n_slot-1 entries,
+ * clock, retire history).  *out is NULL on failure. */
+SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx** out);
+
+/* Load predictor parameters.  params is the concatenation, layer by layer,
+ * of weight then bias in PyTorch layouts (conv [c_out][c_in][2], fc
+ * [out][in]), float32, on the device if on_device != 0 else on the host.
+ * The parameters are copied (and re-laid-out for the kernels), so the
+ * caller may free them afterwards.  The layer list must map the window
+ * [n_slot][n_feat] to n_out outputs; SIM_EUNSUPPORTED if no kernel exists for
+ * the shape, SIM_ENONFINITE on NaN/Inf.  Resets the simulation state. */
+SIMNET_API int sim_load_weights(sim_ctx* ctx, const sim_layer* layers, int32_t n_layers,
+                     const float* params, int32_t on_device);
+
+/* Advance every unfinished sub-trace by up to n_steps instructions
+ * (asynchronous).  lat_table (DEVICE int32, needed for INJECT and SHADOW) is
+ * indexed by the sub-trace's simulated position: row
+ * sum_{k'<k}(warm[k']+len[k']) + p, column o (0 fetch, 1 execution). */
+SIMNET_API int sim_step(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode, const int32_t* lat_table);
+
+/* Run every sub-trace to completion, synchronise, and fill *res.  A context
+ * that has completed must be sim_reset before it runs again. */
+SIMNET_API int sim_run(sim_ctx* ctx, int32_t lat_mode, const int32_t* lat_table, sim_result* res);
+
+/* Return every sub-trace to its first instruction (asynchronous). */
+SIMNET_API int sim_reset(sim_ctx* ctx);
+
+/* Record every prediction's raw float32 outputs into a DEVICE buffer of
+ * [sum(warm+len)][n_out] float32, indexed like lat_table (NULL stops
+ * recording).  Used for parity checks on identical windows. */
+SIMNET_API int sim_record_logits(sim_ctx* ctx, float* logits);
+
+/* Predictor forward on explicit windows (Sec. 2.3): x is DEVICE
+ * [B][n_slot][n_feat] float32, logits DEVICE [B][n_out] float32.
+ * save_or_null is reserved for the training path and must be NULL. */
+SIMNET_API int predictor_fwd(sim_ctx* ctx, const void* x, int64_t B, float* logits, void* save_or_null);
+
+SIMNET_API void sim_destroy(sim_ctx* ctx);
+SIMNET_API const char* sim_last_error(const sim_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIMNET_H */

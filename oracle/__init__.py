@@ -111,6 +111,15 @@ def partition(n_instr: int, n_sub: int, warm_max: int = 0):
     return start, length, warm
 
 
+def default_threads() -> int:
+    """CPU threads for the oracle: the cores this process may use, at most 16."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
 def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=65535):
     return np.array([n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max],
                     dtype=np.int32)
@@ -140,6 +149,8 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
         lat_table = np.ascontiguousarray(lat_table, np.int32)
         assert lat_table.size >= n_pred * n_out
     counters = np.zeros(2, np.int64)
+    if threads <= 0:
+        threads = default_threads()
     rc = lib().ol_simulate(model.ptr if model else None, cfg,
                            feat.ctypes.data if feat is not None else None, n_instr, K,
                            start, length, warm, mode,

@@ -1,0 +1,232 @@
+"""Thin Python binding of libsimnet.so (C ABI in include/simnet.h).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  There
+is no fallback: if the built library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsimnet.so")
+
+SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_ENONFINITE, SIM_EUNSUPPORTED = \
+    0, -1, -2, -3, -4, -5, -6
+SIM_FP32, SIM_BF16, SIM_FP8E4M3 = 0, 1, 2
+SIM_LAT_PREDICT, SIM_LAT_INJECT, SIM_LAT_SHADOW = 0, 1, 2
+SIM_FEAT_F32 = 0
+CONV, FC = 0, 1
+
+STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVICE",
+                -4: "SIM_ESTATE", -5: "SIM_ENONFINITE", -6: "SIM_EUNSUPPORTED"}
+
+EXPORTED = ("sim_validate_config", "sim_init", "sim_load_weights", "sim_step", "sim_run",
+            "sim_reset", "sim_record_logits", "predictor_fwd", "sim_destroy", "sim_last_error")
+
+
+class sim_layer(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("c_in", C.c_int32), ("c_out", C.c_int32),
+                ("relu", C.c_int32)]
+
+
+class sim_config(C.Structure):
+    _fields_ = [("n_feat", C.c_int32), ("n_slot", C.c_int32), ("n_out", C.c_int32),
+                ("retire_width", C.c_int32), ("col_res", C.c_int32), ("col_exe", C.c_int32),
+                ("col_sto", C.c_int32), ("lat_max", C.c_int32), ("prec", C.c_int32),
+                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+
+
+class sim_trace(C.Structure):
+    _fields_ = [("feat", C.c_void_p), ("feat_dtype", C.c_int32), ("n_sub", C.c_int32),
+                ("n_instr", C.c_int64), ("start", C.POINTER(C.c_int64)),
+                ("len", C.POINTER(C.c_int64)), ("warm", C.POINTER(C.c_int32))]
+
+
+class sim_result(C.Structure):
+    _fields_ = [("total_cycles", C.c_int64), ("measured_instr", C.c_int64),
+                ("predicted_instr", C.c_int64), ("n_clamped", C.c_int64),
+                ("n_nonfinite", C.c_int64), ("n_shadow_mismatch", C.c_int64),
+                ("fetch_cycles", C.POINTER(C.c_int64)), ("drain_cycles", C.POINTER(C.c_int64)),
+                ("final_tick", C.POINTER(C.c_int64)), ("warm_tick", C.POINTER(C.c_int64))]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2105_05821_amd.build` (hipcc, gfx950)")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.sim_validate_config.argtypes = [C.POINTER(sim_config), C.POINTER(sim_trace)]
+        L.sim_init.argtypes = [C.POINTER(sim_config), C.POINTER(sim_trace), C.POINTER(P)]
+        L.sim_load_weights.argtypes = [P, C.POINTER(sim_layer), C.c_int32, P, C.c_int32]
+        L.sim_step.argtypes = [P, C.c_int32, C.c_int32, P]
+        L.sim_run.argtypes = [P, C.c_int32, P, C.POINTER(sim_result)]
+        L.sim_reset.argtypes = [P]
+        L.sim_record_logits.argtypes = [P, P]
+        L.predictor_fwd.argtypes = [P, P, C.c_int64, P, P]
+        L.sim_destroy.argtypes = [P]
+        L.sim_destroy.restype = None
+        L.sim_last_error.argtypes = [P]
+        L.sim_last_error.restype = C.c_char_p
+        for n in EXPORTED[:-2]:
+            getattr(L, n).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class SimError(RuntimeError):
+    def __init__(self, call: str, code: int, msg: str = ""):
+        super().__init__(f"{call} -> {STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return t.data_ptr()
+
+
+def make_config(n_feat: int, n_slot: int, cols: Sequence[int], retire_width: int = 8,
+                lat_max: int = 65535, prec: int = SIM_FP32, n_out: int = 2,
+                stream=None) -> sim_config:
+    return sim_config(n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max,
+                      prec, 0, stream)
+
+
+def make_trace(feat_ptr: Optional[int], n_instr: int, start, length, warm):
+    start = np.ascontiguousarray(start, np.int64)
+    length = np.ascontiguousarray(length, np.int64)
+    warm = np.ascontiguousarray(warm, np.int32)
+    tr = sim_trace(feat_ptr, SIM_FEAT_F32, start.shape[0], n_instr,
+                   start.ctypes.data_as(C.POINTER(C.c_int64)),
+                   length.ctypes.data_as(C.POINTER(C.c_int64)),
+                   warm.ctypes.data_as(C.POINTER(C.c_int32)))
+    tr._keep = (start, length, warm)
+    return tr
+
+
+def sim_validate_config(cfg: sim_config, trace: sim_trace) -> int:
+    return lib().sim_validate_config(C.byref(cfg), C.byref(trace))
+
+
+def partition(n_instr: int, n_sub: int, warm_max: int = 0):
+    """Equal contiguous sub-traces (the first n_instr mod n_sub get one more
+    instruction) with warm-up min(warm_max, start)."""
+    if n_sub < 1 or n_instr < n_sub:
+        raise ValueError("need 1 <= n_sub <= n_instr")
+    q, r = divmod(n_instr, n_sub)
+    length = np.full(n_sub, q, np.int64)
+    length[:r] += 1
+    start = np.zeros(n_sub, np.int64)
+    start[1:] = np.cumsum(length)[:-1]
+    warm = np.minimum(start, warm_max).astype(np.int32)
+    return start, length, warm
+
+
+class Simulator:
+    """One sim_ctx.  ``feat`` is a device float32 tensor [n_instr][n_feat]
+    that must outlive the simulator."""
+
+    def __init__(self, feat, n_slot: int, cols: Sequence[int], start, length, warm,
+                 retire_width: int = 8, lat_max: int = 65535, prec: int = SIM_FP32,
+                 stream=None):
+        import torch
+        if not feat.is_cuda or feat.dtype != torch.float32 or not feat.is_contiguous():
+            raise ValueError("feat must be a contiguous float32 device tensor")
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.feat = feat
+        self.cfg = make_config(feat.shape[1], n_slot, cols, retire_width, lat_max, prec,
+                               stream=self.stream.cuda_stream)
+        self.trace = make_trace(feat.data_ptr(), feat.shape[0], start, length, warm)
+        self.n_sub = int(self.trace.n_sub)
+        self.n_pred = int(np.sum(self.trace._keep[1]) + np.sum(self.trace._keep[2]))
+        h = C.c_void_p()
+        rc = lib().sim_init(C.byref(self.cfg), C.byref(self.trace), C.byref(h))
+        if rc != SIM_OK:
+            raise SimError("sim_init", rc)
+        self.ctx = h
+
+    def _check(self, call: str, rc: int):
+        if rc != SIM_OK:
+            raise SimError(call, rc, lib().sim_last_error(self.ctx).decode())
+
+    def load_weights(self, layers, params) -> None:
+        """params: flat float32 (numpy host array or device tensor), PyTorch
+        order: w0, b0, w1, b1, ..."""
+        arr = (sim_layer * len(layers))(*[sim_layer(l.kind, l.c_in, l.c_out, l.relu)
+                                          for l in layers])
+        if isinstance(params, np.ndarray):
+            params = np.ascontiguousarray(params, np.float32)
+            self._check("sim_load_weights",
+                        lib().sim_load_weights(self.ctx, arr, len(layers), params.ctypes.data, 0))
+        else:
+            self._check("sim_load_weights",
+                        lib().sim_load_weights(self.ctx, arr, len(layers), params.data_ptr(), 1))
+
+    def step(self, n_steps: int, lat_mode: int = SIM_LAT_PREDICT, lat_table=None) -> None:
+        self._check("sim_step", lib().sim_step(self.ctx, n_steps, lat_mode, _ptr(lat_table)))
+
+    def run(self, lat_mode: int = SIM_LAT_PREDICT, lat_table=None, per_sub: bool = True) -> dict:
+        K = self.n_sub
+        arrs = {k: np.zeros(K, np.int64) for k in ("fetch", "drain", "final", "warm_tick")}
+        P64 = C.POINTER(C.c_int64)
+        res = sim_result()
+        if per_sub:
+            res.fetch_cycles = arrs["fetch"].ctypes.data_as(P64)
+            res.drain_cycles = arrs["drain"].ctypes.data_as(P64)
+            res.final_tick = arrs["final"].ctypes.data_as(P64)
+            res.warm_tick = arrs["warm_tick"].ctypes.data_as(P64)
+        self._check("sim_run", lib().sim_run(self.ctx, lat_mode, _ptr(lat_table), C.byref(res)))
+        out = {"total": res.total_cycles, "measured": res.measured_instr,
+               "predicted": res.predicted_instr, "n_clamped": res.n_clamped,
+               "n_nonfinite": res.n_nonfinite, "n_shadow_mismatch": res.n_shadow_mismatch}
+        if per_sub:
+            out.update(arrs)
+        return out
+
+    def reset(self) -> None:
+        self._check("sim_reset", lib().sim_reset(self.ctx))
+
+    def record_logits(self, buf) -> None:
+        self._check("sim_record_logits", lib().sim_record_logits(self.ctx, _ptr(buf)))
+
+    def forward(self, x, logits=None):
+        import torch
+        if not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous():
+            raise ValueError("x must be a contiguous float32 device tensor")
+        B = x.shape[0]
+        if logits is None:
+            logits = torch.empty((B, 2), dtype=torch.float32, device=x.device)
+        self._check("predictor_fwd",
+                    lib().predictor_fwd(self.ctx, x.data_ptr(), B, logits.data_ptr(), None))
+        return logits
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None):
+            lib().sim_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def flat_params(ws, bs) -> np.ndarray:
+    parts = []
+    for w, b in zip(ws, bs):
+        parts.append(np.asarray(w, np.float32).ravel())
+        parts.append(np.asarray(b, np.float32).ravel())
+    return np.ascontiguousarray(np.concatenate(parts), np.float32)

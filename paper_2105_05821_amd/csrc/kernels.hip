@@ -1,0 +1,535 @@
+// HIP kernels of libsimnet.so for gfx950 (CDNA4).
+//
+// One workgroup owns a tile of MT = 16 sub-traces and runs the whole step
+// loop for them inside one launch (persistent: sub-traces are independent,
+// Sec. 3.3, so no grid-wide synchronisation is needed).  Each step:
+//   gather   - builds the tile's windows block by block straight into LDS
+//              from the trace rows and the sub-trace's processor queue
+//              (Sec. 2.2: current instruction with zero dynamic columns, then
+//              the in-flight instructions newest first with residence and
+//              execution latency);
+//   predict  - conv levels as MFMA GEMMs on LDS tiles (Sec. 2.3: kernel 2,
+//              stride 2, ReLU), the hidden FC accumulated block by block in
+//              MFMA accumulators, the final FC on the VALU;
+//   update   - rounding and the clock / queue update of Sec. 3.2 in its
+//              timestamp form: instruction i enters at T_i = T_{i-1} + F_i and
+//              leaves at r_i = max(T_i + E_i + 1, r_{i-1}, r_{i-W} + 1); the
+//              queue after the advance is the suffix with r > T_i.
+// The queue ring and the per-sub-trace scalars stay in LDS for the whole
+// launch and are written back to HBM when the launch ends.
+#include "simnet_internal.h"
+
+namespace simnet {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma_k16(v4f acc, float4 a, float4 b) {
+  // Four K=4 steps; lane group g = lane/16 supplies k = 4g + step, so one
+  // float4 per lane covers 16 consecutive k (A and B use the same mapping).
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
+  return acc;
+}
+
+template <class Net>
+struct Geo {
+  static constexpr int NT = Net::WAVES * 64;
+  static constexpr int SX = Net::BS * Net::DP + 4;               // window block, per sub-trace
+  static constexpr int SA1 = (Net::BS / 2) * Net::CH1 + 4;       // conv1 output
+  static constexpr int SA2 = (Net::BS / 4) * Net::CH2 + 4;       // conv2 output
+  static constexpr int SA3 = (Net::NCONV == 3 ? Net::CH3 : 0) + 4;  // conv3 output
+  static constexpr int SAL = Net::NCONV == 3 ? SA3 : SA2;        // last conv output
+};
+
+template <class Net>
+struct NetSmem {
+  float x[MT * Geo<Net>::SX];
+  float a1[MT * Geo<Net>::SA1];
+  float a2[MT * Geo<Net>::SA2];
+  float a3[Net::NCONV == 3 ? MT * Geo<Net>::SA3 : 4];
+  float red[Net::WAVES][MT][Net::NOUT];
+  float logit[MT][Net::NOUT];
+};
+
+// One conv level as a GEMM: rows (s, q) = MT sub-traces x P output positions,
+// A row (s, q) is the K = 2*C_in contiguous floats of input positions 2q, 2q+1
+// at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.
+template <int K, int N, int P, int WAVES, int SA, int SO>
+__device__ __forceinline__ void conv_stage(const float* __restrict__ A, float* __restrict__ O,
+                                           const float4* __restrict__ Bp,
+                                           const float* __restrict__ bias, bool relu, int wave,
+                                           int lane) {
+  constexpr int ROWS = MT * P;
+  constexpr int MTILES = ROWS / 16, NTILES = N / 16, KG = K / 16;
+  constexpr int TILES = MTILES * NTILES;
+  constexpr int TPW = TILES / WAVES;
+  static_assert(ROWS % 16 == 0 && N % 16 == 0 && K % 16 == 0, "tile shape");
+  static_assert(TILES % WAVES == 0 && TPW >= 1 && NTILES % TPW == 0, "wave split");
+  const int t0 = wave * TPW;
+  const int mt = t0 / NTILES, nt0 = t0 % NTILES;
+  const int arow = mt * 16 + (lane & 15);
+  const float* ap = A + (arow / P) * SA + (arow % P) * K + 4 * (lane >> 4);
+  v4f acc[TPW];
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int kg = 0; kg < KG; ++kg) {
+    const float4 a = *reinterpret_cast<const float4*>(ap + kg * 16);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const float4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
+      acc[j] = mfma_k16(acc[j], a, b);
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < TPW; ++j) {
+    const int col = (nt0 + j) * 16 + (lane & 15);
+    const float bb = bias[col];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = mt * 16 + 4 * (lane >> 4) + i;
+      float v = acc[j][i] + bb;
+      if (relu) v = fmaxf(v, 0.f);
+      O[(row / P) * SO + (row % P) * N + col] = v;
+    }
+  }
+}
+
+// Hidden FC, one block's K-slice: acc[MT rows][N cols] += A[MT][K] * B_j.
+template <int K, int N, int WAVES, int SA>
+__device__ __forceinline__ void hidden_accumulate(v4f* acc, const float* __restrict__ A,
+                                                  const float4* __restrict__ Bp, int wave,
+                                                  int lane) {
+  constexpr int NTILES = N / 16, KG = K / 16, TPW = NTILES / WAVES;
+  const int nt0 = wave * TPW;
+  const float* ap = A + (lane & 15) * SA + 4 * (lane >> 4);
+#pragma unroll 4
+  for (int kg = 0; kg < KG; ++kg) {
+    const float4 a = *reinterpret_cast<const float4*>(ap + kg * 16);
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) {
+      const float4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
+      acc[j] = mfma_k16(acc[j], a, b);
+    }
+  }
+}
+
+// The whole predictor on one tile of MT windows.  fill(j, X) writes block j
+// of every window (slots j*BS .. j*BS+BS-1, DP floats each, layout
+// X[s*SX + t*DP + c]) and is called by all threads; the raw outputs land in
+// sm.logit.  relu_mask bit l = ReLU after layer l.
+template <class Net, class Fill>
+__device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
+                                             NetSmem<Net>& sm, Fill&& fill) {
+  using G = Geo<Net>;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int HT = Net::HID > 0 ? (Net::HID / 16) / Net::WAVES : 1;
+  v4f hacc[HT];
+#pragma unroll
+  for (int j = 0; j < HT; ++j) hacc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+  // VALU final FC directly after the convs: (s, o) pairs, LPP lanes each.
+  constexpr int LPP = G::NT / (MT * Net::NOUT);
+  constexpr int CPL = Net::CHL / LPP;
+  float fpart = 0.f;
+  const int fpair = tid / LPP, fsub = tid % LPP;
+  const int fs = fpair / Net::NOUT, fo = fpair % Net::NOUT;
+
+  for (int j = 0; j < Net::NB; ++j) {
+    fill(j, sm.x);
+    __syncthreads();
+    conv_stage<2 * Net::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1>(
+        sm.x, sm.a1, reinterpret_cast<const float4*>(wt.conv_w[0]), wt.conv_b[0],
+        relu_mask & 1u, wave, lane);
+    __syncthreads();
+    conv_stage<2 * Net::CH1, Net::CH2, Net::BS / 4, Net::WAVES, G::SA1, G::SA2>(
+        sm.a1, sm.a2, reinterpret_cast<const float4*>(wt.conv_w[1]), wt.conv_b[1],
+        relu_mask & 2u, wave, lane);
+    __syncthreads();
+    if constexpr (Net::NCONV == 3) {
+      conv_stage<2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3>(
+          sm.a2, sm.a3, reinterpret_cast<const float4*>(wt.conv_w[2]), wt.conv_b[2],
+          relu_mask & 4u, wave, lane);
+      __syncthreads();
+    }
+    const float* last = Net::NCONV == 3 ? sm.a3 : sm.a2;
+    if constexpr (Net::HID > 0) {
+      const float4* bj = reinterpret_cast<const float4*>(wt.hid_w) +
+                         (size_t)j * (Net::CHL / 16) * (Net::HID / 16) * 64;
+      hidden_accumulate<Net::CHL, Net::HID, Net::WAVES, G::SAL>(hacc, last, bj, wave, lane);
+    } else {
+      const float* wrow = wt.last_w + ((size_t)j * Net::NOUT + fo) * Net::CHL + fsub * CPL;
+      const float* arow = last + fs * G::SAL + fsub * CPL;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) fpart = fmaf(arow[c], wrow[c], fpart);
+    }
+  }
+
+  if constexpr (Net::HID > 0) {
+    // bias + ReLU on the hidden layer, then the final FC: each lane holds 4
+    // rows x HT columns; reduce over the 16 lanes sharing rows, then waves.
+    const bool hrelu = relu_mask & (1u << Net::NCONV);
+    float p[4][Net::NOUT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int o = 0; o < Net::NOUT; ++o) p[i][o] = 0.f;
+#pragma unroll
+    for (int jj = 0; jj < HT; ++jj) {
+      const int col = (wave * HT + jj) * 16 + (lane & 15);
+      const float bb = wt.hid_b[col];
+      float wo[Net::NOUT];
+#pragma unroll
+      for (int o = 0; o < Net::NOUT; ++o) wo[o] = wt.last_w[o * Net::HID + col];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        float h = hacc[jj][i] + bb;
+        if (hrelu) h = fmaxf(h, 0.f);
+#pragma unroll
+        for (int o = 0; o < Net::NOUT; ++o) p[i][o] = fmaf(h, wo[o], p[i][o]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int o = 0; o < Net::NOUT; ++o) {
+        float v = p[i][o];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        v += __shfl_xor(v, 4);
+        v += __shfl_xor(v, 8);
+        if ((lane & 15) == 0) sm.red[wave][4 * (lane >> 4) + i][o] = v;
+      }
+    __syncthreads();
+    if (tid < MT * Net::NOUT) {
+      const int s = tid / Net::NOUT, o = tid % Net::NOUT;
+      float v = 0.f;
+#pragma unroll
+      for (int w = 0; w < Net::WAVES; ++w) v += sm.red[w][s][o];
+      v += wt.last_b[o];
+      if (relu_mask & (1u << (Net::NCONV + 1))) v = fmaxf(v, 0.f);
+      sm.logit[s][o] = v;
+    }
+  } else {
+#pragma unroll
+    for (int m = 1; m < LPP; m <<= 1) fpart += __shfl_xor(fpart, m);
+    if (fsub == 0) {
+      float v = fpart + wt.last_b[fo];
+      if (relu_mask & (1u << Net::NCONV)) v = fmaxf(v, 0.f);
+      sm.logit[fs][fo] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Rounded latency in cycles: nearest, ties to even; non-finite -> 0;
+// clamped to [0, lat_max].
+__device__ __forceinline__ int32_t round_latency(float v, int32_t lat_max, uint32_t& clamped,
+                                                 uint32_t& nonfinite) {
+  if (!isfinite(v)) {
+    ++nonfinite;
+    return 0;
+  }
+  const float r = rintf(v);
+  if (r < 0.f) {
+    ++clamped;
+    return 0;
+  }
+  if (r > (float)lat_max) {
+    ++clamped;
+    return lat_max;
+  }
+  return (int32_t)r;
+}
+
+template <class Net>
+struct StepSmem {
+  NetSmem<Net> net;
+  int32_t q_idx[MT][Net::C];
+  int32_t q_e[MT][Net::C];
+  int64_t q_t[MT][Net::C];
+  int64_t q_r[MT][Net::C];
+  int64_t rw[MT][WMAX];
+  int64_t cur[MT], t_w[MT], r_prev[MT], pos[MT], first[MT], n_pos[MT], pred_off[MT];
+  int32_t head[MT], count[MT], warm[MT], active[MT];
+};
+
+template <class Net, bool RUN_NET>
+__global__ void __launch_bounds__(Net::WAVES * 64)
+    step_kernel(DevWeights wt, uint32_t relu_mask, DevState st, StepParams p) {
+  constexpr int C = Net::C, NT = Geo<Net>::NT, D = Net::D, DP = Net::DP, BS = Net::BS;
+  __shared__ StepSmem<Net> sm;
+  const int tid = threadIdx.x;
+  const int k0 = blockIdx.x * MT;
+
+  if (tid < MT) {
+    const int k = k0 + tid;
+    int act = 0;
+    if (k < p.n_sub) {
+      sm.cur[tid] = st.cur[k];
+      sm.t_w[tid] = st.t_w[k];
+      sm.r_prev[tid] = st.r_prev[k];
+      sm.pos[tid] = st.pos[k];
+      sm.first[tid] = st.first[k];
+      sm.n_pos[tid] = st.n_pos[k];
+      sm.pred_off[tid] = st.pred_off[k];
+      sm.head[tid] = st.head[k];
+      sm.count[tid] = st.count[k];
+      sm.warm[tid] = st.warm[k];
+      for (int i = 0; i < p.W; ++i) sm.rw[tid][i] = st.rw[(size_t)k * WMAX + i];
+      act = sm.pos[tid] < sm.n_pos[tid];
+    }
+    sm.active[tid] = act;
+  }
+  for (int i = tid; i < MT * C; i += NT) {
+    const int s = i / C, e = i % C, k = k0 + s;
+    if (k < p.n_sub) {
+      const size_t g = (size_t)k * C + e;
+      sm.q_idx[s][e] = st.q_idx[g];
+      sm.q_e[s][e] = st.q_e[g];
+      sm.q_t[s][e] = st.q_t[g];
+      sm.q_r[s][e] = st.q_r[g];
+    }
+  }
+  uint32_t n_clamped = 0, n_nonfinite = 0, n_mismatch = 0, n_pred = 0;
+  int any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
+
+  for (int it = 0; it < p.n_steps && any; ++it) {
+    if (RUN_NET) {
+      // window block j for the tile: TPR threads per (sub-trace, slot) row
+      constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+      static_assert(NT % ROWS == 0 && DP % TPR == 0, "gather split");
+      const int row = tid / TPR, part = tid % TPR;
+      const int s = row / BS, t = row % BS;
+      auto fill = [&](int j, float* X) {
+        const int w = j * BS + t;
+        int64_t idx = -1;
+        float res = 0.f, ex = 0.f;
+        if (sm.active[s]) {
+          if (w == 0) {
+            idx = sm.first[s] + sm.pos[s];
+          } else if (w <= sm.count[s]) {
+            int e = sm.head[s] + sm.count[s] - w;
+            e = e >= C ? e - C : e;
+            idx = sm.q_idx[s][e];
+            res = (float)(sm.cur[s] - sm.q_t[s][e]);
+            ex = (float)sm.q_e[s][e];
+          }
+        }
+        float* dst = X + s * Geo<Net>::SX + t * DP;
+        const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
+#pragma unroll
+        for (int cc = 0; cc < CPT; ++cc) {
+          const int c = part * CPT + cc;
+          float v = (idx >= 0 && c < D) ? src[c] : 0.f;
+          if (c == p.col_res) v = res;
+          if (c == p.col_exe) v = ex;
+          if (c == p.col_sto) v = 0.f;
+          dst[c] = v;
+        }
+      };
+      predict_tile<Net>(wt, relu_mask, sm.net, fill);
+    }
+
+    if (tid < MT && sm.active[tid]) {
+      const int s = tid, k = k0 + s;
+      const int64_t pos = sm.pos[s];
+      const int64_t g = sm.pred_off[s] + pos;
+      int32_t lat[Net::NOUT];
+      if (RUN_NET) {
+#pragma unroll
+        for (int o = 0; o < Net::NOUT; ++o) {
+          const float v = sm.net.logit[s][o];
+          if (p.logits_out) p.logits_out[g * Net::NOUT + o] = v;
+          lat[o] = round_latency(v, p.lat_max, n_clamped, n_nonfinite);
+        }
+        ++n_pred;
+      }
+      if (p.lat_mode != 0) {
+#pragma unroll
+        for (int o = 0; o < Net::NOUT; ++o) {
+          const int32_t inj = p.lat_table[g * Net::NOUT + o];
+          if (RUN_NET && inj != lat[o]) ++n_mismatch;
+          lat[o] = inj;
+        }
+      }
+      const int64_t T = sm.cur[s] + lat[0];
+      int head = sm.head[s], count = sm.count[s];
+      while (count > 0 && sm.q_r[s][head] <= T) {  // retired by T: a prefix (r is monotone)
+        head = head + 1 == C ? 0 : head + 1;
+        --count;
+      }
+      int64_t r = T + lat[1] + 1;
+      r = r > sm.r_prev[s] ? r : sm.r_prev[s];
+      const int wi = (int)(pos % p.W);
+      if (pos >= p.W) {
+        const int64_t rb = sm.rw[s][wi] + 1;
+        r = r > rb ? r : rb;
+      }
+      sm.rw[s][wi] = r;
+      int slot = head + count;
+      slot = slot >= C ? slot - C : slot;
+      if (count == C) {
+        head = head + 1 == C ? 0 : head + 1;  // only the newest C stay visible
+      } else {
+        ++count;
+      }
+      sm.q_idx[s][slot] = (int32_t)(sm.first[s] + pos);
+      sm.q_e[s][slot] = lat[1];
+      sm.q_t[s][slot] = T;
+      sm.q_r[s][slot] = r;
+      sm.head[s] = head;
+      sm.count[s] = count;
+      sm.r_prev[s] = r;
+      sm.cur[s] = T;
+      sm.pos[s] = pos + 1;
+      if (pos + 1 == sm.warm[s]) sm.t_w[s] = T;
+      if (pos + 1 == sm.n_pos[s]) {  // last instruction: drain ends at r (Eq. 1)
+        st.fetch[k] = T - sm.t_w[s];
+        st.drain[k] = r - T;
+        st.final_tick[k] = r;
+        st.warm_tick[k] = sm.t_w[s];
+        sm.active[s] = 0;
+      }
+    }
+    any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
+  }
+
+  if (tid < MT) {
+    const int k = k0 + tid;
+    if (k < p.n_sub) {
+      st.cur[k] = sm.cur[tid];
+      st.t_w[k] = sm.t_w[tid];
+      st.r_prev[k] = sm.r_prev[tid];
+      st.pos[k] = sm.pos[tid];
+      st.head[k] = sm.head[tid];
+      st.count[k] = sm.count[tid];
+      for (int i = 0; i < p.W; ++i) st.rw[(size_t)k * WMAX + i] = sm.rw[tid][i];
+    }
+    if (n_clamped) atomicAdd(&st.counters[0], (unsigned long long)n_clamped);
+    if (n_nonfinite) atomicAdd(&st.counters[1], (unsigned long long)n_nonfinite);
+    if (n_mismatch) atomicAdd(&st.counters[2], (unsigned long long)n_mismatch);
+    if (n_pred) atomicAdd(&st.counters[3], (unsigned long long)n_pred);
+  }
+  for (int i = tid; i < MT * C; i += NT) {
+    const int s = i / C, e = i % C, k = k0 + s;
+    if (k < p.n_sub) {
+      const size_t g = (size_t)k * C + e;
+      st.q_idx[g] = sm.q_idx[s][e];
+      st.q_e[g] = sm.q_e[s][e];
+      st.q_t[g] = sm.q_t[s][e];
+      st.q_r[g] = sm.q_r[s][e];
+    }
+  }
+}
+
+template <class Net>
+__global__ void __launch_bounds__(Net::WAVES * 64)
+    forward_kernel(DevWeights wt, uint32_t relu_mask, const float* __restrict__ x, int64_t B,
+                   float* __restrict__ logits) {
+  constexpr int NT = Geo<Net>::NT, D = Net::D, DP = Net::DP, BS = Net::BS, L = Net::L;
+  __shared__ NetSmem<Net> sm;
+  const int tid = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * MT;
+  constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+  const int row = tid / TPR, part = tid % TPR;
+  const int s = row / BS, t = row % BS;
+  auto fill = [&](int j, float* X) {
+    const int64_t b = b0 + s;
+    const int w = j * BS + t;
+    const float* src = x + ((b < B ? b : 0) * L + w) * D;
+    float* dst = X + s * Geo<Net>::SX + t * DP;
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+      const int c = part * CPT + cc;
+      dst[c] = (b < B && c < D) ? src[c] : 0.f;
+    }
+  };
+  predict_tile<Net>(wt, relu_mask, sm, fill);
+  if (tid < MT * Net::NOUT) {
+    const int ss = tid / Net::NOUT, o = tid % Net::NOUT;
+    if (b0 + ss < B) logits[(b0 + ss) * Net::NOUT + o] = sm.logit[ss][o];
+  }
+}
+
+__global__ void reset_kernel(DevState st, int32_t n_sub, int32_t C) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_sub) {
+    st.cur[i] = 0;
+    st.t_w[i] = 0;
+    st.r_prev[i] = 0;
+    st.pos[i] = 0;
+    st.head[i] = 0;
+    st.count[i] = 0;
+    st.fetch[i] = 0;
+    st.drain[i] = 0;
+    st.final_tick[i] = 0;
+    st.warm_tick[i] = 0;
+    for (int w = 0; w < WMAX; ++w) st.rw[i * WMAX + w] = 0;
+    for (int e = 0; e < C; ++e) {
+      st.q_idx[i * C + e] = 0;
+      st.q_e[i * C + e] = 0;
+      st.q_t[i * C + e] = 0;
+      st.q_r[i * C + e] = 0;
+    }
+  }
+  if (i < NCOUNTERS) st.counters[i] = 0;
+}
+
+// total = sum_k (final_tick[k] - warm_tick[k]), one workgroup.
+__global__ void __launch_bounds__(256) total_kernel(DevState st, int32_t n_sub, int64_t* total) {
+  __shared__ long long part[4];
+  long long acc = 0;
+  for (int k = threadIdx.x; k < n_sub; k += 256) acc += st.final_tick[k] - st.warm_tick[k];
+  for (int m = 32; m >= 1; m >>= 1) acc += __shfl_xor(acc, m);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) *total = part[0] + part[1] + part[2] + part[3];
+}
+
+template <class Net>
+static hipError_t launch_step_t(const DevWeights& w, uint32_t relu, const DevState& s,
+                                const StepParams& p, hipStream_t stream) {
+  const dim3 grid((p.n_sub + MT - 1) / MT), block(Geo<Net>::NT);
+  if (p.lat_mode == 1)
+    hipLaunchKernelGGL((step_kernel<Net, false>), grid, block, 0, stream, w, relu, s, p);
+  else
+    hipLaunchKernelGGL((step_kernel<Net, true>), grid, block, 0, stream, w, relu, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_step(int net, const DevWeights& w, uint32_t relu, const DevState& s,
+                       const StepParams& p, hipStream_t stream) {
+  return net == 0 ? launch_step_t<NetSmall>(w, relu, s, p, stream)
+                  : launch_step_t<NetC3>(w, relu, s, p, stream);
+}
+
+template <class Net>
+static hipError_t launch_forward_t(const DevWeights& w, uint32_t relu, const float* x, int64_t B,
+                                   float* logits, hipStream_t stream) {
+  const dim3 grid((unsigned)((B + MT - 1) / MT)), block(Geo<Net>::NT);
+  hipLaunchKernelGGL((forward_kernel<Net>), grid, block, 0, stream, w, relu, x, B, logits);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward(int net, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
+                          float* logits, hipStream_t stream) {
+  return net == 0 ? launch_forward_t<NetSmall>(w, relu, x, B, logits, stream)
+                  : launch_forward_t<NetC3>(w, relu, x, B, logits, stream);
+}
+
+hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (n_sub + threads - 1) / threads;
+  hipLaunchKernelGGL(reset_kernel, dim3(blocks > 0 ? blocks : 1), dim3(threads), 0, stream, s,
+                     n_sub, C);
+  return hipGetLastError();
+}
+
+hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream) {
+  hipLaunchKernelGGL(total_kernel, dim3(1), dim3(256), 0, stream, s, n_sub, total);
+  return hipGetLastError();
+}
+
+}  // namespace simnet

@@ -1,0 +1,101 @@
+// Internal declarations shared by the HIP kernels and the C-ABI host code of
+// libsimnet.so.  Not part of the public interface (include/simnet.h is).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace simnet {
+
+constexpr int MT = 16;       // sub-traces (windows) per workgroup tile: one MFMA row block
+constexpr int WMAX = 16;     // largest supported retire width
+constexpr int NCOUNTERS = 4; // clamped, non-finite, shadow mismatches, predictions
+
+// Compile-time shape of a supported predictor.  A kernel-2 stride-2 stack is
+// a tree: output position p of conv level l depends on input slots
+// [p*2^(l+1), (p+1)*2^(l+1)) only, so the window is processed in independent
+// blocks of BS = 2^NCONV slots, each producing one position of the last conv.
+// Slots past NB*BS feed no output (floor lengths) and are never read.
+struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
+  static constexpr int D = 32, L = 16, C = 15;
+  static constexpr int NCONV = 2, BS = 4, NB = 4;
+  static constexpr int DP = 32;              // features per slot as laid out in LDS
+  static constexpr int CH0 = 32, CH1 = 32, CH2 = 64, CH3 = 0;
+  static constexpr int HID = 0, NOUT = 2;
+  static constexpr int WAVES = 4;
+  static constexpr int CHL = CH2;            // channels of the last conv
+};
+struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -> FC 512 -> FC 2
+  static constexpr int D = 50, L = 111, C = 110;
+  static constexpr int NCONV = 3, BS = 8, NB = 13;
+  static constexpr int DP = 56;
+  static constexpr int CH0 = 56, CH1 = 64, CH2 = 128, CH3 = 256;
+  static constexpr int HID = 512, NOUT = 2;
+  static constexpr int WAVES = 8;
+  static constexpr int CHL = CH3;
+};
+
+// Weights re-laid-out for the kernels (device pointers, owned by the context).
+// conv level l: B_l[k][n] with k = t*CH_l + c (t = pair member, c = input
+// channel, zero for padded channels), packed per (k-group of 16, n-tile of 16)
+// as 64 lanes x 4 floats: lane holds B[kg*16 + 4*(lane/16) + s][nt*16 + lane%16].
+// Hidden FC (NetC3): one such packed matrix per block j with
+// B_j[c][n] = W1[n][c*NB + j].  Final FC: wlast[j][o][c] = Wf[o][c*NB + j]
+// when it follows the convs directly, else wlast[o][h] = W2[o][h].
+struct DevWeights {
+  const float* conv_w[3];
+  const float* conv_b[3];
+  const float* hid_w;
+  const float* hid_b;
+  const float* last_w;
+  const float* last_b;
+};
+
+struct DevState {
+  // sub-trace table
+  const int64_t* first;     // start - warm: trace row of position 0
+  const int64_t* n_pos;     // warm + len
+  const int32_t* warm;
+  const int64_t* pred_off;  // sum_{k'<k}(warm+len)
+  // per-sub-trace scalars
+  int64_t* cur;
+  int64_t* t_w;
+  int64_t* r_prev;
+  int64_t* pos;
+  int32_t* head;
+  int32_t* count;
+  int64_t* rw;              // [K][WMAX] retire times of the last W pushes
+  // processor queue ring [K][C]
+  int32_t* q_idx;
+  int32_t* q_e;
+  int64_t* q_t;
+  int64_t* q_r;
+  // results
+  int64_t* fetch;
+  int64_t* drain;
+  int64_t* final_tick;
+  int64_t* warm_tick;
+  unsigned long long* counters;
+};
+
+struct StepParams {
+  const float* feat;
+  int32_t n_sub;
+  int32_t W;
+  int32_t col_res, col_exe, col_sto;
+  int32_t lat_max;
+  int32_t lat_mode;
+  const int32_t* lat_table;
+  float* logits_out;
+  int32_t n_steps;
+};
+
+// Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3.  relu: bit l = ReLU
+// after layer l.
+hipError_t launch_step(int net, const DevWeights& w, uint32_t relu, const DevState& s,
+                       const StepParams& p, hipStream_t stream);
+hipError_t launch_forward(int net, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
+                          float* logits, hipStream_t stream);
+hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream);
+hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream);
+
+}  // namespace simnet

@@ -1,0 +1,78 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates configurations without touching a GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_2105_05821_amd as sn
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "simnet.h")).read()
+    return set(re.findall(r"^SIMNET_API\s+[\w\s\*]*?\b(\w+)\s*\(", text, re.M))
+
+
+def test_header_and_binding_agree():
+    assert declared_symbols() == set(sn.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = sn.lib()
+    for name in declared_symbols():
+        assert hasattr(L, name), name
+
+
+def good(n_sub=4, n_instr=1000, feat_ptr=0x1000):
+    cfg = sn.make_config(50, 111, (47, 48, 49))
+    s, l, w = sn.partition(n_instr, n_sub, 256)
+    return cfg, sn.make_trace(feat_ptr, n_instr, s, l, w)
+
+
+def test_validate_accepts_good_config():
+    cfg, tr = good()
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_OK
+
+
+@pytest.mark.parametrize("field,value", [("n_out", 3), ("retire_width", 0), ("retire_width", 17),
+                                         ("col_res", 50), ("col_exe", 47), ("lat_max", 0),
+                                         ("prec", 7), ("reserved", 1), ("n_slot", 1)])
+def test_validate_rejects_bad_config(field, value):
+    cfg, tr = good()
+    setattr(cfg, field, value)
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_EINVAL
+
+
+def test_validate_rejects_bad_trace():
+    cfg, _ = good()
+    s, l, w = sn.partition(1000, 4, 256)
+    assert sn.sim_validate_config(cfg, sn.make_trace(None, 1000, s, l, w)) == sn.SIM_EINVAL
+    bad_len = l.copy(); bad_len[2] = 0
+    assert sn.sim_validate_config(cfg, sn.make_trace(0x1000, 1000, s, bad_len, w)) == sn.SIM_EINVAL
+    bad_warm = w.copy(); bad_warm[1] = s[1] + 1
+    assert sn.sim_validate_config(cfg, sn.make_trace(0x1000, 1000, s, l, bad_warm)) == sn.SIM_EINVAL
+    over = l.copy(); over[-1] += 1
+    assert sn.sim_validate_config(cfg, sn.make_trace(0x1000, 1000, s, over, w)) == sn.SIM_EINVAL
+    assert sn.sim_validate_config(cfg, sn.make_trace(0x1000, 1 << 31, s, l, w)) == sn.SIM_EINVAL
+
+
+def test_partition_matches_oracle(oracle_lib):
+    for N, K, wm in [(1_000_000, 4096, 256), (10, 3, 0), (1000, 7, 300), (5, 5, 2)]:
+        a = sn.partition(N, K, wm)
+        b = oracle_lib.partition(N, K, wm)
+        for x, y in zip(a, b):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_product_does_not_import_oracle():
+    """The product package must not reach the oracle or any CPU fallback."""
+    src_dir = os.path.join(ROOT, "paper_2105_05821_amd")
+    for dirpath, _, files in os.walk(src_dir):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f
+                assert "simnet_oracle" not in text, f
