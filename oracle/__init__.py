@@ -50,14 +50,14 @@ def lib():
         L.ol_model_nout.restype = C.c_int
         L.ol_model_nout.argtypes = [P]
         L.ol_forward.restype = C.c_int
-        L.ol_forward.argtypes = [P, C.c_int64, f64p, f64p]
+        L.ol_forward.argtypes = [P, C.c_int64, f64p, f64p, P]
         L.ol_round.restype = C.c_int32
         L.ol_round.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_int32)]
         L.ol_partition.restype = C.c_int
         L.ol_partition.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i64p, i32p]
         L.ol_simulate.restype = C.c_int
         L.ol_simulate.argtypes = [P, i32p, P, C.c_int64, C.c_int32, i64p, i64p, i32p,
-                                  C.c_int32, P, i64p, i64p, i64p, i64p, P, P, i64p, C.c_int32]
+                                  C.c_int32, P, i64p, i64p, i64p, i64p, P, P, P, i64p, C.c_int32]
         _lib = L
     return _lib
 
@@ -88,12 +88,16 @@ class Model:
             _lib.ol_model_free(self.ptr)
             self.ptr = None
 
-    def forward(self, x: np.ndarray) -> np.ndarray:
+    def forward(self, x: np.ndarray, want_scale: bool = False):
+        """Outputs [B][n_out]; with want_scale also the last layer's
+        |b| + sum |w a| per output (the magnitude rounding errors scale with)."""
         x = np.ascontiguousarray(x, dtype=np.float64)
         assert x.shape[1:] == (self.n_slot, self.n_feat)
         out = np.zeros((x.shape[0], self.n_out), dtype=np.float64)
-        lib().ol_forward(self.ptr, x.shape[0], x, out)
-        return out
+        scale = np.zeros_like(out) if want_scale else None
+        lib().ol_forward(self.ptr, x.shape[0], x, out,
+                         scale.ctypes.data if want_scale else None)
+        return (out, scale) if want_scale else out
 
 
 def round_latency(v: float, lat_max: int = 65535):
@@ -128,7 +132,8 @@ def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=
 def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
              model: Optional[Model] = None, mode: int = PREDICT,
              lat_table: Optional[np.ndarray] = None, want_logits: bool = False,
-             want_lat: bool = False, n_instr: Optional[int] = None, threads: int = 0) -> dict:
+             want_lat: bool = False, n_instr: Optional[int] = None, threads: int = 0,
+             want_scale: bool = False) -> dict:
     """Run the oracle over every sub-trace; returns per-sub-trace int64 arrays
     and optionally the per-prediction logits (float64) and latencies."""
     start = np.ascontiguousarray(start, np.int64)
@@ -145,6 +150,7 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
     res = {k: np.zeros(K, np.int64) for k in ("fetch", "drain", "final", "warm_tick")}
     logits = np.zeros((n_pred, n_out), np.float64) if want_logits else None
     lat = np.zeros((n_pred, n_out), np.int32) if want_lat else None
+    scale = np.zeros((n_pred, n_out), np.float64) if want_scale else None
     if lat_table is not None:
         lat_table = np.ascontiguousarray(lat_table, np.int32)
         assert lat_table.size >= n_pred * n_out
@@ -157,11 +163,12 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
                            lat_table.ctypes.data if lat_table is not None else None,
                            res["fetch"], res["drain"], res["final"], res["warm_tick"],
                            logits.ctypes.data if logits is not None else None,
+                           scale.ctypes.data if scale is not None else None,
                            lat.ctypes.data if lat is not None else None,
                            counters, threads)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     res["total"] = int(np.sum(res["final"] - res["warm_tick"]))
     res["n_clamped"], res["n_nonfinite"] = int(counters[0]), int(counters[1])
-    res["logits"], res["lat"] = logits, lat
+    res["logits"], res["lat"], res["scale"] = logits, lat, scale
     return res

@@ -116,10 +116,13 @@ void ol_model_free(void* p) {
 int ol_model_nout(const void* p) { return ((const ol_model*)p)->n_out; }
 
 /* Forward pass of one window x[n_slot][n_feat] by the layer definitions
- * (Sec. 2.3).  a/b are scratch of at least max_width doubles.
- * Activations are kept channel-major: act[c * len + pos]. */
+ * (Sec. 2.3).  a/t are scratch of at least max_width doubles.
+ * Activations are kept channel-major: act[c * len + pos].
+ * If scale is not NULL it receives, per output, |b| + sum_j |w_j * a_j| of
+ * the last layer: the magnitude against which the rounding error of any
+ * finite-precision evaluation of that output is measured. */
 static void forward_one(const ol_model* m, const double* x, double* out,
-                        double* a, double* t) {
+                        double* a, double* t, double* scale) {
   int ch = m->n_feat, len = m->n_slot;
   for (int l = 0; l < len; ++l)
     for (int c = 0; c < ch; ++c) a[c * len + l] = x[l * ch + c];
@@ -141,10 +144,16 @@ static void forward_one(const ol_model* m, const double* x, double* out,
       len = lout;
     } else {
       int n_in = ch * len; /* flatten: index c*len + p, already the layout of a */
+      const int is_last = (li == m->n_layers - 1);
       for (int o = 0; o < co; ++o) {
         double s = b[o];
-        for (int j = 0; j < n_in; ++j) s += w[(size_t)o * n_in + j] * a[j];
+        double mag = fabs(b[o]);
+        for (int j = 0; j < n_in; ++j) {
+          s += w[(size_t)o * n_in + j] * a[j];
+          if (is_last && scale) mag += fabs(w[(size_t)o * n_in + j] * a[j]);
+        }
         t[o] = (d[3] && s < 0.0) ? 0.0 : s;
+        if (is_last && scale) scale[o] = mag;
       }
       len = 1;
     }
@@ -154,13 +163,15 @@ static void forward_one(const ol_model* m, const double* x, double* out,
   memcpy(out, a, sizeof(double) * (size_t)m->n_out);
 }
 
-/* Batched forward: x [B][n_slot][n_feat] (double) -> out [B][n_out]. */
-int ol_forward(const void* p, int64_t B, const double* x, double* out) {
+/* Batched forward: x [B][n_slot][n_feat] (double) -> out [B][n_out];
+ * scale (optional) [B][n_out] as in forward_one. */
+int ol_forward(const void* p, int64_t B, const double* x, double* out, double* scale) {
   const ol_model* m = (const ol_model*)p;
   double* a = (double*)malloc(sizeof(double) * m->max_width);
   double* t = (double*)malloc(sizeof(double) * m->max_width);
   size_t win = (size_t)m->n_slot * m->n_feat;
-  for (int64_t i = 0; i < B; ++i) forward_one(m, x + i * win, out + i * m->n_out, a, t);
+  for (int64_t i = 0; i < B; ++i)
+    forward_one(m, x + i * win, out + i * m->n_out, a, t, scale ? scale + i * m->n_out : NULL);
   free(a);
   free(t);
   return 0;
@@ -247,6 +258,7 @@ typedef struct {
   const int32_t* lat_table;
   int64_t *fetch, *drain, *final_tick, *warm_tick;
   double* logits_out;
+  double* scale_out;
   int32_t* lat_out;
   int64_t counters[2]; /* clamped, non-finite (summed under the lock) */
   int32_t next;
@@ -262,7 +274,7 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
   const int32_t lat_max = cfg[CF_LATMAX];
   const int C = L - 1;
   const int need_pred = (J->mode == OL_PREDICT) || (J->logits_out != NULL);
-  double out[8];
+  double out[8], scl[8];
 
   Q->head = Q->tail = 0;
   int64_t cur = 0, t_w = 0;
@@ -289,9 +301,11 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
         if (ce >= 0) row[ce] = (double)e->e;
         if (cs >= 0) row[cs] = (n_out >= 3) ? (double)e->s : 0.0;
       }
-      forward_one(J->m, win, out, a, t);
+      forward_one(J->m, win, out, a, t, J->scale_out ? scl : NULL);
       if (J->logits_out)
         for (int o = 0; o < n_out; ++o) J->logits_out[g * n_out + o] = out[o];
+      if (J->scale_out)
+        for (int o = 0; o < n_out; ++o) J->scale_out[g * n_out + o] = scl[o];
     }
     int32_t lat[8];
     for (int o = 0; o < n_out; ++o) {
@@ -349,14 +363,16 @@ static void* sim_worker(void* arg) {
 /* Simulate every sub-trace.  mode OL_PREDICT advances with the model's own
  * rounded predictions; OL_INJECT advances with lat_table[(pred_off[k] + p) *
  * n_out + o] (the model is then only run when logits_out is requested and
- * may be NULL otherwise).  Per-sub-trace results: fetch = T_last - T_w,
+ * may be NULL otherwise; scale_out, like logits_out, receives each output's
+ * |b| + sum |w a| of the last layer).  Per-sub-trace results: fetch = T_last - T_w,
  * drain = final - T_last, final tick, T_w.  counters[0] = clamped, [1] =
  * non-finite.  Returns 0, or -1 on invalid arguments. */
 int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_t n_instr,
                 int32_t n_sub, const int64_t* start, const int64_t* len, const int32_t* warm,
                 int32_t mode, const int32_t* lat_table,
                 int64_t* fetch, int64_t* drain, int64_t* final_tick, int64_t* warm_tick,
-                double* logits_out, int32_t* lat_out, int64_t* counters, int32_t n_threads) {
+                double* logits_out, double* scale_out, int32_t* lat_out, int64_t* counters,
+                int32_t n_threads) {
   const ol_model* m = (const ol_model*)model;
   if (cfg[CF_NOUT] < 2 || cfg[CF_NOUT] > 2) return -1; /* store latency not modelled */
   if (cfg[CF_W] < 1 || cfg[CF_NSLOT] < 1) return -1;
@@ -379,7 +395,7 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
   J.start = start; J.len = len; J.warm = warm; J.pred_off = pred_off;
   J.mode = mode; J.lat_table = lat_table;
   J.fetch = fetch; J.drain = drain; J.final_tick = final_tick; J.warm_tick = warm_tick;
-  J.logits_out = logits_out; J.lat_out = lat_out;
+  J.logits_out = logits_out; J.scale_out = scale_out; J.lat_out = lat_out;
   pthread_mutex_init(&J.mu, NULL);
   if (n_threads <= 0) n_threads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
   if (n_threads > n_sub) n_threads = n_sub;

@@ -157,7 +157,14 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
     if constexpr (Net::HID > 0) {
       const float4* bj = reinterpret_cast<const float4*>(wt.hid_w) +
                          (size_t)j * (Net::CHL / 16) * (Net::HID / 16) * 64;
-      hidden_accumulate<Net::CHL, Net::HID, Net::WAVES, G::SAL>(hacc, last, bj, wave, lane);
+      // per-block partial in a fresh accumulator, then added: the FP32
+      // summation chain is 16 k-groups + NB blocks instead of NB*16 in a row
+      v4f bacc[HT];
+#pragma unroll
+      for (int jj = 0; jj < HT; ++jj) bacc[jj] = v4f{0.f, 0.f, 0.f, 0.f};
+      hidden_accumulate<Net::CHL, Net::HID, Net::WAVES, G::SAL>(bacc, last, bj, wave, lane);
+#pragma unroll
+      for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[jj];
     } else {
       const float* wrow = wt.last_w + ((size_t)j * Net::NOUT + fo) * Net::CHL + fsub * CPL;
       const float* arow = last + fs * G::SAL + fsub * CPL;

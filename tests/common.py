@@ -19,18 +19,21 @@ def c3_net_inputs(seed_w=2):
     return layers, ws, bs
 
 
-def rel_err(got, ref):
-    """|y32 - y64| / max(|y64|, 1), elementwise."""
+def rel_err(got, ref, scale):
+    """|y32 - y64| / max(s, 1) elementwise, where s = |b| + sum |w a| of the
+    output layer in FP64 (the magnitude rounding errors are proportional to;
+    s >= |y64|, so this is never looser than relative to max(|y|, 1) by more
+    than the cancellation in the last layer)."""
     got = np.asarray(got, np.float64)
     ref = np.asarray(ref, np.float64)
-    return np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
+    return np.abs(got - ref) / np.maximum(np.asarray(scale, np.float64), 1.0)
 
 
-def near_half(logits, tol):
-    """Mask of predictions whose rounding could differ between FP32 and FP64:
-    within tol of a .5 boundary, or of the clamp edges."""
+def near_half(logits, scale, band):
+    """Predictions whose rounding may legitimately differ between an FP32 and
+    an FP64 evaluation: within band * max(s, 1) of a .5 boundary."""
     frac = np.abs(logits - np.floor(logits) - 0.5)
-    return frac <= tol * np.maximum(np.abs(logits), 1.0)
+    return frac <= band * np.maximum(scale, 1.0)
 
 
 def realistic_windows(cfg, feat, n_windows, seed=0):

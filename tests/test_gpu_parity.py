@@ -1,7 +1,9 @@
 """Parity of the HIP path (through the C ABI) with the FP64 oracle.
 
 Bars: cycle and queue results bit-exact given identical latencies; FP32
-predictor outputs within |y32 - y64| <= 1e-5 * max(|y64|, 1); free-running
+predictor outputs within |y32 - y64| <= 1e-5 * max(s, 1), s being the FP64
+magnitude |b| + sum |w a| of the output layer (relative error of a computed
+sum, measured against the magnitude of its terms); free-running
 simulations exact wherever no prediction sits within the FP32/FP64 rounding
 ambiguity of a .5 boundary, and otherwise exactly reproducible by the oracle
 from the GPU's own latency decisions."""
@@ -83,8 +85,8 @@ def test_forward_parity(torch, sn, oracle_lib, net, B):
     if B > 3:
         x[:3] = np.random.default_rng(B).normal(size=(3, S.L, S.D)) * 5
     got = S.sim.forward(dev(torch, x)).cpu().numpy()
-    ref = S.model.forward(x.astype(np.float64))
-    err = rel_err(got, ref)
+    ref, scale = S.model.forward(x.astype(np.float64), want_scale=True)
+    err = rel_err(got, ref, scale)
     assert err.max() <= TOL, (err.max(), np.unravel_index(err.argmax(), err.shape))
 
 
@@ -128,9 +130,10 @@ def test_window_overflow_keeps_newest(torch, sn, oracle_lib):
     logits = torch.zeros((S.n_pred, 2), dtype=torch.float32, device="cuda")
     S.sim.record_logits(logits)
     g = S.sim.run(sn.SIM_LAT_SHADOW, dev(torch, table))
-    o = S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=table, want_logits=True)
+    o = S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=table, want_logits=True,
+                 want_scale=True)
     assert_same_results(g, o, 3)
-    err = rel_err(logits.cpu().numpy(), o["logits"])
+    err = rel_err(logits.cpu().numpy(), o["logits"], o["scale"])
     assert err.max() <= TOL
 
 
@@ -144,12 +147,13 @@ def test_shadow_logits_on_identical_windows(torch, sn, oracle_lib, net, N, K, wa
     logits = torch.zeros((S.n_pred, 2), dtype=torch.float32, device="cuda")
     S.sim.record_logits(logits)
     g = S.sim.run(sn.SIM_LAT_SHADOW, dev(torch, table))
-    o = S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=table, want_logits=True)
+    o = S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=table, want_logits=True,
+                 want_scale=True)
     assert_same_results(g, o, K)
     gl = logits.cpu().numpy()
-    err = rel_err(gl, o["logits"])
+    err = rel_err(gl, o["logits"], o["scale"])
     assert err.max() <= TOL, err.max()
-    ties = int(near_half(o["logits"], TIE_TOL).sum())
+    ties = int(near_half(o["logits"], o["scale"], TIE_TOL).sum())
     assert g["n_shadow_mismatch"] <= ties
 
 
@@ -160,13 +164,14 @@ def check_free_run(torch, sn, oracle_lib, S, g, gl):
     latencies: identical cycles, logits within TOL, identical rounding away
     from near-ties.  Returns the oracle's own free run for exact comparison."""
     lat_gpu = np.clip(np.rint(gl.astype(np.float64)), 0, 65535).astype(np.int32)
-    rep = S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=lat_gpu, want_logits=True)
+    rep = S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=lat_gpu, want_logits=True,
+                   want_scale=True)
     assert_same_results(g, rep, S.sim.n_sub)
-    err = rel_err(gl, rep["logits"])
+    err = rel_err(gl, rep["logits"], rep["scale"])
     assert err.max() <= TOL, err.max()
     lat_o = np.clip(np.rint(rep["logits"]), 0, 65535).astype(np.int32)
     diff = lat_o != lat_gpu
-    assert not np.any(diff & ~near_half(rep["logits"], TIE_TOL))
+    assert not np.any(diff & ~near_half(rep["logits"], rep["scale"], TIE_TOL))
     return rep
 
 
@@ -180,8 +185,8 @@ def test_free_run_tiny_workload(torch, sn, oracle_lib):
     g = S.sim.run()
     gl = logits.cpu().numpy()
     check_free_run(torch, sn, oracle_lib, S, g, gl)
-    o = S.oracle(oracle_lib, want_logits=True)
-    if not near_half(o["logits"], TIE_TOL).any():
+    o = S.oracle(oracle_lib, want_logits=True, want_scale=True)
+    if not near_half(o["logits"], o["scale"], TIE_TOL).any():
         assert_same_results(g, o, 1)
         assert g["n_clamped"] == o["n_clamped"] and g["n_nonfinite"] == 0
 
@@ -193,8 +198,8 @@ def test_free_run_many_subtraces(torch, sn, oracle_lib, net, N, K, warm):
     S.sim.record_logits(logits)
     g = S.sim.run()
     check_free_run(torch, sn, oracle_lib, S, g, logits.cpu().numpy())
-    o = S.oracle(oracle_lib, want_logits=True)
-    if not near_half(o["logits"], TIE_TOL).any():
+    o = S.oracle(oracle_lib, want_logits=True, want_scale=True)
+    if not near_half(o["logits"], o["scale"], TIE_TOL).any():
         assert_same_results(g, o, K)
 
 
@@ -283,13 +288,14 @@ def test_full_c3_workload_sampled(torch, sn, oracle_lib):
     lat_gpu = np.concatenate([np.clip(np.rint(gl[off[k]:off[k + 1]].astype(np.float64)), 0, 65535)
                               for k in ks]).astype(np.int32)
     rep = oracle_lib.simulate(S.cfg, S.feat, S.start[ks], S.len[ks], S.warm[ks], model=S.model,
-                              mode=oracle_lib.INJECT, lat_table=lat_gpu, want_logits=True)
+                              mode=oracle_lib.INJECT, lat_table=lat_gpu, want_logits=True,
+                              want_scale=True)
     for key in ("fetch", "drain", "final", "warm_tick"):
         np.testing.assert_array_equal(rep[key], g[key][ks], err_msg=key)
     glk = np.concatenate([gl[off[k]:off[k + 1]] for k in ks])
-    assert rel_err(glk, rep["logits"]).max() <= TOL
+    assert rel_err(glk, rep["logits"], rep["scale"]).max() <= TOL
     lat_o = np.clip(np.rint(rep["logits"]), 0, 65535).astype(np.int32)
-    assert not np.any((lat_o != lat_gpu) & ~near_half(rep["logits"], TIE_TOL))
+    assert not np.any((lat_o != lat_gpu) & ~near_half(rep["logits"], rep["scale"], TIE_TOL))
 
 
 # ------------------------------------------------------------ error paths ---

@@ -396,3 +396,18 @@ def test_paper_dimension_facts():
     assert wl.n_feat * wl.n_slot == facts["model_input_size"]["value"]
     assert wl.retire_width == facts["retire_width_default_o3"]["value"]
     assert facts["features_inst0_before_padding"]["value"] + 3 == wl.n_feat
+
+
+def test_output_scale_matches_library(oracle_lib):
+    """The conditioning scale |b| + sum_j |W[o,j] h_j| of the last layer, from
+    PyTorch float64 hidden activations."""
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(4, layers)
+    rng = np.random.default_rng(3)
+    x = rng.normal(size=(4, 111, 50)) * 3
+    m = oracle_lib.Model(layers, ws, bs, 50, 111)
+    out, scale = m.forward(x, want_scale=True)
+    h = torch_forward(layers[:-1], ws[:-1], bs[:-1], x).reshape(4, -1)
+    ref = np.abs(bs[-1].astype(np.float64))[None, :] + np.abs(h) @ np.abs(ws[-1].astype(np.float64)).T
+    np.testing.assert_allclose(scale, ref, rtol=1e-12)
+    assert np.all(scale >= np.abs(out))
