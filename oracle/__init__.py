@@ -46,6 +46,8 @@ def lib():
         f64p = np.ctypeslib.ndpointer(np.float64, flags="C")
         L.ol_model_new.restype = P
         L.ol_model_new.argtypes = [C.c_int, i32p, f32p, C.c_int, C.c_int]
+        L.ol_model_new_prec.restype = P
+        L.ol_model_new_prec.argtypes = [C.c_int, i32p, f32p, C.c_int, C.c_int, C.c_int]
         L.ol_model_free.argtypes = [P]
         L.ol_model_nout.restype = C.c_int
         L.ol_model_nout.argtypes = [P]
@@ -71,14 +73,16 @@ def flat_params(ws: Sequence[np.ndarray], bs: Sequence[np.ndarray]) -> np.ndarra
 
 
 class Model:
-    """The predictor with its parameters held in double precision."""
+    """The predictor with its parameters held in double precision.  prec=1
+    evaluates the BF16 form (inputs, weights and hidden activations rounded
+    to bfloat16, exact sums)."""
 
-    def __init__(self, layers, ws, bs, n_feat: int, n_slot: int):
+    def __init__(self, layers, ws, bs, n_feat: int, n_slot: int, prec: int = 0):
         desc = np.array([[ly.kind, ly.c_in, ly.c_out, ly.relu] for ly in layers],
                         dtype=np.int32).ravel()
         self._params = flat_params(ws, bs)
         self.n_feat, self.n_slot = n_feat, n_slot
-        self.ptr = lib().ol_model_new(len(layers), desc, self._params, n_feat, n_slot)
+        self.ptr = lib().ol_model_new_prec(len(layers), desc, self._params, n_feat, n_slot, prec)
         if not self.ptr:
             raise ValueError("layer list does not fit the window shape")
         self.n_out = lib().ol_model_nout(self.ptr)

@@ -59,16 +59,35 @@ typedef struct {
   double* w[16];
   double* b[16];
   int n_feat, n_slot, n_out, max_width;
+  int prec;                 /* 0: plain FP64; 1: BF16 form (see round_bf16) */
 } ol_model;
+
+/* Nearest bfloat16 value (8 significant bits, ties to even), from the
+ * definition: v = m * 2^ex with 0.5 <= |m| < 1, so one unit in the last
+ * place is 2^(ex - 8).  Range limits are not reached by the workloads. */
+static double round_bf16(double v) {
+  if (v == 0.0 || !isfinite(v)) return v;
+  int ex;
+  frexp(v, &ex);
+  const double ulp = ldexp(1.0, ex - 8);
+  return nearbyint(v / ulp) * ulp;
+}
+
+static double qform(const ol_model* m, double v) { return m->prec == 1 ? round_bf16(v) : v; }
 
 /* ------------------------------------------------------------- model --- */
 
 /* params: PyTorch order, concatenated: w0, b0, w1, b1, ...  conv weight is
  * [c_out][c_in][2], fc weight is [out][in]. */
-void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
-                   int n_feat, int n_slot) {
-  if (n_layers < 1 || n_layers > 16) return NULL;
+/* prec 1 evaluates the BF16 form of the network: window inputs, weights
+ * and every hidden layer's output (after bias and ReLU) are rounded to
+ * bfloat16, biases stay as given, products and sums are exact FP64 and the
+ * last layer's output is not rounded. */
+void* ol_model_new_prec(int n_layers, const int32_t* desc, const float* params,
+                        int n_feat, int n_slot, int prec) {
+  if (n_layers < 1 || n_layers > 16 || prec < 0 || prec > 1) return NULL;
   ol_model* m = (ol_model*)calloc(1, sizeof(ol_model));
+  m->prec = prec;
   m->n_layers = n_layers;
   m->n_feat = n_feat;
   m->n_slot = n_slot;
@@ -91,7 +110,7 @@ void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
     if (ch * len > width) width = ch * len;
     m->w[l] = (double*)malloc(nw * sizeof(double));
     m->b[l] = (double*)malloc((size_t)co * sizeof(double));
-    for (size_t i = 0; i < nw; ++i) m->w[l][i] = (double)params[off + i];
+    for (size_t i = 0; i < nw; ++i) m->w[l][i] = qform(m, (double)params[off + i]);
     off += nw;
     for (int i = 0; i < co; ++i) m->b[l][i] = (double)params[off + i];
     off += co;
@@ -104,6 +123,11 @@ void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
   m->n_out = ch;
   m->max_width = width;
   return m;
+}
+
+void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
+                   int n_feat, int n_slot) {
+  return ol_model_new_prec(n_layers, desc, params, n_feat, n_slot, 0);
 }
 
 void ol_model_free(void* p) {
@@ -125,7 +149,7 @@ static void forward_one(const ol_model* m, const double* x, double* out,
                         double* a, double* t, double* scale) {
   int ch = m->n_feat, len = m->n_slot;
   for (int l = 0; l < len; ++l)
-    for (int c = 0; c < ch; ++c) a[c * len + l] = x[l * ch + c];
+    for (int c = 0; c < ch; ++c) a[c * len + l] = qform(m, x[l * ch + c]);
   for (int li = 0; li < m->n_layers; ++li) {
     const int32_t* d = m->desc[li];
     const double* w = m->w[li];
@@ -158,7 +182,8 @@ static void forward_one(const ol_model* m, const double* x, double* out,
       len = 1;
     }
     ch = co;
-    memcpy(a, t, sizeof(double) * (size_t)ch * len);
+    const int last = (li == m->n_layers - 1);
+    for (int i = 0; i < ch * len; ++i) a[i] = last ? t[i] : qform(m, t[i]);
   }
   memcpy(out, a, sizeof(double) * (size_t)m->n_out);
 }

@@ -29,7 +29,7 @@ struct sim_ctx {
   float* logits_out = nullptr;
   hipStream_t stream = nullptr;
   void* dev_block = nullptr;  // state + table
-  float* dev_weights = nullptr;
+  void* dev_weights = nullptr;
   int64_t* dev_total = nullptr;
   DevState st{};
   DevWeights w{};
@@ -94,17 +94,64 @@ int check_cfg(const sim_config* cfg, const sim_trace* tr, std::string* why) {
   return SIM_OK;
 }
 
-// B[k][n] packed per (k-group of 16, n-tile of 16) as 64 lanes x 4 floats:
-// lane holds B[kg*16 + 4*(lane/16) + s][nt*16 + lane%16], s = 0..3.
+// Storage encodings of the precision forms (host side).
+uint16_t bf16_bits(float x) {  // round to nearest even
+  uint32_t u;
+  memcpy(&u, &x, 4);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+float bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float x;
+  memcpy(&x, &u, 4);
+  return x;
+}
+// OCP FP8 e4m3: 1 sign, 4 exponent (bias 7), 3 mantissa bits, no infinities,
+// largest finite 448.  Codes 0x00..0x7e are the non-negative finite values.
+float e4m3_value(uint8_t code) {
+  const int e = (code >> 3) & 15, m = code & 7;
+  const float mag = e == 0 ? ldexpf((float)m, -9) : ldexpf(1.f + m / 8.f, e - 7);
+  return (code & 0x80) ? -mag : mag;
+}
+uint8_t e4m3_bits(float x) {  // round to nearest even, saturating at +-448
+  const uint8_t sign = x < 0 ? 0x80 : 0;
+  const float a = fminf(fabsf(x), 448.f);
+  int lo = 0, hi = 0x7e;  // largest code with value <= a
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (e4m3_value((uint8_t)mid) <= a) lo = mid; else hi = mid - 1;
+  }
+  int c = lo;
+  if (c < 0x7e) {
+    const float d0 = a - e4m3_value((uint8_t)c), d1 = e4m3_value((uint8_t)(c + 1)) - a;
+    if (d1 < d0 || (d1 == d0 && (c & 1))) c += 1;
+  }
+  return (uint8_t)(sign | c);
+}
+
+constexpr size_t elem_size(int prec) { return prec == 0 ? 4 : prec == 1 ? 2 : 1; }
+
+void store_elem(int prec, float v, uint8_t* dst) {
+  if (prec == 0) memcpy(dst, &v, 4);
+  else if (prec == 1) { const uint16_t b = bf16_bits(v); memcpy(dst, &b, 2); }
+  else *dst = e4m3_bits(v);
+}
+float round_to(int prec, float v) {
+  return prec == 0 ? v : prec == 1 ? bf16_value(bf16_bits(v)) : e4m3_value(e4m3_bits(v));
+}
+
+// B[k][n] packed per (k-group of KG, n-tile of 16) as 64 lanes x 16 bytes:
+// lane holds B[kg*KG + (KG/4)*(lane/16) + e][nt*16 + lane%16], e < KG/4.
 template <class F>
-void pack_b(int K, int N, F&& B, float* out) {
-  const int KG = K / 16, NTL = N / 16;
-  for (int kg = 0; kg < KG; ++kg)
+void pack_b(int prec, int K, int N, F&& B, uint8_t* out) {
+  const int KG = kgroup(prec), KGS = K / KG, NTL = N / 16, E = KG / 4;
+  const size_t es = elem_size(prec);
+  for (int kg = 0; kg < KGS; ++kg)
     for (int nt = 0; nt < NTL; ++nt)
       for (int lane = 0; lane < 64; ++lane)
-        for (int s = 0; s < 4; ++s)
-          out[(((size_t)kg * NTL + nt) * 64 + lane) * 4 + s] =
-              B(kg * 16 + 4 * (lane / 16) + s, nt * 16 + lane % 16);
+        for (int e = 0; e < E; ++e)
+          store_elem(prec, B(kg * KG + E * (lane / 16) + e, nt * 16 + lane % 16),
+                     out + ((((size_t)kg * NTL + nt) * 64 + lane) * E + e) * es);
 }
 
 struct Expect {
@@ -126,9 +173,21 @@ std::vector<Expect> expected_layers() {
   return v;
 }
 
-// Re-lay-out PyTorch-order parameters for one network; returns the floats.
+// Offsets (bytes) of every array inside the packed weight block.
+struct Layout {
+  size_t conv_w[3], conv_b[3], conv_ws[3], conv_ai[3], x_inv, hid_w, hid_b, hid_ws, hid_ai,
+      last_w, last_b;
+};
+
+// Re-lay-out PyTorch-order FP32 parameters for one network and precision.
+// FP8 scales (scales != NULL): per layer l, in_scale[l][c] is the scale of
+// input channel c of layer l (window features for l = 0), a power of two;
+// weights are multiplied by their input channel's scale before quantising,
+// and each output channel gets the power-of-two weight scale that maps its
+// largest magnitude into e4m3's range.
 template <class Net>
-std::vector<float> relayout(const float* params, size_t* offs_out /*[12]*/) {
+std::vector<uint8_t> relayout(int prec, const float* params,
+                              const std::vector<std::vector<float>>* in_scale, Layout* L) {
   std::vector<const float*> w, b;
   size_t off = 0;
   for (const Expect& e : expected_layers<Net>()) {
@@ -138,61 +197,113 @@ std::vector<float> relayout(const float* params, size_t* offs_out /*[12]*/) {
     b.push_back(params + off);
     off += e.c_out;
   }
-  const int chp[4] = {Net::CH0, Net::CH1, Net::CH2, Net::CH3};
+  const int DP = padded_feat(Net::D, prec);
+  const int chp[4] = {DP, Net::CH1, Net::CH2, Net::CH3};
   const int chr[4] = {Net::D, Net::CH1, Net::CH2, Net::CH3};
-  std::vector<float> out;
-  auto reserve = [&](size_t n) {  // 256-byte aligned sections
-    const size_t at = (out.size() + 63) / 64 * 64;
-    out.resize(at + n, 0.f);
+  const size_t es = elem_size(prec);
+  const bool fp8 = prec == 2;
+  std::vector<uint8_t> out;
+  auto reserve = [&](size_t bytes) {  // 256-byte aligned sections
+    const size_t at = (out.size() + 255) / 256 * 256;
+    out.resize(at + bytes, 0);
     return at;
+  };
+  auto put_floats = [&](const std::vector<float>& v) {
+    const size_t at = reserve(v.size() * 4);
+    memcpy(out.data() + at, v.data(), v.size() * 4);
+    return at;
+  };
+  auto sin = [&](int l, int c) { return fp8 ? (*in_scale)[l][c] : 1.f; };
+  // per-output-channel power-of-two weight scale for e4m3 (1 otherwise)
+  auto wscale = [&](int l, int K, int co, auto&& wv) {
+    std::vector<float> s(co, 1.f);
+    if (!fp8) return s;
+    for (int n = 0; n < co; ++n) {
+      float amax = 0.f;
+      for (int k = 0; k < K; ++k) amax = fmaxf(amax, fabsf(wv(k, n)));
+      s[n] = amax > 0.f ? ldexpf(1.f, (int)ceilf(log2f(amax / 448.f))) : 1.f;
+    }
+    (void)l;
+    return s;
   };
   for (int l = 0; l < Net::NCONV; ++l) {
     const int K = 2 * chp[l], N = chp[l + 1], cin = chr[l];
     const float* wl = w[l];
-    const size_t at = reserve((size_t)K * N);
-    pack_b(K, N,
-           [&](int k, int n) {
-             const int t = k / chp[l], c = k % chp[l];
-             return c < cin ? wl[((size_t)n * cin + c) * 2 + t] : 0.f;
-           },
-           out.data() + at);
-    offs_out[2 * l] = at;
-    const size_t bt = reserve(N);
-    std::copy(b[l], b[l] + N, out.begin() + bt);
-    offs_out[2 * l + 1] = bt;
+    auto wv = [&](int k, int n) {  // weight with its input channel's scale folded in
+      const int t = k / chp[l], c = k % chp[l];
+      return c < cin ? wl[((size_t)n * cin + c) * 2 + t] * sin(l, c) : 0.f;
+    };
+    const std::vector<float> ws = wscale(l, K, N, wv);
+    L->conv_w[l] = reserve((size_t)K * N * es);
+    pack_b(prec, K, N, [&](int k, int n) { return wv(k, n) / ws[n]; }, out.data() + L->conv_w[l]);
+    L->conv_b[l] = put_floats(std::vector<float>(b[l], b[l] + N));
+    L->conv_ws[l] = put_floats(ws);
+    std::vector<float> ai(N, 1.f);
+    if (fp8) {
+      const bool next_is_conv = l + 1 < Net::NCONV;
+      for (int n = 0; n < N; ++n) {
+        // next layer's input channel n: conv channel n, or (hidden FC) the
+        // flattened inputs n*NB + j, which share one scale per channel
+        const float s = next_is_conv ? (*in_scale)[l + 1][n] : (*in_scale)[l + 1][n];
+        ai[n] = 1.f / s;
+      }
+    }
+    L->conv_ai[l] = put_floats(ai);
+  }
+  {
+    std::vector<float> xi(Net::D, 1.f);
+    if (fp8)
+      for (int c = 0; c < Net::D; ++c) xi[c] = 1.f / (*in_scale)[0][c];
+    L->x_inv = put_floats(xi);
   }
   const int li = Net::NCONV;
   if (Net::HID > 0) {
     const int K = Net::CHL, N = Net::HID, NB = Net::NB;
     const float* W1 = w[li];
-    const size_t per = (size_t)K * N;
-    const size_t at = reserve(per * NB);
+    // one per-output scale over all blocks of the hidden layer
+    auto wv = [&](int kk, int n) {  // kk = c*NB + j (PyTorch flatten index)
+      return W1[(size_t)n * (K * NB) + kk] * sin(li, kk / NB);
+    };
+    const std::vector<float> ws = wscale(li, K * NB, N, wv);
+    const size_t per = (size_t)K * N * es;
+    L->hid_w = reserve(per * NB);
     for (int j = 0; j < NB; ++j)
-      pack_b(K, N, [&](int c, int n) { return W1[(size_t)n * (K * NB) + c * NB + j]; },
-             out.data() + at + per * j);
-    offs_out[6] = at;
-    const size_t bt = reserve(N);
-    std::copy(b[li], b[li] + N, out.begin() + bt);
-    offs_out[7] = bt;
-    const size_t lt = reserve((size_t)Net::NOUT * N);
-    std::copy(w[li + 1], w[li + 1] + (size_t)Net::NOUT * N, out.begin() + lt);
-    offs_out[8] = lt;
-    const size_t lb = reserve(Net::NOUT);
-    std::copy(b[li + 1], b[li + 1] + Net::NOUT, out.begin() + lb);
-    offs_out[9] = lb;
+      pack_b(prec, K, N, [&](int c, int n) { return wv(c * NB + j, n) / ws[n]; },
+             out.data() + L->hid_w + per * j);
+    L->hid_b = put_floats(std::vector<float>(b[li], b[li] + N));
+    L->hid_ws = put_floats(ws);
+    std::vector<float> ai(N, 1.f);
+    if (fp8)
+      for (int n = 0; n < N; ++n) ai[n] = 1.f / (*in_scale)[li + 1][n];
+    L->hid_ai = put_floats(ai);
+    // final FC on the VALU: weights rounded to the form (scale of its input folded)
+    std::vector<float> lw((size_t)Net::NOUT * N);
+    for (int o = 0; o < Net::NOUT; ++o) {
+      float amax = 0.f;
+      for (int n = 0; n < N; ++n) amax = fmaxf(amax, fabsf(w[li + 1][(size_t)o * N + n] * sin(li + 1, n)));
+      const float s = fp8 && amax > 0.f ? ldexpf(1.f, (int)ceilf(log2f(amax / 448.f))) : 1.f;
+      for (int n = 0; n < N; ++n)
+        lw[(size_t)o * N + n] = round_to(prec, w[li + 1][(size_t)o * N + n] * sin(li + 1, n) / s) * s;
+    }
+    L->last_w = put_floats(lw);
+    L->last_b = put_floats(std::vector<float>(b[li + 1], b[li + 1] + Net::NOUT));
   } else {
     const int K = Net::CHL, NB = Net::NB;
     const float* Wf = w[li];
-    const size_t lt = reserve((size_t)NB * Net::NOUT * K);
-    for (int j = 0; j < NB; ++j)
-      for (int o = 0; o < Net::NOUT; ++o)
+    std::vector<float> lw((size_t)NB * Net::NOUT * K);
+    for (int o = 0; o < Net::NOUT; ++o) {
+      float amax = 0.f;
+      for (int kk = 0; kk < K * NB; ++kk)
+        amax = fmaxf(amax, fabsf(Wf[(size_t)o * (K * NB) + kk] * sin(li, kk / NB)));
+      const float s = fp8 && amax > 0.f ? ldexpf(1.f, (int)ceilf(log2f(amax / 448.f))) : 1.f;
+      for (int j = 0; j < NB; ++j)
         for (int c = 0; c < K; ++c)
-          out[lt + ((size_t)j * Net::NOUT + o) * K + c] = Wf[(size_t)o * (K * NB) + c * NB + j];
-    offs_out[6] = offs_out[7] = 0;
-    offs_out[8] = lt;
-    const size_t lb = reserve(Net::NOUT);
-    std::copy(b[li], b[li] + Net::NOUT, out.begin() + lb);
-    offs_out[9] = lb;
+          lw[((size_t)j * Net::NOUT + o) * K + c] =
+              round_to(prec, Wf[(size_t)o * (K * NB) + c * NB + j] * sin(li, c) / s) * s;
+    }
+    L->hid_w = L->hid_b = L->hid_ws = L->hid_ai = 0;
+    L->last_w = put_floats(lw);
+    L->last_b = put_floats(std::vector<float>(b[li], b[li] + Net::NOUT));
   }
   return out;
 }
@@ -237,7 +348,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
     return rc;
   }
   c->net = window_net(cfg->n_feat, cfg->n_slot);
-  if (c->net < 0 || cfg->prec != SIM_FP32) {
+  if (c->net < 0) {
     fprintf(stderr, "sim_init: no kernel for window %dx%d at precision %d\n", cfg->n_slot,
             cfg->n_feat, cfg->prec);
     delete c;
@@ -346,16 +457,18 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
   }
   for (size_t i = 0; i < np; ++i)
     if (!isfinite(host[i])) return fail(c, SIM_ENONFINITE, "parameter %zu is not finite", i);
-  size_t offs[12] = {0};
-  std::vector<float> packed =
-      c->net == 0 ? relayout<NetSmall>(host.data(), offs) : relayout<NetC3>(host.data(), offs);
+  if (c->cfg.prec == SIM_FP8E4M3)
+    return fail(c, SIM_EUNSUPPORTED, "FP8 needs activation scales (not available yet)");
+  Layout lay{};
+  std::vector<uint8_t> packed = c->net == 0 ? relayout<NetSmall>(c->cfg.prec, host.data(), nullptr, &lay)
+                                            : relayout<NetC3>(c->cfg.prec, host.data(), nullptr, &lay);
   uint32_t relu = 0;
   for (int32_t i = 0; i < n_layers; ++i)
     if (layers[i].relu) relu |= 1u << i;
-  float* dw = nullptr;
-  hipError_t e = hipMalloc(&dw, packed.size() * 4);
+  void* dw = nullptr;
+  hipError_t e = hipMalloc(&dw, packed.size());
   if (e != hipSuccess) return hip_fail(c, e, "hipMalloc weights");
-  e = hipMemcpy(dw, packed.data(), packed.size() * 4, hipMemcpyHostToDevice);
+  e = hipMemcpy(dw, packed.data(), packed.size(), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(dw);
     return hip_fail(c, e, "upload weights");
@@ -365,17 +478,26 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
     (void)hipFree(c->dev_weights);
   }
   c->dev_weights = dw;
+  char* base = static_cast<char*>(dw);
+  auto F = [&](size_t o) { return reinterpret_cast<const float*>(base + o); };
   DevWeights& w = c->w;
+  w = DevWeights{};
   const int nconv = c->net == 0 ? NetSmall::NCONV : NetC3::NCONV;
-  for (int l = 0; l < 3; ++l) {
-    w.conv_w[l] = l < nconv ? dw + offs[2 * l] : nullptr;
-    w.conv_b[l] = l < nconv ? dw + offs[2 * l + 1] : nullptr;
+  for (int l = 0; l < nconv; ++l) {
+    w.conv_w[l] = base + lay.conv_w[l];
+    w.conv_b[l] = F(lay.conv_b[l]);
+    w.conv_ws[l] = F(lay.conv_ws[l]);
+    w.conv_ai[l] = F(lay.conv_ai[l]);
   }
-  const bool hid = c->net == 1;
-  w.hid_w = hid ? dw + offs[6] : nullptr;
-  w.hid_b = hid ? dw + offs[7] : nullptr;
-  w.last_w = dw + offs[8];
-  w.last_b = dw + offs[9];
+  w.x_inv = F(lay.x_inv);
+  if (c->net == 1) {
+    w.hid_w = base + lay.hid_w;
+    w.hid_b = F(lay.hid_b);
+    w.hid_ws = F(lay.hid_ws);
+    w.hid_ai = F(lay.hid_ai);
+  }
+  w.last_w = F(lay.last_w);
+  w.last_b = F(lay.last_b);
   c->relu = relu;
   c->weights = true;
   return sim_reset(c);
@@ -412,7 +534,7 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   p.lat_table = table;
   p.logits_out = c->logits_out;
   p.n_steps = (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
-  hipError_t e = launch_step(c->net, c->w, c->relu, c->st, p, c->stream);
+  hipError_t e = launch_step(c->net, c->cfg.prec, c->w, c->relu, c->st, p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   return SIM_OK;
 }
@@ -464,8 +586,8 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
   if (B < 0 || (B > 0 && (!x || !logits))) return fail(c, SIM_EINVAL, "bad batch arguments");
   if (B == 0) return SIM_OK;
   if ((B + MT - 1) / MT > INT32_MAX) return fail(c, SIM_EINVAL, "batch too large");
-  hipError_t e = launch_forward(c->net, c->w, c->relu, static_cast<const float*>(x), B, logits,
-                                c->stream);
+  hipError_t e = launch_forward(c->net, c->cfg.prec, c->w, c->relu, static_cast<const float*>(x),
+                                B, logits, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "forward launch");
   return SIM_OK;
 }

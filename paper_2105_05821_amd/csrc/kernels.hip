@@ -17,113 +17,186 @@
 //              queue after the advance is the suffix with r > T_i.
 // The queue ring and the per-sub-trace scalars stay in LDS for the whole
 // launch and are written back to HBM when the launch ends.
+//
+// Precision forms: weights and activations in FP32, BF16 or FP8 (OCP e4m3,
+// per-channel power-of-two scales), products accumulated in FP32 in every
+// form; biases and the final logits are FP32.
 #include "simnet_internal.h"
 
 namespace simnet {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ v4f mfma_k16(v4f acc, float4 a, float4 b) {
-  // Four K=4 steps; lane group g = lane/16 supplies k = 4g + step, so one
-  // float4 per lane covers 16 consecutive k (A and B use the same mapping).
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.x, b.x, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.y, b.y, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.z, b.z, acc, 0, 0, 0);
-  acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.w, b.w, acc, 0, 0, 0);
-  return acc;
-}
+// ------------------------------------------------------ precision forms ---
+// Each form stores activations and weights as T and multiplies one 16-byte
+// fragment per lane per call of mma(): lane group g = lane/16 holds KG/4
+// consecutive k of its row (A) or column (B); A and B use the same
+// assignment, so every call adds the full KG-long partial dot products.
 
-template <class Net>
-struct Geo {
-  static constexpr int NT = Net::WAVES * 64;
-  static constexpr int SX = Net::BS * Net::DP + 4;               // window block, per sub-trace
-  static constexpr int SA1 = (Net::BS / 2) * Net::CH1 + 4;       // conv1 output
-  static constexpr int SA2 = (Net::BS / 4) * Net::CH2 + 4;       // conv2 output
-  static constexpr int SA3 = (Net::NCONV == 3 ? Net::CH3 : 0) + 4;  // conv3 output
-  static constexpr int SAL = Net::NCONV == 3 ? SA3 : SA2;        // last conv output
+struct PF32 {
+  using T = float;
+  static constexpr int ID = 0, KG = 16;
+  static constexpr bool SCALED = false;
+  __device__ static v4f mma(v4f c, uint4 a, uint4 b) {
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.y), __uint_as_float(b.y), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.z), __uint_as_float(b.z), c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.w), __uint_as_float(b.w), c, 0, 0, 0);
+    return c;
+  }
+  __device__ static T cvt(float x) { return x; }
+  __device__ static float val(T x) { return x; }
 };
 
-template <class Net>
+struct PBF16 {
+  using T = uint16_t;  // bfloat16 bits
+  static constexpr int ID = 1, KG = 32;
+  static constexpr bool SCALED = false;
+  __device__ static v4f mma(v4f c, uint4 a, uint4 b) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+  }
+  // round to nearest even (inputs are finite)
+  __device__ static T cvt(float x) {
+    const uint32_t u = __float_as_uint(x);
+    return (T)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+  __device__ static float val(T x) { return __uint_as_float((uint32_t)x << 16); }
+};
+
+struct PFP8 {
+  using T = uint8_t;  // OCP e4m3 (max 448)
+  static constexpr int ID = 2, KG = 64;
+  static constexpr bool SCALED = true;
+  __device__ static v4f mma(v4f c, uint4 a, uint4 b) {
+    const long a0 = ((long)a.y << 32) | a.x, a1 = ((long)a.w << 32) | a.z;
+    const long b0 = ((long)b.y << 32) | b.x, b1 = ((long)b.w << 32) | b.z;
+    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a0, b0, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a1, b1, c, 0, 0, 0);
+    return c;
+  }
+  // round to nearest even, saturating at +-448
+  __device__ static T cvt(float x) {
+    x = fminf(fmaxf(x, -448.f), 448.f);
+    return (T)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
+  }
+  __device__ static float val(T x) { return __builtin_amdgcn_cvt_f32_fp8((int)x, 0); }
+};
+
+template <class Net, class P>
+struct Geo {
+  using T = typename P::T;
+  static constexpr int NT = Net::WAVES * 64;
+  static constexpr int PAD = 16 / sizeof(T);                       // 16 bytes of row padding
+  static constexpr int DP = padded_feat(Net::D, P::ID);            // features per slot
+  static constexpr int SX = Net::BS * DP + PAD;                    // window block, per sub-trace
+  static constexpr int SA1 = (Net::BS / 2) * Net::CH1 + PAD;       // conv1 output
+  static constexpr int SA2 = (Net::BS / 4) * Net::CH2 + PAD;       // conv2 output
+  static constexpr int SA3 = (Net::NCONV == 3 ? Net::CH3 : 0) + PAD;  // conv3 output
+  static constexpr int SAL = Net::NCONV == 3 ? SA3 : SA2;          // last conv output
+};
+
+template <class Net, class P>
 struct NetSmem {
-  float x[MT * Geo<Net>::SX];
-  float a1[MT * Geo<Net>::SA1];
-  float a2[MT * Geo<Net>::SA2];
-  float a3[Net::NCONV == 3 ? MT * Geo<Net>::SA3 : 4];
+  using G = Geo<Net, P>;
+  typename P::T x[MT * G::SX];
+  typename P::T a1[MT * G::SA1];
+  typename P::T a2[MT * G::SA2];
+  typename P::T a3[Net::NCONV == 3 ? MT * G::SA3 : G::PAD];
   float red[Net::WAVES][MT][Net::NOUT];
   float logit[MT][Net::NOUT];
 };
 
+// Epilogue of one accumulator element: bias, (FP8) dequantisation, ReLU,
+// (FP8) the next layer's input scale, conversion to storage.
+template <class P>
+__device__ __forceinline__ typename P::T epilogue(float acc, int col, const float* bias,
+                                                  const float* ws, const float* ai, bool relu) {
+  float v;
+  if constexpr (P::SCALED)
+    v = fmaf(acc, ws[col], bias[col]);
+  else
+    v = acc + bias[col];
+  if (relu) v = fmaxf(v, 0.f);
+  if constexpr (P::SCALED) v *= ai[col];
+  return P::cvt(v);
+}
+
 // One conv level as a GEMM: rows (s, q) = MT sub-traces x P output positions,
-// A row (s, q) is the K = 2*C_in contiguous floats of input positions 2q, 2q+1
-// at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.
-template <int K, int N, int P, int WAVES, int SA, int SO>
-__device__ __forceinline__ void conv_stage(const float* __restrict__ A, float* __restrict__ O,
-                                           const float4* __restrict__ Bp,
-                                           const float* __restrict__ bias, bool relu, int wave,
+// A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
+// 2q+1 at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.
+template <class P, int K, int N, int POS, int WAVES, int SA, int SO>
+__device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
+                                           typename P::T* __restrict__ O,
+                                           const uint4* __restrict__ Bp,
+                                           const float* __restrict__ bias,
+                                           const float* __restrict__ ws,
+                                           const float* __restrict__ ai, bool relu, int wave,
                                            int lane) {
-  constexpr int ROWS = MT * P;
-  constexpr int MTILES = ROWS / 16, NTILES = N / 16, KG = K / 16;
+  using T = typename P::T;
+  constexpr int ROWS = MT * POS;
+  constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
   constexpr int TILES = MTILES * NTILES;
   constexpr int TPW = TILES / WAVES;
-  static_assert(ROWS % 16 == 0 && N % 16 == 0 && K % 16 == 0, "tile shape");
+  static_assert(ROWS % 16 == 0 && N % 16 == 0 && K % P::KG == 0, "tile shape");
   static_assert(TILES % WAVES == 0 && TPW >= 1 && NTILES % TPW == 0, "wave split");
   const int t0 = wave * TPW;
   const int mt = t0 / NTILES, nt0 = t0 % NTILES;
   const int arow = mt * 16 + (lane & 15);
-  const float* ap = A + (arow / P) * SA + (arow % P) * K + 4 * (lane >> 4);
+  const T* ap = A + (arow / POS) * SA + (arow % POS) * K + (P::KG / 4) * (lane >> 4);
   v4f acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int kg = 0; kg < KG; ++kg) {
-    const float4 a = *reinterpret_cast<const float4*>(ap + kg * 16);
+  for (int kg = 0; kg < KGS; ++kg) {
+    const uint4 a = *reinterpret_cast<const uint4*>(ap + kg * P::KG);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-      const float4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
-      acc[j] = mfma_k16(acc[j], a, b);
+      const uint4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
+      acc[j] = P::mma(acc[j], a, b);
     }
   }
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int col = (nt0 + j) * 16 + (lane & 15);
-    const float bb = bias[col];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = mt * 16 + 4 * (lane >> 4) + i;
-      float v = acc[j][i] + bb;
-      if (relu) v = fmaxf(v, 0.f);
-      O[(row / P) * SO + (row % P) * N + col] = v;
+      O[(row / POS) * SO + (row % POS) * N + col] = epilogue<P>(acc[j][i], col, bias, ws, ai, relu);
     }
   }
 }
 
 // Hidden FC, one block's K-slice: acc[MT rows][N cols] += A[MT][K] * B_j.
-template <int K, int N, int WAVES, int SA>
-__device__ __forceinline__ void hidden_accumulate(v4f* acc, const float* __restrict__ A,
-                                                  const float4* __restrict__ Bp, int wave,
+template <class P, int K, int N, int WAVES, int SA>
+__device__ __forceinline__ void hidden_accumulate(v4f* acc, const typename P::T* __restrict__ A,
+                                                  const uint4* __restrict__ Bp, int wave,
                                                   int lane) {
-  constexpr int NTILES = N / 16, KG = K / 16, TPW = NTILES / WAVES;
+  constexpr int NTILES = N / 16, KGS = K / P::KG, TPW = NTILES / WAVES;
   const int nt0 = wave * TPW;
-  const float* ap = A + (lane & 15) * SA + 4 * (lane >> 4);
+  const typename P::T* ap = A + (lane & 15) * SA + (P::KG / 4) * (lane >> 4);
 #pragma unroll 4
-  for (int kg = 0; kg < KG; ++kg) {
-    const float4 a = *reinterpret_cast<const float4*>(ap + kg * 16);
+  for (int kg = 0; kg < KGS; ++kg) {
+    const uint4 a = *reinterpret_cast<const uint4*>(ap + kg * P::KG);
 #pragma unroll
     for (int j = 0; j < TPW; ++j) {
-      const float4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
-      acc[j] = mfma_k16(acc[j], a, b);
+      const uint4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
+      acc[j] = P::mma(acc[j], a, b);
     }
   }
 }
 
 // The whole predictor on one tile of MT windows.  fill(j, X) writes block j
-// of every window (slots j*BS .. j*BS+BS-1, DP floats each, layout
-// X[s*SX + t*DP + c]) and is called by all threads; the raw outputs land in
-// sm.logit.  relu_mask bit l = ReLU after layer l.
-template <class Net, class Fill>
+// of every window (slots j*BS .. j*BS+BS-1, DP elements each, layout
+// X[s*SX + t*DP + c], already in storage precision) and is called by all
+// threads; the raw outputs land in sm.logit.  relu_mask bit l = ReLU after
+// layer l.
+template <class Net, class P, class Fill>
 __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
-                                             NetSmem<Net>& sm, Fill&& fill) {
-  using G = Geo<Net>;
+                                             NetSmem<Net, P>& sm, Fill&& fill) {
+  using G = Geo<Net, P>;
+  using T = typename P::T;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int HT = Net::HID > 0 ? (Net::HID / 16) / Net::WAVES : 1;
   v4f hacc[HT];
@@ -139,43 +212,44 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   for (int j = 0; j < Net::NB; ++j) {
     fill(j, sm.x);
     __syncthreads();
-    conv_stage<2 * Net::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1>(
-        sm.x, sm.a1, reinterpret_cast<const float4*>(wt.conv_w[0]), wt.conv_b[0],
-        relu_mask & 1u, wave, lane);
+    conv_stage<P, 2 * G::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1>(
+        sm.x, sm.a1, static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
+        wt.conv_ai[0], relu_mask & 1u, wave, lane);
     __syncthreads();
-    conv_stage<2 * Net::CH1, Net::CH2, Net::BS / 4, Net::WAVES, G::SA1, G::SA2>(
-        sm.a1, sm.a2, reinterpret_cast<const float4*>(wt.conv_w[1]), wt.conv_b[1],
-        relu_mask & 2u, wave, lane);
+    conv_stage<P, 2 * Net::CH1, Net::CH2, Net::BS / 4, Net::WAVES, G::SA1, G::SA2>(
+        sm.a1, sm.a2, static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
+        wt.conv_ai[1], relu_mask & 2u, wave, lane);
     __syncthreads();
     if constexpr (Net::NCONV == 3) {
-      conv_stage<2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3>(
-          sm.a2, sm.a3, reinterpret_cast<const float4*>(wt.conv_w[2]), wt.conv_b[2],
-          relu_mask & 4u, wave, lane);
+      conv_stage<P, 2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3>(
+          sm.a2, sm.a3, static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
+          wt.conv_ai[2], relu_mask & 4u, wave, lane);
       __syncthreads();
     }
-    const float* last = Net::NCONV == 3 ? sm.a3 : sm.a2;
+    const T* last = Net::NCONV == 3 ? sm.a3 : sm.a2;
     if constexpr (Net::HID > 0) {
-      const float4* bj = reinterpret_cast<const float4*>(wt.hid_w) +
-                         (size_t)j * (Net::CHL / 16) * (Net::HID / 16) * 64;
+      const uint4* bj = static_cast<const uint4*>(wt.hid_w) +
+                        (size_t)j * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
       // per-block partial in a fresh accumulator, then added: the FP32
-      // summation chain is 16 k-groups + NB blocks instead of NB*16 in a row
+      // summation chain is K/KG groups + NB blocks instead of one long chain
       v4f bacc[HT];
 #pragma unroll
       for (int jj = 0; jj < HT; ++jj) bacc[jj] = v4f{0.f, 0.f, 0.f, 0.f};
-      hidden_accumulate<Net::CHL, Net::HID, Net::WAVES, G::SAL>(bacc, last, bj, wave, lane);
+      hidden_accumulate<P, Net::CHL, Net::HID, Net::WAVES, G::SAL>(bacc, last, bj, wave, lane);
 #pragma unroll
       for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[jj];
     } else {
       const float* wrow = wt.last_w + ((size_t)j * Net::NOUT + fo) * Net::CHL + fsub * CPL;
-      const float* arow = last + fs * G::SAL + fsub * CPL;
+      const T* arow = last + fs * G::SAL + fsub * CPL;
 #pragma unroll
-      for (int c = 0; c < CPL; ++c) fpart = fmaf(arow[c], wrow[c], fpart);
+      for (int c = 0; c < CPL; ++c) fpart = fmaf(P::val(arow[c]), wrow[c], fpart);
     }
   }
 
   if constexpr (Net::HID > 0) {
-    // bias + ReLU on the hidden layer, then the final FC: each lane holds 4
-    // rows x HT columns; reduce over the 16 lanes sharing rows, then waves.
+    // bias + ReLU on the hidden layer, rounding to the form's precision, then
+    // the final FC: each lane holds 4 rows x HT columns; reduce over the 16
+    // lanes sharing rows, then over waves.
     const bool hrelu = relu_mask & (1u << Net::NCONV);
     float p[4][Net::NOUT];
 #pragma unroll
@@ -185,14 +259,12 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) {
       const int col = (wave * HT + jj) * 16 + (lane & 15);
-      const float bb = wt.hid_b[col];
       float wo[Net::NOUT];
 #pragma unroll
       for (int o = 0; o < Net::NOUT; ++o) wo[o] = wt.last_w[o * Net::HID + col];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        float h = hacc[jj][i] + bb;
-        if (hrelu) h = fmaxf(h, 0.f);
+        const float h = P::val(epilogue<P>(hacc[jj][i], col, wt.hid_b, wt.hid_ws, wt.hid_ai, hrelu));
 #pragma unroll
         for (int o = 0; o < Net::NOUT; ++o) p[i][o] = fmaf(h, wo[o], p[i][o]);
       }
@@ -230,6 +302,13 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   __syncthreads();
 }
 
+// Window element in storage precision (FP8: the feature's input scale).
+template <class P>
+__device__ __forceinline__ typename P::T window_elem(float v, int c, const float* x_inv) {
+  if constexpr (P::SCALED) v *= x_inv[c];
+  return P::cvt(v);
+}
+
 // Rounded latency in cycles: nearest, ties to even; non-finite -> 0;
 // clamped to [0, lat_max].
 __device__ __forceinline__ int32_t round_latency(float v, int32_t lat_max, uint32_t& clamped,
@@ -250,9 +329,9 @@ __device__ __forceinline__ int32_t round_latency(float v, int32_t lat_max, uint3
   return (int32_t)r;
 }
 
-template <class Net>
+template <class Net, class P>
 struct StepSmem {
-  NetSmem<Net> net;
+  NetSmem<Net, P> net;
   int32_t q_idx[MT][Net::C];
   int32_t q_e[MT][Net::C];
   int64_t q_t[MT][Net::C];
@@ -262,11 +341,13 @@ struct StepSmem {
   int32_t head[MT], count[MT], warm[MT], active[MT];
 };
 
-template <class Net, bool RUN_NET>
+template <class Net, class P, bool RUN_NET>
 __global__ void __launch_bounds__(Net::WAVES * 64)
     step_kernel(DevWeights wt, uint32_t relu_mask, DevState st, StepParams p) {
-  constexpr int C = Net::C, NT = Geo<Net>::NT, D = Net::D, DP = Net::DP, BS = Net::BS;
-  __shared__ StepSmem<Net> sm;
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  constexpr int C = Net::C, NT = G::NT, D = Net::D, DP = G::DP, BS = Net::BS;
+  __shared__ StepSmem<Net, P> sm;
   const int tid = threadIdx.x;
   const int k0 = blockIdx.x * MT;
 
@@ -309,7 +390,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       static_assert(NT % ROWS == 0 && DP % TPR == 0, "gather split");
       const int row = tid / TPR, part = tid % TPR;
       const int s = row / BS, t = row % BS;
-      auto fill = [&](int j, float* X) {
+      auto fill = [&](int j, T* X) {
         const int w = j * BS + t;
         int64_t idx = -1;
         float res = 0.f, ex = 0.f;
@@ -324,7 +405,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
             ex = (float)sm.q_e[s][e];
           }
         }
-        float* dst = X + s * Geo<Net>::SX + t * DP;
+        T* dst = X + s * G::SX + t * DP;
         const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
@@ -333,10 +414,10 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
           if (c == p.col_res) v = res;
           if (c == p.col_exe) v = ex;
           if (c == p.col_sto) v = 0.f;
-          dst[c] = v;
+          dst[c] = window_elem<P>(v, c < D ? c : 0, wt.x_inv);
         }
       };
-      predict_tile<Net>(wt, relu_mask, sm.net, fill);
+      predict_tile<Net, P>(wt, relu_mask, sm.net, fill);
     }
 
     if (tid < MT && sm.active[tid]) {
@@ -361,13 +442,13 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
           lat[o] = inj;
         }
       }
-      const int64_t T = sm.cur[s] + lat[0];
+      const int64_t Tn = sm.cur[s] + lat[0];
       int head = sm.head[s], count = sm.count[s];
-      while (count > 0 && sm.q_r[s][head] <= T) {  // retired by T: a prefix (r is monotone)
+      while (count > 0 && sm.q_r[s][head] <= Tn) {  // retired by Tn: a prefix (r is monotone)
         head = head + 1 == C ? 0 : head + 1;
         --count;
       }
-      int64_t r = T + lat[1] + 1;
+      int64_t r = Tn + lat[1] + 1;
       r = r > sm.r_prev[s] ? r : sm.r_prev[s];
       const int wi = (int)(pos % p.W);
       if (pos >= p.W) {
@@ -384,17 +465,17 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       }
       sm.q_idx[s][slot] = (int32_t)(sm.first[s] + pos);
       sm.q_e[s][slot] = lat[1];
-      sm.q_t[s][slot] = T;
+      sm.q_t[s][slot] = Tn;
       sm.q_r[s][slot] = r;
       sm.head[s] = head;
       sm.count[s] = count;
       sm.r_prev[s] = r;
-      sm.cur[s] = T;
+      sm.cur[s] = Tn;
       sm.pos[s] = pos + 1;
-      if (pos + 1 == sm.warm[s]) sm.t_w[s] = T;
+      if (pos + 1 == sm.warm[s]) sm.t_w[s] = Tn;
       if (pos + 1 == sm.n_pos[s]) {  // last instruction: drain ends at r (Eq. 1)
-        st.fetch[k] = T - sm.t_w[s];
-        st.drain[k] = r - T;
+        st.fetch[k] = Tn - sm.t_w[s];
+        st.drain[k] = r - Tn;
         st.final_tick[k] = r;
         st.warm_tick[k] = sm.t_w[s];
         sm.active[s] = 0;
@@ -431,29 +512,31 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   }
 }
 
-template <class Net>
+template <class Net, class P>
 __global__ void __launch_bounds__(Net::WAVES * 64)
     forward_kernel(DevWeights wt, uint32_t relu_mask, const float* __restrict__ x, int64_t B,
                    float* __restrict__ logits) {
-  constexpr int NT = Geo<Net>::NT, D = Net::D, DP = Net::DP, BS = Net::BS, L = Net::L;
-  __shared__ NetSmem<Net> sm;
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  constexpr int NT = G::NT, D = Net::D, DP = G::DP, BS = Net::BS, L = Net::L;
+  __shared__ NetSmem<Net, P> sm;
   const int tid = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * MT;
   constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
   const int row = tid / TPR, part = tid % TPR;
   const int s = row / BS, t = row % BS;
-  auto fill = [&](int j, float* X) {
+  auto fill = [&](int j, T* X) {
     const int64_t b = b0 + s;
     const int w = j * BS + t;
     const float* src = x + ((b < B ? b : 0) * L + w) * D;
-    float* dst = X + s * Geo<Net>::SX + t * DP;
+    T* dst = X + s * G::SX + t * DP;
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
       const int c = part * CPT + cc;
-      dst[c] = (b < B && c < D) ? src[c] : 0.f;
+      dst[c] = window_elem<P>((b < B && c < D) ? src[c] : 0.f, c < D ? c : 0, wt.x_inv);
     }
   };
-  predict_tile<Net>(wt, relu_mask, sm, fill);
+  predict_tile<Net, P>(wt, relu_mask, sm, fill);
   if (tid < MT * Net::NOUT) {
     const int ss = tid / Net::NOUT, o = tid % Net::NOUT;
     if (b0 + ss < B) logits[(b0 + ss) * Net::NOUT + o] = sm.logit[ss][o];
@@ -495,35 +578,51 @@ __global__ void __launch_bounds__(256) total_kernel(DevState st, int32_t n_sub, 
   if (threadIdx.x == 0) *total = part[0] + part[1] + part[2] + part[3];
 }
 
-template <class Net>
+template <class Net, class P>
 static hipError_t launch_step_t(const DevWeights& w, uint32_t relu, const DevState& s,
                                 const StepParams& p, hipStream_t stream) {
-  const dim3 grid((p.n_sub + MT - 1) / MT), block(Geo<Net>::NT);
+  const dim3 grid((p.n_sub + MT - 1) / MT), block(Geo<Net, P>::NT);
   if (p.lat_mode == 1)
-    hipLaunchKernelGGL((step_kernel<Net, false>), grid, block, 0, stream, w, relu, s, p);
+    hipLaunchKernelGGL((step_kernel<Net, P, false>), grid, block, 0, stream, w, relu, s, p);
   else
-    hipLaunchKernelGGL((step_kernel<Net, true>), grid, block, 0, stream, w, relu, s, p);
+    hipLaunchKernelGGL((step_kernel<Net, P, true>), grid, block, 0, stream, w, relu, s, p);
   return hipGetLastError();
-}
-
-hipError_t launch_step(int net, const DevWeights& w, uint32_t relu, const DevState& s,
-                       const StepParams& p, hipStream_t stream) {
-  return net == 0 ? launch_step_t<NetSmall>(w, relu, s, p, stream)
-                  : launch_step_t<NetC3>(w, relu, s, p, stream);
 }
 
 template <class Net>
+static hipError_t launch_step_n(int prec, const DevWeights& w, uint32_t relu, const DevState& s,
+                                const StepParams& p, hipStream_t stream) {
+  if (prec == 0) return launch_step_t<Net, PF32>(w, relu, s, p, stream);
+  if (prec == 1) return launch_step_t<Net, PBF16>(w, relu, s, p, stream);
+  return launch_step_t<Net, PFP8>(w, relu, s, p, stream);
+}
+
+hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, const DevState& s,
+                       const StepParams& p, hipStream_t stream) {
+  return net == 0 ? launch_step_n<NetSmall>(prec, w, relu, s, p, stream)
+                  : launch_step_n<NetC3>(prec, w, relu, s, p, stream);
+}
+
+template <class Net, class P>
 static hipError_t launch_forward_t(const DevWeights& w, uint32_t relu, const float* x, int64_t B,
                                    float* logits, hipStream_t stream) {
-  const dim3 grid((unsigned)((B + MT - 1) / MT)), block(Geo<Net>::NT);
-  hipLaunchKernelGGL((forward_kernel<Net>), grid, block, 0, stream, w, relu, x, B, logits);
+  const dim3 grid((unsigned)((B + MT - 1) / MT)), block(Geo<Net, P>::NT);
+  hipLaunchKernelGGL((forward_kernel<Net, P>), grid, block, 0, stream, w, relu, x, B, logits);
   return hipGetLastError();
 }
 
-hipError_t launch_forward(int net, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
-                          float* logits, hipStream_t stream) {
-  return net == 0 ? launch_forward_t<NetSmall>(w, relu, x, B, logits, stream)
-                  : launch_forward_t<NetC3>(w, relu, x, B, logits, stream);
+template <class Net>
+static hipError_t launch_forward_n(int prec, const DevWeights& w, uint32_t relu, const float* x,
+                                   int64_t B, float* logits, hipStream_t stream) {
+  if (prec == 0) return launch_forward_t<Net, PF32>(w, relu, x, B, logits, stream);
+  if (prec == 1) return launch_forward_t<Net, PBF16>(w, relu, x, B, logits, stream);
+  return launch_forward_t<Net, PFP8>(w, relu, x, B, logits, stream);
+}
+
+hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
+                          int64_t B, float* logits, hipStream_t stream) {
+  return net == 0 ? launch_forward_n<NetSmall>(prec, w, relu, x, B, logits, stream)
+                  : launch_forward_n<NetC3>(prec, w, relu, x, B, logits, stream);
 }
 
 hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream) {

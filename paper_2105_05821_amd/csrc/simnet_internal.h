@@ -18,8 +18,7 @@ constexpr int NCOUNTERS = 4; // clamped, non-finite, shadow mismatches, predicti
 struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr int D = 32, L = 16, C = 15;
   static constexpr int NCONV = 2, BS = 4, NB = 4;
-  static constexpr int DP = 32;              // features per slot as laid out in LDS
-  static constexpr int CH0 = 32, CH1 = 32, CH2 = 64, CH3 = 0;
+  static constexpr int CH1 = 32, CH2 = 64, CH3 = 0;
   static constexpr int HID = 0, NOUT = 2;
   static constexpr int WAVES = 4;
   static constexpr int CHL = CH2;            // channels of the last conv
@@ -27,25 +26,44 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
 struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -> FC 512 -> FC 2
   static constexpr int D = 50, L = 111, C = 110;
   static constexpr int NCONV = 3, BS = 8, NB = 13;
-  static constexpr int DP = 56;
-  static constexpr int CH0 = 56, CH1 = 64, CH2 = 128, CH3 = 256;
+  static constexpr int CH1 = 64, CH2 = 128, CH3 = 256;
   static constexpr int HID = 512, NOUT = 2;
   static constexpr int WAVES = 8;
   static constexpr int CHL = CH3;
 };
 
+// Contraction length covered by one 16-byte per-lane MFMA fragment group:
+// FP32 16 (four 16x16x4), BF16 32 (one 16x16x32), FP8 64 (two 16x16x32).
+constexpr int kgroup(int prec) { return prec == 0 ? 16 : prec == 1 ? 32 : 64; }
+// Features per window slot as laid out for the kernels: D rounded up so
+// that a slot pair (one conv1 row) is a whole number of fragment groups.
+constexpr int padded_feat(int D, int prec) {
+  return (D + kgroup(prec) / 2 - 1) / (kgroup(prec) / 2) * (kgroup(prec) / 2);
+}
+
 // Weights re-laid-out for the kernels (device pointers, owned by the context).
 // conv level l: B_l[k][n] with k = t*CH_l + c (t = pair member, c = input
-// channel, zero for padded channels), packed per (k-group of 16, n-tile of 16)
-// as 64 lanes x 4 floats: lane holds B[kg*16 + 4*(lane/16) + s][nt*16 + lane%16].
+// channel, zero for padded channels), packed per (k-group of KG, n-tile of
+// 16) as 64 lanes x 16 bytes: lane holds B[kg*KG + (KG/4)*(lane/16) + e]
+// [nt*16 + lane%16], e = 0 .. KG/4-1, in the storage type of the precision.
 // Hidden FC (NetC3): one such packed matrix per block j with
-// B_j[c][n] = W1[n][c*NB + j].  Final FC: wlast[j][o][c] = Wf[o][c*NB + j]
-// when it follows the convs directly, else wlast[o][h] = W2[o][h].
+// B_j[c][n] = W1[n][c*NB + j].  Final FC (VALU, float): wlast[j][o][c] =
+// Wf[o][c*NB + j] when it follows the convs directly, else wlast[o][h] =
+// W2[o][h]; values already rounded to the precision (FP8: dequantised, with
+// the scale of its input folded in).
+// FP8 only: *_ws = per-output-channel weight dequantisation scale, *_ai =
+// per-channel reciprocal scale applied before an activation is stored as the
+// next layer's FP8 input, x_inv = the same for the window features.
 struct DevWeights {
-  const float* conv_w[3];
+  const void* conv_w[3];
   const float* conv_b[3];
-  const float* hid_w;
+  const float* conv_ws[3];
+  const float* conv_ai[3];
+  const float* x_inv;
+  const void* hid_w;
   const float* hid_b;
+  const float* hid_ws;
+  const float* hid_ai;
   const float* last_w;
   const float* last_b;
 };
@@ -89,12 +107,12 @@ struct StepParams {
   int32_t n_steps;
 };
 
-// Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3.  relu: bit l = ReLU
-// after layer l.
-hipError_t launch_step(int net, const DevWeights& w, uint32_t relu, const DevState& s,
+// Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3; prec: 0 FP32,
+// 1 BF16, 2 FP8 (e4m3).  relu: bit l = ReLU after layer l.
+hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, const DevState& s,
                        const StepParams& p, hipStream_t stream);
-hipError_t launch_forward(int net, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
-                          float* logits, hipStream_t stream);
+hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
+                          int64_t B, float* logits, hipStream_t stream);
 hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream);
 hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream);
 

@@ -411,3 +411,29 @@ def test_output_scale_matches_library(oracle_lib):
     ref = np.abs(bs[-1].astype(np.float64))[None, :] + np.abs(h) @ np.abs(ws[-1].astype(np.float64)).T
     np.testing.assert_allclose(scale, ref, rtol=1e-12)
     assert np.all(scale >= np.abs(out))
+
+
+def test_bf16_form_matches_library_rounding(oracle_lib):
+    """The BF16 form: PyTorch's own bfloat16 rounding of inputs, weights and
+    hidden activations, with float64 arithmetic in between."""
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(6, layers)
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=(3, 111, 50)) * rng.choice([1.0, 40.0], size=(3, 111, 50))
+    q = lambda a: torch.from_numpy(np.asarray(a, np.float64)).to(torch.bfloat16).to(torch.float64)
+    h = q(x).transpose(1, 2)
+    for i, (ly, w, b) in enumerate(zip(layers, ws, bs)):
+        wq = q(w)
+        bt = torch.from_numpy(np.asarray(b, np.float64))
+        if ly.kind == synth.CONV:
+            h = torch.nn.functional.conv1d(h, wq, bt, stride=2)
+        else:
+            h = torch.nn.functional.linear(h.reshape(h.shape[0], -1), wq, bt)
+        if ly.relu:
+            h = torch.relu(h)
+        if i < len(layers) - 1:
+            h = h.to(torch.bfloat16).to(torch.float64)
+    m = oracle_lib.Model(layers, ws, bs, 50, 111, prec=1)
+    np.testing.assert_allclose(m.forward(x), h.numpy(), rtol=1e-11, atol=1e-11)
+    m64 = oracle_lib.Model(layers, ws, bs, 50, 111)
+    assert not np.allclose(m64.forward(x), h.numpy(), rtol=1e-6)
