@@ -90,6 +90,8 @@ def main():
     dfeat = torch.from_numpy(feat).cuda()
     sim = sn.Simulator(dfeat, wl.n_slot, wl.cols, start, length, warm, prec=PREC[args.prec])
     sim.load_weights(wl.layers, sn.flat_params(ws, bs))
+    if args.prec == "fp8":
+        sim.calibrate(64)  # per-channel scales from the first 64 FP32 steps (set-up, untimed)
     stream = sim.stream
     max_pos = int((length + warm).max())
 

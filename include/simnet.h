@@ -153,6 +153,24 @@ SIMNET_API int sim_reset(sim_ctx* ctx);
  * recording).  Used for parity checks on identical windows. */
 SIMNET_API int sim_record_logits(sim_ctx* ctx, float* logits);
 
+/* Calibrate the FP8 form (also allowed for FP32 contexts, to read the
+ * scales): run n_steps steps of every sub-trace with the FP32 predictor
+ * (lat_mode/lat_table as in sim_step), take each layer input channel's
+ * largest magnitude (window features, then every hidden layer's outputs in
+ * order), set that channel's scale to the smallest power of two s with
+ * max <= 448 s, and (FP8) build the e4m3 weights: each weight is multiplied
+ * by its input channel's scale and then gets a power-of-two scale per output
+ * channel on the same rule.  Synchronises; resets the simulation state.
+ * FP8 contexts return SIM_ESTATE from sim_step, sim_run and predictor_fwd
+ * until calibrated.  SIM_EUNSUPPORTED for BF16 contexts. */
+SIMNET_API int sim_calibrate(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
+                             const int32_t* lat_table);
+
+/* Copy the calibrated per-channel activation scales (HOST out, at least n
+ * floats: n_feat + the width of every hidden layer).  SIM_ESTATE before
+ * calibration, SIM_EINVAL if n is too small. */
+SIMNET_API int sim_act_scales(const sim_ctx* ctx, float* out, int32_t n);
+
 /* Predictor forward on explicit windows (Sec. 2.3): x is DEVICE
  * [B][n_slot][n_feat] float32, logits DEVICE [B][n_out] float32.
  * save_or_null is reserved for the training path and must be NULL. */

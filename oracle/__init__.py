@@ -59,7 +59,16 @@ def lib():
         L.ol_partition.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i64p, i32p]
         L.ol_simulate.restype = C.c_int
         L.ol_simulate.argtypes = [P, i32p, P, C.c_int64, C.c_int32, i64p, i64p, i32p,
-                                  C.c_int32, P, i64p, i64p, i64p, i64p, P, P, P, i64p, C.c_int32]
+                                  C.c_int32, P, i64p, i64p, i64p, i64p, P, P, P, i64p, C.c_int32,
+                                  C.c_int64, P]
+        L.ol_model_new_fp8.restype = P
+        L.ol_model_new_fp8.argtypes = [C.c_int, i32p, f32p, C.c_int, C.c_int, f32p]
+        L.ol_scales_from_amax.argtypes = [f64p, C.c_int32, f32p]
+        L.ol_scales_from_amax.restype = None
+        L.ol_round_e4m3.argtypes = [C.c_double]
+        L.ol_round_e4m3.restype = C.c_double
+        L.ol_round_bf16.argtypes = [C.c_double]
+        L.ol_round_bf16.restype = C.c_double
         _lib = L
     return _lib
 
@@ -77,15 +86,25 @@ class Model:
     evaluates the BF16 form (inputs, weights and hidden activations rounded
     to bfloat16, exact sums)."""
 
-    def __init__(self, layers, ws, bs, n_feat: int, n_slot: int, prec: int = 0):
+    def __init__(self, layers, ws, bs, n_feat: int, n_slot: int, prec: int = 0,
+                 scales: Optional[np.ndarray] = None):
+        """prec 2 is the FP8 form and needs ``scales`` (one per input channel
+        of every layer, the window's features first)."""
         desc = np.array([[ly.kind, ly.c_in, ly.c_out, ly.relu] for ly in layers],
                         dtype=np.int32).ravel()
         self._params = flat_params(ws, bs)
         self.n_feat, self.n_slot = n_feat, n_slot
-        self.ptr = lib().ol_model_new_prec(len(layers), desc, self._params, n_feat, n_slot, prec)
+        if prec == 2:
+            self._scales = np.ascontiguousarray(scales, np.float32)
+            self.ptr = lib().ol_model_new_fp8(len(layers), desc, self._params, n_feat, n_slot,
+                                              self._scales)
+        else:
+            self.ptr = lib().ol_model_new_prec(len(layers), desc, self._params, n_feat, n_slot,
+                                               prec)
         if not self.ptr:
             raise ValueError("layer list does not fit the window shape")
         self.n_out = lib().ol_model_nout(self.ptr)
+        self.hidden_widths = [ly.c_out for ly in layers[:-1]]
 
     def __del__(self):
         if getattr(self, "ptr", None) and _lib is not None:
@@ -137,7 +156,7 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
              model: Optional[Model] = None, mode: int = PREDICT,
              lat_table: Optional[np.ndarray] = None, want_logits: bool = False,
              want_lat: bool = False, n_instr: Optional[int] = None, threads: int = 0,
-             want_scale: bool = False) -> dict:
+             want_scale: bool = False, max_pos: int = 0, want_amax: bool = False) -> dict:
     """Run the oracle over every sub-trace; returns per-sub-trace int64 arrays
     and optionally the per-prediction logits (float64) and latencies."""
     start = np.ascontiguousarray(start, np.int64)
@@ -159,6 +178,10 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
         lat_table = np.ascontiguousarray(lat_table, np.int32)
         assert lat_table.size >= n_pred * n_out
     counters = np.zeros(2, np.int64)
+    amax = None
+    if want_amax:
+        n_amax = model.n_feat + sum(ly_out for ly_out in model.hidden_widths)
+        amax = np.zeros(n_amax, np.float64)
     if threads <= 0:
         threads = default_threads()
     rc = lib().ol_simulate(model.ptr if model else None, cfg,
@@ -169,10 +192,29 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
                            logits.ctypes.data if logits is not None else None,
                            scale.ctypes.data if scale is not None else None,
                            lat.ctypes.data if lat is not None else None,
-                           counters, threads)
+                           counters, threads, max_pos,
+                           amax.ctypes.data if amax is not None else None)
     if rc != 0:
         raise ValueError("oracle rejected the arguments")
     res["total"] = int(np.sum(res["final"] - res["warm_tick"]))
     res["n_clamped"], res["n_nonfinite"] = int(counters[0]), int(counters[1])
-    res["logits"], res["lat"], res["scale"] = logits, lat, scale
+    res["logits"], res["lat"], res["scale"], res["amax"] = logits, lat, scale, amax
     return res
+
+
+def fp8_scales(amax: np.ndarray) -> np.ndarray:
+    """Per-channel FP8 scales from calibration maxima (the oracle's rule)."""
+    amax = np.ascontiguousarray(amax, np.float64)
+    out = np.zeros(amax.size, np.float32)
+    lib().ol_scales_from_amax(amax, amax.size, out)
+    return out
+
+
+def calibrate(cfg, feat, start, length, warm, model: Model, n_steps: int,
+              lat_table: Optional[np.ndarray] = None, threads: int = 0) -> np.ndarray:
+    """Largest |input| per channel of every layer over the first n_steps
+    positions of every sub-trace (inject mode when a table is given)."""
+    res = simulate(cfg, feat, start, length, warm, model=model,
+                   mode=INJECT if lat_table is not None else PREDICT, lat_table=lat_table,
+                   threads=threads, max_pos=n_steps, want_amax=True)
+    return res["amax"]

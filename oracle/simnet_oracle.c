@@ -59,7 +59,8 @@ typedef struct {
   double* w[16];
   double* b[16];
   int n_feat, n_slot, n_out, max_width;
-  int prec;                 /* 0: plain FP64; 1: BF16 form (see round_bf16) */
+  int prec;                 /* 0: plain FP64; 1: BF16 form; 2: FP8 form */
+  double* in_scale[17];     /* FP8 form: scale of each input channel of layer l */
 } ol_model;
 
 /* Nearest bfloat16 value (8 significant bits, ties to even), from the
@@ -71,6 +72,45 @@ static double round_bf16(double v) {
   frexp(v, &ex);
   const double ulp = ldexp(1.0, ex - 8);
   return nearbyint(v / ulp) * ulp;
+}
+
+/* Nearest OCP e4m3 value (1 sign, 4 exponent bits with bias 7, 3 mantissa
+ * bits; largest finite 448; subnormal spacing 2^-9), ties to even,
+ * saturating: v = m * 2^ex with 0.5 <= |m| < 1 lies in a binade whose
+ * spacing is 2^(ex - 4), never below the subnormal spacing 2^-9. */
+static double round_e4m3(double v) {
+  if (v > 448.0) v = 448.0;
+  if (v < -448.0) v = -448.0;
+  if (v == 0.0) return v;
+  int ex;
+  frexp(v, &ex);
+  if (ex < -5) ex = -5;
+  const double ulp = ldexp(1.0, ex - 4);
+  double r = nearbyint(v / ulp) * ulp;
+  if (r > 448.0) r = 448.0;
+  if (r < -448.0) r = -448.0;
+  return r;
+}
+
+/* Smallest power of two s with amax <= 448 * s; 1 when amax is 0. */
+static double pow2_scale(double amax) {
+  if (!(amax > 0.0)) return 1.0;
+  int ex;
+  const double f = frexp(amax / 448.0, &ex); /* amax/448 = f * 2^ex */
+  double s = (f == 0.5) ? ldexp(1.0, ex - 1) : ldexp(1.0, ex);
+  while (amax > 448.0 * s) s *= 2.0;        /* guard the division's rounding */
+  while (s > 1e-300 && amax <= 448.0 * (s / 2.0)) s /= 2.0;
+  return s;
+}
+
+/* Rounding of an input value of layer li, channel c, to the form. */
+static double qin(const ol_model* m, int li, int c, double v) {
+  if (m->prec == 1) return round_bf16(v);
+  if (m->prec == 2) {
+    const double s = m->in_scale[li][c];
+    return round_e4m3(v / s) * s;
+  }
+  return v;
 }
 
 static double qform(const ol_model* m, double v) { return m->prec == 1 ? round_bf16(v) : v; }
@@ -130,10 +170,51 @@ void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
   return ol_model_new_prec(n_layers, desc, params, n_feat, n_slot, 0);
 }
 
+/* The FP8 form: scales holds, layer by layer, one power-of-two scale per
+ * input channel of that layer (the window's features first).  An input x of
+ * channel c is used as e4m3(x / s_c) * s_c.  Each weight is multiplied by its
+ * input channel's scale and each output channel n gets the power-of-two
+ * scale w_n for its largest such magnitude; the weight used is
+ * e4m3(W s_c / w_n) * w_n / s_c.  Biases as given, sums exact. */
+void* ol_model_new_fp8(int n_layers, const int32_t* desc, const float* params,
+                       int n_feat, int n_slot, const float* scales) {
+  ol_model* m = (ol_model*)ol_model_new_prec(n_layers, desc, params, n_feat, n_slot, 0);
+  if (!m) return NULL;
+  m->prec = 2;
+  int ch = n_feat, len = n_slot;
+  size_t off = 0;
+  for (int l = 0; l < n_layers; ++l) {
+    m->in_scale[l] = (double*)malloc(sizeof(double) * (size_t)ch);
+    for (int c = 0; c < ch; ++c) m->in_scale[l][c] = (double)scales[off + c];
+    off += (size_t)ch;
+    const int kind = m->desc[l][0], ci = m->desc[l][1], co = m->desc[l][2];
+    const int n_in = kind == OL_CONV ? ci * 2 : ci;
+    /* input channel of weight element k of an output's row */
+    for (int o = 0; o < co; ++o) {
+      double* row = m->w[l] + (size_t)o * n_in;
+      double amax = 0.0;
+      for (int k = 0; k < n_in; ++k) {
+        const int c = kind == OL_CONV ? k / 2 : k / len;
+        const double a = fabs(row[k] * m->in_scale[l][c]);
+        if (a > amax) amax = a;
+      }
+      const double ws = pow2_scale(amax);
+      for (int k = 0; k < n_in; ++k) {
+        const int c = kind == OL_CONV ? k / 2 : k / len;
+        const double sc = m->in_scale[l][c];
+        row[k] = round_e4m3(row[k] * sc / ws) * ws / sc;
+      }
+    }
+    ch = co;
+    len = kind == OL_CONV ? len / 2 : 1;
+  }
+  return m;
+}
+
 void ol_model_free(void* p) {
   ol_model* m = (ol_model*)p;
   if (!m) return;
-  for (int l = 0; l < m->n_layers; ++l) { free(m->w[l]); free(m->b[l]); }
+  for (int l = 0; l < m->n_layers; ++l) { free(m->w[l]); free(m->b[l]); free(m->in_scale[l]); }
   free(m);
 }
 
@@ -145,11 +226,38 @@ int ol_model_nout(const void* p) { return ((const ol_model*)p)->n_out; }
  * If scale is not NULL it receives, per output, |b| + sum_j |w_j * a_j| of
  * the last layer: the magnitude against which the rounding error of any
  * finite-precision evaluation of that output is measured. */
+static void forward_cal(const ol_model* m, const double* x, double* out, double* a, double* t,
+                        double* scale, double* amax);
 static void forward_one(const ol_model* m, const double* x, double* out,
                         double* a, double* t, double* scale) {
+  forward_cal(m, x, out, a, t, scale, NULL);
+}
+
+/* Number of leading positions of conv level li's output that some final
+ * output depends on (the rest are the unpaired tails dropped later). */
+static int live_len(const ol_model* m, int li, int len_out) {
+  int n = len_out;
+  for (int l = li + 1; l < m->n_layers && m->desc[l][0] == OL_CONV; ++l) n /= 2;
+  for (int l = li + 1; l < m->n_layers && m->desc[l][0] == OL_CONV; ++l) n *= 2;
+  return n;
+}
+
+/* forward_one, optionally recording into amax the largest |input| of every
+ * layer per channel over the values some output depends on (window slots
+ * and conv positions past the paired prefix are skipped), laid out layer by
+ * layer as the FP8 scales are. */
+static void forward_cal(const ol_model* m, const double* x, double* out, double* a, double* t,
+                        double* scale, double* amax) {
   int ch = m->n_feat, len = m->n_slot;
+  if (amax) {
+    const int live = live_len(m, -1, len);
+    for (int l = 0; l < live; ++l)
+      for (int c = 0; c < ch; ++c)
+        if (fabs(x[l * ch + c]) > amax[c]) amax[c] = fabs(x[l * ch + c]);
+    amax += ch;
+  }
   for (int l = 0; l < len; ++l)
-    for (int c = 0; c < ch; ++c) a[c * len + l] = qform(m, x[l * ch + c]);
+    for (int c = 0; c < ch; ++c) a[c * len + l] = qin(m, 0, c, x[l * ch + c]);
   for (int li = 0; li < m->n_layers; ++li) {
     const int32_t* d = m->desc[li];
     const double* w = m->w[li];
@@ -183,7 +291,14 @@ static void forward_one(const ol_model* m, const double* x, double* out,
     }
     ch = co;
     const int last = (li == m->n_layers - 1);
-    for (int i = 0; i < ch * len; ++i) a[i] = last ? t[i] : qform(m, t[i]);
+    if (amax && !last) {
+      const int live = d[0] == OL_CONV ? live_len(m, li, len) : len;
+      for (int c = 0; c < ch; ++c)
+        for (int p = 0; p < live; ++p)
+          if (fabs(t[c * len + p]) > amax[c]) amax[c] = fabs(t[c * len + p]);
+      amax += ch;
+    }
+    for (int i = 0; i < ch * len; ++i) a[i] = last ? t[i] : qin(m, li + 1, i / len, t[i]);
   }
   memcpy(out, a, sizeof(double) * (size_t)m->n_out);
 }
@@ -286,24 +401,29 @@ typedef struct {
   double* scale_out;
   int32_t* lat_out;
   int64_t counters[2]; /* clamped, non-finite (summed under the lock) */
+  int64_t max_pos;     /* > 0: stop each sub-trace after this many positions */
+  double* amax;        /* calibration: per layer-input channel max |value| */
+  int n_amax;
   int32_t next;
   int32_t err;
   pthread_mutex_t mu;
 } sim_job;
 
 static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* t,
-                         queue* Q, int64_t* cnt) {
+                         queue* Q, int64_t* cnt, double* amax) {
   const int32_t* cfg = J->cfg;
   const int D = cfg[CF_NFEAT], L = cfg[CF_NSLOT], n_out = cfg[CF_NOUT], W = cfg[CF_W];
   const int cr = cfg[CF_COLRES], ce = cfg[CF_COLEXE], cs = cfg[CF_COLSTO];
   const int32_t lat_max = cfg[CF_LATMAX];
   const int C = L - 1;
-  const int need_pred = (J->mode == OL_PREDICT) || (J->logits_out != NULL);
+  const int need_pred = (J->mode == OL_PREDICT) || (J->logits_out != NULL) || (amax != NULL);
   double out[8], scl[8];
 
   Q->head = Q->tail = 0;
   int64_t cur = 0, t_w = 0;
-  const int64_t w = J->warm[k], n_pos = J->warm[k] + J->len[k];
+  const int64_t w = J->warm[k];
+  int64_t n_pos = J->warm[k] + J->len[k];
+  if (J->max_pos > 0 && J->max_pos < n_pos) n_pos = J->max_pos;
   const int64_t first = J->start[k] - w;
   for (int64_t p = 0; p < n_pos; ++p) {
     const int64_t i = first + p;
@@ -326,7 +446,7 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
         if (ce >= 0) row[ce] = (double)e->e;
         if (cs >= 0) row[cs] = (n_out >= 3) ? (double)e->s : 0.0;
       }
-      forward_one(J->m, win, out, a, t, J->scale_out ? scl : NULL);
+      forward_cal(J->m, win, out, a, t, J->scale_out ? scl : NULL, amax);
       if (J->logits_out)
         for (int o = 0; o < n_out; ++o) J->logits_out[g * n_out + o] = out[o];
       if (J->scale_out)
@@ -350,6 +470,7 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
     q_push(Q, e);
     if (p == w - 1) t_w = cur;
   }
+  if (J->max_pos > 0) return; /* partial run (calibration): no results */
   const int64_t t_last = cur;
   while (Q->tail > Q->head) tick(Q, &cur, W); /* drain */
   J->fetch[k] = t_last - t_w;
@@ -367,17 +488,22 @@ static void* sim_worker(void* arg) {
   double* t = (double*)malloc(sizeof(double) * (size_t)width);
   queue Q = {NULL, 0, 0, 0};
   int64_t cnt[2] = {0, 0};
+  double* amax = J->amax ? (double*)calloc((size_t)J->n_amax, sizeof(double)) : NULL;
   for (;;) {
     pthread_mutex_lock(&J->mu);
     int32_t k = J->next++;
     pthread_mutex_unlock(&J->mu);
     if (k >= J->n_sub) break;
-    simulate_one(J, k, win, a, t, &Q, cnt);
+    simulate_one(J, k, win, a, t, &Q, cnt, amax);
   }
   pthread_mutex_lock(&J->mu);
   J->counters[0] += cnt[0];
   J->counters[1] += cnt[1];
+  if (amax)
+    for (int i = 0; i < J->n_amax; ++i)
+      if (amax[i] > J->amax[i]) J->amax[i] = amax[i];
   pthread_mutex_unlock(&J->mu);
+  free(amax);
   free(Q.q);
   free(win);
   free(a);
@@ -389,7 +515,10 @@ static void* sim_worker(void* arg) {
  * rounded predictions; OL_INJECT advances with lat_table[(pred_off[k] + p) *
  * n_out + o] (the model is then only run when logits_out is requested and
  * may be NULL otherwise; scale_out, like logits_out, receives each output's
- * |b| + sum |w a| of the last layer).  Per-sub-trace results: fetch = T_last - T_w,
+ * |b| + sum |w a| of the last layer).  max_pos > 0 stops every sub-trace
+ * after its first max_pos positions (no per-sub-trace results then); amax,
+ * if given, receives per layer-input channel the largest |value| an output
+ * depends on (window features, then every hidden layer).  Per-sub-trace results: fetch = T_last - T_w,
  * drain = final - T_last, final tick, T_w.  counters[0] = clamped, [1] =
  * non-finite.  Returns 0, or -1 on invalid arguments. */
 int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_t n_instr,
@@ -397,7 +526,7 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
                 int32_t mode, const int32_t* lat_table,
                 int64_t* fetch, int64_t* drain, int64_t* final_tick, int64_t* warm_tick,
                 double* logits_out, double* scale_out, int32_t* lat_out, int64_t* counters,
-                int32_t n_threads) {
+                int32_t n_threads, int64_t max_pos, double* amax) {
   const ol_model* m = (const ol_model*)model;
   if (cfg[CF_NOUT] < 2 || cfg[CF_NOUT] > 2) return -1; /* store latency not modelled */
   if (cfg[CF_W] < 1 || cfg[CF_NSLOT] < 1) return -1;
@@ -421,6 +550,18 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
   J.mode = mode; J.lat_table = lat_table;
   J.fetch = fetch; J.drain = drain; J.final_tick = final_tick; J.warm_tick = warm_tick;
   J.logits_out = logits_out; J.scale_out = scale_out; J.lat_out = lat_out;
+  J.max_pos = max_pos;
+  J.amax = amax;
+  if (amax) {
+    if (!m) { free(pred_off); return -1; }
+    int width = m->n_feat, len = m->n_slot;
+    for (int l = 0; l < m->n_layers - 1; ++l) {
+      width += m->desc[l][2];
+      (void)len;
+    }
+    J.n_amax = width;
+    for (int i = 0; i < width; ++i) amax[i] = 0.0;
+  }
   pthread_mutex_init(&J.mu, NULL);
   if (n_threads <= 0) n_threads = (int32_t)sysconf(_SC_NPROCESSORS_ONLN);
   if (n_threads > n_sub) n_threads = n_sub;
@@ -434,3 +575,13 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
   free(pred_off);
   return 0;
 }
+
+/* FP8 scales from calibration maxima: the smallest power of two s with
+ * amax <= 448 s, per entry. */
+void ol_scales_from_amax(const double* amax, int32_t n, float* scales) {
+  for (int32_t i = 0; i < n; ++i) scales[i] = (float)pow2_scale(amax[i]);
+}
+
+/* e4m3 rounding of single values (exposed for its pin tests). */
+double ol_round_e4m3(double v) { return round_e4m3(v); }
+double ol_round_bf16(double v) { return round_bf16(v); }

@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVIC
                 -4: "SIM_ESTATE", -5: "SIM_ENONFINITE", -6: "SIM_EUNSUPPORTED"}
 
 EXPORTED = ("sim_validate_config", "sim_init", "sim_load_weights", "sim_step", "sim_run",
-            "sim_reset", "sim_record_logits", "predictor_fwd", "sim_destroy", "sim_last_error")
+            "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "predictor_fwd",
+            "sim_destroy", "sim_last_error")
 
 
 class sim_layer(C.Structure):
@@ -75,6 +76,8 @@ def lib():
         L.sim_reset.argtypes = [P]
         L.sim_record_logits.argtypes = [P, P]
         L.predictor_fwd.argtypes = [P, P, C.c_int64, P, P]
+        L.sim_calibrate.argtypes = [P, C.c_int32, C.c_int32, P]
+        L.sim_act_scales.argtypes = [P, P, C.c_int32]
         L.sim_destroy.argtypes = [P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = [P]
@@ -197,6 +200,15 @@ class Simulator:
 
     def reset(self) -> None:
         self._check("sim_reset", lib().sim_reset(self.ctx))
+
+    def calibrate(self, n_steps: int = 64, lat_mode: int = SIM_LAT_PREDICT, lat_table=None):
+        self._check("sim_calibrate",
+                    lib().sim_calibrate(self.ctx, n_steps, lat_mode, _ptr(lat_table)))
+
+    def act_scales(self) -> np.ndarray:
+        out = np.zeros(4096, np.float32)
+        self._check("sim_act_scales", lib().sim_act_scales(self.ctx, out.ctypes.data, out.size))
+        return out
 
     def record_logits(self, buf) -> None:
         self._check("sim_record_logits", lib().sim_record_logits(self.ctx, _ptr(buf)))

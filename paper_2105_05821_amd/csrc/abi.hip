@@ -30,6 +30,12 @@ struct sim_ctx {
   hipStream_t stream = nullptr;
   void* dev_block = nullptr;  // state + table
   void* dev_weights = nullptr;
+  void* dev_w32 = nullptr;          // FP8 form: FP32 weights for calibration
+  DevWeights w32{};
+  std::vector<float> params;        // FP8 form: FP32 parameters as loaded
+  std::vector<float> act_scale;     // per layer-input channel, after calibration
+  bool calibrated = false;
+  int64_t steps_launched = 0;
   int64_t* dev_total = nullptr;
   DevState st{};
   DevWeights w{};
@@ -129,6 +135,17 @@ uint8_t e4m3_bits(float x) {  // round to nearest even, saturating at +-448
   return (uint8_t)(sign | c);
 }
 
+// Smallest power of two s with amax <= 448 * s (1 when amax is 0): the scale
+// that maps a channel's largest magnitude into e4m3's finite range.
+float pow2_scale(float amax) {
+  if (!(amax > 0.f)) return 1.f;
+  const double a = amax;
+  int e = (int)ceil(log2(a / 448.0));
+  while (a > 448.0 * ldexp(1.0, e)) ++e;
+  while (a <= 448.0 * ldexp(1.0, e - 1)) --e;
+  return (float)ldexp(1.0, e);
+}
+
 constexpr size_t elem_size(int prec) { return prec == 0 ? 4 : prec == 1 ? 2 : 1; }
 
 void store_elem(int prec, float v, uint8_t* dst) {
@@ -221,7 +238,7 @@ std::vector<uint8_t> relayout(int prec, const float* params,
     for (int n = 0; n < co; ++n) {
       float amax = 0.f;
       for (int k = 0; k < K; ++k) amax = fmaxf(amax, fabsf(wv(k, n)));
-      s[n] = amax > 0.f ? ldexpf(1.f, (int)ceilf(log2f(amax / 448.f))) : 1.f;
+      s[n] = pow2_scale(amax);
     }
     (void)l;
     return s;
@@ -244,8 +261,8 @@ std::vector<uint8_t> relayout(int prec, const float* params,
       for (int n = 0; n < N; ++n) {
         // next layer's input channel n: conv channel n, or (hidden FC) the
         // flattened inputs n*NB + j, which share one scale per channel
-        const float s = next_is_conv ? (*in_scale)[l + 1][n] : (*in_scale)[l + 1][n];
-        ai[n] = 1.f / s;
+        ai[n] = 1.f / (*in_scale)[l + 1][n];  // next layer's input channel n
+        (void)next_is_conv;
       }
     }
     L->conv_ai[l] = put_floats(ai);
@@ -281,7 +298,7 @@ std::vector<uint8_t> relayout(int prec, const float* params,
     for (int o = 0; o < Net::NOUT; ++o) {
       float amax = 0.f;
       for (int n = 0; n < N; ++n) amax = fmaxf(amax, fabsf(w[li + 1][(size_t)o * N + n] * sin(li + 1, n)));
-      const float s = fp8 && amax > 0.f ? ldexpf(1.f, (int)ceilf(log2f(amax / 448.f))) : 1.f;
+      const float s = fp8 ? pow2_scale(amax) : 1.f;
       for (int n = 0; n < N; ++n)
         lw[(size_t)o * N + n] = round_to(prec, w[li + 1][(size_t)o * N + n] * sin(li + 1, n) / s) * s;
     }
@@ -295,7 +312,7 @@ std::vector<uint8_t> relayout(int prec, const float* params,
       float amax = 0.f;
       for (int kk = 0; kk < K * NB; ++kk)
         amax = fmaxf(amax, fabsf(Wf[(size_t)o * (K * NB) + kk] * sin(li, kk / NB)));
-      const float s = fp8 && amax > 0.f ? ldexpf(1.f, (int)ceilf(log2f(amax / 448.f))) : 1.f;
+      const float s = fp8 ? pow2_scale(amax) : 1.f;
       for (int j = 0; j < NB; ++j)
         for (int c = 0; c < K; ++c)
           lw[((size_t)j * Net::NOUT + o) * K + c] =
@@ -328,6 +345,49 @@ bool layers_match(const sim_layer* layers, int32_t n) {
 }
 
 }  // namespace
+
+// Pack params for one precision and upload them into *dev (replacing any
+// previous block); fills *w with the device pointers.
+static int upload_weights(sim_ctx* c, int prec, const float* params,
+                          const std::vector<std::vector<float>>* scales, void** dev,
+                          DevWeights* w) {
+  Layout lay{};
+  std::vector<uint8_t> packed = c->net == 0 ? relayout<NetSmall>(prec, params, scales, &lay)
+                                            : relayout<NetC3>(prec, params, scales, &lay);
+  void* dw = nullptr;
+  hipError_t e = hipMalloc(&dw, packed.size());
+  if (e != hipSuccess) return hip_fail(c, e, "hipMalloc weights");
+  e = hipMemcpy(dw, packed.data(), packed.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(dw);
+    return hip_fail(c, e, "upload weights");
+  }
+  if (*dev) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(*dev);
+  }
+  *dev = dw;
+  char* base = static_cast<char*>(dw);
+  auto F = [&](size_t o) { return reinterpret_cast<const float*>(base + o); };
+  *w = DevWeights{};
+  const int nconv = c->net == 0 ? NetSmall::NCONV : NetC3::NCONV;
+  for (int l = 0; l < nconv; ++l) {
+    w->conv_w[l] = base + lay.conv_w[l];
+    w->conv_b[l] = F(lay.conv_b[l]);
+    w->conv_ws[l] = F(lay.conv_ws[l]);
+    w->conv_ai[l] = F(lay.conv_ai[l]);
+  }
+  w->x_inv = F(lay.x_inv);
+  if (c->net == 1) {
+    w->hid_w = base + lay.hid_w;
+    w->hid_b = F(lay.hid_b);
+    w->hid_ws = F(lay.hid_ws);
+    w->hid_ai = F(lay.hid_ai);
+  }
+  w->last_w = F(lay.last_w);
+  w->last_b = F(lay.last_b);
+  return SIM_OK;
+}
 
 extern "C" {
 
@@ -457,48 +517,22 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
   }
   for (size_t i = 0; i < np; ++i)
     if (!isfinite(host[i])) return fail(c, SIM_ENONFINITE, "parameter %zu is not finite", i);
-  if (c->cfg.prec == SIM_FP8E4M3)
-    return fail(c, SIM_EUNSUPPORTED, "FP8 needs activation scales (not available yet)");
-  Layout lay{};
-  std::vector<uint8_t> packed = c->net == 0 ? relayout<NetSmall>(c->cfg.prec, host.data(), nullptr, &lay)
-                                            : relayout<NetC3>(c->cfg.prec, host.data(), nullptr, &lay);
   uint32_t relu = 0;
   for (int32_t i = 0; i < n_layers; ++i)
     if (layers[i].relu) relu |= 1u << i;
-  void* dw = nullptr;
-  hipError_t e = hipMalloc(&dw, packed.size());
-  if (e != hipSuccess) return hip_fail(c, e, "hipMalloc weights");
-  e = hipMemcpy(dw, packed.data(), packed.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) {
-    (void)hipFree(dw);
-    return hip_fail(c, e, "upload weights");
-  }
-  if (c->dev_weights) {
-    (void)hipStreamSynchronize(c->stream);
-    (void)hipFree(c->dev_weights);
-  }
-  c->dev_weights = dw;
-  char* base = static_cast<char*>(dw);
-  auto F = [&](size_t o) { return reinterpret_cast<const float*>(base + o); };
-  DevWeights& w = c->w;
-  w = DevWeights{};
-  const int nconv = c->net == 0 ? NetSmall::NCONV : NetC3::NCONV;
-  for (int l = 0; l < nconv; ++l) {
-    w.conv_w[l] = base + lay.conv_w[l];
-    w.conv_b[l] = F(lay.conv_b[l]);
-    w.conv_ws[l] = F(lay.conv_ws[l]);
-    w.conv_ai[l] = F(lay.conv_ai[l]);
-  }
-  w.x_inv = F(lay.x_inv);
-  if (c->net == 1) {
-    w.hid_w = base + lay.hid_w;
-    w.hid_b = F(lay.hid_b);
-    w.hid_ws = F(lay.hid_ws);
-    w.hid_ai = F(lay.hid_ai);
-  }
-  w.last_w = F(lay.last_w);
-  w.last_b = F(lay.last_b);
   c->relu = relu;
+  if (c->cfg.prec == SIM_FP8E4M3) {
+    // FP8 needs activation scales: keep the parameters, build FP32 weights
+    // for the calibration pass; the FP8 weights are built by sim_calibrate.
+    c->params = host;
+    c->calibrated = false;
+    int rc = upload_weights(c, SIM_FP32, host.data(), nullptr, &c->dev_w32, &c->w32);
+    if (rc != SIM_OK) return rc;
+    c->weights = true;
+    return sim_reset(c);
+  }
+  int rc = upload_weights(c, c->cfg.prec, host.data(), nullptr, &c->dev_weights, &c->w);
+  if (rc != SIM_OK) return rc;
   c->weights = true;
   return sim_reset(c);
 }
@@ -508,6 +542,76 @@ int sim_reset(sim_ctx* c) {
   hipError_t e = launch_reset(c->st, c->n_sub, c->C, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reset");
   c->completed = false;
+  c->steps_launched = 0;
+  return SIM_OK;
+}
+
+int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* table) {
+  if (!c) return SIM_EINVAL;
+  if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
+  if (c->cfg.prec == SIM_BF16) return fail(c, SIM_EUNSUPPORTED, "calibration runs FP32 weights");
+  if (n_steps < 1) return fail(c, SIM_EINVAL, "n_steps < 1");
+  if (mode < SIM_LAT_PREDICT || mode > SIM_LAT_SHADOW) return fail(c, SIM_EINVAL, "bad lat_mode");
+  if (mode != SIM_LAT_PREDICT && !table) return fail(c, SIM_EINVAL, "lat_table required");
+  const DevWeights& w32 = c->cfg.prec == SIM_FP8E4M3 ? c->w32 : c->w;
+  const int n = calibration_size(c->net);
+  unsigned* amax = nullptr;
+  hipError_t e = hipMalloc(&amax, sizeof(unsigned) * n);
+  if (e != hipSuccess) return hip_fail(c, e, "hipMalloc calibration");
+  int rc = sim_reset(c);
+  std::vector<unsigned> host(n, 0u);
+  if (rc == SIM_OK) {
+    e = hipMemsetAsync(amax, 0, sizeof(unsigned) * n, c->stream);
+    StepParams p{};
+    p.feat = c->feat;
+    p.n_sub = c->n_sub;
+    p.W = c->cfg.retire_width;
+    p.col_res = c->cfg.col_res;
+    p.col_exe = c->cfg.col_exe;
+    p.col_sto = c->cfg.col_sto;
+    p.lat_max = c->cfg.lat_max;
+    p.lat_mode = mode;
+    p.lat_table = table;
+    p.logits_out = nullptr;
+    p.n_steps = n_steps;
+    p.cal_out = amax;
+    if (e == hipSuccess) e = launch_calibrate(c->net, w32, c->relu, c->st, p, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(host.data(), amax, sizeof(unsigned) * n, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) rc = hip_fail(c, e, "calibration run");
+  }
+  (void)hipFree(amax);
+  if (rc != SIM_OK) return rc;
+  // power-of-two scale per layer-input channel (window features first)
+  c->act_scale.assign(n, 1.f);
+  for (int i = 0; i < n; ++i) {
+    float a;
+    memcpy(&a, &host[i], 4);
+    c->act_scale[i] = pow2_scale(a);
+  }
+  if (c->cfg.prec == SIM_FP8E4M3) {
+    std::vector<int> sizes = c->net == 0 ? std::vector<int>{NetSmall::D, NetSmall::CH1, NetSmall::CH2}
+                                         : std::vector<int>{NetC3::D, NetC3::CH1, NetC3::CH2,
+                                                            NetC3::CH3, NetC3::HID};
+    std::vector<std::vector<float>> per_layer;
+    size_t off = 0;
+    for (int sz : sizes) {
+      per_layer.emplace_back(c->act_scale.begin() + off, c->act_scale.begin() + off + sz);
+      off += sz;
+    }
+    rc = upload_weights(c, SIM_FP8E4M3, c->params.data(), &per_layer, &c->dev_weights, &c->w);
+    if (rc != SIM_OK) return rc;
+  }
+  c->calibrated = true;
+  return sim_reset(c);
+}
+
+int sim_act_scales(const sim_ctx* c, float* out, int32_t n) {
+  if (!c || !out) return SIM_EINVAL;
+  if (!c->calibrated) return SIM_ESTATE;
+  if (n < (int32_t)c->act_scale.size()) return SIM_EINVAL;
+  memcpy(out, c->act_scale.data(), sizeof(float) * c->act_scale.size());
   return SIM_OK;
 }
 
@@ -521,7 +625,11 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   if (mode < SIM_LAT_PREDICT || mode > SIM_LAT_SHADOW) return fail(c, SIM_EINVAL, "bad lat_mode");
   if (mode != SIM_LAT_PREDICT && !table) return fail(c, SIM_EINVAL, "lat_table required");
   if (mode != SIM_LAT_INJECT && !c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
+  if (mode != SIM_LAT_INJECT && c->cfg.prec == SIM_FP8E4M3 && !c->calibrated)
+    return fail(c, SIM_ESTATE, "FP8 form needs sim_calibrate first");
   if (c->completed) return fail(c, SIM_ESTATE, "run completed; call sim_reset");
+  if (c->steps_launched >= c->max_pos) return SIM_OK;  // every sub-trace has finished
+  c->steps_launched = std::min<int64_t>(c->max_pos, c->steps_launched + n_steps);
   StepParams p{};
   p.feat = c->feat;
   p.n_sub = c->n_sub;
@@ -534,6 +642,7 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   p.lat_table = table;
   p.logits_out = c->logits_out;
   p.n_steps = (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
+  p.cal_out = nullptr;
   hipError_t e = launch_step(c->net, c->cfg.prec, c->w, c->relu, c->st, p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   return SIM_OK;
@@ -582,6 +691,8 @@ int sim_run(sim_ctx* c, int32_t mode, const int32_t* table, sim_result* res) {
 int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* save_or_null) {
   if (!c) return SIM_EINVAL;
   if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
+  if (c->cfg.prec == SIM_FP8E4M3 && !c->calibrated)
+    return fail(c, SIM_ESTATE, "FP8 form needs sim_calibrate first");
   if (save_or_null) return fail(c, SIM_EUNSUPPORTED, "save buffer not supported");
   if (B < 0 || (B > 0 && (!x || !logits))) return fail(c, SIM_EINVAL, "bad batch arguments");
   if (B == 0) return SIM_OK;
@@ -596,6 +707,7 @@ void sim_destroy(sim_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   if (c->dev_weights) (void)hipFree(c->dev_weights);
+  if (c->dev_w32) (void)hipFree(c->dev_w32);
   if (c->dev_block) (void)hipFree(c->dev_block);
   delete c;
 }

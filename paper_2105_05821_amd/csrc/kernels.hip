@@ -108,32 +108,94 @@ struct NetSmem {
   float logit[MT][Net::NOUT];
 };
 
-// Epilogue of one accumulator element: bias, (FP8) dequantisation, ReLU,
-// (FP8) the next layer's input scale, conversion to storage.
+// Epilogue of one accumulator element: bias, (FP8) dequantisation, ReLU.
 template <class P>
-__device__ __forceinline__ typename P::T epilogue(float acc, int col, const float* bias,
-                                                  const float* ws, const float* ai, bool relu) {
+__device__ __forceinline__ float activation(float acc, int col, const float* bias, const float* ws,
+                                            bool relu) {
   float v;
   if constexpr (P::SCALED)
     v = fmaf(acc, ws[col], bias[col]);
   else
     v = acc + bias[col];
-  if (relu) v = fmaxf(v, 0.f);
+  return relu ? fmaxf(v, 0.f) : v;
+}
+// ... then (FP8) the next layer's input scale and conversion to storage.
+template <class P>
+__device__ __forceinline__ typename P::T to_storage(float v, int col, const float* ai) {
   if constexpr (P::SCALED) v *= ai[col];
   return P::cvt(v);
+}
+// Calibration: running per-channel max of |activation| (LDS, as ordered bits).
+__device__ __forceinline__ void cal_max(unsigned* cal, int i, float v) {
+  atomicMax(cal + i, __float_as_uint(fabsf(v)));
+}
+
+// k-groups per chunk when streaming B: two chunks of TPW fragments in flight
+// are at most 16 fragments (64 VGPRs) per lane; must divide the k-groups.
+constexpr int stream_chunk(int kgs, int tpw) {
+  int c = 8 / tpw;
+  if (c < 1) c = 1;
+  if (c > kgs) c = kgs;
+  while (kgs % c) --c;
+  return c;
+}
+
+// acc[j] += A(rows of this lane's fragment, all K) * B(k, tiles nt0 + j):
+// B fragments are requested one chunk ahead of their use (double
+// buffering) and the scheduler is kept from sinking the requests.
+// One 16-byte B fragment through a raw buffer load: the resource and the
+// fragment's offset are wave-uniform (scalar registers), only the lane's
+// 16-byte offset is per lane, so many fragments can be in flight without a
+// 64-bit address register each.
+__device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_off, int frag_off) {
+  return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, frag_off, 0));
+}
+
+template <class P, int KGS, int NTILES, int TPW>
+__device__ __forceinline__ void mma_stream(v4f* acc, const typename P::T* __restrict__ ap,
+                                           const uint4* __restrict__ Bp, int nt0, int lane) {
+  constexpr int CH = stream_chunk(KGS, TPW), NCH = KGS / CH;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<uint4*>(Bp), (short)0, KGS * NTILES * 1024, 0x00020000);
+  const int lo = lane * 16;
+  const int wn = __builtin_amdgcn_readfirstlane(nt0) * 1024;
+  uint4 b[2][CH][TPW];
+#pragma unroll
+  for (int kg = 0; kg < CH; ++kg)
+#pragma unroll
+    for (int j = 0; j < TPW; ++j) b[0][kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    if (c + 1 < NCH) {
+#pragma unroll
+      for (int kg = 0; kg < CH; ++kg)
+#pragma unroll
+        for (int j = 0; j < TPW; ++j)
+          b[(c + 1) & 1][kg][j] = load_frag(rs, lo, wn + (((c + 1) * CH + kg) * NTILES + j) * 1024);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kg = 0; kg < CH; ++kg) {
+      const uint4 a = *reinterpret_cast<const uint4*>(ap + (c * CH + kg) * P::KG);
+#pragma unroll
+      for (int j = 0; j < TPW; ++j) acc[j] = P::mma(acc[j], a, b[c & 1][kg][j]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // One conv level as a GEMM: rows (s, q) = MT sub-traces x P output positions,
 // A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
 // 2q+1 at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.
-template <class P, int K, int N, int POS, int WAVES, int SA, int SO>
+template <class P, int K, int N, int POS, int WAVES, int SA, int SO, bool CAL = false>
 __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
                                            typename P::T* __restrict__ O,
                                            const uint4* __restrict__ Bp,
                                            const float* __restrict__ bias,
                                            const float* __restrict__ ws,
                                            const float* __restrict__ ai, bool relu, int wave,
-                                           int lane) {
+                                           int lane, unsigned* cal = nullptr,
+                                           const int* row_live = nullptr) {
   using T = typename P::T;
   constexpr int ROWS = MT * POS;
   constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
@@ -148,22 +210,17 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
   v4f acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int kg = 0; kg < KGS; ++kg) {
-    const uint4 a = *reinterpret_cast<const uint4*>(ap + kg * P::KG);
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      const uint4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
-      acc[j] = P::mma(acc[j], a, b);
-    }
-  }
+  mma_stream<P, KGS, NTILES, TPW>(acc, ap, Bp, nt0, lane);
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
     const int col = (nt0 + j) * 16 + (lane & 15);
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const int row = mt * 16 + 4 * (lane >> 4) + i;
-      O[(row / POS) * SO + (row % POS) * N + col] = epilogue<P>(acc[j][i], col, bias, ws, ai, relu);
+      const float v = activation<P>(acc[j][i], col, bias, ws, relu);
+      if constexpr (CAL)
+        if (row_live[row / POS]) cal_max(cal, col, v);
+      O[(row / POS) * SO + (row % POS) * N + col] = to_storage<P>(v, col, ai);
     }
   }
 }
@@ -174,27 +231,22 @@ __device__ __forceinline__ void hidden_accumulate(v4f* acc, const typename P::T*
                                                   const uint4* __restrict__ Bp, int wave,
                                                   int lane) {
   constexpr int NTILES = N / 16, KGS = K / P::KG, TPW = NTILES / WAVES;
-  const int nt0 = wave * TPW;
   const typename P::T* ap = A + (lane & 15) * SA + (P::KG / 4) * (lane >> 4);
-#pragma unroll 4
-  for (int kg = 0; kg < KGS; ++kg) {
-    const uint4 a = *reinterpret_cast<const uint4*>(ap + kg * P::KG);
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      const uint4 b = Bp[(kg * NTILES + nt0 + j) * 64 + lane];
-      acc[j] = P::mma(acc[j], a, b);
-    }
-  }
+  mma_stream<P, KGS, NTILES, TPW>(acc, ap, Bp, wave * TPW, lane);
 }
 
 // The whole predictor on one tile of MT windows.  fill(j, X) writes block j
 // of every window (slots j*BS .. j*BS+BS-1, DP elements each, layout
 // X[s*SX + t*DP + c], already in storage precision) and is called by all
 // threads; the raw outputs land in sm.logit.  relu_mask bit l = ReLU after
-// layer l.
-template <class Net, class P, class Fill>
+// layer l.  CAL: also record per-channel max |input| of every layer into
+// cal (offsets: window D, conv1 out, conv2 out[, conv3 out, hidden out]),
+// counting only tile rows whose row_live[s] is set (real windows).
+template <class Net, class P, bool CAL = false, class Fill>
 __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
-                                             NetSmem<Net, P>& sm, Fill&& fill) {
+                                             NetSmem<Net, P>& sm, Fill&& fill,
+                                             unsigned* cal = nullptr,
+                                             const int* row_live = nullptr) {
   using G = Geo<Net, P>;
   using T = typename P::T;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -212,18 +264,19 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   for (int j = 0; j < Net::NB; ++j) {
     fill(j, sm.x);
     __syncthreads();
-    conv_stage<P, 2 * G::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1>(
+    conv_stage<P, 2 * G::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1, CAL>(
         sm.x, sm.a1, static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
-        wt.conv_ai[0], relu_mask & 1u, wave, lane);
+        wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live);
     __syncthreads();
-    conv_stage<P, 2 * Net::CH1, Net::CH2, Net::BS / 4, Net::WAVES, G::SA1, G::SA2>(
+    conv_stage<P, 2 * Net::CH1, Net::CH2, Net::BS / 4, Net::WAVES, G::SA1, G::SA2, CAL>(
         sm.a1, sm.a2, static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
-        wt.conv_ai[1], relu_mask & 2u, wave, lane);
+        wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live);
     __syncthreads();
     if constexpr (Net::NCONV == 3) {
-      conv_stage<P, 2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3>(
+      conv_stage<P, 2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3, CAL>(
           sm.a2, sm.a3, static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
-          wt.conv_ai[2], relu_mask & 4u, wave, lane);
+          wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2,
+          row_live);
       __syncthreads();
     }
     const T* last = Net::NCONV == 3 ? sm.a3 : sm.a2;
@@ -264,7 +317,11 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
       for (int o = 0; o < Net::NOUT; ++o) wo[o] = wt.last_w[o * Net::HID + col];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float h = P::val(epilogue<P>(hacc[jj][i], col, wt.hid_b, wt.hid_ws, wt.hid_ai, hrelu));
+        const float hv = activation<P>(hacc[jj][i], col, wt.hid_b, wt.hid_ws, hrelu);
+        if constexpr (CAL)
+          if (row_live[4 * (lane >> 4) + i])
+            cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col, hv);
+        const float h = P::val(to_storage<P>(hv, col, wt.hid_ai));
 #pragma unroll
         for (int o = 0; o < Net::NOUT; ++o) p[i][o] = fmaf(h, wo[o], p[i][o]);
       }
@@ -341,15 +398,23 @@ struct StepSmem {
   int32_t head[MT], count[MT], warm[MT], active[MT];
 };
 
-template <class Net, class P, bool RUN_NET>
+template <class Net>
+constexpr int n_cal() {
+  return Net::D + Net::CH1 + Net::CH2 + Net::CH3 + Net::HID;
+}
+
+template <class Net, class P, bool RUN_NET, bool CAL = false>
 __global__ void __launch_bounds__(Net::WAVES * 64)
     step_kernel(DevWeights wt, uint32_t relu_mask, DevState st, StepParams p) {
   using G = Geo<Net, P>;
   using T = typename P::T;
   constexpr int C = Net::C, NT = G::NT, D = Net::D, DP = G::DP, BS = Net::BS;
   __shared__ StepSmem<Net, P> sm;
+  __shared__ unsigned cal[CAL ? n_cal<Net>() : 1];
   const int tid = threadIdx.x;
   const int k0 = blockIdx.x * MT;
+  if constexpr (CAL)
+    for (int i = tid; i < n_cal<Net>(); i += NT) cal[i] = 0u;
 
   if (tid < MT) {
     const int k = k0 + tid;
@@ -407,17 +472,28 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
         }
         T* dst = X + s * G::SX + t * DP;
         const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
+        // every load is in bounds (column clamped into the row), so they are
+        // all issued before the first is used
+        static_assert(CPT % 2 == 0 && D % 2 == 0, "pairs of features");
+        float2 v2[CPT / 2];
+#pragma unroll
+        for (int cc = 0; cc < CPT; cc += 2) {
+          const int c = part * CPT + cc;
+          v2[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+        }
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
           const int c = part * CPT + cc;
-          float v = (idx >= 0 && c < D) ? src[c] : 0.f;
+          float v = (idx >= 0 && c < D) ? (cc & 1 ? v2[cc / 2].y : v2[cc / 2].x) : 0.f;
           if (c == p.col_res) v = res;
           if (c == p.col_exe) v = ex;
           if (c == p.col_sto) v = 0.f;
+          if constexpr (CAL)
+            if (c < D && idx >= 0) cal_max(cal, c, v);
           dst[c] = window_elem<P>(v, c < D ? c : 0, wt.x_inv);
         }
       };
-      predict_tile<Net, P>(wt, relu_mask, sm.net, fill);
+      predict_tile<Net, P, CAL>(wt, relu_mask, sm.net, fill, cal, sm.active);
     }
 
     if (tid < MT && sm.active[tid]) {
@@ -500,6 +576,11 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     if (n_mismatch) atomicAdd(&st.counters[2], (unsigned long long)n_mismatch);
     if (n_pred) atomicAdd(&st.counters[3], (unsigned long long)n_pred);
   }
+  if constexpr (CAL) {
+    __syncthreads();
+    for (int i = tid; i < n_cal<Net>(); i += NT)
+      if (cal[i]) atomicMax(p.cal_out + i, cal[i]);
+  }
   for (int i = tid; i < MT * C; i += NT) {
     const int s = i / C, e = i % C, k = k0 + s;
     if (k < p.n_sub) {
@@ -530,10 +611,17 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     const int w = j * BS + t;
     const float* src = x + ((b < B ? b : 0) * L + w) * D;
     T* dst = X + s * G::SX + t * DP;
+    float2 v2[CPT / 2];
+#pragma unroll
+    for (int cc = 0; cc < CPT; cc += 2) {
+      const int c = part * CPT + cc;
+      v2[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+    }
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
       const int c = part * CPT + cc;
-      dst[c] = window_elem<P>((b < B && c < D) ? src[c] : 0.f, c < D ? c : 0, wt.x_inv);
+      const float v = (b < B && c < D) ? (cc & 1 ? v2[cc / 2].y : v2[cc / 2].x) : 0.f;
+      dst[c] = window_elem<P>(v, c < D ? c : 0, wt.x_inv);
     }
   };
   predict_tile<Net, P>(wt, relu_mask, sm, fill);
@@ -618,6 +706,22 @@ static hipError_t launch_forward_n(int prec, const DevWeights& w, uint32_t relu,
   if (prec == 1) return launch_forward_t<Net, PBF16>(w, relu, x, B, logits, stream);
   return launch_forward_t<Net, PFP8>(w, relu, x, B, logits, stream);
 }
+
+template <class Net>
+static hipError_t launch_cal_t(const DevWeights& w, uint32_t relu, const DevState& s,
+                               const StepParams& p, hipStream_t stream) {
+  const dim3 grid((p.n_sub + MT - 1) / MT), block(Geo<Net, PF32>::NT);
+  hipLaunchKernelGGL((step_kernel<Net, PF32, true, true>), grid, block, 0, stream, w, relu, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_calibrate(int net, const DevWeights& w, uint32_t relu, const DevState& s,
+                            const StepParams& p, hipStream_t stream) {
+  return net == 0 ? launch_cal_t<NetSmall>(w, relu, s, p, stream)
+                  : launch_cal_t<NetC3>(w, relu, s, p, stream);
+}
+
+int calibration_size(int net) { return net == 0 ? n_cal<NetSmall>() : n_cal<NetC3>(); }
 
 hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
                           int64_t B, float* logits, hipStream_t stream) {

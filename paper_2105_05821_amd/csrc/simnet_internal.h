@@ -105,6 +105,7 @@ struct StepParams {
   const int32_t* lat_table;
   float* logits_out;
   int32_t n_steps;
+  unsigned* cal_out;  // calibration launches: per-channel max |input| (float bits)
 };
 
 // Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3; prec: 0 FP32,
@@ -113,6 +114,12 @@ hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, co
                        const StepParams& p, hipStream_t stream);
 hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
                           int64_t B, float* logits, hipStream_t stream);
+// FP32 step launch that also records per-channel max |input| of every layer
+// into p.cal_out (calibration_size(net) entries: window features, then each
+// hidden layer's outputs in order).
+hipError_t launch_calibrate(int net, const DevWeights& w, uint32_t relu, const DevState& s,
+                            const StepParams& p, hipStream_t stream);
+int calibration_size(int net);
 hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream);
 hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream);
 

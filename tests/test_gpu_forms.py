@@ -1,13 +1,14 @@
-"""Reduced-precision forms of the predictor inside the step loop (BF16; FP8
-once scales are available).
+"""Reduced-precision forms of the predictor inside the step loop (BF16, FP8).
 
 Each form is checked against the oracle's FP64 evaluation of the same form
 (the same roundings at the same points, exact sums).  The GPU accumulates in
 FP32, so a hidden activation can land on the other side of a rounding
 boundary; the bar is one unit in the last place of the form at the output's
-magnitude: |y_gpu - y_form| <= 2^-8 * max(s, 1) for BF16, s being the form's
-|b| + sum |w a| of the output layer.  Cycle results are bit-exact given the
-same latencies."""
+magnitude: |y_gpu - y_form| <= u * max(s, 1), u = 2^-8 for BF16 and 2^-4 for
+FP8 (half of e4m3's 2^-3 spacing), s being the form's |b| + sum |w a| of the
+output layer.  Cycle results are bit-exact given the same latencies.  FP8
+scales come from each side's own calibration on identical windows and must
+be equal."""
 import numpy as np
 import pytest
 
@@ -16,7 +17,8 @@ from tests.common import near_half, realistic_windows, rel_err
 
 pytestmark = pytest.mark.gpu
 
-FORMS = {"bf16": (1, 2.0 ** -8)}
+FORMS = {"bf16": (1, 2.0 ** -8), "fp8": (2, 2.0 ** -4)}
+CAL_STEPS = 64
 
 
 @pytest.fixture(scope="module")
@@ -51,9 +53,19 @@ def setup(torch, sn, oracle, net, N, K, warm, prec):
     sim = sn.Simulator(dfeat, L, cols, start, length, warm_, prec=prec)
     sim.load_weights(layers, sn.flat_params(ws, bs))
     cfg = oracle.sim_cfg(D, L, 2, 8, cols)
-    form = oracle.Model(layers, ws, bs, D, L, prec=prec)
     exact = oracle.Model(layers, ws, bs, D, L)
+    scales = None
+    if prec == 2:
+        # both sides calibrate on the same windows: latencies injected
+        n_pred = int(length.sum() + warm_.sum())
+        table = synth.latency_table(77, n_pred, 2)
+        sim.calibrate(CAL_STEPS, sn.SIM_LAT_INJECT, dev(torch, table))
+        amax = oracle.calibrate(cfg, feat, start, length, warm_, exact, CAL_STEPS, lat_table=table)
+        scales = oracle.fp8_scales(amax)
+        np.testing.assert_array_equal(sim.act_scales()[:scales.size], scales)
+    form = oracle.Model(layers, ws, bs, D, L, prec=prec, scales=scales)
     return dict(sim=sim, feat=feat, dfeat=dfeat, cfg=cfg, form=form, exact=exact, start=start,
+                scales=scales,
                 len=length, warm=warm_, n_pred=int(length.sum() + warm_.sum()), layers=layers,
                 ws=ws, bs=bs)
 
@@ -93,3 +105,18 @@ def test_form_free_run_replayed_by_oracle(torch, sn, oracle_lib, form, net, N, K
     assert err.max() <= tol, err.max()
     lat_o = np.clip(np.rint(rep["logits"]), 0, 65535).astype(np.int32)
     assert not np.any((lat_o != lat) & ~near_half(rep["logits"], rep["scale"], tol))
+
+
+@pytest.mark.parametrize("net", ["small", "c3"])
+def test_fp8_needs_calibration(torch, sn, oracle_lib, net):
+    D, L, layers = (32, 16, synth.net_small()) if net == "small" else (50, 111, synth.net_c3())
+    feat = dev(torch, synth.trace_features(1, 500, D))
+    start, length, warm = sn.partition(500, 3, 0)
+    sim = sn.Simulator(feat, L, synth.dynamic_columns(D), start, length, warm, prec=sn.SIM_FP8E4M3)
+    ws, bs = synth.init_weights(2, layers)
+    sim.load_weights(layers, sn.flat_params(ws, bs))
+    with pytest.raises(sn.SimError) as e:
+        sim.run()
+    assert e.value.code == sn.SIM_ESTATE
+    sim.calibrate(8)
+    sim.run()

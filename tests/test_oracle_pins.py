@@ -437,3 +437,104 @@ def test_bf16_form_matches_library_rounding(oracle_lib):
     np.testing.assert_allclose(m.forward(x), h.numpy(), rtol=1e-11, atol=1e-11)
     m64 = oracle_lib.Model(layers, ws, bs, 50, 111)
     assert not np.allclose(m64.forward(x), h.numpy(), rtol=1e-6)
+
+
+def test_e4m3_rounding_matches_torch(oracle_lib):
+    rng = np.random.default_rng(9)
+    v = np.concatenate([rng.uniform(-448, 448, 4000), rng.uniform(-0.02, 0.02, 2000),
+                        rng.normal(size=2000) * 3, [0.0, 448.0, -448.0, 2 ** -9, 3 * 2 ** -10]])
+    want = torch.from_numpy(v.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = np.array([oracle_lib.lib().ol_round_e4m3(float(np.float32(x))) for x in v])
+    np.testing.assert_array_equal(got, want)
+    # saturation (the library's cast turns these into NaN; the form saturates)
+    for x, s in [(600.0, 448.0), (-1e9, -448.0), (465.0, 448.0)]:
+        assert oracle_lib.lib().ol_round_e4m3(x) == s
+
+
+def test_bf16_rounding_matches_torch(oracle_lib):
+    rng = np.random.default_rng(10)
+    v = np.concatenate([rng.normal(size=3000) * 100, rng.uniform(-1, 1, 1000)]).astype(np.float32)
+    want = torch.from_numpy(v).to(torch.bfloat16).to(torch.float64).numpy()
+    got = np.array([oracle_lib.lib().ol_round_bf16(float(x)) for x in v])
+    np.testing.assert_array_equal(got, want)
+
+
+@pytest.mark.parametrize("amax,scale", [(448.0, 1.0), (448.0001, 2.0), (1.0, 2.0 ** -8),
+                                        (224.0, 0.5), (224.5, 1.0), (0.0, 1.0),
+                                        (1792.0, 4.0), (1792.5, 8.0), (3e-3, 2.0 ** -17)])
+def test_fp8_scale_rule(oracle_lib, amax, scale):
+    """Smallest power of two s with amax <= 448 s (hand-worked)."""
+    assert oracle_lib.fp8_scales(np.array([amax]))[0] == scale
+
+
+def test_fp8_form_matches_library_rounding(oracle_lib):
+    """The FP8 form evaluated with PyTorch's float8_e4m3fn rounding: inputs
+    e4m3(x/s)*s per channel, weights with input scales folded in and a
+    power-of-two scale per output channel, exact sums in float64."""
+    layers = synth.net_small()
+    ws, bs = synth.init_weights(6, layers)
+    rng = np.random.default_rng(11)
+    x = np.abs(rng.normal(size=(4, 16, 32))) * rng.choice([0.5, 30.0], size=(4, 16, 32))
+    widths = [32, 32, 64]
+    scales = [2.0 ** rng.integers(-8, 2, size=w) for w in widths]
+    flat = np.concatenate(scales).astype(np.float32)
+    # saturating e4m3: clamp to the largest finite value, then the library's rounding
+    q8 = lambda a: (torch.as_tensor(np.asarray(a, np.float64)).clamp(-448, 448)
+                    .to(torch.float8_e4m3fn).to(torch.float64))
+    h = (q8(x / scales[0][None, None, :]) * torch.from_numpy(scales[0])).transpose(1, 2)
+    for i, (ly, w, b) in enumerate(zip(layers, ws, bs)):
+        w = np.asarray(w, np.float64)
+        if ly.kind == synth.CONV:
+            wf = w * scales[i][None, :, None]
+            wsc = oracle_lib.fp8_scales(np.abs(wf).reshape(w.shape[0], -1).max(1)).astype(np.float64)
+            wq = q8(wf / wsc[:, None, None]) * torch.from_numpy(wsc)[:, None, None] / torch.from_numpy(scales[i])[None, :, None]
+            h = torch.nn.functional.conv1d(h, wq, torch.from_numpy(np.asarray(b, np.float64)), stride=2)
+        else:
+            L = h.shape[2]
+            sc = np.repeat(scales[i], L)          # flatten index c*L + p
+            wf = w * sc[None, :]
+            wsc = oracle_lib.fp8_scales(np.abs(wf).max(1)).astype(np.float64)
+            wq = q8(wf / wsc[:, None]) * torch.from_numpy(wsc)[:, None] / torch.from_numpy(sc)[None, :]
+            h = torch.nn.functional.linear(h.reshape(h.shape[0], -1), wq,
+                                           torch.from_numpy(np.asarray(b, np.float64)))
+        if ly.relu:
+            h = torch.relu(h)
+        if i < len(layers) - 1:
+            s_next = torch.from_numpy(scales[i + 1])[None, :, None]
+            h = q8(h / s_next) * s_next
+    m = oracle_lib.Model(layers, ws, bs, 32, 16, prec=2, scales=flat)
+    np.testing.assert_allclose(m.forward(x), h.numpy(), rtol=1e-11, atol=1e-11)
+
+
+def test_calibration_maxima_brute_force(oracle_lib):
+    """Calibration maxima equal the maxima over explicitly built windows
+    (library forward on each window), restricted to live slots/positions."""
+    layers = synth.net_small()
+    ws, bs = synth.init_weights(2, layers)
+    m = oracle_lib.Model(layers, ws, bs, 32, 16)
+    N, steps = 300, 40
+    feat = synth.trace_features(3, N, 32)
+    F = np.random.default_rng(2).integers(0, 3, size=N)
+    E = np.random.default_rng(3).integers(0, 30, size=N)
+    cfg = oracle_lib.sim_cfg(32, 16, 2, 8, (30, 31, -1))
+    table = np.stack([F, E], 1).astype(np.int32)
+    amax = oracle_lib.calibrate(cfg, feat, [0], [N], [0], m, steps, lat_table=table)
+    # explicit windows from the recurrence
+    T, r = recurrence_final(F, E, 8)
+    want = np.zeros(32 + 32 + 64)
+    for i in range(steps):
+        t_prev = T[i - 1] if i > 0 else 0
+        infl = [j for j in range(i) if r[j] > t_prev][::-1][:15]
+        x = np.zeros((16, 32))
+        x[0] = feat[i]; x[0, 30:32] = 0
+        for k, j in enumerate(infl, start=1):
+            x[k] = feat[j]; x[k, 30] = t_prev - T[j]; x[k, 31] = E[j]
+        h = torch.from_numpy(x).T[None]
+        want[:32] = np.maximum(want[:32], np.abs(x).max(0))
+        h1 = torch.relu(torch.nn.functional.conv1d(h, torch.from_numpy(ws[0].astype(np.float64)),
+                                                   torch.from_numpy(bs[0].astype(np.float64)), stride=2))
+        want[32:64] = np.maximum(want[32:64], h1[0].numpy().max(1))
+        h2 = torch.relu(torch.nn.functional.conv1d(h1, torch.from_numpy(ws[1].astype(np.float64)),
+                                                   torch.from_numpy(bs[1].astype(np.float64)), stride=2))
+        want[64:] = np.maximum(want[64:], h2[0].numpy().max(1))
+    np.testing.assert_allclose(amax, want, rtol=1e-12)
