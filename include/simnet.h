@@ -61,7 +61,13 @@ typedef enum { SIM_FP32 = 0, SIM_BF16 = 1, SIM_FP8E4M3 = 2 } sim_precision;
  *            from the table is counted in n_shadow_mismatch. */
 typedef enum { SIM_LAT_PREDICT = 0, SIM_LAT_INJECT = 1, SIM_LAT_SHADOW = 2 } sim_lat_mode;
 
-typedef enum { SIM_FEAT_F32 = 0 } sim_feat_dtype;
+/* Trace encodings.  F32: rows of n_feat float32.  CODE32: one uint32 per
+ * instruction, expanded in the kernel into the categorical feature layout
+ * op | reg0 << 3 | reg1 << 8 | reg2 << 13 | level << 18 | mispredict << 20
+ * -> columns [0,5) op one-hot, [5,26) each register id (0..31) one-hot in
+ * 7 buckets (id*7/32), [26,29) data level one-hot, [29] mispredict, the rest
+ * zero (needs n_feat >= 30); 4 bytes per instruction instead of 4*n_feat. */
+typedef enum { SIM_FEAT_F32 = 0, SIM_FEAT_CODE32 = 1 } sim_feat_dtype;
 
 /* One predictor layer.  kind 0: 1-D convolution over instructions, kernel 2,
  * stride 2, no padding, output length floor(L/2) (Sec. 2.3: non-overlapping
@@ -90,9 +96,10 @@ typedef struct {
  * rows [start[k] - warm[k], start[k] + len[k]) in order; the first warm[k]
  * are warm-up (predicted and queued, their fetch cycles not counted). */
 typedef struct {
-  const void* feat;      /* DEVICE, [n_instr][n_feat] float32 row-major; the
-                            dynamic columns are ignored.  Borrowed: must stay
-                            valid and unchanged for the context's lifetime. */
+  const void* feat;      /* DEVICE, [n_instr][n_feat] float32 row-major (the
+                            dynamic columns are ignored), or [n_instr] uint32
+                            codes.  Borrowed: must stay valid and unchanged
+                            for the context's lifetime. */
   int32_t feat_dtype;    /* sim_feat_dtype */
   int32_t n_sub;         /* number of sub-traces K >= 1 */
   int64_t n_instr;       /* rows in feat, < 2^31 */
@@ -135,13 +142,18 @@ SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx**
 SIMNET_API int sim_load_weights(sim_ctx* ctx, const sim_layer* layers, int32_t n_layers,
                      const float* params, int32_t on_device);
 
-/* Advance every unfinished sub-trace by up to n_steps instructions
- * (asynchronous).  lat_table (DEVICE int32, needed for INJECT and SHADOW) is
+/* Advance the simulation by up to n_steps steps (asynchronous).  The
+ * library runs a fixed number of sub-trace slots (a multiple of 16, at most
+ * a few per compute unit); a slot whose sub-trace finishes takes the next
+ * unstarted one, longest first, so with more sub-traces than slots one step
+ * advances only the sub-traces currently in slots.  Results do not depend on
+ * the slot assignment.  lat_table (DEVICE int32, needed for INJECT and SHADOW) is
  * indexed by the sub-trace's simulated position: row
  * sum_{k'<k}(warm[k']+len[k']) + p, column o (0 fetch, 1 execution). */
 SIMNET_API int sim_step(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode, const int32_t* lat_table);
 
-/* Run every sub-trace to completion, synchronise, and fill *res.  A context
+/* Run every sub-trace to completion (one launch that ends when every slot
+ * is empty), synchronise, and fill *res.  A context
  * that has completed must be sim_reset before it runs again. */
 SIMNET_API int sim_run(sim_ctx* ctx, int32_t lat_mode, const int32_t* lat_table, sim_result* res);
 

@@ -19,7 +19,7 @@ SIM_OK, SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_ESTATE, SIM_ENONFINITE, SIM_EUN
     0, -1, -2, -3, -4, -5, -6
 SIM_FP32, SIM_BF16, SIM_FP8E4M3 = 0, 1, 2
 SIM_LAT_PREDICT, SIM_LAT_INJECT, SIM_LAT_SHADOW = 0, 1, 2
-SIM_FEAT_F32 = 0
+SIM_FEAT_F32, SIM_FEAT_CODE32 = 0, 1
 CONV, FC = 0, 1
 
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVICE",
@@ -107,11 +107,12 @@ def make_config(n_feat: int, n_slot: int, cols: Sequence[int], retire_width: int
                       prec, 0, stream)
 
 
-def make_trace(feat_ptr: Optional[int], n_instr: int, start, length, warm):
+def make_trace(feat_ptr: Optional[int], n_instr: int, start, length, warm,
+               feat_dtype: int = SIM_FEAT_F32):
     start = np.ascontiguousarray(start, np.int64)
     length = np.ascontiguousarray(length, np.int64)
     warm = np.ascontiguousarray(warm, np.int32)
-    tr = sim_trace(feat_ptr, SIM_FEAT_F32, start.shape[0], n_instr,
+    tr = sim_trace(feat_ptr, feat_dtype, start.shape[0], n_instr,
                    start.ctypes.data_as(C.POINTER(C.c_int64)),
                    length.ctypes.data_as(C.POINTER(C.c_int64)),
                    warm.ctypes.data_as(C.POINTER(C.c_int32)))
@@ -138,20 +139,27 @@ def partition(n_instr: int, n_sub: int, warm_max: int = 0):
 
 
 class Simulator:
-    """One sim_ctx.  ``feat`` is a device float32 tensor [n_instr][n_feat]
-    that must outlive the simulator."""
+    """One sim_ctx.  ``feat`` is a device tensor that must outlive the
+    simulator: float32 [n_instr][n_feat] rows, or int32 [n_instr] packed
+    instruction codes (then ``n_feat`` gives the expanded width)."""
 
     def __init__(self, feat, n_slot: int, cols: Sequence[int], start, length, warm,
                  retire_width: int = 8, lat_max: int = 65535, prec: int = SIM_FP32,
-                 stream=None):
+                 stream=None, n_feat: Optional[int] = None):
         import torch
-        if not feat.is_cuda or feat.dtype != torch.float32 or not feat.is_contiguous():
-            raise ValueError("feat must be a contiguous float32 device tensor")
+        if not feat.is_cuda or not feat.is_contiguous():
+            raise ValueError("feat must be a contiguous device tensor")
+        if feat.dtype == torch.float32 and feat.dim() == 2:
+            kind, width = SIM_FEAT_F32, feat.shape[1]
+        elif feat.dtype == torch.int32 and feat.dim() == 1 and n_feat:
+            kind, width = SIM_FEAT_CODE32, n_feat
+        else:
+            raise ValueError("feat must be float32 [n][D] rows or int32 [n] codes with n_feat")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.feat = feat
-        self.cfg = make_config(feat.shape[1], n_slot, cols, retire_width, lat_max, prec,
+        self.cfg = make_config(width, n_slot, cols, retire_width, lat_max, prec,
                                stream=self.stream.cuda_stream)
-        self.trace = make_trace(feat.data_ptr(), feat.shape[0], start, length, warm)
+        self.trace = make_trace(feat.data_ptr(), feat.shape[0], start, length, warm, kind)
         self.n_sub = int(self.trace.n_sub)
         self.n_pred = int(np.sum(self.trace._keep[1]) + np.sum(self.trace._keep[2]))
         h = C.c_void_p()
@@ -176,6 +184,8 @@ class Simulator:
         else:
             self._check("sim_load_weights",
                         lib().sim_load_weights(self.ctx, arr, len(layers), params.data_ptr(), 1))
+
+    RUN_TO_END = 2 ** 31 - 1
 
     def step(self, n_steps: int, lat_mode: int = SIM_LAT_PREDICT, lat_table=None) -> None:
         self._check("sim_step", lib().sim_step(self.ctx, n_steps, lat_mode, _ptr(lat_table)))

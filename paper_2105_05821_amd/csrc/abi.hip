@@ -26,6 +26,8 @@ struct sim_ctx {
   bool weights = false;
   bool completed = false;
   int64_t max_pos = 0, n_pred = 0, n_meas = 0;
+  int32_t n_wg = 0;                 // persistent workgroups; slots = n_wg * MT
+  const uint32_t* codes = nullptr;  // packed trace (SIM_FEAT_CODE32)
   float* logits_out = nullptr;
   hipStream_t stream = nullptr;
   void* dev_block = nullptr;  // state + table
@@ -35,7 +37,7 @@ struct sim_ctx {
   std::vector<float> params;        // FP8 form: FP32 parameters as loaded
   std::vector<float> act_scale;     // per layer-input channel, after calibration
   bool calibrated = false;
-  int64_t steps_launched = 0;
+  bool ran_to_end = false;          // an unbounded step launch has been issued
   int64_t* dev_total = nullptr;
   DevState st{};
   DevWeights w{};
@@ -87,7 +89,10 @@ int check_cfg(const sim_config* cfg, const sim_trace* tr, std::string* why) {
   if (cfg->prec < SIM_FP32 || cfg->prec > SIM_FP8E4M3) return bad("unknown precision");
   if (cfg->reserved != 0) return bad("reserved field must be 0");
   if (!tr->feat) return bad("feat is NULL");
-  if (tr->feat_dtype != SIM_FEAT_F32) return bad("unknown feat_dtype");
+  if (tr->feat_dtype != SIM_FEAT_F32 && tr->feat_dtype != SIM_FEAT_CODE32)
+    return bad("unknown feat_dtype");
+  if (tr->feat_dtype == SIM_FEAT_CODE32 && cfg->n_feat < 30)
+    return bad("packed codes expand to 30 static features: n_feat must be >= 30");
   if (tr->n_instr < 1 || tr->n_instr >= (int64_t)1 << 31) return bad("n_instr must be in [1, 2^31)");
   if (tr->n_sub < 1) return bad("n_sub must be >= 1");
   if (!tr->start || !tr->len || !tr->warm) return bad("sub-trace table is NULL");
@@ -418,7 +423,10 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   c->C = cfg->n_slot - 1;
   c->n_sub = tr->n_sub;
   c->n_instr = tr->n_instr;
-  c->feat = static_cast<const float*>(tr->feat);
+  if (tr->feat_dtype == SIM_FEAT_CODE32)
+    c->codes = static_cast<const uint32_t*>(tr->feat);
+  else
+    c->feat = static_cast<const float*>(tr->feat);
   c->stream = static_cast<hipStream_t>(cfg->stream);
 
   const int32_t K = tr->n_sub, C = c->C;
@@ -435,6 +443,24 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
     c->max_pos = std::max(c->max_pos, npos[k]);
   }
   c->n_pred = acc;
+  // claim order: longest first (ties by index) so the long ones start early
+  std::vector<int32_t> order(K);
+  for (int32_t k = 0; k < K; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return npos[a] > npos[b]; });
+  int dev = 0, n_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      n_cu < 1) {
+    fprintf(stderr, "sim_init: cannot query the device\n");
+    delete c;
+    return SIM_EDEVICE;
+  }
+  // one persistent workgroup per CU for the large network (LDS-bound), a few
+  // per CU for the small one
+  const int per_cu = c->net == 0 ? 4 : 1;
+  c->n_wg = (int32_t)std::min<int64_t>((K + MT - 1) / MT, (int64_t)n_cu * per_cu);
+  const int32_t n_slots = c->n_wg * MT;
 
   // one device block: table + state + results + counters + total
   size_t off = 0;
@@ -450,7 +476,8 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
                o_qi = take(4 * (size_t)K * C), o_qe = take(4 * (size_t)K * C),
                o_qt = take(8 * (size_t)K * C), o_qr = take(8 * (size_t)K * C),
                o_fe = take(8 * K), o_dr = take(8 * K), o_fi = take(8 * K), o_wt = take(8 * K),
-               o_ctr = take(8 * NCOUNTERS), o_tot = take(8);
+               o_ctr = take(8 * NCOUNTERS), o_tot = take(8), o_order = take(4 * K),
+               o_slot = take(4 * (size_t)n_slots), o_next = take(4);
   hipError_t e = hipMalloc(&c->dev_block, off);
   if (e != hipSuccess) {
     fprintf(stderr, "sim_init: hipMalloc(%zu): %s\n", off, hipGetErrorString(e));
@@ -480,14 +507,18 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   s.warm_tick = reinterpret_cast<int64_t*>(base + o_wt);
   s.counters = reinterpret_cast<unsigned long long*>(base + o_ctr);
   c->dev_total = reinterpret_cast<int64_t*>(base + o_tot);
+  s.order = reinterpret_cast<int32_t*>(base + o_order);
+  s.slot_kid = reinterpret_cast<int32_t*>(base + o_slot);
+  s.next = reinterpret_cast<unsigned*>(base + o_next);
 
   hipError_t e1 = hipMemcpyAsync(base + o_first, first.data(), 8 * K, hipMemcpyHostToDevice, c->stream);
   hipError_t e2 = hipMemcpyAsync(base + o_npos, npos.data(), 8 * K, hipMemcpyHostToDevice, c->stream);
   hipError_t e3 = hipMemcpyAsync(base + o_warm, warm.data(), 4 * K, hipMemcpyHostToDevice, c->stream);
   hipError_t e4 = hipMemcpyAsync(base + o_poff, poff.data(), 8 * K, hipMemcpyHostToDevice, c->stream);
-  hipError_t e5 = launch_reset(s, K, C, c->stream);
+  hipError_t e7 = hipMemcpyAsync(base + o_order, order.data(), 4 * K, hipMemcpyHostToDevice, c->stream);
+  hipError_t e5 = launch_reset(s, K, C, n_slots, c->stream);
   hipError_t e6 = hipStreamSynchronize(c->stream);  // host vectors die at return
-  for (hipError_t x : {e1, e2, e3, e4, e5, e6})
+  for (hipError_t x : {e1, e2, e3, e4, e7, e5, e6})
     if (x != hipSuccess) {
       fprintf(stderr, "sim_init: %s\n", hipGetErrorString(x));
       (void)hipFree(c->dev_block);
@@ -539,10 +570,10 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
 
 int sim_reset(sim_ctx* c) {
   if (!c) return SIM_EINVAL;
-  hipError_t e = launch_reset(c->st, c->n_sub, c->C, c->stream);
+  hipError_t e = launch_reset(c->st, c->n_sub, c->C, c->n_wg * MT, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reset");
   c->completed = false;
-  c->steps_launched = 0;
+  c->ran_to_end = false;
   return SIM_OK;
 }
 
@@ -564,6 +595,8 @@ int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* tabl
     e = hipMemsetAsync(amax, 0, sizeof(unsigned) * n, c->stream);
     StepParams p{};
     p.feat = c->feat;
+    p.codes = c->codes;
+    p.n_wg = c->n_wg;
     p.n_sub = c->n_sub;
     p.W = c->cfg.retire_width;
     p.col_res = c->cfg.col_res;
@@ -628,10 +661,12 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   if (mode != SIM_LAT_INJECT && c->cfg.prec == SIM_FP8E4M3 && !c->calibrated)
     return fail(c, SIM_ESTATE, "FP8 form needs sim_calibrate first");
   if (c->completed) return fail(c, SIM_ESTATE, "run completed; call sim_reset");
-  if (c->steps_launched >= c->max_pos) return SIM_OK;  // every sub-trace has finished
-  c->steps_launched = std::min<int64_t>(c->max_pos, c->steps_launched + n_steps);
+  if (c->ran_to_end) return SIM_OK;  // every sub-trace has already finished
+  if (n_steps >= INT32_MAX) c->ran_to_end = true;
   StepParams p{};
   p.feat = c->feat;
+  p.codes = c->codes;
+  p.n_wg = c->n_wg;
   p.n_sub = c->n_sub;
   p.W = c->cfg.retire_width;
   p.col_res = c->cfg.col_res;
@@ -658,7 +693,7 @@ int sim_step(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* table) {
 int sim_run(sim_ctx* c, int32_t mode, const int32_t* table, sim_result* res) {
   if (!c) return SIM_EINVAL;
   if (!res) return fail(c, SIM_EINVAL, "null result");
-  int rc = step_launch(c, c->max_pos, mode, table);
+  int rc = step_launch(c, INT32_MAX, mode, table);
   if (rc != SIM_OK) return rc;
   hipError_t e = launch_total(c->st, c->n_sub, c->dev_total, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "total launch");

@@ -395,8 +395,52 @@ struct StepSmem {
   int64_t q_r[MT][Net::C];
   int64_t rw[MT][WMAX];
   int64_t cur[MT], t_w[MT], r_prev[MT], pos[MT], first[MT], n_pos[MT], pred_off[MT];
-  int32_t head[MT], count[MT], warm[MT], active[MT];
+  int32_t head[MT], count[MT], warm[MT], active[MT], kid[MT];
 };
+
+// Slot s of the tile takes sub-trace k: its scalars come from the global
+// state (the reset state for a sub-trace that has not started).
+template <class SM>
+__device__ __forceinline__ void load_slot(SM& sm, int s, int k, const DevState& st, int W) {
+  sm.kid[s] = k;
+  if (k < 0) {
+    sm.active[s] = 0;
+    return;
+  }
+  sm.cur[s] = st.cur[k];
+  sm.t_w[s] = st.t_w[k];
+  sm.r_prev[s] = st.r_prev[k];
+  sm.pos[s] = st.pos[k];
+  sm.first[s] = st.first[k];
+  sm.n_pos[s] = st.n_pos[k];
+  sm.pred_off[s] = st.pred_off[k];
+  sm.head[s] = st.head[k];
+  sm.count[s] = st.count[k];
+  sm.warm[s] = st.warm[k];
+  for (int i = 0; i < W; ++i) sm.rw[s][i] = st.rw[(size_t)k * WMAX + i];
+  sm.active[s] = sm.pos[s] < sm.n_pos[s];
+}
+
+// Next unstarted sub-trace in claim order (longest first), or -1.
+__device__ __forceinline__ int claim_subtrace(const DevState& st, int n_sub) {
+  const unsigned q = atomicAdd(st.next, 1u);
+  return q < (unsigned)n_sub ? st.order[q] : -1;
+}
+
+// Feature c of an instruction given as a packed code (trace encoding
+// SIM_FEAT_CODE32): op class one-hot [0,5), three register ids one-hot in 7
+// buckets each [5,26), data level one-hot [26,29), mispredict flag [29].
+__device__ __forceinline__ float code_feature(uint32_t code, int c) {
+  if (c < 5) return (int)(code & 7u) == c ? 1.f : 0.f;
+  if (c < 26) {
+    const int r = (c - 5) / 7, b = (c - 5) % 7;
+    const int id = (int)((code >> (3 + 5 * r)) & 31u);
+    return (id * 7) >> 5 == b ? 1.f : 0.f;
+  }
+  if (c < 29) return (int)((code >> 18) & 3u) == c - 26 ? 1.f : 0.f;
+  if (c == 29) return (float)((code >> 20) & 1u);
+  return 0.f;
+}
 
 template <class Net>
 constexpr int n_cal() {
@@ -412,32 +456,22 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   __shared__ StepSmem<Net, P> sm;
   __shared__ unsigned cal[CAL ? n_cal<Net>() : 1];
   const int tid = threadIdx.x;
-  const int k0 = blockIdx.x * MT;
+  const int slot0 = blockIdx.x * MT;
   if constexpr (CAL)
     for (int i = tid; i < n_cal<Net>(); i += NT) cal[i] = 0u;
 
+  // Work queue: a slot keeps its sub-trace across launches; an empty slot
+  // claims the next unstarted sub-trace (longest first).  Results are
+  // indexed by sub-trace, so they do not depend on which slot runs it.
   if (tid < MT) {
-    const int k = k0 + tid;
-    int act = 0;
-    if (k < p.n_sub) {
-      sm.cur[tid] = st.cur[k];
-      sm.t_w[tid] = st.t_w[k];
-      sm.r_prev[tid] = st.r_prev[k];
-      sm.pos[tid] = st.pos[k];
-      sm.first[tid] = st.first[k];
-      sm.n_pos[tid] = st.n_pos[k];
-      sm.pred_off[tid] = st.pred_off[k];
-      sm.head[tid] = st.head[k];
-      sm.count[tid] = st.count[k];
-      sm.warm[tid] = st.warm[k];
-      for (int i = 0; i < p.W; ++i) sm.rw[tid][i] = st.rw[(size_t)k * WMAX + i];
-      act = sm.pos[tid] < sm.n_pos[tid];
-    }
-    sm.active[tid] = act;
+    int k = st.slot_kid[slot0 + tid];
+    if (k < 0) k = claim_subtrace(st, p.n_sub);
+    load_slot(sm, tid, k, st, p.W);
   }
+  __syncthreads();
   for (int i = tid; i < MT * C; i += NT) {
-    const int s = i / C, e = i % C, k = k0 + s;
-    if (k < p.n_sub) {
+    const int s = i / C, e = i % C, k = sm.kid[s];
+    if (k >= 0) {
       const size_t g = (size_t)k * C + e;
       sm.q_idx[s][e] = st.q_idx[g];
       sm.q_e[s][e] = st.q_e[g];
@@ -471,20 +505,27 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
           }
         }
         T* dst = X + s * G::SX + t * DP;
-        const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
-        // every load is in bounds (column clamped into the row), so they are
-        // all issued before the first is used
+        // every load is in bounds (row 0 / column clamped into the row), so
+        // they are all issued before the first is used
         static_assert(CPT % 2 == 0 && D % 2 == 0, "pairs of features");
         float2 v2[CPT / 2];
+        uint32_t code = 0;
+        if (p.codes) {
+          code = p.codes[idx < 0 ? 0 : idx];
+        } else {
+          const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
 #pragma unroll
-        for (int cc = 0; cc < CPT; cc += 2) {
-          const int c = part * CPT + cc;
-          v2[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+          for (int cc = 0; cc < CPT; cc += 2) {
+            const int c = part * CPT + cc;
+            v2[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+          }
         }
 #pragma unroll
         for (int cc = 0; cc < CPT; ++cc) {
           const int c = part * CPT + cc;
-          float v = (idx >= 0 && c < D) ? (cc & 1 ? v2[cc / 2].y : v2[cc / 2].x) : 0.f;
+          float v = 0.f;
+          if (idx >= 0 && c < D)
+            v = p.codes ? code_feature(code, c) : (cc & 1 ? v2[cc / 2].y : v2[cc / 2].x);
           if (c == p.col_res) v = res;
           if (c == p.col_exe) v = ex;
           if (c == p.col_sto) v = 0.f;
@@ -497,7 +538,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
 
     if (tid < MT && sm.active[tid]) {
-      const int s = tid, k = k0 + s;
+      const int s = tid, k = sm.kid[s];
       const int64_t pos = sm.pos[s];
       const int64_t g = sm.pred_off[s] + pos;
       int32_t lat[Net::NOUT];
@@ -554,15 +595,19 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
         st.drain[k] = r - Tn;
         st.final_tick[k] = r;
         st.warm_tick[k] = sm.t_w[s];
-        sm.active[s] = 0;
+        st.pos[k] = pos + 1;
+        st.cur[k] = Tn;
+        // the finished sub-trace leaves the batch; the slot takes the next
+        load_slot(sm, s, claim_subtrace(st, p.n_sub), st, p.W);
       }
     }
     any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
   }
 
   if (tid < MT) {
-    const int k = k0 + tid;
-    if (k < p.n_sub) {
+    const int k = sm.kid[tid];
+    st.slot_kid[slot0 + tid] = k;
+    if (k >= 0) {
       st.cur[k] = sm.cur[tid];
       st.t_w[k] = sm.t_w[tid];
       st.r_prev[k] = sm.r_prev[tid];
@@ -582,8 +627,8 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       if (cal[i]) atomicMax(p.cal_out + i, cal[i]);
   }
   for (int i = tid; i < MT * C; i += NT) {
-    const int s = i / C, e = i % C, k = k0 + s;
-    if (k < p.n_sub) {
+    const int s = i / C, e = i % C, k = sm.kid[s];
+    if (k >= 0) {
       const size_t g = (size_t)k * C + e;
       st.q_idx[g] = sm.q_idx[s][e];
       st.q_e[g] = sm.q_e[s][e];
@@ -631,8 +676,10 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   }
 }
 
-__global__ void reset_kernel(DevState st, int32_t n_sub, int32_t C) {
+__global__ void reset_kernel(DevState st, int32_t n_sub, int32_t C, int32_t n_slots) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n_slots) st.slot_kid[i] = -1;
+  if (i == 0) *st.next = 0u;
   if (i < n_sub) {
     st.cur[i] = 0;
     st.t_w[i] = 0;
@@ -669,7 +716,7 @@ __global__ void __launch_bounds__(256) total_kernel(DevState st, int32_t n_sub, 
 template <class Net, class P>
 static hipError_t launch_step_t(const DevWeights& w, uint32_t relu, const DevState& s,
                                 const StepParams& p, hipStream_t stream) {
-  const dim3 grid((p.n_sub + MT - 1) / MT), block(Geo<Net, P>::NT);
+  const dim3 grid(p.n_wg), block(Geo<Net, P>::NT);
   if (p.lat_mode == 1)
     hipLaunchKernelGGL((step_kernel<Net, P, false>), grid, block, 0, stream, w, relu, s, p);
   else
@@ -710,7 +757,7 @@ static hipError_t launch_forward_n(int prec, const DevWeights& w, uint32_t relu,
 template <class Net>
 static hipError_t launch_cal_t(const DevWeights& w, uint32_t relu, const DevState& s,
                                const StepParams& p, hipStream_t stream) {
-  const dim3 grid((p.n_sub + MT - 1) / MT), block(Geo<Net, PF32>::NT);
+  const dim3 grid(p.n_wg), block(Geo<Net, PF32>::NT);
   hipLaunchKernelGGL((step_kernel<Net, PF32, true, true>), grid, block, 0, stream, w, relu, s, p);
   return hipGetLastError();
 }
@@ -729,11 +776,13 @@ hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu,
                   : launch_forward_n<NetC3>(prec, w, relu, x, B, logits, stream);
 }
 
-hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream) {
+hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, int32_t n_slots,
+                        hipStream_t stream) {
   const int threads = 256;
-  const int blocks = (n_sub + threads - 1) / threads;
+  const int n = n_sub > n_slots ? n_sub : n_slots;
+  const int blocks = (n + threads - 1) / threads;
   hipLaunchKernelGGL(reset_kernel, dim3(blocks > 0 ? blocks : 1), dim3(threads), 0, stream, s,
-                     n_sub, C);
+                     n_sub, C, n_slots);
   return hipGetLastError();
 }
 

@@ -93,10 +93,16 @@ struct DevState {
   int64_t* final_tick;
   int64_t* warm_tick;
   unsigned long long* counters;
+  // work queue
+  int32_t* slot_kid;        // [n_wg * MT] sub-trace held by each slot, -1 = none
+  const int32_t* order;     // claim order of the sub-traces (longest first)
+  unsigned* next;           // claim counter
 };
 
 struct StepParams {
-  const float* feat;
+  const float* feat;        // dense rows [n_instr][D], or
+  const uint32_t* codes;    // packed instruction codes [n_instr] (one of the two)
+  int32_t n_wg;             // persistent workgroups (slots = n_wg * MT)
   int32_t n_sub;
   int32_t W;
   int32_t col_res, col_exe, col_sto;
@@ -120,7 +126,8 @@ hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu,
 hipError_t launch_calibrate(int net, const DevWeights& w, uint32_t relu, const DevState& s,
                             const StepParams& p, hipStream_t stream);
 int calibration_size(int net);
-hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, hipStream_t stream);
+hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, int32_t n_slots,
+                        hipStream_t stream);
 hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream);
 
 }  // namespace simnet

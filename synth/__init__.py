@@ -130,6 +130,53 @@ def trace_codes(seed: int, n_instr: int, lo: int = 0, hi: Optional[int] = None,
     return out
 
 
+def _t_shr(x, k: int):
+    """Logical right shift of int64 tensors holding uint64 bit patterns."""
+    return (x >> k) & ((1 << (64 - k)) - 1)
+
+
+def _t_mix(z):
+    z = (z ^ _t_shr(z, 30)) * _signed(0xBF58476D1CE4E5B9)
+    z = (z ^ _t_shr(z, 27)) * _signed(0x94D049BB133111EB)
+    return z ^ _t_shr(z, 31)
+
+
+def _signed(u: int) -> int:
+    return u - (1 << 64) if u >= 1 << 63 else u
+
+
+def trace_codes_torch(seed: int, lo: int, hi: int, device="cpu"):
+    """The same packed codes as trace_codes, computed with torch int64
+    (wrapping) arithmetic on any device; returns an int32 tensor whose bits
+    are the uint32 codes."""
+    import torch
+    n = torch.arange(lo, hi, dtype=torch.int64, device=device)
+    key = _signed(int(stream_key(seed, TRACE_STREAM)))
+    gold = _signed(int(GOLDEN))
+    base = n * N_FIELDS
+
+    def raw(f):
+        return _t_mix(key + (base + (f + 1)) * gold)
+
+    def unif(f):
+        return _t_shr(raw(f), 11).to(torch.float64) * (2.0 ** -53)
+
+    def cat(u, probs):
+        edges = torch.tensor(np.cumsum(np.asarray(probs, np.float64)), dtype=torch.float64,
+                             device=device)
+        edges[-1] = 1.0 + 1e-12
+        return torch.searchsorted(edges, u, right=True)
+
+    op = cat(unif(0), OP_PROBS)
+    code = op.clone()
+    for r in range(3):
+        code |= _t_shr(raw(1 + r), 59) << (3 + 5 * r)
+    code |= cat(unif(4), LEVEL_PROBS) << 18
+    mis = (unif(5) < MISPREDICT_RATE) & (op == OP_BRANCH)
+    code |= mis.to(torch.int64) << 20
+    return code.to(torch.int32)
+
+
 def trace_features(seed: int, n_instr: int, n_feat: int, lo: int = 0,
                    hi: Optional[int] = None) -> np.ndarray:
     return expand_codes(trace_codes(seed, n_instr, lo, hi), n_feat)

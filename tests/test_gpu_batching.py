@@ -1,0 +1,150 @@
+"""Uneven sub-traces through the persistent work queue (more sub-traces than
+slots, finished ones replaced by unstarted ones, longest first) and the
+packed 32-bit trace encoding."""
+import numpy as np
+import pytest
+
+import synth
+from tests.common import near_half, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def sn():
+    import paper_2105_05821_amd as m
+    m.lib()
+    return m
+
+
+def independent_streams(n_sub, lo, hi, seed=3):
+    length = synth.loguniform_lengths(seed, n_sub, lo, hi)
+    start = np.concatenate([[0], np.cumsum(length)[:-1]]).astype(np.int64)
+    return start, length.astype(np.int64), np.zeros(n_sub, np.int32), int(length.sum())
+
+
+def assert_same(a, b, keys=("fetch", "drain", "final", "warm_tick")):
+    for k in keys:
+        np.testing.assert_array_equal(a[k], b[k], err_msg=k)
+    assert a["total"] == b["total"]
+
+
+def test_codes_equal_dense_rows(torch, sn):
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(2, layers)
+    N = 6000
+    codes = synth.trace_codes(1, N)
+    feat = synth.expand_codes(codes, 50)
+    start, length, warm = sn.partition(N, 24, 256)
+    cols = synth.dynamic_columns(50)
+    out = []
+    for prec in (sn.SIM_FP32, sn.SIM_BF16):
+        for src in ("rows", "codes"):
+            t = (torch.from_numpy(feat).cuda() if src == "rows"
+                 else torch.from_numpy(codes.view(np.int32)).cuda())
+            sim = sn.Simulator(t, 111, cols, start, length, warm, prec=prec, n_feat=50)
+            sim.load_weights(layers, sn.flat_params(ws, bs))
+            lg = torch.zeros((sim.n_pred, 2), dtype=torch.float32, device="cuda")
+            sim.record_logits(lg)
+            res = sim.run()
+            out.append((res, lg.cpu().numpy()))
+        assert_same(out[-2][0], out[-1][0])
+        np.testing.assert_array_equal(out[-2][1], out[-1][1])
+
+
+def test_more_subtraces_than_slots_inject(torch, sn, oracle_lib):
+    """5,000 uneven streams on the C3 window: more than the slots one GPU
+    holds, so slots are refilled; bit-exact against the oracle."""
+    start, length, warm, N = independent_streams(5000, 1, 60)
+    feat = synth.trace_features(1, N, 50)
+    n_pred = int(length.sum())
+    table = synth.latency_table(21, n_pred, 2, heavy=0.05)
+    sim = sn.Simulator(torch.from_numpy(feat).cuda(), 111, synth.dynamic_columns(50),
+                       start, length, warm)
+    g = sim.run(sn.SIM_LAT_INJECT, torch.from_numpy(table).cuda())
+    cfg = oracle_lib.sim_cfg(50, 111, 2, 8, synth.dynamic_columns(50))
+    o = oracle_lib.simulate(cfg, None, start, length, warm, mode=oracle_lib.INJECT,
+                            lat_table=table, n_instr=N)
+    assert_same(g, o)
+
+
+def test_more_subtraces_than_slots_predict(torch, sn, oracle_lib):
+    """Free run with refills, replayed by the oracle from the GPU's own
+    rounded latencies."""
+    start, length, warm, N = independent_streams(4500, 1, 25, seed=5)
+    codes = synth.trace_codes(7, N)
+    feat = synth.expand_codes(codes, 50)
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(2, layers)
+    sim = sn.Simulator(torch.from_numpy(codes.view(np.int32)).cuda(), 111,
+                       synth.dynamic_columns(50), start, length, warm, n_feat=50)
+    sim.load_weights(layers, sn.flat_params(ws, bs))
+    lg = torch.zeros((sim.n_pred, 2), dtype=torch.float32, device="cuda")
+    sim.record_logits(lg)
+    g = sim.run()
+    gl = lg.cpu().numpy().astype(np.float64)
+    lat = np.clip(np.rint(gl), 0, 65535).astype(np.int32)
+    cfg = oracle_lib.sim_cfg(50, 111, 2, 8, synth.dynamic_columns(50))
+    model = oracle_lib.Model(layers, ws, bs, 50, 111)
+    rep = oracle_lib.simulate(cfg, feat, start, length, warm, model=model, mode=oracle_lib.INJECT,
+                              lat_table=lat, want_logits=True, want_scale=True)
+    assert_same(g, rep)
+    assert rel_err(gl, rep["logits"], rep["scale"]).max() <= 1e-5
+    lat_o = np.clip(np.rint(rep["logits"]), 0, 65535).astype(np.int32)
+    assert not np.any((lat_o != lat) & ~near_half(rep["logits"], rep["scale"], 1e-4))
+
+
+def test_chunked_steps_with_refills_equal_one_run(torch, sn):
+    start, length, warm, N = independent_streams(5000, 1, 40, seed=9)
+    feat = synth.trace_features(2, N, 50)
+    n_pred = int(length.sum())
+    table = torch.from_numpy(synth.latency_table(5, n_pred, 2)).cuda()
+    sim = sn.Simulator(torch.from_numpy(feat).cuda(), 111, synth.dynamic_columns(50),
+                       start, length, warm)
+    a = sim.run(sn.SIM_LAT_INJECT, table)
+    sim.reset()
+    for _ in range(30):
+        sim.step(3, sn.SIM_LAT_INJECT, table)
+    b = sim.run(sn.SIM_LAT_INJECT, table)
+    assert_same(a, b)
+    sim.reset()
+    c = sim.run(sn.SIM_LAT_INJECT, table)
+    assert_same(a, c)
+
+
+def test_uneven_bf16_sample_replayed(torch, sn, oracle_lib):
+    """A scaled-down uneven workload (300 streams, 100..2,000 instructions,
+    BF16): a sample of sub-traces replayed by the oracle's BF16 form."""
+    start, length, warm, N = independent_streams(300, 100, 2000, seed=3)
+    codes = synth.trace_codes(1, N)
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(2, layers)
+    sim = sn.Simulator(torch.from_numpy(codes.view(np.int32)).cuda(), 111,
+                       synth.dynamic_columns(50), start, length, warm, prec=sn.SIM_BF16,
+                       n_feat=50)
+    sim.load_weights(layers, sn.flat_params(ws, bs))
+    lg = torch.zeros((sim.n_pred, 2), dtype=torch.float32, device="cuda")
+    sim.record_logits(lg)
+    g = sim.run()
+    gl = lg.cpu().numpy().astype(np.float64)
+    off = np.concatenate([[0], np.cumsum(length)]).astype(np.int64)
+    ks = np.array([0, 1, 57, 150, 299, int(np.argmax(length)), int(np.argmin(length))])
+    lat = np.concatenate([np.clip(np.rint(gl[off[k]:off[k + 1]]), 0, 65535) for k in ks]).astype(np.int32)
+    feat = synth.expand_codes(codes, 50)
+    cfg = oracle_lib.sim_cfg(50, 111, 2, 8, synth.dynamic_columns(50))
+    form = oracle_lib.Model(layers, ws, bs, 50, 111, prec=1)
+    rep = oracle_lib.simulate(cfg, feat, start[ks], length[ks], warm[ks], model=form,
+                              mode=oracle_lib.INJECT, lat_table=lat, want_logits=True,
+                              want_scale=True)
+    for key in ("fetch", "drain", "final", "warm_tick"):
+        np.testing.assert_array_equal(rep[key], g[key][ks], err_msg=key)
+    glk = np.concatenate([gl[off[k]:off[k + 1]] for k in ks])
+    assert rel_err(glk, rep["logits"], rep["scale"]).max() <= 2.0 ** -8

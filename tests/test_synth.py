@@ -53,3 +53,9 @@ def test_loguniform_lengths_range():
     n = synth.loguniform_lengths(3, 20_000, 1e3, 2e5)
     assert n.min() >= 1000 and n.max() <= 200_000
     assert abs(n.mean() / ((2e5 - 1e3) / np.log(200)) - 1) < 0.03
+
+
+def test_torch_code_generator_matches_numpy():
+    a = synth.trace_codes(1, 300_000, 12_345, 300_000)
+    b = synth.trace_codes_torch(1, 12_345, 300_000).numpy().view(np.uint32)
+    np.testing.assert_array_equal(a, b)
