@@ -106,6 +106,7 @@ struct NetSmem {
   typename P::T a3[Net::NCONV == 3 ? MT * G::SA3 : G::PAD];
   float red[Net::WAVES][MT][Net::NOUT];
   float logit[MT][Net::NOUT];
+  float x_inv[Net::D];  // FP8: reciprocal input scale of each window feature
 };
 
 // Epilogue of one accumulator element: bias, (FP8) dequantisation, ReLU.
@@ -140,17 +141,20 @@ constexpr int stream_chunk(int kgs, int tpw) {
   return c;
 }
 
-// acc[j] += A(rows of this lane's fragment, all K) * B(k, tiles nt0 + j):
-// B fragments are requested one chunk ahead of their use (double
-// buffering) and the scheduler is kept from sinking the requests.
-// One 16-byte B fragment through a raw buffer load: the resource and the
-// fragment's offset are wave-uniform (scalar registers), only the lane's
+// One 16-byte weight fragment through a raw buffer load: the resource and
+// the fragment's offset are wave-uniform (scalar registers), only the lane's
 // 16-byte offset is per lane, so many fragments can be in flight without a
 // 64-bit address register each.
 __device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_off, int frag_off) {
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, frag_off, 0));
 }
 
+// acc[j] += W(tile nt0 + j) x A(this lane's 16 rows), all K.  The weight
+// fragment is the MFMA's first operand, so lane l ends up holding row
+// l % 16 of the activations and output columns 4*(l/16) .. +3 of the tile:
+// consecutive columns, stored with one vector write.  Weight fragments are
+// requested one chunk ahead of their use (double buffering) and the
+// scheduler is kept from sinking the requests.
 template <class P, int KGS, int NTILES, int TPW>
 __device__ __forceinline__ void mma_stream(v4f* acc, const typename P::T* __restrict__ ap,
                                            const uint4* __restrict__ Bp, int nt0, int lane) {
@@ -178,9 +182,33 @@ __device__ __forceinline__ void mma_stream(v4f* acc, const typename P::T* __rest
     for (int kg = 0; kg < CH; ++kg) {
       const uint4 a = *reinterpret_cast<const uint4*>(ap + (c * CH + kg) * P::KG);
 #pragma unroll
-      for (int j = 0; j < TPW; ++j) acc[j] = P::mma(acc[j], a, b[c & 1][kg][j]);
+      for (int j = 0; j < TPW; ++j) acc[j] = P::mma(acc[j], b[c & 1][kg][j], a);
     }
     __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+// N consecutive storage elements written with the widest stores the
+// destination's alignment (ALIGN bytes) allows.
+template <int ALIGN, class T, int N>
+__device__ __forceinline__ void store_run(T* dst, const T (&e)[N]) {
+  constexpr int BYTES = N * (int)sizeof(T);
+  constexpr int W = (ALIGN % 16 == 0 && BYTES % 16 == 0) ? 16
+                    : (ALIGN % 8 == 0 && BYTES % 8 == 0) ? 8
+                    : (ALIGN % 4 == 0 && BYTES % 4 == 0) ? 4 : (int)sizeof(T);
+  uint32_t w[(BYTES + 3) / 4];
+  __builtin_memcpy(w, e, BYTES);
+  char* d = reinterpret_cast<char*>(dst);
+#pragma unroll
+  for (int o = 0; o < BYTES; o += W) {
+    if constexpr (W == 16)
+      *reinterpret_cast<uint4*>(d + o) = uint4{w[o / 4], w[o / 4 + 1], w[o / 4 + 2], w[o / 4 + 3]};
+    else if constexpr (W == 8)
+      *reinterpret_cast<uint2*>(d + o) = uint2{w[o / 4], w[o / 4 + 1]};
+    else if constexpr (W == 4)
+      *reinterpret_cast<uint32_t*>(d + o) = w[o / 4];
+    else
+      *reinterpret_cast<T*>(d + o) = e[o / sizeof(T)];
   }
 }
 
@@ -205,27 +233,31 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
   static_assert(TILES % WAVES == 0 && TPW >= 1 && NTILES % TPW == 0, "wave split");
   const int t0 = wave * TPW;
   const int mt = t0 / NTILES, nt0 = t0 % NTILES;
-  const int arow = mt * 16 + (lane & 15);
-  const T* ap = A + (arow / POS) * SA + (arow % POS) * K + (P::KG / 4) * (lane >> 4);
+  const int row = mt * 16 + (lane & 15);
+  const T* ap = A + (row / POS) * SA + (row % POS) * K + (P::KG / 4) * (lane >> 4);
   v4f acc[TPW];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
   mma_stream<P, KGS, NTILES, TPW>(acc, ap, Bp, nt0, lane);
+  T* orow = O + (row / POS) * SO + (row % POS) * N;
+  const bool live = !CAL || row_live[row / POS];
 #pragma unroll
   for (int j = 0; j < TPW; ++j) {
-    const int col = (nt0 + j) * 16 + (lane & 15);
+    const int col0 = (nt0 + j) * 16 + 4 * (lane >> 4);
+    T e[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = mt * 16 + 4 * (lane >> 4) + i;
-      const float v = activation<P>(acc[j][i], col, bias, ws, relu);
+      const float v = activation<P>(acc[j][i], col0 + i, bias, ws, relu);
       if constexpr (CAL)
-        if (row_live[row / POS]) cal_max(cal, col, v);
-      O[(row / POS) * SO + (row % POS) * N + col] = to_storage<P>(v, col, ai);
+        if (live) cal_max(cal, col0 + i, v);
+      e[i] = to_storage<P>(v, col0 + i, ai);
     }
+    store_run<4 * sizeof(T)>(orow + col0, e);
   }
 }
 
-// Hidden FC, one block's K-slice: acc[MT rows][N cols] += A[MT][K] * B_j.
+// Hidden FC, one block's K-slice: acc[MT rows][N cols] += A[MT][K] * B_j
+// (lane l: row l % 16, columns 4*(l/16) .. +3 of each tile).
 template <class P, int K, int N, int WAVES, int SA>
 __device__ __forceinline__ void hidden_accumulate(v4f* acc, const typename P::T* __restrict__ A,
                                                   const uint4* __restrict__ Bp, int wave,
@@ -235,16 +267,18 @@ __device__ __forceinline__ void hidden_accumulate(v4f* acc, const typename P::T*
   mma_stream<P, KGS, NTILES, TPW>(acc, ap, Bp, wave * TPW, lane);
 }
 
-// The whole predictor on one tile of MT windows.  fill(j, X) writes block j
-// of every window (slots j*BS .. j*BS+BS-1, DP elements each, layout
-// X[s*SX + t*DP + c], already in storage precision) and is called by all
-// threads; the raw outputs land in sm.logit.  relu_mask bit l = ReLU after
-// layer l.  CAL: also record per-channel max |input| of every layer into
-// cal (offsets: window D, conv1 out, conv2 out[, conv3 out, hidden out]),
-// counting only tile rows whose row_live[s] is set (real windows).
-template <class Net, class P, bool CAL = false, class Fill>
+// The whole predictor on one tile of MT windows.  The window arrives block
+// by block: load(j) requests block j's rows (slots j*BS .. j*BS+BS-1) into
+// registers, commit(j, regs, X) writes them, in storage precision, to
+// X[s*SX + t*DP + c].  Block j+1 is requested before block j's convolutions
+// and committed after them, so its memory latency is hidden.  Both are
+// called by all threads; the raw outputs land in sm.logit.  relu_mask bit l
+// = ReLU after layer l.  CAL: also record per-channel max |input| of every
+// layer into cal (offsets: window D, conv1 out, conv2 out[, conv3 out,
+// hidden out]), counting only tile rows whose row_live[s] is set.
+template <class Net, class P, bool CAL = false, class Load, class Commit>
 __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
-                                             NetSmem<Net, P>& sm, Fill&& fill,
+                                             NetSmem<Net, P>& sm, Load&& load, Commit&& commit,
                                              unsigned* cal = nullptr,
                                              const int* row_live = nullptr) {
   using G = Geo<Net, P>;
@@ -261,9 +295,11 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   const int fpair = tid / LPP, fsub = tid % LPP;
   const int fs = fpair / Net::NOUT, fo = fpair % Net::NOUT;
 
+  auto regs = load(0);
+  commit(0, regs, sm.x);
   for (int j = 0; j < Net::NB; ++j) {
-    fill(j, sm.x);
     __syncthreads();
+    if (j + 1 < Net::NB) regs = load(j + 1);
     conv_stage<P, 2 * G::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1, CAL>(
         sm.x, sm.a1, static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
         wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live);
@@ -297,46 +333,40 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
 #pragma unroll
       for (int c = 0; c < CPL; ++c) fpart = fmaf(P::val(arow[c]), wrow[c], fpart);
     }
+    // X was last read by conv1 of this block, before the barriers above
+    if (j + 1 < Net::NB) commit(j + 1, regs, sm.x);
   }
 
   if constexpr (Net::HID > 0) {
     // bias + ReLU on the hidden layer, rounding to the form's precision, then
-    // the final FC: each lane holds 4 rows x HT columns; reduce over the 16
-    // lanes sharing rows, then over waves.
+    // the final FC: lane l holds row l % 16 and 4 columns of each of its HT
+    // tiles; reduce over the 4 lanes sharing the row, then over waves.
     const bool hrelu = relu_mask & (1u << Net::NCONV);
-    float p[4][Net::NOUT];
+    const int row = lane & 15;
+    const bool live = !CAL || row_live[row];
+    float p[Net::NOUT];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int o = 0; o < Net::NOUT; ++o) p[i][o] = 0.f;
+    for (int o = 0; o < Net::NOUT; ++o) p[o] = 0.f;
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) {
-      const int col = (wave * HT + jj) * 16 + (lane & 15);
-      float wo[Net::NOUT];
-#pragma unroll
-      for (int o = 0; o < Net::NOUT; ++o) wo[o] = wt.last_w[o * Net::HID + col];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
+        const int col = (wave * HT + jj) * 16 + 4 * (lane >> 4) + i;
         const float hv = activation<P>(hacc[jj][i], col, wt.hid_b, wt.hid_ws, hrelu);
         if constexpr (CAL)
-          if (row_live[4 * (lane >> 4) + i])
-            cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col, hv);
+          if (live) cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col, hv);
         const float h = P::val(to_storage<P>(hv, col, wt.hid_ai));
 #pragma unroll
-        for (int o = 0; o < Net::NOUT; ++o) p[i][o] = fmaf(h, wo[o], p[i][o]);
+        for (int o = 0; o < Net::NOUT; ++o) p[o] = fmaf(h, wt.last_w[o * Net::HID + col], p[o]);
       }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int o = 0; o < Net::NOUT; ++o) {
-        float v = p[i][o];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        v += __shfl_xor(v, 4);
-        v += __shfl_xor(v, 8);
-        if ((lane & 15) == 0) sm.red[wave][4 * (lane >> 4) + i][o] = v;
-      }
+    for (int o = 0; o < Net::NOUT; ++o) {
+      float v = p[o];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (lane < 16) sm.red[wave][row][o] = v;
+    }
     __syncthreads();
     if (tid < MT * Net::NOUT) {
       const int s = tid / Net::NOUT, o = tid % Net::NOUT;
@@ -359,12 +389,29 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   __syncthreads();
 }
 
-// Window element in storage precision (FP8: the feature's input scale).
-template <class P>
-__device__ __forceinline__ typename P::T window_elem(float v, int c, const float* x_inv) {
-  if constexpr (P::SCALED) v *= x_inv[c];
-  return P::cvt(v);
+// One thread's share of a window row: CPT consecutive features from column
+// c0.  FP8: the features' input scales are applied (xs: reciprocals by
+// feature, in LDS).
+template <class P, int CPT, int D>
+__device__ __forceinline__ void window_elems(const float (&v)[CPT], const float* xs, int c0,
+                                             typename P::T (&e)[CPT]) {
+#pragma unroll
+  for (int i = 0; i < CPT; ++i) {
+    float x = v[i];
+    if constexpr (P::SCALED) x *= xs[c0 + i < D ? c0 + i : 0];
+    e[i] = P::cvt(x);
+  }
 }
+
+// Registers carrying one thread's share of one window row between load and
+// commit.
+template <int CPT>
+struct RowRegs {
+  float2 v[CPT / 2];
+  uint32_t code;
+  float res, ex;
+  int valid;
+};
 
 // Rounded latency in cycles: nearest, ties to even; non-finite -> 0;
 // clamped to [0, lat_max].
@@ -480,61 +527,74 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
   }
   uint32_t n_clamped = 0, n_nonfinite = 0, n_mismatch = 0, n_pred = 0;
+
+  // Window gather: TPR threads per (sub-trace, slot) row, CPT features each.
+  constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+  static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
+  const int grow = tid / TPR, part = tid % TPR;
+  const int gs = grow / BS, gt = grow % BS;
+  if constexpr (P::SCALED)
+    for (int c = tid; c < D; c += NT) sm.net.x_inv[c] = wt.x_inv[c];
+  // load(j): the row's trace index from the queue ring, then the row's
+  // features requested (every address in bounds, so all are in flight
+  // together); commit(j): dynamic columns, conversion, one vector store.
+  auto load = [&](int j) {
+    RowRegs<CPT> r;
+    const int w = j * BS + gt;
+    int64_t idx = -1;
+    r.res = 0.f;
+    r.ex = 0.f;
+    if (sm.active[gs]) {
+      if (w == 0) {
+        idx = sm.first[gs] + sm.pos[gs];
+      } else if (w <= sm.count[gs]) {
+        int e = sm.head[gs] + sm.count[gs] - w;
+        e = e >= C ? e - C : e;
+        idx = sm.q_idx[gs][e];
+        r.res = (float)(sm.cur[gs] - sm.q_t[gs][e]);
+        r.ex = (float)sm.q_e[gs][e];
+      }
+    }
+    r.valid = idx >= 0;
+    r.code = 0;
+    if (p.codes) {
+      r.code = p.codes[idx < 0 ? 0 : idx];
+    } else {
+      const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
+#pragma unroll
+      for (int cc = 0; cc < CPT; cc += 2) {
+        const int c = part * CPT + cc;
+        r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+      }
+    }
+    return r;
+  };
+  auto commit = [&](int j, const RowRegs<CPT>& r, T* X) {
+    (void)j;
+    float v[CPT];
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+      const int c = part * CPT + cc;
+      float x = 0.f;
+      if (r.valid && c < D)
+        x = p.codes ? code_feature(r.code, c) : (cc & 1 ? r.v[cc / 2].y : r.v[cc / 2].x);
+      if (c == p.col_res) x = r.res;
+      if (c == p.col_exe) x = r.ex;
+      if (c == p.col_sto) x = 0.f;
+      if constexpr (CAL)
+        if (c < D && r.valid) cal_max(cal, c, x);
+      v[cc] = x;
+    }
+    T e[CPT];
+    window_elems<P, CPT, D>(v, sm.net.x_inv, part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(X + gs * G::SX + gt * DP + part * CPT, e);
+  };
+
   int any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
 
   for (int it = 0; it < p.n_steps && any; ++it) {
     if (RUN_NET) {
-      // window block j for the tile: TPR threads per (sub-trace, slot) row
-      constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
-      static_assert(NT % ROWS == 0 && DP % TPR == 0, "gather split");
-      const int row = tid / TPR, part = tid % TPR;
-      const int s = row / BS, t = row % BS;
-      auto fill = [&](int j, T* X) {
-        const int w = j * BS + t;
-        int64_t idx = -1;
-        float res = 0.f, ex = 0.f;
-        if (sm.active[s]) {
-          if (w == 0) {
-            idx = sm.first[s] + sm.pos[s];
-          } else if (w <= sm.count[s]) {
-            int e = sm.head[s] + sm.count[s] - w;
-            e = e >= C ? e - C : e;
-            idx = sm.q_idx[s][e];
-            res = (float)(sm.cur[s] - sm.q_t[s][e]);
-            ex = (float)sm.q_e[s][e];
-          }
-        }
-        T* dst = X + s * G::SX + t * DP;
-        // every load is in bounds (row 0 / column clamped into the row), so
-        // they are all issued before the first is used
-        static_assert(CPT % 2 == 0 && D % 2 == 0, "pairs of features");
-        float2 v2[CPT / 2];
-        uint32_t code = 0;
-        if (p.codes) {
-          code = p.codes[idx < 0 ? 0 : idx];
-        } else {
-          const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
-#pragma unroll
-          for (int cc = 0; cc < CPT; cc += 2) {
-            const int c = part * CPT + cc;
-            v2[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
-          }
-        }
-#pragma unroll
-        for (int cc = 0; cc < CPT; ++cc) {
-          const int c = part * CPT + cc;
-          float v = 0.f;
-          if (idx >= 0 && c < D)
-            v = p.codes ? code_feature(code, c) : (cc & 1 ? v2[cc / 2].y : v2[cc / 2].x);
-          if (c == p.col_res) v = res;
-          if (c == p.col_exe) v = ex;
-          if (c == p.col_sto) v = 0.f;
-          if constexpr (CAL)
-            if (c < D && idx >= 0) cal_max(cal, c, v);
-          dst[c] = window_elem<P>(v, c < D ? c : 0, wt.x_inv);
-        }
-      };
-      predict_tile<Net, P, CAL>(wt, relu_mask, sm.net, fill, cal, sm.active);
+      predict_tile<Net, P, CAL>(wt, relu_mask, sm.net, load, commit, cal, sm.active);
     }
 
     if (tid < MT && sm.active[tid]) {
@@ -651,25 +711,36 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
   const int row = tid / TPR, part = tid % TPR;
   const int s = row / BS, t = row % BS;
-  auto fill = [&](int j, T* X) {
-    const int64_t b = b0 + s;
-    const int w = j * BS + t;
-    const float* src = x + ((b < B ? b : 0) * L + w) * D;
-    T* dst = X + s * G::SX + t * DP;
-    float2 v2[CPT / 2];
+  static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
+  if constexpr (P::SCALED) {
+    for (int c = tid; c < D; c += NT) sm.x_inv[c] = wt.x_inv[c];
+    __syncthreads();
+  }
+  const int64_t b = b0 + s;
+  auto load = [&](int j) {
+    RowRegs<CPT> r;
+    r.valid = b < B;
+    const float* src = x + ((b < B ? b : 0) * L + j * BS + t) * D;
 #pragma unroll
     for (int cc = 0; cc < CPT; cc += 2) {
       const int c = part * CPT + cc;
-      v2[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+      r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
     }
+    return r;
+  };
+  auto commit = [&](int j, const RowRegs<CPT>& r, T* X) {
+    (void)j;
+    float v[CPT];
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
       const int c = part * CPT + cc;
-      const float v = (b < B && c < D) ? (cc & 1 ? v2[cc / 2].y : v2[cc / 2].x) : 0.f;
-      dst[c] = window_elem<P>(v, c < D ? c : 0, wt.x_inv);
+      v[cc] = (r.valid && c < D) ? (cc & 1 ? r.v[cc / 2].y : r.v[cc / 2].x) : 0.f;
     }
+    T e[CPT];
+    window_elems<P, CPT, D>(v, sm.x_inv, part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(X + s * G::SX + t * DP + part * CPT, e);
   };
-  predict_tile<Net, P>(wt, relu_mask, sm, fill);
+  predict_tile<Net, P>(wt, relu_mask, sm, load, commit);
   if (tid < MT * Net::NOUT) {
     const int ss = tid / Net::NOUT, o = tid % Net::NOUT;
     if (b0 + ss < B) logits[(b0 + ss) * Net::NOUT + o] = sm.logit[ss][o];
