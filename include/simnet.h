@@ -157,6 +157,12 @@ SIMNET_API int sim_step(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode, const i
  * that has completed must be sim_reset before it runs again. */
 SIMNET_API int sim_run(sim_ctx* ctx, int32_t lat_mode, const int32_t* lat_table, sim_result* res);
 
+/* enable != 0: sim_run replays a graph of its kernels (the persistent step
+ * kernel run until every slot is empty, then the reduction of the total),
+ * instantiated on first use and rebuilt when lat_mode, lat_table, the
+ * logits buffer or the weights change.  The graph holds kernel nodes only. */
+SIMNET_API int sim_set_graph(sim_ctx* ctx, int32_t enable);
+
 /* Return every sub-trace to its first instruction (asynchronous). */
 SIMNET_API int sim_reset(sim_ctx* ctx);
 

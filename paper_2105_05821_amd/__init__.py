@@ -26,7 +26,8 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVIC
                 -4: "SIM_ESTATE", -5: "SIM_ENONFINITE", -6: "SIM_EUNSUPPORTED"}
 
 EXPORTED = ("sim_validate_config", "sim_init", "sim_load_weights", "sim_step", "sim_run",
-            "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "predictor_fwd",
+            "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
+            "predictor_fwd",
             "sim_destroy", "sim_last_error")
 
 
@@ -78,6 +79,7 @@ def lib():
         L.predictor_fwd.argtypes = [P, P, C.c_int64, P, P]
         L.sim_calibrate.argtypes = [P, C.c_int32, C.c_int32, P]
         L.sim_act_scales.argtypes = [P, P, C.c_int32]
+        L.sim_set_graph.argtypes = [P, C.c_int32]
         L.sim_destroy.argtypes = [P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = [P]
@@ -219,6 +221,9 @@ class Simulator:
         out = np.zeros(4096, np.float32)
         self._check("sim_act_scales", lib().sim_act_scales(self.ctx, out.ctypes.data, out.size))
         return out
+
+    def use_graph(self, enable: bool = True) -> None:
+        self._check("sim_set_graph", lib().sim_set_graph(self.ctx, int(enable)))
 
     def record_logits(self, buf) -> None:
         self._check("sim_record_logits", lib().sim_record_logits(self.ctx, _ptr(buf)))

@@ -38,6 +38,11 @@ struct sim_ctx {
   std::vector<float> act_scale;     // per layer-input channel, after calibration
   bool calibrated = false;
   bool ran_to_end = false;          // an unbounded step launch has been issued
+  bool use_graph = false;           // sim_run replays a graph of its kernels
+  hipGraphExec_t graph_exec = nullptr;
+  int32_t graph_mode = -1;
+  const int32_t* graph_table = nullptr;
+  float* graph_logits = nullptr;
   int64_t* dev_total = nullptr;
   DevState st{};
   DevWeights w{};
@@ -351,6 +356,12 @@ bool layers_match(const sim_layer* layers, int32_t n) {
 
 }  // namespace
 
+static void drop_graph(sim_ctx* c) {
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  c->graph_exec = nullptr;
+  c->graph_mode = -1;
+}
+
 // Pack params for one precision and upload them into *dev (replacing any
 // previous block); fills *w with the device pointers.
 static int upload_weights(sim_ctx* c, int prec, const float* params,
@@ -372,6 +383,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
     (void)hipFree(*dev);
   }
   *dev = dw;
+  drop_graph(c);
   char* base = static_cast<char*>(dw);
   auto F = [&](size_t o) { return reinterpret_cast<const float*>(base + o); };
   *w = DevWeights{};
@@ -640,6 +652,13 @@ int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* tabl
   return sim_reset(c);
 }
 
+int sim_set_graph(sim_ctx* c, int32_t enable) {
+  if (!c) return SIM_EINVAL;
+  c->use_graph = enable != 0;
+  if (!c->use_graph) drop_graph(c);
+  return SIM_OK;
+}
+
 int sim_act_scales(const sim_ctx* c, float* out, int32_t n) {
   if (!c || !out) return SIM_EINVAL;
   if (!c->calibrated) return SIM_ESTATE;
@@ -654,15 +673,8 @@ int sim_record_logits(sim_ctx* c, float* logits) {
   return SIM_OK;
 }
 
-static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t* table) {
-  if (mode < SIM_LAT_PREDICT || mode > SIM_LAT_SHADOW) return fail(c, SIM_EINVAL, "bad lat_mode");
-  if (mode != SIM_LAT_PREDICT && !table) return fail(c, SIM_EINVAL, "lat_table required");
-  if (mode != SIM_LAT_INJECT && !c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
-  if (mode != SIM_LAT_INJECT && c->cfg.prec == SIM_FP8E4M3 && !c->calibrated)
-    return fail(c, SIM_ESTATE, "FP8 form needs sim_calibrate first");
-  if (c->completed) return fail(c, SIM_ESTATE, "run completed; call sim_reset");
-  if (c->ran_to_end) return SIM_OK;  // every sub-trace has already finished
-  if (n_steps >= INT32_MAX) c->ran_to_end = true;
+static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
+                              const int32_t* table) {
   StepParams p{};
   p.feat = c->feat;
   p.codes = c->codes;
@@ -678,6 +690,20 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   p.logits_out = c->logits_out;
   p.n_steps = (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
   p.cal_out = nullptr;
+  return p;
+}
+
+static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t* table) {
+  if (mode < SIM_LAT_PREDICT || mode > SIM_LAT_SHADOW) return fail(c, SIM_EINVAL, "bad lat_mode");
+  if (mode != SIM_LAT_PREDICT && !table) return fail(c, SIM_EINVAL, "lat_table required");
+  if (mode != SIM_LAT_INJECT && !c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
+  if (mode != SIM_LAT_INJECT && c->cfg.prec == SIM_FP8E4M3 && !c->calibrated)
+    return fail(c, SIM_ESTATE, "FP8 form needs sim_calibrate first");
+  if (c->completed) return fail(c, SIM_ESTATE, "run completed; call sim_reset");
+  if (c->ran_to_end) return SIM_OK;  // every sub-trace has already finished
+  if (n_steps == 0) return SIM_OK;   // checks only
+  if (n_steps >= INT32_MAX) c->ran_to_end = true;
+  const StepParams p = step_params(c, n_steps, mode, table);
   hipError_t e = launch_step(c->net, c->cfg.prec, c->w, c->relu, c->st, p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   return SIM_OK;
@@ -693,10 +719,33 @@ int sim_step(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* table) {
 int sim_run(sim_ctx* c, int32_t mode, const int32_t* table, sim_result* res) {
   if (!c) return SIM_EINVAL;
   if (!res) return fail(c, SIM_EINVAL, "null result");
-  int rc = step_launch(c, INT32_MAX, mode, table);
-  if (rc != SIM_OK) return rc;
-  hipError_t e = launch_total(c->st, c->n_sub, c->dev_total, c->stream);
-  if (e != hipSuccess) return hip_fail(c, e, "total launch");
+  hipError_t e = hipSuccess;
+  if (c->use_graph && !c->ran_to_end) {
+    // same checks as a step launch, then replay (rebuilt when its inputs change)
+    int rc = step_launch(c, 0, mode, table);
+    if (rc != SIM_OK) return rc;
+    if (!c->graph_exec || c->graph_mode != mode || c->graph_table != table ||
+        c->graph_logits != c->logits_out) {
+      drop_graph(c);
+      hipGraph_t g = nullptr;
+      e = build_run_graph(c->net, c->cfg.prec, c->w, c->relu, c->st,
+                          step_params(c, INT32_MAX, mode, table), c->dev_total, &g);
+      if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+      if (g) (void)hipGraphDestroy(g);
+      if (e != hipSuccess) return hip_fail(c, e, "build run graph");
+      c->graph_mode = mode;
+      c->graph_table = table;
+      c->graph_logits = c->logits_out;
+    }
+    e = hipGraphLaunch(c->graph_exec, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "graph launch");
+    c->ran_to_end = true;
+  } else {
+    int rc = step_launch(c, INT32_MAX, mode, table);
+    if (rc != SIM_OK) return rc;
+    e = launch_total(c->st, c->n_sub, c->dev_total, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "total launch");
+  }
   int64_t total = 0;
   unsigned long long ctr[NCOUNTERS] = {0};
   e = hipMemcpyAsync(&total, c->dev_total, 8, hipMemcpyDeviceToHost, c->stream);
@@ -741,6 +790,7 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
 void sim_destroy(sim_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
+  drop_graph(c);
   if (c->dev_weights) (void)hipFree(c->dev_weights);
   if (c->dev_w32) (void)hipFree(c->dev_w32);
   if (c->dev_block) (void)hipFree(c->dev_block);

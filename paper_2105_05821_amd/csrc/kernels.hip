@@ -862,4 +862,63 @@ hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStr
   return hipGetLastError();
 }
 
+// The run as a graph of kernel nodes (no memset nodes): the persistent step
+// kernel until every slot is empty, then the total.
+template <class Net, class P>
+static void* step_fn(bool run_net) {
+  return run_net ? reinterpret_cast<void*>(&step_kernel<Net, P, true>)
+                 : reinterpret_cast<void*>(&step_kernel<Net, P, false>);
+}
+
+hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu,
+                           const DevState& s, const StepParams& p, int64_t* total,
+                           hipGraph_t* out) {
+  const bool run_net = p.lat_mode != 1;
+  void* fn;
+  int nt;
+  if (net == 0) {
+    fn = prec == 0 ? step_fn<NetSmall, PF32>(run_net)
+         : prec == 1 ? step_fn<NetSmall, PBF16>(run_net) : step_fn<NetSmall, PFP8>(run_net);
+    nt = Geo<NetSmall, PF32>::NT;
+  } else {
+    fn = prec == 0 ? step_fn<NetC3, PF32>(run_net)
+         : prec == 1 ? step_fn<NetC3, PBF16>(run_net) : step_fn<NetC3, PFP8>(run_net);
+    nt = Geo<NetC3, PF32>::NT;
+  }
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  DevWeights wa = w;
+  uint32_t ra = relu;
+  DevState sa = s;
+  StepParams pa = p;
+  void* step_args[] = {&wa, &ra, &sa, &pa};
+  hipKernelNodeParams kp{};
+  kp.func = fn;
+  kp.gridDim = dim3(p.n_wg);
+  kp.blockDim = dim3(nt);
+  kp.sharedMemBytes = 0;
+  kp.kernelParams = step_args;
+  kp.extra = nullptr;
+  hipGraphNode_t step_node = nullptr, total_node = nullptr;
+  e = hipGraphAddKernelNode(&step_node, g, nullptr, 0, &kp);
+  int32_t n_sub = p.n_sub;
+  int64_t* tot = total;
+  void* total_args[] = {&sa, &n_sub, &tot};
+  hipKernelNodeParams kt{};
+  kt.func = reinterpret_cast<void*>(&total_kernel);
+  kt.gridDim = dim3(1);
+  kt.blockDim = dim3(256);
+  kt.sharedMemBytes = 0;
+  kt.kernelParams = total_args;
+  kt.extra = nullptr;
+  if (e == hipSuccess) e = hipGraphAddKernelNode(&total_node, g, &step_node, 1, &kt);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return e;
+  }
+  *out = g;
+  return hipSuccess;
+}
+
 }  // namespace simnet

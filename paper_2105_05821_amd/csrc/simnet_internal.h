@@ -129,5 +129,9 @@ int calibration_size(int net);
 hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, int32_t n_slots,
                         hipStream_t stream);
 hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream);
+// Graph of the run: step kernel until every slot is empty, then the total.
+hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu,
+                           const DevState& s, const StepParams& p, int64_t* total,
+                           hipGraph_t* out);
 
 }  // namespace simnet

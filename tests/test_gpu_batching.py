@@ -148,3 +148,28 @@ def test_uneven_bf16_sample_replayed(torch, sn, oracle_lib):
         np.testing.assert_array_equal(rep[key], g[key][ks], err_msg=key)
     glk = np.concatenate([gl[off[k]:off[k + 1]] for k in ks])
     assert rel_err(glk, rep["logits"], rep["scale"]).max() <= 2.0 ** -8
+
+
+def test_graph_replay_equals_direct_run(torch, sn):
+    start, length, warm, N = independent_streams(5000, 1, 40, seed=12)
+    codes = synth.trace_codes(3, N)
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(2, layers)
+    sim = sn.Simulator(torch.from_numpy(codes.view(np.int32)).cuda(), 111,
+                       synth.dynamic_columns(50), start, length, warm, prec=sn.SIM_BF16, n_feat=50)
+    sim.load_weights(layers, sn.flat_params(ws, bs))
+    a = sim.run()
+    sim.use_graph(True)
+    for _ in range(3):  # replays, with eager work and synchronisation between them
+        sim.reset()
+        b = sim.run()
+        assert_same(a, b)
+        torch.cuda.synchronize()
+    table = torch.from_numpy(synth.latency_table(4, sim.n_pred, 2)).cuda()
+    sim.use_graph(False)
+    sim.reset()
+    c = sim.run(sn.SIM_LAT_INJECT, table)
+    sim.use_graph(True)
+    sim.reset()
+    d = sim.run(sn.SIM_LAT_INJECT, table)
+    assert_same(c, d)
