@@ -69,6 +69,10 @@ def lib():
         L.ol_round_e4m3.restype = C.c_double
         L.ol_round_bf16.argtypes = [C.c_double]
         L.ol_round_bf16.restype = C.c_double
+        L.ol_train.restype = C.c_int
+        L.ol_train.argtypes = [P, C.c_int64, f64p, i32p, C.c_int32, P, f64p, P, P, C.c_int32]
+        L.ol_hybrid_loss.restype = C.c_double
+        L.ol_hybrid_loss.argtypes = [f64p, i32p, C.c_int64, C.c_int32]
         _lib = L
     return _lib
 
@@ -218,3 +222,33 @@ def calibrate(cfg, feat, start, length, warm, model: Model, n_steps: int,
                    mode=INJECT if lat_table is not None else PREDICT, lat_table=lat_table,
                    threads=threads, max_pos=n_steps, want_amax=True)
     return res["amax"]
+
+
+N_BINS = 400
+
+
+def train_step(model: Model, x: np.ndarray, lat: np.ndarray, want_dlogits: bool = False,
+               want_dx: bool = False, threads: int = 0):
+    """FP64 hybrid loss, its gradient w.r.t. the flat PyTorch-order
+    parameters, and optionally w.r.t. the head outputs and the input."""
+    x = np.ascontiguousarray(x, np.float64)
+    lat = np.ascontiguousarray(lat, np.int32)
+    B = x.shape[0]
+    n_params = model._params.size
+    dparams = np.zeros(n_params, np.float64)
+    loss = C.c_double(0.0)
+    dlogits = np.zeros((B, model.n_out), np.float64) if want_dlogits else None
+    dx = np.zeros_like(x) if want_dx else None
+    rc = lib().ol_train(model.ptr, B, x, lat, N_BINS, C.byref(loss), dparams,
+                        dlogits.ctypes.data if dlogits is not None else None,
+                        dx.ctypes.data if dx is not None else None,
+                        threads if threads > 0 else default_threads())
+    if rc != 0:
+        raise ValueError("oracle rejected the training arguments")
+    return {"loss": loss.value, "dparams": dparams, "dlogits": dlogits, "dx": dx}
+
+
+def hybrid_loss(z: np.ndarray, lat: np.ndarray) -> float:
+    z = np.ascontiguousarray(z, np.float64)
+    lat = np.ascontiguousarray(lat, np.int32)
+    return lib().ol_hybrid_loss(z, lat, z.shape[0], N_BINS)

@@ -585,3 +585,213 @@ void ol_scales_from_amax(const double* amax, int32_t n, float* scales) {
 /* e4m3 rounding of single values (exposed for its pin tests). */
 double ol_round_e4m3(double v) { return round_e4m3(v); }
 double ol_round_bf16(double v) { return round_bf16(v); }
+
+/* ------------------------------------------------------------ training --- */
+
+/* Hybrid loss of one prediction (training form, read from Sec. 2.3's
+ * hybrid scheme and the training of Sec. 2.4): per latency type t the head
+ * gives n_bins class logits and one regression output; loss = cross-entropy
+ * of the class min(lat, n_bins - 1) + |reg - log1p(lat)|.  Writes d(loss)/d
+ * (head outputs) scaled by `scale` into dz (if not NULL); returns the loss. */
+static double hybrid_loss(const double* z, const int32_t* lat, int n_types, int n_bins,
+                          double scale, double* dz) {
+  double loss = 0.0;
+  const int per = n_bins + 1;
+  for (int t = 0; t < n_types; ++t) {
+    const double* zt = z + t * per;
+    const int bin = lat[t] < n_bins - 1 ? lat[t] : n_bins - 1;
+    double m = zt[0];
+    for (int i = 1; i < n_bins; ++i) m = zt[i] > m ? zt[i] : m;
+    double se = 0.0;
+    for (int i = 0; i < n_bins; ++i) se += exp(zt[i] - m);
+    const double lse = m + log(se);
+    const double target = log1p((double)lat[t]);
+    const double r = zt[n_bins] - target;
+    loss += lse - zt[bin] + fabs(r);
+    if (dz) {
+      for (int i = 0; i < n_bins; ++i)
+        dz[t * per + i] = scale * (exp(zt[i] - lse) - (i == bin ? 1.0 : 0.0));
+      dz[t * per + n_bins] = scale * (r > 0.0 ? 1.0 : (r < 0.0 ? -1.0 : 0.0));
+    }
+  }
+  return loss;
+}
+
+typedef struct {
+  const ol_model* m;
+  int64_t B;
+  const double* x;
+  const int32_t* lat;
+  int n_bins;
+  int64_t next;
+  int n_params;
+  double* dparams; /* [n_threads][n_params] */
+  double* loss;    /* [n_threads] */
+  double* dlogits; /* optional [B][n_out] */
+  double* dx;      /* optional [B][L][D] */
+  pthread_mutex_t mu;
+} train_job;
+
+/* Offsets of each layer's weight and bias in the flat PyTorch-order vector. */
+static void param_offsets(const ol_model* m, size_t* woff, size_t* boff, size_t* total) {
+  int ch = m->n_feat, len = m->n_slot;
+  size_t off = 0;
+  for (int l = 0; l < m->n_layers; ++l) {
+    const int kind = m->desc[l][0], ci = m->desc[l][1], co = m->desc[l][2];
+    const size_t nw = kind == OL_CONV ? (size_t)co * ci * 2 : (size_t)co * ci;
+    woff[l] = off;
+    off += nw;
+    boff[l] = off;
+    off += co;
+    ch = co;
+    len = kind == OL_CONV ? len / 2 : 1;
+  }
+  (void)ch;
+  (void)len;
+  *total = off;
+}
+
+static void* train_worker(void* arg) {
+  train_job* J = (train_job*)arg;
+  const ol_model* m = J->m;
+  const int NL = m->n_layers, L = m->n_slot, D = m->n_feat;
+  /* thread index (high bits of the shared counter), assigned under the lock */
+  pthread_mutex_lock(&J->mu);
+  int tid = (int)(J->next >> 40);
+  J->next += (int64_t)1 << 40;
+  pthread_mutex_unlock(&J->mu);
+  double* dp = J->dparams + (size_t)tid * J->n_params;
+  size_t woff[16], boff[16], tot;
+  param_offsets(m, woff, boff, &tot);
+  /* activations: a[0] = input (channel-major), a[l+1] = output of layer l */
+  int ch[17], len[17];
+  ch[0] = D;
+  len[0] = L;
+  for (int l = 0; l < NL; ++l) {
+    ch[l + 1] = m->desc[l][2];
+    len[l + 1] = m->desc[l][0] == OL_CONV ? len[l] / 2 : 1;
+  }
+  double* a[17];
+  double* g[17];
+  for (int l = 0; l <= NL; ++l) {
+    a[l] = (double*)calloc((size_t)ch[l] * len[l], sizeof(double));
+    g[l] = (double*)calloc((size_t)ch[l] * len[l], sizeof(double));
+  }
+  for (;;) {
+    pthread_mutex_lock(&J->mu);
+    const int64_t b = J->next & (((int64_t)1 << 40) - 1);
+    if (b < J->B) J->next += 1;
+    pthread_mutex_unlock(&J->mu);
+    if (b >= J->B) break;
+    const double* xb = J->x + (size_t)b * L * D;
+    for (int l = 0; l < L; ++l)
+      for (int c = 0; c < D; ++c) a[0][c * L + l] = xb[l * D + c];
+    /* forward, keeping every layer's output */
+    for (int l = 0; l < NL; ++l) {
+      const int kind = m->desc[l][0], ci = ch[l], co = ch[l + 1], li = len[l], lo = len[l + 1];
+      const double* w = m->w[l];
+      const double* bb = m->b[l];
+      for (int o = 0; o < co; ++o)
+        for (int p = 0; p < lo; ++p) {
+          double s = bb[o];
+          if (kind == OL_CONV) {
+            for (int c = 0; c < ci; ++c)
+              for (int t = 0; t < 2; ++t) s += w[((size_t)o * ci + c) * 2 + t] * a[l][c * li + 2 * p + t];
+          } else {
+            const int n_in = ci * li;
+            for (int j = 0; j < n_in; ++j) s += w[(size_t)o * n_in + j] * a[l][j];
+          }
+          a[l + 1][o * lo + p] = (m->desc[l][3] && s < 0.0) ? 0.0 : s;
+        }
+    }
+    /* loss and its gradient w.r.t. the head outputs */
+    const int n_out = ch[NL];
+    const double lb = hybrid_loss(a[NL], J->lat + 2 * b, 2, J->n_bins, 1.0 / (double)J->B, g[NL]);
+    J->loss[tid] += lb / (double)J->B;
+    if (J->dlogits)
+      for (int o = 0; o < n_out; ++o) J->dlogits[(size_t)b * n_out + o] = g[NL][o];
+    /* backward */
+    for (int l = NL - 1; l >= 0; --l) {
+      const int kind = m->desc[l][0], ci = ch[l], co = ch[l + 1], li = len[l], lo = len[l + 1];
+      const double* w = m->w[l];
+      double* gw = dp + woff[l];
+      double* gb = dp + boff[l];
+      /* through the ReLU: output gradient where the output is positive */
+      if (m->desc[l][3])
+        for (int i = 0; i < co * lo; ++i)
+          if (!(a[l + 1][i] > 0.0)) g[l + 1][i] = 0.0;
+      for (int i = 0; i < ci * li; ++i) g[l][i] = 0.0;
+      for (int o = 0; o < co; ++o)
+        for (int p = 0; p < lo; ++p) {
+          const double dy = g[l + 1][o * lo + p];
+          gb[o] += dy;
+          if (kind == OL_CONV) {
+            for (int c = 0; c < ci; ++c)
+              for (int t = 0; t < 2; ++t) {
+                gw[((size_t)o * ci + c) * 2 + t] += dy * a[l][c * li + 2 * p + t];
+                g[l][c * li + 2 * p + t] += w[((size_t)o * ci + c) * 2 + t] * dy;
+              }
+          } else {
+            const int n_in = ci * li;
+            for (int j = 0; j < n_in; ++j) {
+              gw[(size_t)o * n_in + j] += dy * a[l][j];
+              g[l][j] += w[(size_t)o * n_in + j] * dy;
+            }
+          }
+        }
+    }
+    if (J->dx)
+      for (int l = 0; l < L; ++l)
+        for (int c = 0; c < D; ++c) J->dx[((size_t)b * L + l) * D + c] = g[0][c * L + l];
+  }
+  for (int l = 0; l <= NL; ++l) {
+    free(a[l]);
+    free(g[l]);
+  }
+  return NULL;
+}
+
+/* Training form in FP64: mean hybrid loss over B windows x [B][L][D] with
+ * integer latency labels lat [B][2], its gradient w.r.t. every parameter
+ * (flat, PyTorch order) and optionally w.r.t. the head outputs and the
+ * input.  The network's last layer must have 2 * (n_bins + 1) outputs. */
+int ol_train(const void* p, int64_t B, const double* x, const int32_t* lat, int32_t n_bins,
+             double* loss, double* dparams, double* dlogits, double* dx, int32_t n_threads) {
+  const ol_model* m = (const ol_model*)p;
+  if (!m || m->prec != 0 || m->n_out != 2 * (n_bins + 1) || B < 1) return -1;
+  size_t woff[16], boff[16], tot;
+  param_offsets(m, woff, boff, &tot);
+  if (n_threads <= 0) n_threads = 1;
+  if (n_threads > B) n_threads = (int32_t)B;
+  train_job J;
+  memset(&J, 0, sizeof(J));
+  J.m = m; J.B = B; J.x = x; J.lat = lat; J.n_bins = n_bins;
+  J.n_params = (int)tot;
+  J.dparams = (double*)calloc((size_t)n_threads * tot, sizeof(double));
+  J.loss = (double*)calloc((size_t)n_threads, sizeof(double));
+  J.dlogits = dlogits;
+  J.dx = dx;
+  pthread_mutex_init(&J.mu, NULL);
+  pthread_t* th = (pthread_t*)malloc(sizeof(pthread_t) * (size_t)n_threads);
+  for (int i = 0; i < n_threads; ++i) pthread_create(&th[i], NULL, train_worker, &J);
+  for (int i = 0; i < n_threads; ++i) pthread_join(th[i], NULL);
+  free(th);
+  pthread_mutex_destroy(&J.mu);
+  *loss = 0.0;
+  for (size_t i = 0; i < tot; ++i) dparams[i] = 0.0;
+  for (int t = 0; t < n_threads; ++t) {
+    *loss += J.loss[t];
+    for (size_t i = 0; i < tot; ++i) dparams[i] += J.dparams[(size_t)t * tot + i];
+  }
+  free(J.dparams);
+  free(J.loss);
+  return 0;
+}
+
+/* Mean hybrid loss of given head outputs (for finite differences). */
+double ol_hybrid_loss(const double* z, const int32_t* lat, int64_t B, int32_t n_bins) {
+  double s = 0.0;
+  for (int64_t b = 0; b < B; ++b)
+    s += hybrid_loss(z + (size_t)b * 2 * (n_bins + 1), lat + 2 * b, 2, n_bins, 0.0, NULL);
+  return s / (double)B;
+}

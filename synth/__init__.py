@@ -267,6 +267,55 @@ def latency_table(seed: int, n_pred: int, n_out: int, f_max: int = 12, e_max: in
     return t.astype(np.int32)
 
 
+# ------------------------------------------------------- training labels ---
+
+# A small analytic pipeline model labels synthetic traces with fetch and
+# execution latencies for the training form (the paper's labels come from a
+# modified gem5, Sec. 2.4, which is not available).  It is a label source
+# for training data, not part of the simulator.  Latencies by op class
+# (int-ALU, load, store, branch, FP) and memory level (L1 5 and L2 29 cycles
+# from the default O3CPU configuration table; DRAM 200 assumed).
+EXEC_BASE = (1, 1, 1, 1, 4)
+MEM_LATENCY = (5, 29, 200)
+FETCH_WIDTH = 3
+LABEL_MAX = 400
+
+
+def analytic_latencies(fields: dict) -> np.ndarray:
+    """(fetch, execution) latency per instruction, int32 [n][2], in [0, 400].
+
+    Fetch: one cycle per group of FETCH_WIDTH instructions (the first of each
+    group pays it), plus the execution latency of a mispredicted branch just
+    before.  Execution: the instruction starts when its source registers
+    (reg1, reg2) are ready and ends EXEC_BASE[op] (+ MEM_LATENCY[level] for
+    loads and stores) cycles later; it is measured from its fetch; every
+    instruction other than stores and branches writes reg0."""
+    op = fields["op"]
+    regs = fields["regs"]
+    level = fields["level"]
+    mis = fields["mispredict"]
+    n = op.shape[0]
+    out = np.zeros((n, 2), np.int32)
+    done = np.zeros(32, np.int64)
+    t_fetch = 0
+    prev_mis_e = 0
+    for i in range(n):
+        f = (1 if i % FETCH_WIDTH == 0 else 0) + prev_mis_e
+        f = min(f, LABEL_MAX)
+        t_fetch += f
+        o = int(op[i])
+        start = max(t_fetch, int(done[regs[i, 1]]), int(done[regs[i, 2]]))
+        lat = EXEC_BASE[o] + (MEM_LATENCY[int(level[i])] if o in (OP_LOAD, OP_STORE) else 0)
+        end = start + lat
+        e = min(end - t_fetch, LABEL_MAX)
+        if o not in (OP_STORE, OP_BRANCH):
+            done[regs[i, 0]] = end
+        out[i, 0] = f
+        out[i, 1] = e
+        prev_mis_e = e if (o == OP_BRANCH and mis[i]) else 0
+    return out
+
+
 # ------------------------------------------------------------ sub-traces ---
 
 LEN_STREAM = 301
@@ -313,6 +362,12 @@ def net_c3() -> List[Layer]:
     """50 -> conv 64 -> conv 128 -> conv 256 -> FC 512 -> FC 2 over 111 slots."""
     return [Layer(CONV, 50, 64, 1), Layer(CONV, 64, 128, 1), Layer(CONV, 128, 256, 1),
             Layer(FC, 256 * 13, 512, 1), Layer(FC, 512, 2, 0)]
+
+
+def net_c3_hybrid() -> List[Layer]:
+    """The C3 trunk with the training head: per latency type 400 class
+    logits and one regression output, FC 512 -> 2 x 401."""
+    return net_c3()[:-1] + [Layer(FC, 512, 2 * 401, 0)]
 
 
 def workload(name: str) -> Workload:

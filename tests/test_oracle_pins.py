@@ -538,3 +538,114 @@ def test_calibration_maxima_brute_force(oracle_lib):
                                                    torch.from_numpy(bs[1].astype(np.float64)), stride=2))
         want[64:] = np.maximum(want[64:], h2[0].numpy().max(1))
     np.testing.assert_allclose(amax, want, rtol=1e-12)
+
+
+# ------------------------------------------------------------ training ---
+
+def torch_hybrid_loss(z, lat, n_bins=400):
+    per = n_bins + 1
+    total = 0.0
+    for t in range(2):
+        zt = z[:, t * per:(t + 1) * per]
+        target = torch.from_numpy(np.minimum(lat[:, t], n_bins - 1).astype(np.int64))
+        ce = torch.nn.functional.cross_entropy(zt[:, :n_bins], target, reduction="sum")
+        l1 = torch.abs(zt[:, n_bins] - torch.log1p(torch.from_numpy(lat[:, t].astype(np.float64))))
+        total = total + ce + l1.sum()
+    return total / z.shape[0]
+
+
+def small_hybrid_net():
+    return synth.net_small()[:-1] + [synth.Layer(synth.FC, 256, 802, 0)]
+
+
+def train_inputs(layers, D, L, B, seed):
+    ws, bs = synth.init_weights(seed, layers, out_bias=None, out_gain=1.0)
+    rng = np.random.default_rng(seed)
+    x = rng.normal(size=(B, L, D)) * rng.choice([1.0, 5.0], size=(B, L, D))
+    lat = rng.integers(0, 420, size=(B, 2)).astype(np.int32)
+    return ws, bs, x, lat
+
+
+@pytest.mark.parametrize("net", ["small", "c3"])
+def test_training_gradient_matches_torch_autograd(oracle_lib, net):
+    layers = small_hybrid_net() if net == "small" else synth.net_c3_hybrid()
+    D, L = (32, 16) if net == "small" else (50, 111)
+    B = 6
+    ws, bs, x, lat = train_inputs(layers, D, L, B, 3)
+    m = oracle_lib.Model(layers, ws, bs, D, L)
+    got = oracle_lib.train_step(m, x, lat, want_dlogits=True, want_dx=True, threads=3)
+    params = []
+    for w, b in zip(ws, bs):
+        params += [torch.tensor(np.asarray(w, np.float64), requires_grad=True),
+                   torch.tensor(np.asarray(b, np.float64), requires_grad=True)]
+    xt = torch.tensor(x, requires_grad=True)
+    h = xt.transpose(1, 2)
+    for i, ly in enumerate(layers):
+        w, b = params[2 * i], params[2 * i + 1]
+        if ly.kind == synth.CONV:
+            h = torch.nn.functional.conv1d(h, w, b, stride=2)
+        else:
+            h = torch.nn.functional.linear(h.reshape(h.shape[0], -1), w, b)
+        if ly.relu:
+            h = torch.relu(h)
+    h.retain_grad()
+    loss = torch_hybrid_loss(h, lat)
+    loss.backward()
+    assert abs(got["loss"] - loss.item()) <= 1e-12 * abs(loss.item())
+    ref = np.concatenate([p.grad.numpy().ravel() for p in params])
+    np.testing.assert_allclose(got["dparams"], ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_allclose(got["dlogits"], h.grad.numpy(), rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(got["dx"], xt.grad.numpy(), rtol=1e-9,
+                               atol=1e-12 * np.abs(xt.grad.numpy()).max())
+
+
+def test_training_gradient_finite_differences(oracle_lib):
+    """Central differences of the oracle's own loss, away from ReLU and L1
+    kinks (a sample of parameters of every layer)."""
+    layers = small_hybrid_net()
+    B = 5
+    ws, bs, x, lat = train_inputs(layers, 32, 16, B, 5)
+    m = oracle_lib.Model(layers, ws, bs, 32, 16)
+    g = oracle_lib.train_step(m, x, lat, threads=2)["dparams"]
+    flat = oracle_lib.flat_params(ws, bs).astype(np.float64)
+    rng = np.random.default_rng(0)
+    idx = rng.choice(flat.size, 40, replace=False)
+    shapes = synth.layer_param_shapes(layers)
+
+    def loss_at(v):
+        parts, off = [], 0
+        ws2, bs2 = [], []
+        for ws_shape, b_shape in shapes:
+            n = int(np.prod(ws_shape))
+            ws2.append(v[off:off + n].reshape(ws_shape)); off += n
+            bs2.append(v[off:off + b_shape[0]]); off += b_shape[0]
+        # the oracle holds float32 parameters: evaluate with exact float64
+        # perturbations through the library forward instead
+        h = torch.from_numpy(x).transpose(1, 2)
+        for ly, w, b in zip(layers, ws2, bs2):
+            w, b = torch.from_numpy(w), torch.from_numpy(b)
+            h = (torch.nn.functional.conv1d(h, w, b, stride=2) if ly.kind == synth.CONV
+                 else torch.nn.functional.linear(h.reshape(h.shape[0], -1), w, b))
+            if ly.relu:
+                h = torch.relu(h)
+        return oracle_lib.hybrid_loss(h.numpy(), lat)
+
+    for i in idx:
+        hstep = 1e-6 * max(1.0, abs(flat[i]))
+        vp, vm = flat.copy(), flat.copy()
+        vp[i] += hstep
+        vm[i] -= hstep
+        fd = (loss_at(vp) - loss_at(vm)) / (2 * hstep)
+        assert abs(fd - g[i]) <= 1e-5 * max(1e-3, abs(g[i])), (i, fd, g[i])
+
+
+def test_uniform_logits_cross_entropy_is_log_bins(oracle_lib):
+    """Equal class logits: CE = ln 400 per type; L1 = |reg - log1p(lat)|."""
+    B = 3
+    z = np.zeros((B, 802))
+    lat = np.array([[0, 5], [399, 1000], [7, 0]], np.int32)
+    z[:, 400] = 0.25
+    z[:, 801] = -1.0
+    want = np.mean([2 * np.log(400) + abs(0.25 - np.log1p(a)) + abs(-1.0 - np.log1p(b))
+                    for a, b in lat])
+    assert abs(oracle_lib.hybrid_loss(z, lat) - want) < 1e-12

@@ -59,3 +59,25 @@ def test_torch_code_generator_matches_numpy():
     a = synth.trace_codes(1, 300_000, 12_345, 300_000)
     b = synth.trace_codes_torch(1, 12_345, 300_000).numpy().view(np.uint32)
     np.testing.assert_array_equal(a, b)
+
+
+def test_analytic_labeller_hand_worked():
+    """Tiny traces worked by hand (builder-defined pipeline model)."""
+    def fields(ops, regs, levels, mis):
+        return {"op": np.array(ops), "regs": np.array(regs), "level": np.array(levels),
+                "mispredict": np.array(mis)}
+    # int, int (depends on the first), load L2, FP
+    f = fields([0, 0, 1, 4], [[1, 0, 0], [2, 1, 0], [3, 0, 0], [4, 3, 2]],
+               [0, 0, 1, 0], [0, 0, 0, 0])
+    lat = synth.analytic_latencies(f)
+    # fetch: groups of 3 -> 1, 0, 0, 1 ; times 1, 1, 1, 2
+    np.testing.assert_array_equal(lat[:, 0], [1, 0, 0, 1])
+    # i0: start 1, end 2, E 1; i1 waits for r1 (2): end 3, E 2; i2 load L2: 1+29 = 30, end 31,
+    # E 30; i3 FP waits r3 (31) and r2 (3): end 35, E 33
+    np.testing.assert_array_equal(lat[:, 1], [1, 2, 30, 33])
+    # a mispredicted branch adds its execution latency to the next fetch
+    g = fields([3, 0], [[0, 0, 0], [0, 0, 0]], [0, 0], [1, 0])
+    lat = synth.analytic_latencies(g)
+    np.testing.assert_array_equal(lat, [[1, 1], [1, 1]])
+    h = synth.analytic_latencies(synth.trace_fields(1, 0, 5000))
+    assert h.min() >= 0 and h.max() <= 400 and h[:, 1].mean() > 1
