@@ -101,7 +101,9 @@ typedef struct {
                             codes.  Borrowed: must stay valid and unchanged
                             for the context's lifetime. */
   int32_t feat_dtype;    /* sim_feat_dtype */
-  int32_t n_sub;         /* number of sub-traces K >= 1 */
+  int32_t n_sub;         /* number of sub-traces K >= 1; 0 with feat NULL makes a
+                            predictor-only context (predictor_fwd/_bwd, no
+                            simulation) */
   int64_t n_instr;       /* rows in feat, < 2^31 */
   const int64_t* start;  /* HOST [n_sub] */
   const int64_t* len;    /* HOST [n_sub], each >= 1 */
@@ -190,9 +192,56 @@ SIMNET_API int sim_calibrate(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
 SIMNET_API int sim_act_scales(const sim_ctx* ctx, float* out, int32_t n);
 
 /* Predictor forward on explicit windows (Sec. 2.3): x is DEVICE
- * [B][n_slot][n_feat] float32, logits DEVICE [B][n_out] float32.
- * save_or_null is reserved for the training path and must be NULL. */
+ * [B][n_slot][n_feat] float32, logits DEVICE [B][n_out] float32 (n_out = 2
+ * for the regression head).  save_or_null must be NULL except for the
+ * training head, where it is required.
+ *
+ * Training head (Sec. 2.3's hybrid output, Sec. 4's training set-up): a
+ * 111x50 context loaded with the layer list conv 50->64, conv 64->128,
+ * conv 128->256 (ReLU each), fc 3328->512 (ReLU), fc 512->802 (no ReLU).
+ * The 802 logits of a window are, per latency o in (fetch, execution), 400
+ * class logits at [o*401, o*401+400) and one regression output at o*401+400.
+ * FP32 and BF16 forms (BF16: the window, the weights and every hidden
+ * activation are rounded to BF16, products accumulate in FP32).  For this
+ * head sim_load_weights keeps the parameters on the device and does not
+ * check them for NaN/Inf.  save is a
+ * DEVICE buffer of predictor_save_bytes(ctx, B) bytes that receives the
+ * activations the backward pass needs. */
 SIMNET_API int predictor_fwd(sim_ctx* ctx, const void* x, int64_t B, float* logits, void* save_or_null);
+
+/* Bytes of the save buffer predictor_fwd/predictor_bwd need for B windows
+ * (training head only; -1 otherwise). */
+SIMNET_API int64_t predictor_save_bytes(const sim_ctx* ctx, int64_t B);
+
+/* Hybrid loss of the training head (Sec. 2.3, Sec. 4): for each window b and
+ * latency o (fetch, execution) with integer label y = labels[b][o] >= 0
+ * (DEVICE int32 [B][2]): cross-entropy over the 400 class logits with target
+ * class min(y, 399) (the last class collects every latency >= 399), plus
+ * |r - log(1 + y)| on the regression output r.  *loss (DEVICE, one float)
+ * receives the mean over windows of the sum of the four terms; dlogits
+ * (DEVICE [B][802]) its gradient (sign(0) = 0 for the L1 term). */
+SIMNET_API int sim_loss(sim_ctx* ctx, const float* logits, const int32_t* labels, int64_t B,
+                        float* loss, float* dlogits);
+
+/* Backward of predictor_fwd (training head), the chain rule through the
+ * head, the hidden layer, the three convolutions and their ReLUs: x and save
+ * as passed to the forward, dlogits DEVICE [B][802].  dparams (DEVICE,
+ * float32) has the layout of sim_load_weights's params and receives the
+ * parameter gradients (accumulate != 0 adds to what it holds).  dx (DEVICE
+ * [B][111][50] float32, or NULL) receives the gradient with respect to the
+ * window, zero in the slots no output depends on.  Gradients are computed
+ * with the current parameters, in FP32 (BF16 form: from the BF16 saved
+ * activations). */
+SIMNET_API int predictor_bwd(sim_ctx* ctx, const void* x, const void* save, const float* dlogits,
+                             int64_t B, float* dx, float* dparams, int32_t accumulate);
+
+/* One Adam step (Kingma and Ba, bias-corrected) on n DEVICE float32
+ * parameters, in place, with moments m and v (DEVICE, n floats each, zero
+ * before step 1); step counts from 1.  To train a context's predictor: keep
+ * the master parameters in a device buffer, update them here, then
+ * sim_load_weights(..., on_device = 1) to re-lay them out for the kernels. */
+SIMNET_API int sim_adam(sim_ctx* ctx, float* params, const float* grads, float* m, float* v,
+                        int64_t n, float lr, float beta1, float beta2, float eps, int32_t step);
 
 SIMNET_API void sim_destroy(sim_ctx* ctx);
 SIMNET_API const char* sim_last_error(const sim_ctx* ctx);

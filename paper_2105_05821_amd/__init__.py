@@ -27,7 +27,7 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVIC
 
 EXPORTED = ("sim_validate_config", "sim_init", "sim_load_weights", "sim_step", "sim_run",
             "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
-            "predictor_fwd",
+            "predictor_fwd", "predictor_save_bytes", "sim_loss", "predictor_bwd", "sim_adam",
             "sim_destroy", "sim_last_error")
 
 
@@ -80,12 +80,18 @@ def lib():
         L.sim_calibrate.argtypes = [P, C.c_int32, C.c_int32, P]
         L.sim_act_scales.argtypes = [P, P, C.c_int32]
         L.sim_set_graph.argtypes = [P, C.c_int32]
+        L.predictor_save_bytes.argtypes = [P, C.c_int64]
+        L.sim_loss.argtypes = [P, P, P, C.c_int64, P, P]
+        L.predictor_bwd.argtypes = [P, P, P, P, C.c_int64, P, P, C.c_int32]
+        L.sim_adam.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float,
+                               C.c_float, C.c_int32]
         L.sim_destroy.argtypes = [P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = [P]
         L.sim_last_error.restype = C.c_char_p
         for n in EXPORTED[:-2]:
             getattr(L, n).restype = C.c_int
+        L.predictor_save_bytes.restype = C.c_int64
         _lib = L
     return _lib
 
@@ -257,3 +263,165 @@ def flat_params(ws, bs) -> np.ndarray:
         parts.append(np.asarray(w, np.float32).ravel())
         parts.append(np.asarray(b, np.float32).ravel())
     return np.ascontiguousarray(np.concatenate(parts), np.float32)
+
+
+# ----------------------------------------------------------------- training ---
+
+N_BINS = 400
+TRAIN_OUT = 2 * (N_BINS + 1)
+
+
+class Predictor:
+    """A predictor-only context for the training head (C3 trunk + FC 512 ->
+    802): forward with saved activations, hybrid loss, backward and Adam, all
+    in the library's kernels.  Windows are float32 [B][111][50] device
+    tensors; labels int32 [B][2]."""
+
+    def __init__(self, layers, prec: int = SIM_FP32, stream=None, n_feat: int = 50,
+                 n_slot: int = 111):
+        import torch
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.cfg = make_config(n_feat, n_slot, (-1, -1, -1), prec=prec,
+                               stream=self.stream.cuda_stream)
+        z64 = np.zeros(0, np.int64)
+        self.trace = make_trace(None, 0, z64, z64, np.zeros(0, np.int32))
+        h = C.c_void_p()
+        rc = lib().sim_init(C.byref(self.cfg), C.byref(self.trace), C.byref(h))
+        if rc != SIM_OK:
+            raise SimError("sim_init", rc)
+        self.ctx = h
+        self.layers = list(layers)
+        self.n_slot, self.n_feat = n_slot, n_feat
+
+    _check = Simulator._check
+    load_weights = Simulator.load_weights
+    close = Simulator.close
+    __del__ = Simulator.__del__
+
+    def save_bytes(self, B: int) -> int:
+        n = lib().predictor_save_bytes(self.ctx, B)
+        if n < 0:
+            raise SimError("predictor_save_bytes", SIM_ESTATE, "weights of the training head "
+                           "not loaded")
+        return int(n)
+
+    def forward(self, x):
+        """Logits [B][802] and the save buffer for backward."""
+        import torch
+        _check_windows(x, self.n_slot, self.n_feat)
+        B = x.shape[0]
+        logits = torch.empty((B, TRAIN_OUT), dtype=torch.float32, device=x.device)
+        save = torch.empty(max(1, self.save_bytes(B)), dtype=torch.uint8, device=x.device)
+        self._check("predictor_fwd", lib().predictor_fwd(self.ctx, x.data_ptr(), B,
+                                                         logits.data_ptr(), save.data_ptr()))
+        return logits, save
+
+    def loss(self, logits, labels):
+        """Mean hybrid loss (device scalar) and its gradient w.r.t. logits."""
+        import torch
+        if labels.dtype != torch.int32 or not labels.is_contiguous():
+            raise ValueError("labels must be contiguous int32 [B][2]")
+        B = logits.shape[0]
+        loss = torch.empty((), dtype=torch.float32, device=logits.device)
+        dz = torch.empty_like(logits)
+        self._check("sim_loss", lib().sim_loss(self.ctx, logits.data_ptr(), labels.data_ptr(), B,
+                                               loss.data_ptr(), dz.data_ptr()))
+        return loss, dz
+
+    def backward(self, x, save, dlogits, dparams, want_dx: bool = False,
+                 accumulate: bool = False):
+        import torch
+        dlogits = dlogits.contiguous().float()
+        B = x.shape[0]
+        dx = torch.empty_like(x) if want_dx else None
+        self._check("predictor_bwd",
+                    lib().predictor_bwd(self.ctx, x.data_ptr(), save.data_ptr(),
+                                        dlogits.data_ptr(), B, _ptr(dx), dparams.data_ptr(),
+                                        int(accumulate)))
+        return dx
+
+    def adam(self, params, grads, m, v, step: int, lr: float = 1e-3, betas=(0.9, 0.999),
+             eps: float = 1e-8):
+        self._check("sim_adam", lib().sim_adam(self.ctx, params.data_ptr(), grads.data_ptr(),
+                                               m.data_ptr(), v.data_ptr(), params.numel(), lr,
+                                               betas[0], betas[1], eps, step))
+
+
+def _check_windows(x, n_slot, n_feat):
+    import torch
+    if (not x.is_cuda or x.dtype != torch.float32 or not x.is_contiguous() or x.dim() != 3
+            or x.shape[1] != n_slot or x.shape[2] != n_feat):
+        raise ValueError(f"x must be a contiguous float32 device tensor [B][{n_slot}][{n_feat}]")
+
+
+def _autograd():
+    import torch
+
+    class PredictorFunction(torch.autograd.Function):
+        """logits = predictor(x; params) through the library's forward and
+        backward kernels.  params is the flat PyTorch-order float32 device
+        vector; it is (re)loaded into the context on every forward."""
+
+        @staticmethod
+        def forward(ctx, x, params, pred):
+            x = x.contiguous()
+            pred.load_weights(pred.layers, params.detach().contiguous())
+            logits, save = pred.forward(x)
+            ctx.pred = pred
+            ctx.save_for_backward(x, save)
+            return logits
+
+        @staticmethod
+        def backward(ctx, dlogits):
+            x, save = ctx.saved_tensors
+            dparams = torch.empty(ctx.pred.n_params, dtype=torch.float32, device=x.device)
+            dx = ctx.pred.backward(x, save, dlogits, dparams, want_dx=ctx.needs_input_grad[0])
+            return dx, dparams, None
+
+    return PredictorFunction
+
+
+_fn = None
+
+
+def predictor_apply(x, params, pred: Predictor):
+    """Differentiable predictor forward (torch.autograd)."""
+    global _fn
+    if _fn is None:
+        _fn = _autograd()
+    pred.n_params = params.numel()
+    return _fn.apply(x, params, pred)
+
+
+class Trainer:
+    """Training loop of the predictor on windows and labelled latencies:
+    forward, hybrid loss, backward and Adam, every step in the library's
+    kernels, parameters resident on the device."""
+
+    def __init__(self, layers, params, prec: int = SIM_FP32, lr: float = 1e-3,
+                 betas=(0.9, 0.999), eps: float = 1e-8):
+        import torch
+        self.pred = Predictor(layers, prec)
+        p = torch.as_tensor(np.ascontiguousarray(params, np.float32))
+        self.params = p.cuda().contiguous()
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.t = 0
+        self.lr, self.betas, self.eps = lr, betas, eps
+        self.pred.load_weights(layers, self.params)
+
+    def step(self, x, labels):
+        """One optimisation step on a batch; returns the loss (device scalar)
+        measured before the update."""
+        logits, save = self.pred.forward(x)
+        loss, dz = self.pred.loss(logits, labels)
+        self.pred.backward(x, save, dz, self.grads)
+        self.t += 1
+        self.pred.adam(self.params, self.grads, self.m, self.v, self.t, self.lr, self.betas,
+                       self.eps)
+        self.pred.load_weights(self.pred.layers, self.params)
+        return loss
+
+    def close(self):
+        self.pred.close()

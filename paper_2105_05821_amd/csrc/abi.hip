@@ -15,6 +15,25 @@
 
 using namespace simnet;
 
+// Training form (net 2: C3 trunk, hidden layer kept, head FC 512 -> 802):
+// FP32 master parameters, index maps for the device-side re-layouts, the
+// packed trunk weights in the form's precision, FP32 permuted copies used by
+// the backward products, and the backward workspace.
+struct TrainState {
+  float* master = nullptr;
+  int32_t* maps = nullptr;
+  size_t map_pack[4] = {0}, n_pack[4] = {0};
+  size_t map_perm[5] = {0}, n_perm[5] = {0};  // w1c, w2c, w3, w1, w2t
+  void* packed = nullptr;
+  size_t pack_off[4] = {0};
+  float* perm = nullptr;
+  size_t perm_off[5] = {0};
+  float* work = nullptr;
+  int64_t work_B = 0;
+  size_t woff[5] = {0}, boff[5] = {0};
+  size_t n_params = 0;
+};
+
 struct sim_ctx {
   sim_config cfg;
   int32_t n_sub = 0;
@@ -43,6 +62,8 @@ struct sim_ctx {
   int32_t graph_mode = -1;
   const int32_t* graph_table = nullptr;
   float* graph_logits = nullptr;
+  bool has_trace = true;
+  TrainState tr;
   int64_t* dev_total = nullptr;
   DevState st{};
   DevWeights w{};
@@ -93,6 +114,7 @@ int check_cfg(const sim_config* cfg, const sim_trace* tr, std::string* why) {
   if (cfg->lat_max < 1) return bad("lat_max must be >= 1");
   if (cfg->prec < SIM_FP32 || cfg->prec > SIM_FP8E4M3) return bad("unknown precision");
   if (cfg->reserved != 0) return bad("reserved field must be 0");
+  if (tr->n_sub == 0 && !tr->feat) return SIM_OK;  // predictor-only context (no trace)
   if (!tr->feat) return bad("feat is NULL");
   if (tr->feat_dtype != SIM_FEAT_F32 && tr->feat_dtype != SIM_FEAT_CODE32)
     return bad("unknown feat_dtype");
@@ -406,6 +428,218 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
   return SIM_OK;
 }
 
+// ------------------------------------------------------------ training ---
+
+constexpr int TRAIN_BINS = 400, TRAIN_OUT = 2 * (TRAIN_BINS + 1);
+
+static bool train_layers_match(const sim_layer* l, int32_t n) {
+  const int32_t want[5][4] = {{0, 50, 64, 1}, {0, 64, 128, 1}, {0, 128, 256, 1},
+                              {1, 3328, 512, 1}, {1, 512, TRAIN_OUT, 0}};
+  if (n != 5) return false;
+  for (int i = 0; i < 5; ++i)
+    if (l[i].kind != want[i][0] || l[i].c_in != want[i][1] || l[i].c_out != want[i][2] ||
+        (l[i].relu != 0) != (want[i][3] != 0))
+      return false;
+  return true;
+}
+
+// Index maps (source parameter, -1 for padding) of every re-layout the
+// training form uses; built once per context.
+static void build_train_maps(sim_ctx* c, std::vector<int32_t>* maps) {
+  TrainState& T = c->tr;
+  const int prec = c->cfg.prec;
+  const int chs[4] = {50, 64, 128, 256};
+  size_t off = 0;
+  const int douts[5] = {64, 128, 256, 512, TRAIN_OUT};
+  const int dins[5] = {50 * 2, 64 * 2, 128 * 2, 3328, 512};
+  for (int l = 0; l < 5; ++l) {
+    T.woff[l] = off;
+    off += (size_t)douts[l] * dins[l];
+    T.boff[l] = off;
+    off += douts[l];
+  }
+  T.n_params = off;
+  auto packed = [&](int K, int N, auto&& idx) {  // same order as the kernels' B fragments
+    const int KG = kgroup(prec), KGS = K / KG, NTL = N / 16, E = KG / 4;
+    for (int kg = 0; kg < KGS; ++kg)
+      for (int nt = 0; nt < NTL; ++nt)
+        for (int lane = 0; lane < 64; ++lane)
+          for (int e = 0; e < E; ++e)
+            maps->push_back(idx(kg * KG + E * (lane / 16) + e, nt * 16 + lane % 16));
+  };
+  const int DP = padded_feat(50, prec);
+  const int chp[3] = {DP, 64, 128};
+  for (int l = 0; l < 3; ++l) {
+    T.map_pack[l] = maps->size();
+    const int cin = chs[l];
+    packed(2 * chp[l], chs[l + 1], [&](int k, int n) {
+      const int t = k / chp[l], ch = k % chp[l];
+      return ch < cin ? (int32_t)(T.woff[l] + ((size_t)n * cin + ch) * 2 + t) : -1;
+    });
+    T.n_pack[l] = maps->size() - T.map_pack[l];
+  }
+  T.map_pack[3] = maps->size();
+  for (int j = 0; j < 13; ++j)
+    packed(256, 512, [&](int ch, int n) { return (int32_t)(T.woff[3] + (size_t)n * 3328 + ch * 13 + j); });
+  T.n_pack[3] = maps->size() - T.map_pack[3];
+  // FP32 row-major copies for the backward: conv l as [c_out][2*c_in] with
+  // column t*c_in + c, the hidden layer with column p*256 + c, the head
+  // transposed [512][802]
+  for (int l = 0; l < 3; ++l) {
+    T.map_perm[l] = maps->size();
+    const int ci = chs[l], co = chs[l + 1];
+    for (int o = 0; o < co; ++o)
+      for (int k = 0; k < 2 * ci; ++k)
+        maps->push_back((int32_t)(T.woff[l] + ((size_t)o * ci + k % ci) * 2 + k / ci));
+    T.n_perm[l] = maps->size() - T.map_perm[l];
+  }
+  T.map_perm[3] = maps->size();
+  for (int o = 0; o < 512; ++o)
+    for (int k = 0; k < 3328; ++k)
+      maps->push_back((int32_t)(T.woff[3] + (size_t)o * 3328 + (k % 256) * 13 + k / 256));
+  T.n_perm[3] = maps->size() - T.map_perm[3];
+  T.map_perm[4] = maps->size();
+  for (int j = 0; j < 512; ++j)
+    for (int o = 0; o < TRAIN_OUT; ++o) maps->push_back((int32_t)(T.woff[4] + (size_t)o * 512 + j));
+  T.n_perm[4] = maps->size() - T.map_perm[4];
+}
+
+// Re-lay-out the master parameters on the device (packed trunk weights in
+// the form's precision, FP32 permuted copies).
+static int relayout_train(sim_ctx* c) {
+  TrainState& T = c->tr;
+  const int bf16 = c->cfg.prec == SIM_BF16;
+  hipError_t e = hipSuccess;
+  for (int l = 0; l < 4 && e == hipSuccess; ++l)
+    e = launch_map_gather(T.master, T.maps + T.map_pack[l], (int64_t)T.n_pack[l],
+                          static_cast<char*>(T.packed) + T.pack_off[l], bf16, c->stream);
+  // the head's transposed copy is the forward's operand: in the form's
+  // precision; the others serve the backward products in FP32
+  for (int l = 0; l < 5 && e == hipSuccess; ++l)
+    e = launch_map_gather(T.master, T.maps + T.map_perm[l], (int64_t)T.n_perm[l],
+                          T.perm + T.perm_off[l], l == 4 ? bf16 : 0, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "training re-layout");
+  DevWeights& w = c->w;
+  w = DevWeights{};
+  for (int l = 0; l < 3; ++l) {
+    w.conv_w[l] = static_cast<char*>(T.packed) + T.pack_off[l];
+    w.conv_b[l] = T.master + T.boff[l];
+  }
+  w.hid_w = static_cast<char*>(T.packed) + T.pack_off[3];
+  w.hid_b = T.master + T.boff[3];
+  return SIM_OK;
+}
+
+static int load_train_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers,
+                              const float* params, int32_t on_device) {
+  TrainState& T = c->tr;
+  hipError_t e = hipSuccess;
+  if (!T.maps) {
+    std::vector<int32_t> maps;
+    build_train_maps(c, &maps);
+    e = hipMalloc(&T.maps, maps.size() * 4);
+    if (e == hipSuccess) e = hipMemcpy(T.maps, maps.data(), maps.size() * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&T.master, T.n_params * 4);
+    size_t pb = 0;
+    for (int l = 0; l < 4; ++l) {
+      T.pack_off[l] = pb;
+      pb += (T.n_pack[l] * elem_size(c->cfg.prec) + 255) / 256 * 256;
+    }
+    if (e == hipSuccess) e = hipMalloc(&T.packed, pb);
+    size_t qf = 0;
+    for (int l = 0; l < 5; ++l) {
+      T.perm_off[l] = qf;
+      qf += (T.n_perm[l] + 63) / 64 * 64;
+    }
+    if (e == hipSuccess) e = hipMalloc(&T.perm, qf * 4);
+    if (e != hipSuccess) return hip_fail(c, e, "training buffers");
+  }
+  e = hipMemcpyAsync(T.master, params, T.n_params * 4,
+                     on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "copy parameters");
+  if (!on_device)  // host parameters must stay valid until copied
+    if ((e = hipStreamSynchronize(c->stream)) != hipSuccess) return hip_fail(c, e, "copy parameters");
+  uint32_t relu = 0;
+  for (int32_t i = 0; i < n_layers; ++i)
+    if (layers[i].relu) relu |= 1u << i;
+  c->relu = relu;
+  int rc = relayout_train(c);
+  if (rc != SIM_OK) return rc;
+  c->weights = true;
+  return SIM_OK;
+}
+
+// Backward workspace (floats): [0] per-window losses, [1] dH [B][512],
+// [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] a
+// weight-gradient staging matrix (largest [512][3328]), [6] column sums.
+static size_t train_work_off(int64_t B, int part) {
+  const size_t sizes[7] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
+                           (size_t)B * 3328, (size_t)512 * 3328, colsum_workspace(TRAIN_OUT) / 4};
+  size_t off = 0;
+  for (int i = 0; i < part; ++i) off += (sizes[i] + 63) / 64 * 64;
+  return off;
+}
+
+static int ensure_train_work(sim_ctx* c, int64_t B) {
+  TrainState& T = c->tr;
+  if (T.work && T.work_B >= B) return SIM_OK;
+  if (T.work) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(T.work);
+    T.work = nullptr;
+  }
+  hipError_t e = hipMalloc(&T.work, train_work_off(B, 7) * 4);
+  if (e != hipSuccess) return hip_fail(c, e, "training workspace");
+  T.work_B = B;
+  return SIM_OK;
+}
+
+// Per-window activation bytes kept by the training forward.
+static int64_t save_bytes_per_window(int prec) {
+  return (int64_t)(52 * 64 + 26 * 128 + 13 * 256 + 512) * (int64_t)elem_size(prec);
+}
+
+static SaveBlock save_block(const sim_ctx* c, void* save, int64_t B) {
+  const size_t es = elem_size(c->cfg.prec);
+  char* p = static_cast<char*>(save);
+  SaveBlock sb;
+  sb.a1 = p;
+  sb.a2 = p + (size_t)B * 52 * 64 * es;
+  sb.a3 = p + (size_t)B * (52 * 64 + 26 * 128) * es;
+  sb.h = p + (size_t)B * (52 * 64 + 26 * 128 + 13 * 256) * es;
+  return sb;
+}
+
+static GemmOperand opnd(const void* p, int bf16, int64_t rs, int64_t cs,
+                        int64_t grp = (int64_t)1 << 62, int64_t gs = 0) {
+  GemmOperand o;
+  o.p = p;
+  o.bf16 = bf16;
+  o.rs = rs;
+  o.cs = cs;
+  o.grp = grp;
+  o.gs = gs;
+  return o;
+}
+
+static GemmArgs gemm(GemmOperand A, GemmOperand B, float* C, int64_t ldc, int64_t M, int64_t N,
+                     int64_t K, int beta) {
+  GemmArgs g{};
+  g.A = A;
+  g.B = B;
+  g.mask = opnd(nullptr, 0, 0, 0);
+  g.C = C;
+  g.ldc = ldc;
+  g.cgrp = (int64_t)1 << 62;
+  g.cgs = 0;
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.bias = nullptr;
+  g.beta = beta;
+  return g;
+}
+
 extern "C" {
 
 int sim_validate_config(const sim_config* cfg, const sim_trace* trace) {
@@ -433,6 +667,12 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   }
   c->cfg = *cfg;
   c->C = cfg->n_slot - 1;
+  c->stream = static_cast<hipStream_t>(cfg->stream);
+  if (tr->n_sub == 0) {  // predictor-only: forward/backward on explicit windows
+    c->has_trace = false;
+    *out = c;
+    return SIM_OK;
+  }
   c->n_sub = tr->n_sub;
   c->n_instr = tr->n_instr;
   if (tr->feat_dtype == SIM_FEAT_CODE32)
@@ -545,6 +785,12 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
                      int32_t on_device) {
   if (!c) return SIM_EINVAL;
   if (!layers || n_layers < 1 || !params) return fail(c, SIM_EINVAL, "null layers or params");
+  if (c->net != 0 && train_layers_match(layers, n_layers)) {
+    if (c->cfg.prec == SIM_FP8E4M3) return fail(c, SIM_EUNSUPPORTED, "no FP8 training form");
+    c->net = 2;
+    return load_train_weights(c, layers, n_layers, params, on_device);
+  }
+  if (c->net == 2) c->net = 1;
   const bool ok = c->net == 0 ? layers_match<NetSmall>(layers, n_layers)
                               : layers_match<NetC3>(layers, n_layers);
   if (!ok) return fail(c, SIM_EUNSUPPORTED, "no kernel for this layer list");
@@ -582,6 +828,7 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
 
 int sim_reset(sim_ctx* c) {
   if (!c) return SIM_EINVAL;
+  if (!c->has_trace) return SIM_OK;
   hipError_t e = launch_reset(c->st, c->n_sub, c->C, c->n_wg * MT, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reset");
   c->completed = false;
@@ -591,6 +838,8 @@ int sim_reset(sim_ctx* c) {
 
 int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* table) {
   if (!c) return SIM_EINVAL;
+  if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
+  if (c->net == 2) return fail(c, SIM_EUNSUPPORTED, "no FP8 training form");
   if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
   if (c->cfg.prec == SIM_BF16) return fail(c, SIM_EUNSUPPORTED, "calibration runs FP32 weights");
   if (n_steps < 1) return fail(c, SIM_EINVAL, "n_steps < 1");
@@ -694,6 +943,8 @@ static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
 }
 
 static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t* table) {
+  if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
+  if (c->net == 2) return fail(c, SIM_EUNSUPPORTED, "the training head does not drive the simulation");
   if (mode < SIM_LAT_PREDICT || mode > SIM_LAT_SHADOW) return fail(c, SIM_EINVAL, "bad lat_mode");
   if (mode != SIM_LAT_PREDICT && !table) return fail(c, SIM_EINVAL, "lat_table required");
   if (mode != SIM_LAT_INJECT && !c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
@@ -777,13 +1028,135 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
   if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
   if (c->cfg.prec == SIM_FP8E4M3 && !c->calibrated)
     return fail(c, SIM_ESTATE, "FP8 form needs sim_calibrate first");
-  if (save_or_null) return fail(c, SIM_EUNSUPPORTED, "save buffer not supported");
   if (B < 0 || (B > 0 && (!x || !logits))) return fail(c, SIM_EINVAL, "bad batch arguments");
   if (B == 0) return SIM_OK;
   if ((B + MT - 1) / MT > INT32_MAX) return fail(c, SIM_EINVAL, "batch too large");
+  if (c->net == 2) {
+    if (!save_or_null) return fail(c, SIM_EINVAL, "the training form needs a save buffer");
+    const SaveBlock sb = save_block(c, save_or_null, B);
+    hipError_t e = launch_forward_save(c->cfg.prec, c->w, c->relu, static_cast<const float*>(x),
+                                       B, sb, c->stream);
+    TrainState& T = c->tr;
+    const int bf = c->cfg.prec == SIM_BF16;
+    GemmArgs g = gemm(opnd(sb.h, bf, 512, 1), opnd(T.perm + T.perm_off[4], bf, TRAIN_OUT, 1),
+                      logits, TRAIN_OUT, B, TRAIN_OUT, 512, 0);
+    g.bias = T.master + T.boff[4];
+    if (e == hipSuccess) e = launch_gemm(g, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "training forward");
+    return SIM_OK;
+  }
+  if (save_or_null) return fail(c, SIM_EUNSUPPORTED, "save buffer not supported");
   hipError_t e = launch_forward(c->net, c->cfg.prec, c->w, c->relu, static_cast<const float*>(x),
                                 B, logits, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "forward launch");
+  return SIM_OK;
+}
+
+int64_t predictor_save_bytes(const sim_ctx* c, int64_t B) {
+  if (!c || c->net != 2 || B < 0) return -1;
+  return B * save_bytes_per_window(c->cfg.prec);
+}
+
+int sim_loss(sim_ctx* c, const float* logits, const int32_t* labels, int64_t B, float* loss,
+             float* dlogits) {
+  if (!c) return SIM_EINVAL;
+  if (c->net != 2) return fail(c, SIM_EUNSUPPORTED, "the loss needs the training head");
+  if (B < 1 || !logits || !labels || !loss || !dlogits) return fail(c, SIM_EINVAL, "bad arguments");
+  int rc = ensure_train_work(c, B);
+  if (rc != SIM_OK) return rc;
+  hipError_t e = launch_loss(logits, labels, B, TRAIN_BINS, c->tr.work, loss, dlogits, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "loss");
+  return SIM_OK;
+}
+
+int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlogits, int64_t B,
+                  float* dx, float* dparams, int32_t accumulate) {
+  if (!c) return SIM_EINVAL;
+  if (c->net != 2) return fail(c, SIM_EUNSUPPORTED, "the backward pass needs the training head");
+  if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
+  if (B < 1 || !x || !save || !dlogits || !dparams) return fail(c, SIM_EINVAL, "bad arguments");
+  int rc = ensure_train_work(c, B);
+  if (rc != SIM_OK) return rc;
+  TrainState& T = c->tr;
+  const int bf = c->cfg.prec == SIM_BF16;
+  const int beta = accumulate ? 1 : 0;
+  const SaveBlock sb = save_block(c, const_cast<void*>(save), B);
+  float* W = T.work;
+  float* dH = W + train_work_off(B, 1);
+  float* dY3 = W + train_work_off(B, 2);
+  float* dY2 = W + train_work_off(B, 3);
+  float* dY1 = W + train_work_off(B, 4);
+  float* dWt = W + train_work_off(B, 5);
+  float* csw = W + train_work_off(B, 6);
+  const float* P = T.master;
+  hipError_t e = hipSuccess;
+  auto run = [&](const GemmArgs& g) {
+    if (e == hipSuccess) e = launch_gemm(g, c->stream);
+  };
+  auto colsum = [&](const float* y, int64_t M, int64_t N, float* out) {
+    if (e == hipSuccess) e = launch_colsum(y, M, N, N, out, beta, csw, c->stream);
+  };
+  auto scatter = [&](int l, float* dst) {
+    if (e == hipSuccess)
+      e = launch_map_scatter(dWt, T.maps + T.map_perm[l], (int64_t)T.n_perm[l], dst, beta,
+                             c->stream);
+  };
+  // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H
+  GemmArgs g = gemm(opnd(dlogits, 0, TRAIN_OUT, 1), opnd(P + T.woff[4], 0, 512, 1), dH, 512, B,
+                    512, TRAIN_OUT, 0);
+  g.mask = opnd(sb.h, bf, 512, 1);
+  run(g);
+  run(gemm(opnd(dlogits, 0, 1, TRAIN_OUT), opnd(sb.h, bf, 512, 1), dparams + T.woff[4], 512,
+           TRAIN_OUT, 512, B, beta));
+  colsum(dlogits, B, TRAIN_OUT, dparams + T.boff[4]);
+  // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU
+  g = gemm(opnd(dH, 0, 512, 1), opnd(T.perm + T.perm_off[3], 0, 3328, 1), dY3, 3328, B, 3328,
+           512, 0);
+  g.mask = opnd(sb.a3, bf, 3328, 1);
+  run(g);
+  run(gemm(opnd(dH, 0, 1, 512), opnd(sb.a3, bf, 3328, 1), dWt, 3328, 512, 3328, B, 0));
+  scatter(3, dparams);
+  colsum(dH, B, 512, dparams + T.boff[3]);
+  // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
+  g = gemm(opnd(dY3, 0, 256, 1), opnd(T.perm + T.perm_off[2], 0, 256, 1), dY2, 256, B * 13, 256,
+           256, 0);
+  g.mask = opnd(sb.a2, bf, 256, 1);
+  run(g);
+  run(gemm(opnd(dY3, 0, 1, 256), opnd(sb.a2, bf, 256, 1), dWt, 256, 256, 256, B * 13, 0));
+  scatter(2, dparams);
+  colsum(dY3, B * 13, 256, dparams + T.boff[2]);
+  // conv2: rows (b, p), 26 per window
+  g = gemm(opnd(dY2, 0, 128, 1), opnd(T.perm + T.perm_off[1], 0, 128, 1), dY1, 128, B * 26, 128,
+           128, 0);
+  g.mask = opnd(sb.a1, bf, 128, 1);
+  run(g);
+  run(gemm(opnd(dY2, 0, 1, 128), opnd(sb.a1, bf, 128, 1), dWt, 128, 128, 128, B * 26, 0));
+  scatter(1, dparams);
+  colsum(dY2, B * 26, 128, dparams + T.boff[1]);
+  // conv1: rows (b, p), 52 per window; input pairs of window slots, rows of
+  // window b at x + b*111*50 (the last 7 slots feed no output)
+  const int64_t win = (int64_t)c->cfg.n_slot * c->cfg.n_feat;
+  run(gemm(opnd(dY1, 0, 1, 64), opnd(x, 0, 100, 1, 52, win), dWt, 100, 64, 100, B * 52, 0));
+  scatter(0, dparams);
+  colsum(dY1, B * 52, 64, dparams + T.boff[0]);
+  if (dx) {
+    if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);
+    g = gemm(opnd(dY1, 0, 64, 1), opnd(T.perm + T.perm_off[0], 0, 100, 1), dx, 100, B * 52, 100,
+             64, 0);
+    g.cgrp = 52;
+    g.cgs = win;
+    run(g);
+  }
+  if (e != hipSuccess) return hip_fail(c, e, "backward");
+  return SIM_OK;
+}
+
+int sim_adam(sim_ctx* c, float* params, const float* grads, float* m, float* v, int64_t n,
+             float lr, float beta1, float beta2, float eps, int32_t step) {
+  if (!c) return SIM_EINVAL;
+  if (!params || !grads || !m || !v || n < 0 || step < 1) return fail(c, SIM_EINVAL, "bad arguments");
+  hipError_t e = launch_adam(params, grads, m, v, n, lr, beta1, beta2, eps, step, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adam");
   return SIM_OK;
 }
 
@@ -793,6 +1166,11 @@ void sim_destroy(sim_ctx* c) {
   drop_graph(c);
   if (c->dev_weights) (void)hipFree(c->dev_weights);
   if (c->dev_w32) (void)hipFree(c->dev_w32);
+  if (c->tr.master) (void)hipFree(c->tr.master);
+  if (c->tr.maps) (void)hipFree(c->tr.maps);
+  if (c->tr.packed) (void)hipFree(c->tr.packed);
+  if (c->tr.perm) (void)hipFree(c->tr.perm);
+  if (c->tr.work) (void)hipFree(c->tr.work);
   if (c->dev_block) (void)hipFree(c->dev_block);
   delete c;
 }

@@ -215,7 +215,10 @@ __device__ __forceinline__ void store_run(T* dst, const T (&e)[N]) {
 // One conv level as a GEMM: rows (s, q) = MT sub-traces x P output positions,
 // A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
 // 2q+1 at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.
-template <class P, int K, int N, int POS, int WAVES, int SA, int SO, bool CAL = false>
+// SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
+// s < sv_rows only), the layer's activations kept for the backward pass.
+template <class P, int K, int N, int POS, int WAVES, int SA, int SO, bool CAL = false,
+          bool SAVE = false>
 __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
                                            typename P::T* __restrict__ O,
                                            const uint4* __restrict__ Bp,
@@ -223,7 +226,9 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
                                            const float* __restrict__ ws,
                                            const float* __restrict__ ai, bool relu, int wave,
                                            int lane, unsigned* cal = nullptr,
-                                           const int* row_live = nullptr) {
+                                           const int* row_live = nullptr,
+                                           typename P::T* sv = nullptr, int64_t sv_s = 0,
+                                           int sv_rows = 0) {
   using T = typename P::T;
   constexpr int ROWS = MT * POS;
   constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
@@ -253,6 +258,9 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
       e[i] = to_storage<P>(v, col0 + i, ai);
     }
     store_run<4 * sizeof(T)>(orow + col0, e);
+    if constexpr (SAVE)
+      if (row / POS < sv_rows)
+        store_run<4 * sizeof(T)>(sv + (row / POS) * sv_s + (row % POS) * N + col0, e);
   }
 }
 
@@ -276,11 +284,22 @@ __device__ __forceinline__ void hidden_accumulate(v4f* acc, const typename P::T*
 // = ReLU after layer l.  CAL: also record per-channel max |input| of every
 // layer into cal (offsets: window D, conv1 out, conv2 out[, conv3 out,
 // hidden out]), counting only tile rows whose row_live[s] is set.
-template <class Net, class P, bool CAL = false, class Load, class Commit>
+// Activations kept for the backward pass (training form, SAVE): per window
+// b, channels-last, in storage precision: a1 [NB*BS/2][CH1], a2
+// [NB*BS/4][CH2], a3 [NB][CH3], h [HID]; pointers already at the tile's
+// first window, rows = windows of the tile that exist.
+template <class T>
+struct SavePtrs {
+  T *a1, *a2, *a3, *h;
+  int rows;
+};
+
+template <class Net, class P, bool CAL = false, bool SAVE = false, class Load, class Commit>
 __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
                                              NetSmem<Net, P>& sm, Load&& load, Commit&& commit,
                                              unsigned* cal = nullptr,
-                                             const int* row_live = nullptr) {
+                                             const int* row_live = nullptr,
+                                             SavePtrs<typename P::T> sv = {}) {
   using G = Geo<Net, P>;
   using T = typename P::T;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -300,19 +319,22 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   for (int j = 0; j < Net::NB; ++j) {
     __syncthreads();
     if (j + 1 < Net::NB) regs = load(j + 1);
-    conv_stage<P, 2 * G::DP, Net::CH1, Net::BS / 2, Net::WAVES, G::SX, G::SA1, CAL>(
+    constexpr int P1 = Net::BS / 2, P2 = Net::BS / 4;
+    conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::SA1, CAL, SAVE>(
         sm.x, sm.a1, static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
-        wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live);
+        wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live,
+        sv.a1 + (size_t)j * P1 * Net::CH1, (int64_t)Net::NB * P1 * Net::CH1, sv.rows);
     __syncthreads();
-    conv_stage<P, 2 * Net::CH1, Net::CH2, Net::BS / 4, Net::WAVES, G::SA1, G::SA2, CAL>(
+    conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::SA2, CAL, SAVE>(
         sm.a1, sm.a2, static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
-        wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live);
+        wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live,
+        sv.a2 + (size_t)j * P2 * Net::CH2, (int64_t)Net::NB * P2 * Net::CH2, sv.rows);
     __syncthreads();
     if constexpr (Net::NCONV == 3) {
-      conv_stage<P, 2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3, CAL>(
+      conv_stage<P, 2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3, CAL, SAVE>(
           sm.a2, sm.a3, static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
           wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2,
-          row_live);
+          row_live, sv.a3 + (size_t)j * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows);
       __syncthreads();
     }
     const T* last = Net::NCONV == 3 ? sm.a3 : sm.a2;
@@ -337,7 +359,22 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
     if (j + 1 < Net::NB) commit(j + 1, regs, sm.x);
   }
 
-  if constexpr (Net::HID > 0) {
+  if constexpr (SAVE && Net::HID > 0) {
+    // training form: the hidden layer's output is kept, the head runs as a
+    // separate GEMM over the whole batch
+    const bool hrelu = relu_mask & (1u << Net::NCONV);
+    const int row = lane & 15;
+#pragma unroll
+    for (int jj = 0; jj < HT; ++jj) {
+      const int col0 = (wave * HT + jj) * 16 + 4 * (lane >> 4);
+      T e[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        e[i] = to_storage<P>(activation<P>(hacc[jj][i], col0 + i, wt.hid_b, wt.hid_ws, hrelu),
+                             col0 + i, wt.hid_ai);
+      if (row < sv.rows) store_run<4 * sizeof(T)>(sv.h + (size_t)row * Net::HID + col0, e);
+    }
+  } else if constexpr (Net::HID > 0) {
     // bias + ReLU on the hidden layer, rounding to the form's precision, then
     // the final FC: lane l holds row l % 16 and 4 columns of each of its HT
     // tiles; reduce over the 4 lanes sharing the row, then over waves.
@@ -745,6 +782,73 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     const int ss = tid / Net::NOUT, o = tid % Net::NOUT;
     if (b0 + ss < B) logits[(b0 + ss) * Net::NOUT + o] = sm.logit[ss][o];
   }
+}
+
+// Training-form forward over explicit windows: the trunk and the hidden
+// layer, keeping every activation (the head runs as a GEMM afterwards).
+template <class Net, class P>
+__global__ void __launch_bounds__(Net::WAVES * 64)
+    forward_save_kernel(DevWeights wt, uint32_t relu_mask, const float* __restrict__ x,
+                        int64_t B, SaveBlock sb) {
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  constexpr int NT = G::NT, D = Net::D, DP = G::DP, BS = Net::BS, L = Net::L;
+  __shared__ NetSmem<Net, P> sm;
+  const int tid = threadIdx.x;
+  const int64_t b0 = (int64_t)blockIdx.x * MT;
+  constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+  const int row = tid / TPR, part = tid % TPR;
+  const int s = row / BS, t = row % BS;
+  static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
+  if constexpr (P::SCALED) {
+    for (int c = tid; c < D; c += NT) sm.x_inv[c] = wt.x_inv[c];
+    __syncthreads();
+  }
+  const int64_t b = b0 + s;
+  auto load = [&](int j) {
+    RowRegs<CPT> r;
+    r.valid = b < B;
+    const float* src = x + ((b < B ? b : 0) * L + j * BS + t) * D;
+#pragma unroll
+    for (int cc = 0; cc < CPT; cc += 2) {
+      const int c = part * CPT + cc;
+      r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+    }
+    return r;
+  };
+  auto commit = [&](int j, const RowRegs<CPT>& r, T* X) {
+    (void)j;
+    float v[CPT];
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) {
+      const int c = part * CPT + cc;
+      v[cc] = (r.valid && c < D) ? (cc & 1 ? r.v[cc / 2].y : r.v[cc / 2].x) : 0.f;
+    }
+    T e[CPT];
+    window_elems<P, CPT, D>(v, sm.x_inv, part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(X + s * G::SX + t * DP + part * CPT, e);
+  };
+  SavePtrs<T> sv;
+  sv.a1 = static_cast<T*>(sb.a1) + b0 * (Net::NB * BS / 2) * Net::CH1;
+  sv.a2 = static_cast<T*>(sb.a2) + b0 * (Net::NB * BS / 4) * Net::CH2;
+  sv.a3 = static_cast<T*>(sb.a3) + b0 * Net::NB * Net::CH3;
+  sv.h = static_cast<T*>(sb.h) + b0 * Net::HID;
+  sv.rows = (int)(B - b0 < MT ? B - b0 : MT);
+  predict_tile<Net, P, false, true>(wt, relu_mask, sm, load, commit, nullptr, nullptr, sv);
+}
+
+template <class P>
+static hipError_t launch_fwd_save_t(const DevWeights& w, uint32_t relu, const float* x, int64_t B,
+                                    const SaveBlock& sb, hipStream_t stream) {
+  const dim3 grid((unsigned)((B + MT - 1) / MT)), block(Geo<NetC3, P>::NT);
+  hipLaunchKernelGGL((forward_save_kernel<NetC3, P>), grid, block, 0, stream, w, relu, x, B, sb);
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_save(int prec, const DevWeights& w, uint32_t relu, const float* x,
+                               int64_t B, const SaveBlock& sb, hipStream_t stream) {
+  return prec == 0 ? launch_fwd_save_t<PF32>(w, relu, x, B, sb, stream)
+                   : launch_fwd_save_t<PBF16>(w, relu, x, B, sb, stream);
 }
 
 __global__ void reset_kernel(DevState st, int32_t n_sub, int32_t C, int32_t n_slots) {

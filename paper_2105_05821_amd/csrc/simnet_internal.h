@@ -129,6 +129,47 @@ int calibration_size(int net);
 hipError_t launch_reset(const DevState& s, int32_t n_sub, int32_t C, int32_t n_slots,
                         hipStream_t stream);
 hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStream_t stream);
+// Training form (C3 trunk, hidden layer kept): activations saved by the
+// forward for the backward pass, per window, channels-last, in the form's
+// storage precision: a1 [52][64], a2 [26][128], a3 [13][256], h [512].
+struct SaveBlock {
+  void *a1, *a2, *a3, *h;
+};
+hipError_t launch_forward_save(int prec, const DevWeights& w, uint32_t relu, const float* x,
+                               int64_t B, const SaveBlock& sb, hipStream_t stream);
+
+// A GEMM operand: element (r, c) at p[(r / grp) * gs + (r % grp) * rs + c * cs]
+// (grp splits the rows into groups with their own stride, e.g. the window
+// rows of a batch of 111-slot windows), FP32 or BF16.
+struct GemmOperand {
+  const void* p;
+  int32_t bf16;
+  int64_t rs, cs, grp, gs;
+};
+// C[M][N] (+)= A(m, k) B(k, n) [+ bias[n]], then zeroed where mask(m, n) <= 0;
+// C(m, n) at C + (m / cgrp) * cgs + (m % cgrp) * ldc + n.
+struct GemmArgs {
+  GemmOperand A, B, mask;
+  float* C;
+  int64_t ldc, cgrp, cgs;
+  int64_t M, N, K;
+  const float* bias;
+  int32_t beta;
+};
+hipError_t launch_gemm(const GemmArgs& g, hipStream_t stream);
+hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
+                       float* loss_b, float* loss, float* dz, hipStream_t stream);
+size_t colsum_workspace(int64_t N);
+hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float* out, int beta,
+                         float* work, hipStream_t stream);
+hipError_t launch_map_gather(const float* src, const int32_t* map, int64_t n, void* dst, int bf16,
+                             hipStream_t stream);
+hipError_t launch_map_scatter(const float* src, const int32_t* map, int64_t n, float* dst,
+                              int beta, hipStream_t stream);
+hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, int32_t t, hipStream_t stream);
+
 // Graph of the run: step kernel until every slot is empty, then the total.
 hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu,
                            const DevState& s, const StepParams& p, int64_t* total,

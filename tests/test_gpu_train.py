@@ -1,0 +1,226 @@
+"""Training form of the predictor on the GPU (Sec. 2.3's hybrid head, Sec. 4's
+training set-up): forward with saved activations, hybrid loss, hand-written
+backward, Adam, through the C ABI.
+
+Bars.  The forward is held to the inference bar, |y32 - y64| <= 1e-5 *
+max(s, 1) with s = |b| + sum |w a| of the head (BF16 form: 2^-8 * max(s, 1)
+against the oracle's BF16 form).  Gradients are FP32 sums of up to B*52 or
+3,328 products through five layers; each parameter tensor, dlogits and dx
+are held to a normwise relative error of 5e-5 against the oracle's FP64
+gradient (unit roundoff 6e-8 times the square root of the longest sum,
+times a depth margin), and elementwise to 1e-4 of the tensor's largest
+entry.  The finite-difference check uses the GPU's own FP32 loss along each
+layer's gradient direction, where the derivative is the gradient's norm."""
+import numpy as np
+import pytest
+
+import synth
+from tests.common import realistic_windows, rel_err
+
+pytestmark = pytest.mark.gpu
+
+D, L = 50, 111
+COLS = synth.dynamic_columns(D)
+CFG = (D, L, 2, 8, COLS[0], COLS[1], COLS[2])
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    if not t.cuda.is_available():
+        pytest.skip("no GPU")
+    return t
+
+
+@pytest.fixture(scope="module")
+def sn():
+    import paper_2105_05821_amd as m
+    m.lib()
+    return m
+
+
+def dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def inputs(B, seed, with_rows=False):
+    layers = synth.net_c3_hybrid()
+    ws, bs = synth.init_weights(seed, layers, out_bias=None, out_gain=1.0)
+    feat = synth.trace_features(1, 4000, D)
+    x = realistic_windows(CFG, feat, B, seed=seed)
+    rng = np.random.default_rng(seed)
+    lat = rng.integers(0, 420, size=(B, 2)).astype(np.int32)  # includes the overflow class
+    return layers, ws, bs, x, lat
+
+
+def layer_slices(layers):
+    out, off = [], 0
+    for (ws, bs) in synth.layer_param_shapes(layers):
+        n = int(np.prod(ws))
+        out.append(("w", off, off + n))
+        off += n
+        out.append(("b", off, off + bs[0]))
+        off += bs[0]
+    return out
+
+
+def normwise(got, ref):
+    ref = np.asarray(ref, np.float64)
+    return np.linalg.norm(np.asarray(got, np.float64) - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def check_grad(name, got, ref, nw=5e-5, ew=1e-4):
+    e = normwise(got, ref)
+    m = np.abs(np.asarray(got, np.float64) - ref).max() / max(np.abs(ref).max(), 1e-300)
+    assert e <= nw and m <= ew, (name, e, m)
+
+
+@pytest.mark.parametrize("B", [1, 37])
+def test_train_forward_parity_f32(torch, sn, oracle_lib, B):
+    layers, ws, bs, x, _ = inputs(B, 11 + B)
+    pred = sn.Predictor(layers, sn.SIM_FP32)
+    pred.load_weights(layers, sn.flat_params(ws, bs))
+    z, _ = pred.forward(dev(torch, x))
+    ref, scale = oracle_lib.Model(layers, ws, bs, D, L).forward(x, want_scale=True)
+    assert rel_err(z.cpu().numpy(), ref, scale).max() <= 1e-5
+    pred.close()
+
+
+def test_train_forward_parity_bf16(torch, sn, oracle_lib):
+    B = 37
+    layers, ws, bs, x, _ = inputs(B, 5)
+    pred = sn.Predictor(layers, sn.SIM_BF16)
+    pred.load_weights(layers, sn.flat_params(ws, bs))
+    z, _ = pred.forward(dev(torch, x))
+    ref, scale = oracle_lib.Model(layers, ws, bs, D, L, prec=1).forward(x, want_scale=True)
+    err = rel_err(z.cpu().numpy(), ref, scale)
+    assert err.max() <= 2.0 ** -8 and np.median(err) <= 1e-4, (err.max(), np.median(err))
+    pred.close()
+
+
+def gpu_grads(torch, sn, pred, x, lat, want_dx=True):
+    dx_ = dev(torch, x)
+    z, save = pred.forward(dx_)
+    loss, dz = pred.loss(z, dev(torch, lat))
+    dparams = torch.empty(2_204_642, dtype=torch.float32, device="cuda")
+    dx = pred.backward(dx_, save, dz, dparams, want_dx=want_dx)
+    torch.cuda.synchronize()
+    return (float(loss.item()), dz.cpu().numpy(), dparams.cpu().numpy(),
+            None if dx is None else dx.cpu().numpy())
+
+
+@pytest.mark.parametrize("B", [1, 37])
+def test_train_gradients_match_oracle_f32(torch, sn, oracle_lib, B):
+    layers, ws, bs, x, lat = inputs(B, 21 + B)
+    pred = sn.Predictor(layers, sn.SIM_FP32)
+    pred.load_weights(layers, sn.flat_params(ws, bs))
+    loss, dz, dp, dx = gpu_grads(torch, sn, pred, x, lat)
+    ref = oracle_lib.train_step(oracle_lib.Model(layers, ws, bs, D, L), x, lat,
+                                want_dlogits=True, want_dx=True)
+    assert abs(loss - ref["loss"]) <= 1e-5 * abs(ref["loss"])
+    check_grad("dlogits", dz, ref["dlogits"])
+    for (kind, lo, hi), li in zip(layer_slices(layers), np.repeat(np.arange(len(layers)), 2)):
+        check_grad(f"layer {li} {kind}", dp[lo:hi], ref["dparams"][lo:hi])
+    check_grad("dx", dx, ref["dx"])
+    # slots past the 104 that feed conv1 get no gradient
+    assert not np.any(dx[:, 104:, :])
+    pred.close()
+
+
+def test_train_finite_differences_f32(torch, sn):
+    """(L(p + h u) - L(p - h u)) / 2h along u = g_l / |g_l| for each layer's
+    weight tensor, and along dx / |dx| for the windows; the GPU loss at the
+    perturbed parameters is the FP32 forward + loss."""
+    B = 24
+    layers, ws, bs, x, lat = inputs(B, 31)
+    p0 = sn.flat_params(ws, bs).astype(np.float64)
+    pred = sn.Predictor(layers, sn.SIM_FP32)
+    pred.load_weights(layers, p0.astype(np.float32))
+    _, _, g, gx = gpu_grads(torch, sn, pred, x, lat)
+    dlat = dev(torch, lat)
+
+    def loss_at(p, xx):
+        pred.load_weights(layers, np.asarray(p, np.float32))
+        z, _ = pred.forward(dev(torch, np.asarray(xx, np.float32)))
+        loss, _ = pred.loss(z, dlat)
+        return float(loss.item())
+
+    for kind, lo, hi in layer_slices(layers):
+        if kind != "w":
+            continue
+        gl = g[lo:hi].astype(np.float64)
+        n = np.linalg.norm(gl)
+        u = np.zeros_like(p0)
+        u[lo:hi] = gl / n
+        h = 1e-2 * np.linalg.norm(p0[lo:hi]) / np.sqrt(hi - lo)
+        fd = (loss_at(p0 + h * u, x) - loss_at(p0 - h * u, x)) / (2 * h)
+        assert abs(fd - n) <= 2e-2 * n, (lo, fd, n)
+    n = np.linalg.norm(gx)
+    h = 1e-2
+    fd = (loss_at(p0, x + h * gx / n) - loss_at(p0, x - h * gx / n)) / (2 * h)
+    assert abs(fd - n) <= 2e-2 * n, ("dx", fd, n)
+    pred.close()
+
+
+def test_train_accumulate_and_autograd(torch, sn):
+    """accumulate=1 adds to dparams; the torch.autograd.Function returns the
+    same gradients as predictor_bwd for the same upstream gradient."""
+    B = 20
+    layers, ws, bs, x, lat = inputs(B, 41)
+    flat = sn.flat_params(ws, bs)
+    pred = sn.Predictor(layers, sn.SIM_FP32)
+    pred.load_weights(layers, flat)
+    xd = dev(torch, x)
+    z, save = pred.forward(xd)
+    gen = torch.Generator(device="cpu").manual_seed(0)
+    up = torch.randn(z.shape, generator=gen).cuda()
+    g1 = torch.empty(flat.size, dtype=torch.float32, device="cuda")
+    dx = pred.backward(xd, save, up, g1, want_dx=True)
+    g2 = g1.clone()
+    pred.backward(xd, save, up, g2, accumulate=True)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(g2.cpu().numpy(), 2 * g1.cpu().numpy(), rtol=1e-6,
+                               atol=1e-6 * float(g1.abs().max()))
+    params = dev(torch, flat).requires_grad_(True)
+    xa = xd.clone().requires_grad_(True)
+    za = sn.predictor_apply(xa, params, pred)
+    (za * up).sum().backward()
+    np.testing.assert_array_equal(za.detach().cpu().numpy(), z.cpu().numpy())
+    np.testing.assert_array_equal(params.grad.cpu().numpy(), g1.cpu().numpy())
+    np.testing.assert_array_equal(xa.grad.cpu().numpy(), dx.cpu().numpy())
+    pred.close()
+
+
+def analytic_batch(B, seed):
+    """Windows ending at trace row i with the analytic model's latencies of
+    row i as labels."""
+    fields = synth.trace_fields(1, 0, 4000)
+    feat = synth.trace_features(1, 4000, D)
+    lab = synth.analytic_latencies(fields)
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(L, 4000, size=B)
+    x = np.zeros((B, L, D), np.float32)
+    for b, i in enumerate(rows):
+        occ = int(rng.integers(0, L))
+        x[b, 0] = feat[i]
+        x[b, 0, COLS[0]] = 0
+        x[b, 0, COLS[1]] = 0
+        for k in range(1, occ + 1):
+            x[b, k] = feat[i - k]
+            x[b, k, COLS[0]] = k
+            x[b, k, COLS[1]] = lab[i - k, 1]
+    return x, lab[rows].astype(np.int32)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_trainer_reduces_loss(torch, sn, prec):
+    layers = synth.net_c3_hybrid()
+    ws, bs = synth.init_weights(3, layers, out_bias=None, out_gain=1.0)
+    x, lat = analytic_batch(64, 3)
+    tr = sn.Trainer(layers, sn.flat_params(ws, bs),
+                    prec=sn.SIM_FP32 if prec == "f32" else sn.SIM_BF16, lr=1e-3)
+    xd, ld = dev(torch, x), dev(torch, lat)
+    losses = [float(tr.step(xd, ld).item()) for _ in range(30)]
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.5 * losses[0], losses
+    tr.close()
