@@ -685,7 +685,7 @@ static void* train_worker(void* arg) {
     if (b >= J->B) break;
     const double* xb = J->x + (size_t)b * L * D;
     for (int l = 0; l < L; ++l)
-      for (int c = 0; c < D; ++c) a[0][c * L + l] = xb[l * D + c];
+      for (int c = 0; c < D; ++c) a[0][c * L + l] = qform(m, xb[l * D + c]);
     /* forward, keeping every layer's output */
     for (int l = 0; l < NL; ++l) {
       const int kind = m->desc[l][0], ci = ch[l], co = ch[l + 1], li = len[l], lo = len[l + 1];
@@ -701,7 +701,8 @@ static void* train_worker(void* arg) {
             const int n_in = ci * li;
             for (int j = 0; j < n_in; ++j) s += w[(size_t)o * n_in + j] * a[l][j];
           }
-          a[l + 1][o * lo + p] = (m->desc[l][3] && s < 0.0) ? 0.0 : s;
+          s = (m->desc[l][3] && s < 0.0) ? 0.0 : s;
+          a[l + 1][o * lo + p] = l < NL - 1 ? qform(m, s) : s;
         }
     }
     /* loss and its gradient w.r.t. the head outputs */
@@ -723,8 +724,10 @@ static void* train_worker(void* arg) {
       for (int i = 0; i < ci * li; ++i) g[l][i] = 0.0;
       for (int o = 0; o < co; ++o)
         for (int p = 0; p < lo; ++p) {
-          const double dy = g[l + 1][o * lo + p];
-          gb[o] += dy;
+          /* BF16 form: the output gradient enters the weight and input
+           * products rounded to bfloat16, the bias gradient unrounded */
+          const double dy = qform(m, g[l + 1][o * lo + p]);
+          gb[o] += g[l + 1][o * lo + p];
           if (kind == OL_CONV) {
             for (int c = 0; c < ci; ++c)
               for (int t = 0; t < 2; ++t) {
@@ -754,11 +757,15 @@ static void* train_worker(void* arg) {
 /* Training form in FP64: mean hybrid loss over B windows x [B][L][D] with
  * integer latency labels lat [B][2], its gradient w.r.t. every parameter
  * (flat, PyTorch order) and optionally w.r.t. the head outputs and the
- * input.  The network's last layer must have 2 * (n_bins + 1) outputs. */
+ * input.  The network's last layer must have 2 * (n_bins + 1) outputs.
+ * A BF16-form model (prec 1) evaluates the forward as ol_forward's BF16
+ * form and, in the backward, rounds each layer's output gradient to
+ * bfloat16 where it multiplies weights or activations (the bias gradient
+ * sums it unrounded); sums stay exact FP64. */
 int ol_train(const void* p, int64_t B, const double* x, const int32_t* lat, int32_t n_bins,
              double* loss, double* dparams, double* dlogits, double* dx, int32_t n_threads) {
   const ol_model* m = (const ol_model*)p;
-  if (!m || m->prec != 0 || m->n_out != 2 * (n_bins + 1) || B < 1) return -1;
+  if (!m || m->prec > 1 || m->n_out != 2 * (n_bins + 1) || B < 1) return -1;
   size_t woff[16], boff[16], tot;
   param_offsets(m, woff, boff, &tot);
   if (n_threads <= 0) n_threads = 1;

@@ -599,6 +599,89 @@ def test_training_gradient_matches_torch_autograd(oracle_lib, net):
                                atol=1e-12 * np.abs(xt.grad.numpy()).max())
 
 
+def _bf16(t):
+    """float64 -> nearest bfloat16 value (8 significant bits, ties to even),
+    rounded once.  torch's float64 -> bfloat16 cast goes through float32 and
+    rounds twice, which differs where the float32 value is a bfloat16 tie."""
+    m, e = torch.frexp(t)
+    return torch.ldexp(torch.round(m * 256.0) / 256.0, e)
+
+
+def test_bf16_helper_matches_torch_cast_on_float32():
+    """On float32 inputs torch's cast rounds once, so it must agree."""
+    g = torch.Generator().manual_seed(0)
+    v = (torch.randn(200_000, generator=g) * torch.exp(torch.randn(200_000, generator=g) * 8))
+    v = torch.cat([v, torch.tensor([1 + 2.0 ** -8, 1 + 3 * 2.0 ** -8, -(1 + 2.0 ** -8), 0.0])])
+    want = v.to(torch.bfloat16).to(torch.float64)
+    assert torch.equal(_bf16(v.to(torch.float64)), want)
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Identity forward; the incoming gradient rounded to bfloat16."""
+
+    @staticmethod
+    def forward(ctx, z):
+        return z.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return _bf16(g)
+
+
+class _RoundValue(torch.autograd.Function):
+    """Value rounded to bfloat16; gradient passed through."""
+
+    @staticmethod
+    def forward(ctx, z):
+        return _bf16(z)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+@pytest.mark.parametrize("net", ["small", "c3"])
+def test_training_bf16_form_matches_torch_autograd(oracle_lib, net):
+    """The BF16 training form against torch autograd over the same
+    roundings: input, weights and hidden outputs rounded to bfloat16 in the
+    forward; each layer's output gradient rounded where it multiplies
+    (RoundGrad before the bias-free product), the bias gradient unrounded."""
+    layers = small_hybrid_net() if net == "small" else synth.net_c3_hybrid()
+    D, L = (32, 16) if net == "small" else (50, 111)
+    B = 5
+    ws, bs, x, lat = train_inputs(layers, D, L, B, 7)
+    m = oracle_lib.Model(layers, ws, bs, D, L, prec=1)
+    got = oracle_lib.train_step(m, x, lat, want_dlogits=True, want_dx=True, threads=3)
+    params = []
+    for w, b in zip(ws, bs):
+        params += [torch.tensor(np.asarray(w, np.float64), requires_grad=True),
+                   torch.tensor(np.asarray(b, np.float64), requires_grad=True)]
+    xt = torch.tensor(x, requires_grad=True)
+    h = _RoundValue.apply(xt).transpose(1, 2)
+    for i, ly in enumerate(layers):
+        w = _RoundValue.apply(params[2 * i])  # the gradient w.r.t. w stays unrounded
+        b = params[2 * i + 1]
+        if ly.kind == synth.CONV:
+            z = torch.nn.functional.conv1d(h, w, None, stride=2)
+            h = _RoundGrad.apply(z) + b[None, :, None]
+        else:
+            z = torch.nn.functional.linear(h.reshape(h.shape[0], -1), w, None)
+            h = _RoundGrad.apply(z) + b
+        if ly.relu:
+            h = torch.relu(h)
+        if i < len(layers) - 1:
+            h = _RoundValue.apply(h)
+    h.retain_grad()
+    loss = torch_hybrid_loss(h, lat)
+    loss.backward()
+    assert abs(got["loss"] - loss.item()) <= 1e-12 * abs(loss.item())
+    ref = np.concatenate([p.grad.numpy().ravel() for p in params])
+    np.testing.assert_allclose(got["dparams"], ref, rtol=1e-9, atol=1e-12 * np.abs(ref).max())
+    np.testing.assert_allclose(got["dlogits"], h.grad.numpy(), rtol=1e-10, atol=1e-14)
+    np.testing.assert_allclose(got["dx"], xt.grad.numpy(), rtol=1e-9,
+                               atol=1e-12 * np.abs(xt.grad.numpy()).max())
+
+
 def test_training_gradient_finite_differences(oracle_lib):
     """Central differences of the oracle's own loss, away from ReLU and L1
     kinks (a sample of parameters of every layer)."""
