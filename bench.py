@@ -18,6 +18,10 @@ Workloads (--workload):
   c3_uneven        20,000 independent streams with log-uniform lengths in
                    [1e3, 2e5] (7.5e8 instructions), packed instruction codes,
                    BF16, slots refilled longest-first, run as one graph.
+  c3_train         predictor training: one step = forward with saved
+                   activations, hybrid loss (400-bin CE + L1 on log1p), backward
+                   and Adam on 4,096 labelled 111x50 contexts, C3 trunk + FC
+                   512 -> 802 head, BF16 (FP32 master weights); contexts/s.
 """
 from __future__ import annotations
 
@@ -37,6 +41,9 @@ METRIC = "simulated MIPS on 1 MI355X, FP32 vs BF16/FP8 at ≤1% total-cycle erro
 # skip window slots and conv positions no output depends on, so they execute
 # slightly fewer (6,631,424 for the C3 network).
 FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560}
+# Training step per context: forward 3,760,896 MAC (trunk + FC 512 -> 802),
+# backward twice that less conv1's input gradient (352,000 MAC), x 2 FLOP.
+FLOP_PER_TRAIN_CTX = 21_861_376
 PEAK = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}  # published dense MFMA, TFLOP/s
 PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 
@@ -120,6 +127,38 @@ def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, wa
     return {"elapsed": elapsed, "kernel_ms": k_ms, "res": res}
 
 
+def train_bench(sn, torch, wl, steps, warmup, prec):
+    """Training steps on one fixed synthetic batch resident in HBM; HIP events
+    on the library's stream around each step."""
+    import synth
+    B = wl.extra["batch"]
+    x, lat = synth.training_batch(wl.trace_seed, wl.n_instr, wl.n_feat, wl.n_slot, B, 5)
+    ws, bs = synth.init_weights(wl.weight_seed, wl.layers, out_bias=None, out_gain=1.0)
+    tr = sn.Trainer(wl.layers, sn.flat_params(ws, bs), prec=PREC[prec], lr=1e-4)
+    xd = torch.from_numpy(x).cuda()
+    ld = torch.from_numpy(lat).cuda()
+    stream = tr.pred.stream
+    losses = []
+    for i in range(warmup):
+        losses.append(float(tr.step(xd, ld).item()))
+        log(f"[bench] train warmup {i}: loss {losses[-1]:.4f}")
+    torch.cuda.synchronize()
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(steps)]
+    loss_dev = []
+    t0 = time.perf_counter()
+    for i in range(steps):
+        events[i][0].record(stream)
+        loss_dev.append(tr.step(xd, ld))
+        events[i][1].record(stream)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    losses += [float(l.item()) for l in loss_dev]
+    tr.close()
+    return {"elapsed": elapsed, "kernel_ms": k_ms, "B": B, "losses": losses}
+
+
 WORKLOAD_TEXT = {
     "c3_1m": "c3_1m: 1,000,000-instruction synthetic trace, 4,096 sub-traces (244/245 instr) "
              "+ 256 warm-up, 111x50 windows, conv 64/128/256 k2s2 + FC 512 + FC 2, "
@@ -128,6 +167,9 @@ WORKLOAD_TEXT = {
             "conv 32/64 k2s2 + FC 2, random-init weights",
     "c3_uneven": "c3_uneven: 20,000 streams, log-uniform lengths 1e3..2e5, packed codes, "
                  "111x50 windows, C3 network, slots refilled longest-first",
+    "c3_train": "c3_train: training step on 4,096 labelled 111x50 contexts (analytic "
+                "latencies 0..400), conv 64/128/256 k2s2 + FC 512 + FC 802 hybrid head, "
+                "400-bin CE + L1 log1p loss, Adam, FP32 master weights",
 }
 
 
@@ -140,7 +182,20 @@ def main():
     ap.add_argument("--prec", default=None, choices=sorted(PREC),
                     help="run one form only (c3_1m default: all three)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES, 3 times (the "
+                         "reference kernel that scales HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 4, "launches": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the sub-traces "
               "are independent, a multi-GPU run would shard them with no communication, and "
@@ -154,6 +209,34 @@ def main():
 
     torch.cuda.set_device(0)
     wl = synth.workload(args.workload)
+    if args.workload == "c3_train":
+        steps = args.steps if args.steps is not None else 20
+        warmup = args.warmup if args.warmup is not None else 3
+        prec = args.prec or "bf16"
+        if prec == "fp8":
+            print("no FP8 training form", file=sys.stderr)
+            sys.exit(2)
+        r = train_bench(sn, torch, wl, steps, warmup, prec)
+        tflops = FLOP_PER_TRAIN_CTX * r["B"] / (r["kernel_ms"] / 1e3) / 1e12
+        out = {
+            "metric": "training contexts/s on 1 MI355X (forward + hybrid loss + backward + "
+                      "Adam)",
+            "value": round(r["B"] * steps / r["elapsed"], 1), "unit": "contexts/s",
+            "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": round(r["elapsed"] / steps * 1e3, 3), "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+            "config": {"workload": WORKLOAD_TEXT["c3_train"], "batch": r["B"],
+                       "loss_first": round(r["losses"][0], 5),
+                       "loss_last": round(r["losses"][-1], 5)},
+            "roofline": {"bound": "mfma", "achieved": round(tflops, 3),
+                         "peak": PEAK[prec], "unit": "TFLOP/s",
+                         "frac": round(tflops / PEAK[prec], 4), "traffic": None,
+                         "kernel": "whole training step (forward kernel, GEMMs, loss, "
+                                   "column sums, scatters, Adam, re-layout)",
+                         "kernel_ms": round(r["kernel_ms"], 3)},
+        }
+        print(json.dumps(out), flush=True)
+        return
     ws, bs = synth.init_weights(wl.weight_seed, wl.layers)
     net = "small" if args.workload == "tiny" else "c3"
     n_feat = None

@@ -571,10 +571,13 @@ static int load_train_weights(sim_ctx* c, const sim_layer* layers, int32_t n_lay
 
 // Backward workspace (floats): [0] per-window losses, [1] dH [B][512],
 // [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] a
-// weight-gradient staging matrix (largest [512][3328]), [6] column sums.
+// weight-gradient staging matrix (largest [512][3328]), [6] column sums,
+// [7] split-K partial products.
+constexpr size_t SPLITK_CAP = (size_t)8 << 20;
 static size_t train_work_off(int64_t B, int part) {
-  const size_t sizes[7] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
-                           (size_t)B * 3328, (size_t)512 * 3328, colsum_workspace(TRAIN_OUT) / 4};
+  const size_t sizes[8] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
+                           (size_t)B * 3328, (size_t)512 * 3328, colsum_workspace(TRAIN_OUT) / 4,
+                           SPLITK_CAP};
   size_t off = 0;
   for (int i = 0; i < part; ++i) off += (sizes[i] + 63) / 64 * 64;
   return off;
@@ -588,7 +591,7 @@ static int ensure_train_work(sim_ctx* c, int64_t B) {
     (void)hipFree(T.work);
     T.work = nullptr;
   }
-  hipError_t e = hipMalloc(&T.work, train_work_off(B, 7) * 4);
+  hipError_t e = hipMalloc(&T.work, train_work_off(B, 8) * 4);
   if (e != hipSuccess) return hip_fail(c, e, "training workspace");
   T.work_B = B;
   return SIM_OK;
@@ -611,7 +614,7 @@ static SaveBlock save_block(const sim_ctx* c, void* save, int64_t B) {
 }
 
 static GemmOperand opnd(const void* p, int bf16, int64_t rs, int64_t cs,
-                        int64_t grp = (int64_t)1 << 62, int64_t gs = 0) {
+                        int64_t grp = NO_GROUP, int64_t gs = 0) {
   GemmOperand o;
   o.p = p;
   o.bf16 = bf16;
@@ -630,7 +633,7 @@ static GemmArgs gemm(GemmOperand A, GemmOperand B, float* C, int64_t ldc, int64_
   g.mask = opnd(nullptr, 0, 0, 0);
   g.C = C;
   g.ldc = ldc;
-  g.cgrp = (int64_t)1 << 62;
+  g.cgrp = NO_GROUP;
   g.cgs = 0;
   g.M = M;
   g.N = N;
@@ -1041,7 +1044,7 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
     GemmArgs g = gemm(opnd(sb.h, bf, 512, 1), opnd(T.perm + T.perm_off[4], bf, TRAIN_OUT, 1),
                       logits, TRAIN_OUT, B, TRAIN_OUT, 512, 0);
     g.bias = T.master + T.boff[4];
-    if (e == hipSuccess) e = launch_gemm(g, c->stream);
+    if (e == hipSuccess) e = launch_gemm(g, bf, nullptr, 0, c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "training forward");
     return SIM_OK;
   }
@@ -1088,10 +1091,11 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   float* dY1 = W + train_work_off(B, 4);
   float* dWt = W + train_work_off(B, 5);
   float* csw = W + train_work_off(B, 6);
+  float* part = W + train_work_off(B, 7);
   const float* P = T.master;
   hipError_t e = hipSuccess;
   auto run = [&](const GemmArgs& g) {
-    if (e == hipSuccess) e = launch_gemm(g, c->stream);
+    if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
   };
   auto colsum = [&](const float* y, int64_t M, int64_t N, float* out) {
     if (e == hipSuccess) e = launch_colsum(y, M, N, N, out, beta, csw, c->stream);

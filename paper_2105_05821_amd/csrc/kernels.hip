@@ -84,29 +84,48 @@ struct PFP8 {
   __device__ static float val(T x) { return __builtin_amdgcn_cvt_f32_fp8((int)x, 0); }
 };
 
+// Blocks per group: the window is processed a group of NG consecutive
+// blocks at a time (the conv levels as one GEMM over all the group's
+// positions, so each weight fragment serves NG times more rows), as many as
+// the form's LDS budget allows beside the queue rings.
+template <class Net, class P>
+constexpr int group_blocks() {
+  return Net::NCONV == 2 ? Net::NB : (P::ID == 0 ? 2 : 4);
+}
+
 template <class Net, class P>
 struct Geo {
   using T = typename P::T;
   static constexpr int NT = Net::WAVES * 64;
+  static constexpr int NG = group_blocks<Net, P>();
   static constexpr int PAD = 16 / sizeof(T);                       // 16 bytes of row padding
   static constexpr int DP = padded_feat(Net::D, P::ID);            // features per slot
-  static constexpr int SX = Net::BS * DP + PAD;                    // window block, per sub-trace
-  static constexpr int SA1 = (Net::BS / 2) * Net::CH1 + PAD;       // conv1 output
-  static constexpr int SA2 = (Net::BS / 4) * Net::CH2 + PAD;       // conv2 output
-  static constexpr int SA3 = (Net::NCONV == 3 ? Net::CH3 : 0) + PAD;  // conv3 output
+  static constexpr int SX = NG * Net::BS * DP + PAD;               // a group's window rows, per window
+  static constexpr int SA1 = NG * (Net::BS / 2) * Net::CH1 + PAD;  // conv1 output
+  static constexpr int SA2 = NG * (Net::BS / 4) * Net::CH2 + PAD;  // conv2 output
+  static constexpr int SA3 = (Net::NCONV == 3 ? NG * Net::CH3 : 0) + PAD;  // conv3 output
   static constexpr int SAL = Net::NCONV == 3 ? SA3 : SA2;          // last conv output
+  // three conv levels: X and conv2's output share memory (X is dead once
+  // conv1 has read it), and so do conv1's and conv3's outputs
+  static constexpr bool ALIAS = Net::NCONV == 3;
+  static constexpr int NXA2 = ALIAS ? (SX > SA2 ? MT * SX : MT * SA2) : MT * SX;
+  static constexpr int NA1A3 = ALIAS ? (SA1 > SA3 ? MT * SA1 : MT * SA3) : MT * SA1;
+  static constexpr int NA2 = ALIAS ? PAD : MT * SA2;
 };
 
 template <class Net, class P>
 struct NetSmem {
   using G = Geo<Net, P>;
-  typename P::T x[MT * G::SX];
-  typename P::T a1[MT * G::SA1];
-  typename P::T a2[MT * G::SA2];
-  typename P::T a3[Net::NCONV == 3 ? MT * G::SA3 : G::PAD];
+  typename P::T xa2[G::NXA2];   // window rows of the group (X), then conv2's output
+  typename P::T a1a3[G::NA1A3]; // conv1's output, then conv3's output
+  typename P::T a2own[G::NA2];  // conv2's output when it does not alias X
   float red[Net::WAVES][MT][Net::NOUT];
   float logit[MT][Net::NOUT];
   float x_inv[Net::D];  // FP8: reciprocal input scale of each window feature
+  __device__ typename P::T* x() { return xa2; }
+  __device__ typename P::T* a1() { return a1a3; }
+  __device__ typename P::T* a2() { return G::ALIAS ? xa2 : a2own; }
+  __device__ typename P::T* a3() { return a1a3; }
 };
 
 // Epilogue of one accumulator element: bias, (FP8) dequantisation, ReLU.
@@ -149,40 +168,45 @@ __device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_of
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, frag_off, 0));
 }
 
-// acc[j] += W(tile nt0 + j) x A(this lane's 16 rows), all K.  The weight
-// fragment is the MFMA's first operand, so lane l ends up holding row
-// l % 16 of the activations and output columns 4*(l/16) .. +3 of the tile:
-// consecutive columns, stored with one vector write.  Weight fragments are
-// requested one chunk ahead of their use (double buffering) and the
-// scheduler is kept from sinking the requests.
-template <class P, int KGS, int NTILES, int TPW>
-__device__ __forceinline__ void mma_stream(v4f* acc, const typename P::T* __restrict__ ap,
+// acc[i][j] += W(tile nt0 + j) x A(m-tile i: this lane's row of it), all K.
+// The weight fragment is the MFMA's first operand, so lane l ends up
+// holding row l % 16 of the activations and output columns 4*(l/16) .. +3
+// of the tile: consecutive columns, stored with one vector write.  Each
+// weight fragment serves MPW m-tiles.  Weight fragments are requested one
+// chunk ahead of their use (double buffering) and the scheduler is kept
+// from sinking the requests.
+template <class P, int KGS, int NTILES, int NPW, int MPW>
+__device__ __forceinline__ void mma_stream(v4f (&acc)[MPW][NPW],
+                                           const typename P::T* const (&ap)[MPW],
                                            const uint4* __restrict__ Bp, int nt0, int lane) {
-  constexpr int CH = stream_chunk(KGS, TPW), NCH = KGS / CH;
+  constexpr int CH = stream_chunk(KGS, NPW), NCH = KGS / CH;
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint4*>(Bp), (short)0, KGS * NTILES * 1024, 0x00020000);
   const int lo = lane * 16;
   const int wn = __builtin_amdgcn_readfirstlane(nt0) * 1024;
-  uint4 b[2][CH][TPW];
+  uint4 b[2][CH][NPW];
 #pragma unroll
   for (int kg = 0; kg < CH; ++kg)
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) b[0][kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
+    for (int j = 0; j < NPW; ++j) b[0][kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     if (c + 1 < NCH) {
 #pragma unroll
       for (int kg = 0; kg < CH; ++kg)
 #pragma unroll
-        for (int j = 0; j < TPW; ++j)
+        for (int j = 0; j < NPW; ++j)
           b[(c + 1) & 1][kg][j] = load_frag(rs, lo, wn + (((c + 1) * CH + kg) * NTILES + j) * 1024);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kg = 0; kg < CH; ++kg) {
-      const uint4 a = *reinterpret_cast<const uint4*>(ap + (c * CH + kg) * P::KG);
 #pragma unroll
-      for (int j = 0; j < TPW; ++j) acc[j] = P::mma(acc[j], b[c & 1][kg][j], a);
+      for (int i = 0; i < MPW; ++i) {
+        const uint4 a = *reinterpret_cast<const uint4*>(ap[i] + (c * CH + kg) * P::KG);
+#pragma unroll
+        for (int j = 0; j < NPW; ++j) acc[i][j] = P::mma(acc[i][j], b[c & 1][kg][j], a);
+      }
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -212,9 +236,11 @@ __device__ __forceinline__ void store_run(T* dst, const T (&e)[N]) {
   }
 }
 
-// One conv level as a GEMM: rows (s, q) = MT sub-traces x P output positions,
+// One conv level as a GEMM: rows (s, q) = MT windows x POS output positions,
 // A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
-// 2q+1 at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.
+// 2q+1 at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.  The
+// waves split the N tiles first (each weight fragment is read by as few
+// waves as possible), then the M tiles; a wave runs MPW x NPW tiles.
 // SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
 // s < sv_rows only), the layer's activations kept for the backward pass.
 template <class P, int K, int N, int POS, int WAVES, int SA, int SO, bool CAL = false,
@@ -232,58 +258,49 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
   using T = typename P::T;
   constexpr int ROWS = MT * POS;
   constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
-  constexpr int TILES = MTILES * NTILES;
-  constexpr int TPW = TILES / WAVES;
+  constexpr int WN = NTILES < WAVES ? NTILES : WAVES, WM = WAVES / WN;
+  constexpr int MPW = MTILES / WM, NPW = NTILES / WN;
   static_assert(ROWS % 16 == 0 && N % 16 == 0 && K % P::KG == 0, "tile shape");
-  static_assert(TILES % WAVES == 0 && TPW >= 1 && NTILES % TPW == 0, "wave split");
-  const int t0 = wave * TPW;
-  const int mt = t0 / NTILES, nt0 = t0 % NTILES;
-  const int row = mt * 16 + (lane & 15);
-  const T* ap = A + (row / POS) * SA + (row % POS) * K + (P::KG / 4) * (lane >> 4);
-  v4f acc[TPW];
+  static_assert(WAVES % WN == 0 && MTILES % WM == 0 && NTILES % WN == 0 && MPW >= 1,
+                "wave split");
+  const int wm = wave / WN, wn = wave % WN;
+  const int nt0 = wn * NPW;
+  const T* ap[MPW];
 #pragma unroll
-  for (int j = 0; j < TPW; ++j) acc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-  mma_stream<P, KGS, NTILES, TPW>(acc, ap, Bp, nt0, lane);
-  T* orow = O + (row / POS) * SO + (row % POS) * N;
-  const bool live = !CAL || row_live[row / POS];
+  for (int i = 0; i < MPW; ++i) {
+    const int row = (wm * MPW + i) * 16 + (lane & 15);
+    ap[i] = A + (row / POS) * SA + (row % POS) * K + (P::KG / 4) * (lane >> 4);
+  }
+  v4f acc[MPW][NPW];
 #pragma unroll
-  for (int j = 0; j < TPW; ++j) {
-    const int col0 = (nt0 + j) * 16 + 4 * (lane >> 4);
-    T e[4];
+  for (int i = 0; i < MPW; ++i)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const float v = activation<P>(acc[j][i], col0 + i, bias, ws, relu);
-      if constexpr (CAL)
-        if (live) cal_max(cal, col0 + i, v);
-      e[i] = to_storage<P>(v, col0 + i, ai);
+    for (int j = 0; j < NPW; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  mma_stream<P, KGS, NTILES, NPW, MPW>(acc, ap, Bp, nt0, lane);
+#pragma unroll
+  for (int i = 0; i < MPW; ++i) {
+    const int row = (wm * MPW + i) * 16 + (lane & 15);
+    T* orow = O + (row / POS) * SO + (row % POS) * N;
+    const bool live = !CAL || row_live[row / POS];
+#pragma unroll
+    for (int j = 0; j < NPW; ++j) {
+      const int col0 = (nt0 + j) * 16 + 4 * (lane >> 4);
+      T e[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float v = activation<P>(acc[i][j][q], col0 + q, bias, ws, relu);
+        if constexpr (CAL)
+          if (live) cal_max(cal, col0 + q, v);
+        e[q] = to_storage<P>(v, col0 + q, ai);
+      }
+      store_run<4 * sizeof(T)>(orow + col0, e);
+      if constexpr (SAVE)
+        if (row / POS < sv_rows)
+          store_run<4 * sizeof(T)>(sv + (row / POS) * sv_s + (row % POS) * N + col0, e);
     }
-    store_run<4 * sizeof(T)>(orow + col0, e);
-    if constexpr (SAVE)
-      if (row / POS < sv_rows)
-        store_run<4 * sizeof(T)>(sv + (row / POS) * sv_s + (row % POS) * N + col0, e);
   }
 }
 
-// Hidden FC, one block's K-slice: acc[MT rows][N cols] += A[MT][K] * B_j
-// (lane l: row l % 16, columns 4*(l/16) .. +3 of each tile).
-template <class P, int K, int N, int WAVES, int SA>
-__device__ __forceinline__ void hidden_accumulate(v4f* acc, const typename P::T* __restrict__ A,
-                                                  const uint4* __restrict__ Bp, int wave,
-                                                  int lane) {
-  constexpr int NTILES = N / 16, KGS = K / P::KG, TPW = NTILES / WAVES;
-  const typename P::T* ap = A + (lane & 15) * SA + (P::KG / 4) * (lane >> 4);
-  mma_stream<P, KGS, NTILES, TPW>(acc, ap, Bp, wave * TPW, lane);
-}
-
-// The whole predictor on one tile of MT windows.  The window arrives block
-// by block: load(j) requests block j's rows (slots j*BS .. j*BS+BS-1) into
-// registers, commit(j, regs, X) writes them, in storage precision, to
-// X[s*SX + t*DP + c].  Block j+1 is requested before block j's convolutions
-// and committed after them, so its memory latency is hidden.  Both are
-// called by all threads; the raw outputs land in sm.logit.  relu_mask bit l
-// = ReLU after layer l.  CAL: also record per-channel max |input| of every
-// layer into cal (offsets: window D, conv1 out, conv2 out[, conv3 out,
-// hidden out]), counting only tile rows whose row_live[s] is set.
 // Activations kept for the backward pass (training form, SAVE): per window
 // b, channels-last, in storage precision: a1 [NB*BS/2][CH1], a2
 // [NB*BS/4][CH2], a3 [NB][CH3], h [HID]; pointers already at the tile's
@@ -294,6 +311,85 @@ struct SavePtrs {
   int rows;
 };
 
+// The conv levels and the hidden-FC (or final-FC) contribution of one group
+// of NBG blocks starting at block j0, for the tile of MT windows whose
+// window rows are in sm.x().  relu_mask bit l = ReLU after layer l.  Ends
+// with the group's last-conv output consumed.  issue() is called after the
+// conv levels (it requests the next group's rows into registers) and
+// finish(regs) after the FC (it writes them into sm.x(), the region conv2's
+// output used, dead by then): the FC's weight stream hides the gather.
+template <class Net, class P, int NBG, bool CAL, bool SAVE, class Issue, class Finish>
+__device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_mask,
+                                          NetSmem<Net, P>& sm, int j0, unsigned* cal,
+                                          const int* row_live, SavePtrs<typename P::T> sv,
+                                          v4f* hacc, float& fpart, Issue&& issue,
+                                          Finish&& finish) {
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  constexpr int P1 = NBG * Net::BS / 2, P2 = NBG * Net::BS / 4;
+  constexpr int Q1 = Net::BS / 2, Q2 = Net::BS / 4;  // positions per block
+  conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::SA1, CAL, SAVE>(
+      sm.x(), sm.a1(), static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
+      wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live,
+      sv.a1 + (size_t)j0 * Q1 * Net::CH1, (int64_t)Net::NB * Q1 * Net::CH1, sv.rows);
+  __syncthreads();
+  conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::SA2, CAL, SAVE>(
+      sm.a1(), sm.a2(), static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
+      wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live,
+      sv.a2 + (size_t)j0 * Q2 * Net::CH2, (int64_t)Net::NB * Q2 * Net::CH2, sv.rows);
+  __syncthreads();
+  if constexpr (Net::NCONV == 3) {
+    conv_stage<P, 2 * Net::CH2, Net::CH3, NBG, Net::WAVES, G::SA2, G::SA3, CAL, SAVE>(
+        sm.a2(), sm.a3(), static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
+        wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2, row_live,
+        sv.a3 + (size_t)j0 * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows);
+    __syncthreads();
+  }
+  const T* last = Net::NCONV == 3 ? sm.a3() : sm.a2();
+  auto next_rows = issue();
+  if constexpr (Net::HID > 0) {
+    // hidden FC over the group's NBG*CHL inputs per window (block-major, as
+    // the packed per-block matrices are consecutive): a fresh accumulator
+    // per group, then added, so the FP32 chain is per group
+    constexpr int HT = (Net::HID / 16) / Net::WAVES;
+    constexpr int KGS = NBG * Net::CHL / P::KG;
+    const uint4* bj = static_cast<const uint4*>(wt.hid_w) +
+                      (size_t)j0 * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
+    const T* const ap[1] = {last + (lane & 15) * G::SAL + (P::KG / 4) * (lane >> 4)};
+    v4f bacc[1][HT];
+#pragma unroll
+    for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
+    mma_stream<P, KGS, Net::HID / 16, HT, 1>(bacc, ap, bj, wave * HT, lane);
+#pragma unroll
+    for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
+  } else {
+    // final FC on the VALU straight after the convs: (s, o) pairs, LPP lanes each
+    constexpr int LPP = G::NT / (MT * Net::NOUT);
+    constexpr int CPL = Net::CHL / LPP;
+    const int fpair = tid / LPP, fsub = tid % LPP;
+    const int fs = fpair / Net::NOUT, fo = fpair % Net::NOUT;
+#pragma unroll
+    for (int jb = 0; jb < NBG; ++jb) {
+      const float* wrow = wt.last_w + ((size_t)(j0 + jb) * Net::NOUT + fo) * Net::CHL + fsub * CPL;
+      const T* arow = last + fs * G::SAL + jb * Net::CHL + fsub * CPL;
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) fpart = fmaf(P::val(arow[c]), wrow[c], fpart);
+    }
+  }
+  finish(next_rows);
+}
+
+// The whole predictor on one tile of MT windows.  The window arrives a group
+// of NG blocks (NG*BS slots) at a time: load(j0, nb) requests the rows of
+// blocks j0 .. j0+nb-1 into registers, commit(j0, nb, regs, X) writes them,
+// in storage precision, to X[s*SX + t*DP + c] (t = slot within the group).
+// The next group's rows are requested after the current group's conv levels
+// and committed before its FC, so their memory latency is hidden.  Both are
+// called by all threads; the raw outputs land in sm.logit.  CAL: also record
+// per-channel max |input| of every layer into cal (offsets: window D, conv1
+// out, conv2 out[, conv3 out, hidden out]), counting only tile rows whose
+// row_live[s] is set.
 template <class Net, class P, bool CAL = false, bool SAVE = false, class Load, class Commit>
 __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
                                              NetSmem<Net, P>& sm, Load&& load, Commit&& commit,
@@ -302,61 +398,33 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
                                              SavePtrs<typename P::T> sv = {}) {
   using G = Geo<Net, P>;
   using T = typename P::T;
+  constexpr int NG = G::NG, NFULL = Net::NB / NG, TAIL = Net::NB % NG;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int HT = Net::HID > 0 ? (Net::HID / 16) / Net::WAVES : 1;
   v4f hacc[HT];
 #pragma unroll
   for (int j = 0; j < HT; ++j) hacc[j] = v4f{0.f, 0.f, 0.f, 0.f};
-  // VALU final FC directly after the convs: (s, o) pairs, LPP lanes each.
-  constexpr int LPP = G::NT / (MT * Net::NOUT);
-  constexpr int CPL = Net::CHL / LPP;
   float fpart = 0.f;
-  const int fpair = tid / LPP, fsub = tid % LPP;
-  const int fs = fpair / Net::NOUT, fo = fpair % Net::NOUT;
 
-  auto regs = load(0);
-  commit(0, regs, sm.x);
-  for (int j = 0; j < Net::NB; ++j) {
+  {
+    auto regs = load(0, NFULL > 0 ? NG : TAIL);
+    commit(0, NFULL > 0 ? NG : TAIL, regs, sm.x());
+  }
+  for (int g = 0; g < NFULL; ++g) {
     __syncthreads();
-    if (j + 1 < Net::NB) regs = load(j + 1);
-    constexpr int P1 = Net::BS / 2, P2 = Net::BS / 4;
-    conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::SA1, CAL, SAVE>(
-        sm.x, sm.a1, static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
-        wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live,
-        sv.a1 + (size_t)j * P1 * Net::CH1, (int64_t)Net::NB * P1 * Net::CH1, sv.rows);
+    const int j0 = g * NG;
+    const int nj = j0 + NG, nnb = g + 1 < NFULL ? NG : TAIL;
+    run_group<Net, P, NG, CAL, SAVE>(
+        wt, relu_mask, sm, j0, cal, row_live, sv, hacc, fpart, [&]() { return load(nj, nnb); },
+        [&](const auto& regs) {
+          if (nnb > 0) commit(nj, nnb, regs, sm.x());
+        });
+  }
+  if constexpr (TAIL > 0) {
     __syncthreads();
-    conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::SA2, CAL, SAVE>(
-        sm.a1, sm.a2, static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
-        wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live,
-        sv.a2 + (size_t)j * P2 * Net::CH2, (int64_t)Net::NB * P2 * Net::CH2, sv.rows);
-    __syncthreads();
-    if constexpr (Net::NCONV == 3) {
-      conv_stage<P, 2 * Net::CH2, Net::CH3, 1, Net::WAVES, G::SA2, G::SA3, CAL, SAVE>(
-          sm.a2, sm.a3, static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
-          wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2,
-          row_live, sv.a3 + (size_t)j * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows);
-      __syncthreads();
-    }
-    const T* last = Net::NCONV == 3 ? sm.a3 : sm.a2;
-    if constexpr (Net::HID > 0) {
-      const uint4* bj = static_cast<const uint4*>(wt.hid_w) +
-                        (size_t)j * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
-      // per-block partial in a fresh accumulator, then added: the FP32
-      // summation chain is K/KG groups + NB blocks instead of one long chain
-      v4f bacc[HT];
-#pragma unroll
-      for (int jj = 0; jj < HT; ++jj) bacc[jj] = v4f{0.f, 0.f, 0.f, 0.f};
-      hidden_accumulate<P, Net::CHL, Net::HID, Net::WAVES, G::SAL>(bacc, last, bj, wave, lane);
-#pragma unroll
-      for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[jj];
-    } else {
-      const float* wrow = wt.last_w + ((size_t)j * Net::NOUT + fo) * Net::CHL + fsub * CPL;
-      const T* arow = last + fs * G::SAL + fsub * CPL;
-#pragma unroll
-      for (int c = 0; c < CPL; ++c) fpart = fmaf(P::val(arow[c]), wrow[c], fpart);
-    }
-    // X was last read by conv1 of this block, before the barriers above
-    if (j + 1 < Net::NB) commit(j + 1, regs, sm.x);
+    run_group<Net, P, TAIL, CAL, SAVE>(
+        wt, relu_mask, sm, NFULL * NG, cal, row_live, sv, hacc, fpart, []() { return 0; },
+        [](int) {});
   }
 
   if constexpr (SAVE && Net::HID > 0) {
@@ -415,6 +483,9 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
       sm.logit[s][o] = v;
     }
   } else {
+    constexpr int LPP = G::NT / (MT * Net::NOUT);
+    const int fpair = tid / LPP, fsub = tid % LPP;
+    const int fs = fpair / Net::NOUT, fo = fpair % Net::NOUT;
 #pragma unroll
     for (int m = 1; m < LPP; m <<= 1) fpart += __shfl_xor(fpart, m);
     if (fsub == 0) {
@@ -565,23 +636,25 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   }
   uint32_t n_clamped = 0, n_nonfinite = 0, n_mismatch = 0, n_pred = 0;
 
-  // Window gather: TPR threads per (sub-trace, slot) row, CPT features each.
-  constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+  // Window gather: TPR threads per (sub-trace, slot-of-the-group) row, CPT
+  // features each.
+  constexpr int GSL = G::NG * BS;
+  constexpr int ROWS = MT * GSL, TPR = NT / ROWS, CPT = DP / TPR;
   static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
   const int grow = tid / TPR, part = tid % TPR;
-  const int gs = grow / BS, gt = grow % BS;
+  const int gs = grow / GSL, gt = grow % GSL;
   if constexpr (P::SCALED)
     for (int c = tid; c < D; c += NT) sm.net.x_inv[c] = wt.x_inv[c];
-  // load(j): the row's trace index from the queue ring, then the row's
+  // load(j0, nb): the row's trace index from the queue ring, then the row's
   // features requested (every address in bounds, so all are in flight
-  // together); commit(j): dynamic columns, conversion, one vector store.
-  auto load = [&](int j) {
+  // together); commit: dynamic columns, conversion, one vector store.
+  auto load = [&](int j0, int nb) {
     RowRegs<CPT> r;
-    const int w = j * BS + gt;
+    const int w = j0 * BS + gt;
     int64_t idx = -1;
     r.res = 0.f;
     r.ex = 0.f;
-    if (sm.active[gs]) {
+    if (gt < nb * BS && sm.active[gs]) {
       if (w == 0) {
         idx = sm.first[gs] + sm.pos[gs];
       } else if (w <= sm.count[gs]) {
@@ -601,13 +674,18 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
 #pragma unroll
       for (int cc = 0; cc < CPT; cc += 2) {
         const int c = part * CPT + cc;
-        r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+        // one thread per row: the padding columns are known at compile time
+        if (TPR > 1 || cc < D)
+          r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+        else
+          r.v[cc / 2] = make_float2(0.f, 0.f);
       }
     }
     return r;
   };
-  auto commit = [&](int j, const RowRegs<CPT>& r, T* X) {
-    (void)j;
+  auto commit = [&](int j0, int nb, const RowRegs<CPT>& r, T* X) {
+    (void)j0;
+    if (gt >= nb * BS) return;  // slots past a short group's blocks are never read
     float v[CPT];
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
@@ -745,28 +823,33 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   __shared__ NetSmem<Net, P> sm;
   const int tid = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * MT;
-  constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+  constexpr int GSL = G::NG * BS;
+  constexpr int ROWS = MT * GSL, TPR = NT / ROWS, CPT = DP / TPR;
   const int row = tid / TPR, part = tid % TPR;
-  const int s = row / BS, t = row % BS;
+  const int s = row / GSL, t = row % GSL;
   static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
   if constexpr (P::SCALED) {
     for (int c = tid; c < D; c += NT) sm.x_inv[c] = wt.x_inv[c];
     __syncthreads();
   }
   const int64_t b = b0 + s;
-  auto load = [&](int j) {
+  auto load = [&](int j0, int nb) {
     RowRegs<CPT> r;
-    r.valid = b < B;
-    const float* src = x + ((b < B ? b : 0) * L + j * BS + t) * D;
+    r.valid = b < B && t < nb * BS;
+    const float* src = x + ((r.valid ? b : 0) * L + (r.valid ? j0 * BS + t : 0)) * D;
 #pragma unroll
     for (int cc = 0; cc < CPT; cc += 2) {
       const int c = part * CPT + cc;
-      r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+      if (TPR > 1 || cc < D)
+        r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+      else
+        r.v[cc / 2] = make_float2(0.f, 0.f);
     }
     return r;
   };
-  auto commit = [&](int j, const RowRegs<CPT>& r, T* X) {
-    (void)j;
+  auto commit = [&](int j0, int nb, const RowRegs<CPT>& r, T* X) {
+    (void)j0;
+    if (t >= nb * BS) return;
     float v[CPT];
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
@@ -796,28 +879,33 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   __shared__ NetSmem<Net, P> sm;
   const int tid = threadIdx.x;
   const int64_t b0 = (int64_t)blockIdx.x * MT;
-  constexpr int ROWS = MT * BS, TPR = NT / ROWS, CPT = DP / TPR;
+  constexpr int GSL = G::NG * BS;
+  constexpr int ROWS = MT * GSL, TPR = NT / ROWS, CPT = DP / TPR;
   const int row = tid / TPR, part = tid % TPR;
-  const int s = row / BS, t = row % BS;
+  const int s = row / GSL, t = row % GSL;
   static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
   if constexpr (P::SCALED) {
     for (int c = tid; c < D; c += NT) sm.x_inv[c] = wt.x_inv[c];
     __syncthreads();
   }
   const int64_t b = b0 + s;
-  auto load = [&](int j) {
+  auto load = [&](int j0, int nb) {
     RowRegs<CPT> r;
-    r.valid = b < B;
-    const float* src = x + ((b < B ? b : 0) * L + j * BS + t) * D;
+    r.valid = b < B && t < nb * BS;
+    const float* src = x + ((r.valid ? b : 0) * L + (r.valid ? j0 * BS + t : 0)) * D;
 #pragma unroll
     for (int cc = 0; cc < CPT; cc += 2) {
       const int c = part * CPT + cc;
-      r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+      if (TPR > 1 || cc < D)
+        r.v[cc / 2] = *reinterpret_cast<const float2*>(src + (c < D ? c : D - 2));
+      else
+        r.v[cc / 2] = make_float2(0.f, 0.f);
     }
     return r;
   };
-  auto commit = [&](int j, const RowRegs<CPT>& r, T* X) {
-    (void)j;
+  auto commit = [&](int j0, int nb, const RowRegs<CPT>& r, T* X) {
+    (void)j0;
+    if (t >= nb * BS) return;
     float v[CPT];
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {

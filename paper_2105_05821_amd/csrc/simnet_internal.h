@@ -141,6 +141,7 @@ hipError_t launch_forward_save(int prec, const DevWeights& w, uint32_t relu, con
 // A GEMM operand: element (r, c) at p[(r / grp) * gs + (r % grp) * rs + c * cs]
 // (grp splits the rows into groups with their own stride, e.g. the window
 // rows of a batch of 111-slot windows), FP32 or BF16.
+constexpr int64_t NO_GROUP = (int64_t)1 << 62;  // GemmOperand.grp of an ungrouped operand
 struct GemmOperand {
   const void* p;
   int32_t bf16;
@@ -155,8 +156,14 @@ struct GemmArgs {
   int64_t M, N, K;
   const float* bias;
   int32_t beta;
+  // set by launch_gemm
+  int32_t ksplit, amode, avec, bmode, bvec;
+  float* part;
 };
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t stream);
+// bf16_mma: BF16 MFMA with operands rounded to BF16 (else FP32 MFMA).  part
+// (part_cap floats, may be NULL) is scratch for split-K partial products.
+hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
+                       hipStream_t stream);
 hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
                        float* loss_b, float* loss, float* dz, hipStream_t stream);
 size_t colsum_workspace(int64_t N);

@@ -1,10 +1,12 @@
 // Training-form kernels of libsimnet.so (gfx950): the pieces of a predictor
 // training step that are not the fused trunk forward.
 //
-//   gemm_kernel      C = op(A) x op(B) on FP32 MFMA, LDS-staged 64x64 tiles;
-//                    operands in FP32 or BF16 with arbitrary strides; epilogue
-//                    with bias, ReLU mask (a saved activation > 0) and
-//                    accumulation.  Used for the head and for every
+//   gemm kernels     C = op(A) x op(B): FP32 form on FP32 MFMA (64x64
+//                    tiles), BF16 form on BF16 MFMA (128x128 tiles, operands
+//                    rounded to BF16 in LDS); operands in FP32 or BF16 with
+//                    arbitrary strides; split-K with an ordered reduction
+//                    when the output is small; epilogue with bias, ReLU mask
+//                    (a saved activation > 0) and accumulation.  Used for the head and for every
 //                    input-gradient and weight-gradient product of the
 //                    backward pass (a kernel-2 stride-2 convolution is a
 //                    GEMM over position pairs).
@@ -25,8 +27,61 @@ __device__ __forceinline__ float ld_elem(const void* p, int bf16, int64_t i) {
   return static_cast<const float*>(p)[i];
 }
 
+// Rows are grouped (row r at (r / grp) * gs + (r % grp) * rs) only where an
+// operand skips memory between groups of rows; ungrouped operands carry
+// grp >= NO_GROUP and take no division.  Grouped row indices are below
+// 2^32 (the host checks), so their division is 32-bit.
+__device__ __forceinline__ int64_t grouped_row(int64_t r, int64_t grp, int64_t gs, int64_t rs) {
+  if (grp >= NO_GROUP) return r * rs;
+  const uint32_t q = (uint32_t)r / (uint32_t)grp;
+  return (int64_t)q * gs + (int64_t)((uint32_t)r - q * (uint32_t)grp) * rs;
+}
+
 __device__ __forceinline__ int64_t op_index(const GemmOperand& o, int64_t r, int64_t c) {
-  return (r / o.grp) * o.gs + (r % o.grp) * o.rs + c * o.cs;
+  return grouped_row(r, o.grp, o.gs, o.rs) + c * o.cs;
+}
+
+// C(m, n) epilogue shared by every GEMM path: bias, ReLU mask, accumulate,
+// grouped row addressing.
+__device__ __forceinline__ void gemm_store(const GemmArgs& g, int64_t m, int64_t n, float v) {
+  if (g.bias) v += g.bias[n];
+  if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, op_index(g.mask, m, n)) > 0.f)) v = 0.f;
+  float* c = g.C + grouped_row(m, g.cgrp, g.cgs, g.ldc) + n;
+  *c = g.beta ? *c + v : v;
+}
+
+// The same for the four columns n0 + 16*j (j < 4) of one row m, with the
+// row's addresses computed once.
+__device__ __forceinline__ void gemm_store_row4(const GemmArgs& g, int64_t m, int64_t n0,
+                                                const float (&v)[4]) {
+  float* crow = g.C + grouped_row(m, g.cgrp, g.cgs, g.ldc);
+  const int64_t mrow = g.mask.p ? grouped_row(m, g.mask.grp, g.mask.gs, g.mask.rs) : 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t n = n0 + 16 * j;
+    if (n >= g.N) continue;
+    float x = v[j];
+    if (g.bias) x += g.bias[n];
+    if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, mrow + n * g.mask.cs) > 0.f)) x = 0.f;
+    crow[n] = g.beta ? crow[n] + x : x;
+  }
+}
+
+// Split-K: workgroup z covers k in [z*kc, min(K, (z+1)*kc)) and writes its
+// raw partial product to part[z][M][N]; gemm_reduce sums the partials in
+// order and applies the epilogue.
+__device__ __forceinline__ void k_range(const GemmArgs& g, int step, int64_t* kb, int64_t* ke) {
+  const int64_t per = (g.K + g.ksplit - 1) / g.ksplit;
+  const int64_t kc = (per + step - 1) / step * step;
+  *kb = (int64_t)blockIdx.z * kc;
+  *ke = *kb + kc < g.K ? *kb + kc : g.K;
+}
+
+__device__ __forceinline__ void gemm_out(const GemmArgs& g, int64_t m, int64_t n, float v) {
+  if (g.ksplit > 1)
+    g.part[((int64_t)blockIdx.z * g.M + m) * g.N + n] = v;
+  else
+    gemm_store(g, m, n, v);
 }
 
 constexpr int GB = 64, GK = 16, GPAD = 4;
@@ -37,7 +92,7 @@ __device__ __forceinline__ void load_tile(const GemmOperand& o, int64_t R, int64
                                           int64_t c0, bool rows_are_k, int tid, float (&v)[4],
                                           int (&rr)[4], int (&cc)[4]) {
   // tile is GB (non-k) x GK (k); "along" = the contiguous dimension
-  const bool k_contig = rows_are_k ? (o.rs == 1 && o.grp > (int64_t)1 << 40) : (o.cs == 1);
+  const bool k_contig = rows_are_k ? (o.rs == 1 && o.grp >= NO_GROUP) : (o.cs == 1);
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     int kk, mm;
@@ -57,32 +112,35 @@ __device__ __forceinline__ void load_tile(const GemmOperand& o, int64_t R, int64
   }
 }
 
+// FP32 form: 64x64 tiles on mfma_f32_16x16x4f32, 2x2 waves of 32x32.
 __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
   __shared__ float As[GK][GB + GPAD];  // [k][m]
   __shared__ float Bs[GK][GB + GPAD];  // [k][n]
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t m0 = (int64_t)blockIdx.y * GB, n0 = (int64_t)blockIdx.x * GB;
   const int wm = wave >> 1, wn = wave & 1;
+  int64_t kb, ke;
+  k_range(g, GK, &kb, &ke);
   v4f acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   float va[4], vb[4];
-  int ka[4], ma[4], kb[4], nb[4];
-  load_tile(g.A, g.M, g.K, m0, 0, false, tid, va, ka, ma);
-  load_tile(g.B, g.K, g.N, 0, n0, true, tid, vb, kb, nb);
-  for (int64_t k0 = 0; k0 < g.K; k0 += GK) {
+  int ka[4], ma[4], kb4[4], nb[4];
+  load_tile(g.A, g.M, ke, m0, kb, false, tid, va, ka, ma);
+  load_tile(g.B, ke, g.N, kb, n0, true, tid, vb, kb4, nb);
+  for (int64_t k0 = kb; k0 < ke; k0 += GK) {
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       As[ka[e]][ma[e]] = va[e];
-      Bs[kb[e]][nb[e]] = vb[e];
+      Bs[kb4[e]][nb[e]] = vb[e];
     }
     __syncthreads();
-    if (k0 + GK < g.K) {  // next tile in flight while this one is multiplied
-      load_tile(g.A, g.M, g.K, m0, k0 + GK, false, tid, va, ka, ma);
-      load_tile(g.B, g.K, g.N, k0 + GK, n0, true, tid, vb, kb, nb);
+    if (k0 + GK < ke) {  // next tile in flight while this one is multiplied
+      load_tile(g.A, g.M, ke, m0, k0 + GK, false, tid, va, ka, ma);
+      load_tile(g.B, ke, g.N, k0 + GK, n0, true, tid, vb, kb4, nb);
     }
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 4) {
@@ -108,20 +166,271 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int64_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + r;
         const int64_t n = n0 + wn * 32 + j * 16 + (lane & 15);
-        if (m < g.M && n < g.N) {
-          float v = acc[i][j][r];
-          if (g.bias) v += g.bias[n];
-          if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, op_index(g.mask, m, n)) > 0.f)) v = 0.f;
-          float* c = g.C + (m / g.cgrp) * g.cgs + (m % g.cgrp) * g.ldc + n;
-          *c = g.beta ? *c + v : v;
-        }
+        if (m < g.M && n < g.N) gemm_out(g, m, n, acc[i][j][r]);
       }
 }
 
-hipError_t launch_gemm(const GemmArgs& g, hipStream_t stream) {
+// BF16 form: 128x128 tiles, k-steps of 32 on mfma_f32_16x16x32_bf16, 2x2
+// waves of 64x64, operands rounded to BF16 (nearest even) into LDS, FP32
+// accumulation.  Both LDS tiles are [outer][k] so that a lane's fragment (8
+// consecutive k of one row or column) is one 16-byte read.  Each thread
+// stages 16 elements of each operand per k-step, read along the operand's
+// contiguous dimension: mode 1 = along k (written to LDS as two 16-byte
+// runs), mode 2 = along the outer dimension (written as 16 scalars, a
+// transpose), mode 0 = no unit stride (scalar reads, k-major mapping).
+constexpr int HB = 128, HK = 32, HLD = HK + 8;
+
+typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+struct Stage {
+  float v[16];
+};
+
+// Element (outer, k) of an operand: A is (m, k), B is (k, n).
+__device__ __forceinline__ int64_t elem_addr(const GemmOperand& o, bool is_b, int64_t outer,
+                                             int64_t k) {
+  return is_b ? op_index(o, k, outer) : op_index(o, outer, k);
+}
+
+__device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int mode, bool vec,
+                                           int64_t outer0, int64_t k0, int64_t outer_lim,
+                                           int64_t k_lim, int tid, Stage& st) {
+  int64_t outer, k;
+  int cnt;
+  if (mode == 2) {
+    k = k0 + tid / 8;
+    outer = outer0 + (tid % 8) * 16;
+    const int64_t left = outer_lim - outer;
+    cnt = k < k_lim ? (left > 16 ? 16 : (left > 0 ? (int)left : 0)) : 0;
+  } else {
+    outer = outer0 + tid / 2;
+    k = k0 + (tid % 2) * 16;
+    const int64_t left = k_lim - k;
+    cnt = outer < outer_lim ? (left > 16 ? 16 : (left > 0 ? (int)left : 0)) : 0;
+  }
+  if (mode != 0 && vec && cnt == 16) {
+    const int64_t a = elem_addr(o, is_b, outer, k);
+    if (o.bf16) {
+      const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(o.p) + a);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint4 w = p[h];
+        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          st.v[h * 8 + 2 * q] = __uint_as_float(ws[q] << 16);
+          st.v[h * 8 + 2 * q + 1] = __uint_as_float(ws[q] & 0xffff0000u);
+        }
+      }
+    } else {
+      const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(o.p) + a);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const float4 w = p[h];
+        st.v[4 * h] = w.x;
+        st.v[4 * h + 1] = w.y;
+        st.v[4 * h + 2] = w.z;
+        st.v[4 * h + 3] = w.w;
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int e = 0; e < 16; ++e) {
+    float v = 0.f;
+    if (e < cnt)
+      v = ld_elem(o.p, o.bf16,
+                  mode == 2 ? elem_addr(o, is_b, outer + e, k) : elem_addr(o, is_b, outer, k + e));
+    st.v[e] = v;
+  }
+}
+
+// LDS tiles hold 8-element (16-byte) k-chunks; chunk c of row r sits at
+// position c ^ ((r >> 4) & 3), so that the transposing stores of rows 16
+// apart (same banks otherwise) spread over four bank groups.
+__device__ __forceinline__ int chunk_at(int row, int c) { return c ^ ((row >> 4) & 3); }
+
+__device__ __forceinline__ void stage_store(uint16_t (*S)[HLD], int mode, int tid,
+                                            const Stage& st) {
+  if (mode == 2) {
+    const int k = tid / 8, outer = (tid % 8) * 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      S[outer + e][8 * chunk_at(outer + e, k >> 3) + (k & 7)] = bf16_rne(st.v[e]);
+  } else {
+    const int outer = tid / 2, c0 = (tid % 2) * 2;
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      w[q] = (uint32_t)bf16_rne(st.v[2 * q]) | ((uint32_t)bf16_rne(st.v[2 * q + 1]) << 16);
+    *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0)]) = uint4{w[0], w[1], w[2], w[3]};
+    *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0 + 1)]) =
+        uint4{w[4], w[5], w[6], w[7]};
+  }
+}
+
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][HB][HLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HB][HLD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.y * HB, n0 = (int64_t)blockIdx.x * HB;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t kb, ke;
+  k_range(g, HK, &kb, &ke);
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  Stage sa, sb;
+  stage_load(g.A, false, g.amode, g.avec, m0, kb, g.M, ke, tid, sa);
+  stage_load(g.B, true, g.bmode, g.bvec, n0, kb, g.N, ke, tid, sb);
+  stage_store(As[0], g.amode, tid, sa);
+  stage_store(Bs[0], g.bmode, tid, sb);
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += HK) {
+    const bool more = k0 + HK < ke;
+    if (more) {  // next k-step's operands in flight during this one's MFMAs
+      stage_load(g.A, false, g.amode, g.avec, m0, k0 + HK, g.M, ke, tid, sa);
+      stage_load(g.B, true, g.bmode, g.bvec, n0, k0 + HK, g.N, ke, tid, sb);
+    }
+    uint4 af[4], bfr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm * 64 + i * 16 + (lane & 15);
+      af[i] = *reinterpret_cast<const uint4*>(&As[cur][row][8 * chunk_at(row, lane >> 4)]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wn * 64 + j * 16 + (lane & 15);
+      bfr[j] = *reinterpret_cast<const uint4*>(&Bs[cur][row][8 * chunk_at(row, lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf_t, af[i]),
+                                                           __builtin_bit_cast(v8bf_t, bfr[j]),
+                                                           acc[i][j], 0, 0, 0);
+    if (more) {
+      stage_store(As[cur ^ 1], g.amode, tid, sa);
+      stage_store(Bs[cur ^ 1], g.bmode, tid, sb);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const int64_t nb = n0 + wn * 64 + (lane & 15);
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
+      if (m >= g.M) continue;
+      const float v[4] = {acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
+      if (g.ksplit > 1) {
+        float* prow = g.part + ((int64_t)blockIdx.z * g.M + m) * g.N;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          if (nb + 16 * j < g.N) prow[nb + 16 * j] = v[j];
+      } else {
+        gemm_store_row4(g, m, nb, v);
+      }
+    }
+}
+
+// out[n] = sum_{c < cnt} src[c * stride + n] for n < N, in a fixed order:
+// 64 outputs per workgroup, four lanes per output summing every fourth c,
+// then the four partial sums in lane order.  Split-K partials (with the
+// GEMM epilogue) and column-sum partials both reduce through this.
+template <bool GEMM>
+__global__ void __launch_bounds__(256) strided_reduce(const float* __restrict__ src, int64_t cnt,
+                                                      int64_t stride, int64_t N, GemmArgs g,
+                                                      float* __restrict__ out, int beta) {
+  __shared__ float red[4][64];
+  const int col = threadIdx.x % 64, lane4 = threadIdx.x / 64;
+  const int64_t n = (int64_t)blockIdx.x * 64 + col;
+  float s = 0.f;
+  if (n < N) {
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    int64_t c = lane4;
+    for (; c + 12 < cnt; c += 16) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += src[(c + 4 * u) * stride + n];
+    }
+    for (; c < cnt; c += 4) acc[0] += src[c * stride + n];
+    s = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  }
+  red[lane4][col] = s;
+  __syncthreads();
+  if (lane4 == 0 && n < N) {
+    const float v = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
+    if constexpr (GEMM) {
+      gemm_store(g, n / g.N, n % g.N, v);
+    } else {
+      out[n] = beta ? out[n] + v : v;
+    }
+  }
+}
+
+// Operand access mode for the BF16 kernel (see gemm_bf16_kernel) and whether
+// 16-byte vector reads are aligned.
+static void operand_mode(const GemmOperand& o, bool is_b, int32_t* mode, int32_t* vec) {
+  const bool grouped = o.grp < NO_GROUP;
+  const int64_t k_stride = is_b ? o.rs : o.cs, outer_stride = is_b ? o.cs : o.rs;
+  const bool k_is_row = is_b;  // grouping applies to the row index
+  if (k_stride == 1 && !(k_is_row && grouped))
+    *mode = 1;
+  else if (outer_stride == 1 && !(!k_is_row && grouped))
+    *mode = 2;
+  else
+    *mode = 0;
+  const int64_t q = o.bf16 ? 8 : 4;  // elements per 16 bytes
+  const int64_t other = *mode == 1 ? outer_stride : k_stride;
+  *vec = *mode != 0 && (reinterpret_cast<uintptr_t>(o.p) % 16 == 0) && other % q == 0 &&
+         (!grouped || o.gs % q == 0);
+}
+
+hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
+                       hipStream_t stream) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  const dim3 grid((unsigned)((g.N + GB - 1) / GB), (unsigned)((g.M + GB - 1) / GB));
-  hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, stream, g);
+  const int TB = bf16_mma ? HB : GB;
+  const int64_t tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);
+  // split K when the output is too small to fill the chip: aim at ~1024
+  // workgroups, at least 8 k-steps each, within the partial buffer
+  int64_t ks = 1;
+  if (part && tiles < 512) {
+    ks = (1024 + tiles - 1) / tiles;
+    const int64_t steps = g.K / ((bf16_mma ? HK : GK) * 8);
+    if (ks > steps) ks = steps;
+    if (ks > part_cap / (g.M * g.N)) ks = part_cap / (g.M * g.N);
+    if (ks > 65535) ks = 65535;
+    if (ks < 2) ks = 1;
+  }
+  // grouped rows are divided in 32 bits
+  const int64_t big = (int64_t)1 << 32;
+  if ((g.A.grp < NO_GROUP && g.M >= big) || (g.B.grp < NO_GROUP && g.K >= big) ||
+      (g.mask.p && g.mask.grp < NO_GROUP && g.M >= big) || (g.cgrp < NO_GROUP && g.M >= big))
+    return hipErrorInvalidValue;
+  g.ksplit = (int32_t)ks;
+  g.part = part;
+  operand_mode(g.A, false, &g.amode, &g.avec);
+  operand_mode(g.B, true, &g.bmode, &g.bvec);
+  const dim3 grid((unsigned)((g.N + TB - 1) / TB), (unsigned)((g.M + TB - 1) / TB), (unsigned)ks);
+  if (bf16_mma)
+    hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
+  else
+    hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, stream, g);
+  if (ks > 1) {
+    const int64_t MN = g.M * g.N;
+    hipLaunchKernelGGL(strided_reduce<true>, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, stream,
+                       part, ks, MN, MN, g, nullptr, 0);
+  }
   return hipGetLastError();
 }
 
@@ -189,35 +498,47 @@ hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_
   return hipGetLastError();
 }
 
-// Column sums of Y [M][ld] over rows, in two fixed-order passes.
-constexpr int CS_CHUNKS = 128;
-__global__ void colsum_partial(const float* __restrict__ y, int64_t M, int64_t N, int64_t ld,
-                               float* __restrict__ part) {
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  const int64_t c = blockIdx.y;
-  const int64_t per = (M + CS_CHUNKS - 1) / CS_CHUNKS;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int64_t m = c * per; m < M && m < (c + 1) * per; ++m) s += y[m * ld + n];
-  part[c * N + n] = s;
+// Column sums of Y [M][ld] over rows in a fixed order: chunks of rows
+// summed by 4 row lanes x 64 columns per workgroup, then the chunk partials
+// through strided_reduce.
+constexpr int CS_MAX_CHUNKS = 1024;
+__global__ void __launch_bounds__(256) colsum_partial(const float* __restrict__ y, int64_t M,
+                                                      int64_t N, int64_t ld, int64_t per,
+                                                      float* __restrict__ part) {
+  __shared__ float red[4][64];
+  const int col = threadIdx.x % 64, lane4 = threadIdx.x / 64;
+  const int64_t n = (int64_t)blockIdx.x * 64 + col;
+  const int64_t c = blockIdx.y, lo = c * per, hi = lo + per < M ? lo + per : M;
+  float acc[2] = {0.f, 0.f};
+  if (n < N) {
+    int64_t m = lo + lane4;
+    for (; m + 4 < hi; m += 8) {
+      acc[0] += y[m * ld + n];
+      acc[1] += y[(m + 4) * ld + n];
+    }
+    for (; m < hi; m += 4) acc[0] += y[m * ld + n];
+  }
+  red[lane4][col] = acc[0] + acc[1];
+  __syncthreads();
+  if (lane4 == 0 && n < N)
+    part[c * N + n] = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
 }
 
-__global__ void colsum_final(const float* __restrict__ part, int64_t N, float* __restrict__ out,
-                             int beta) {
-  const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int c = 0; c < CS_CHUNKS; ++c) s += part[c * N + n];
-  out[n] = beta ? out[n] + s : s;
-}
-
-size_t colsum_workspace(int64_t N) { return sizeof(float) * CS_CHUNKS * (size_t)N; }
+size_t colsum_workspace(int64_t N) { return sizeof(float) * CS_MAX_CHUNKS * (size_t)N; }
 
 hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float* out, int beta,
                          float* work, hipStream_t stream) {
-  const unsigned nb = (unsigned)((N + 255) / 256);
-  hipLaunchKernelGGL(colsum_partial, dim3(nb, CS_CHUNKS), dim3(256), 0, stream, y, M, N, ld, work);
-  hipLaunchKernelGGL(colsum_final, dim3(nb), dim3(256), 0, stream, work, N, out, beta);
+  if (N <= 0) return hipSuccess;
+  int64_t chunks = (M + 63) / 64;
+  if (chunks > CS_MAX_CHUNKS) chunks = CS_MAX_CHUNKS;
+  if (chunks < 1) chunks = 1;
+  const int64_t per = (M + chunks - 1) / chunks;
+  const unsigned nb = (unsigned)((N + 63) / 64);
+  hipLaunchKernelGGL(colsum_partial, dim3(nb, (unsigned)chunks), dim3(256), 0, stream, y, M, N, ld,
+                     per, work);
+  GemmArgs none{};
+  hipLaunchKernelGGL(strided_reduce<false>, dim3(nb), dim3(256), 0, stream, work, chunks, N, N,
+                     none, out, beta);
   return hipGetLastError();
 }
 

@@ -316,6 +316,42 @@ def analytic_latencies(fields: dict) -> np.ndarray:
     return out
 
 
+# -------------------------------------------------------- training batches ---
+
+TRAIN_STREAM = 401
+
+
+def training_batch(trace_seed: int, n_instr: int, n_feat: int, n_slot: int, B: int,
+                   batch_seed: int):
+    """Synthetic training contexts labelled by ``analytic_latencies``.
+
+    Context b ends at trace row i_b (uniform in [n_slot, n_instr)) and holds
+    occ_b (uniform in [0, n_slot)) older rows: slot 0 is row i_b with the
+    dynamic columns zero, slot k the row i_b - k with residence = the fetch
+    cycles from its fetch to i_b's and execution = its analytic execution
+    latency; slots past occ_b are zero.  Labels are row i_b's (fetch,
+    execution) latencies.  Returns x float32 [B][n_slot][n_feat] and labels
+    int32 [B][2]."""
+    fields = trace_fields(trace_seed, 0, n_instr)
+    lab = analytic_latencies(fields)
+    feat = trace_features(trace_seed, n_instr, n_feat)
+    cres, cexe, _ = dynamic_columns(n_feat)
+    ctr = np.arange(B, dtype=np.uint64) * np.uint64(2)
+    rows = n_slot + (uniform(batch_seed, TRAIN_STREAM, ctr) * (n_instr - n_slot)).astype(np.int64)
+    occ = (uniform(batch_seed, TRAIN_STREAM, ctr + np.uint64(1)) * n_slot).astype(np.int64)
+    k = np.arange(n_slot)
+    src = rows[:, None] - k[None, :]                       # [B][n_slot]
+    live = k[None, :] <= occ[:, None]
+    x = np.where(live[:, :, None], feat[np.maximum(src, 0)], 0.0).astype(np.float32)
+    cum = np.concatenate([[0], np.cumsum(lab[:, 0].astype(np.int64))])
+    res = cum[rows + 1][:, None] - cum[np.maximum(src, 0) + 1]
+    x[:, :, cres] = np.where(live, res, 0)
+    x[:, :, cexe] = np.where(live, lab[np.maximum(src, 0), 1], 0)
+    x[:, 0, cres] = 0
+    x[:, 0, cexe] = 0
+    return x, lab[rows].astype(np.int32)
+
+
 # ------------------------------------------------------------ sub-traces ---
 
 LEN_STREAM = 301
@@ -375,6 +411,8 @@ def workload(name: str) -> Workload:
         return Workload("tiny", 10_000, 32, 16, net_small())
     if name == "c3_1m":       # 1M instructions, 4,096 sub-traces, 256 warm-up, 111 x 50
         return Workload("c3_1m", 1_000_000, 50, 111, net_c3(), n_sub=4096, warmup=256)
+    if name == "c3_train":    # 4,096 labelled contexts per step, hybrid head, BF16
+        return Workload("c3_train", 200_000, 50, 111, net_c3_hybrid(), extra={"batch": 4096})
     if name == "c3_uneven":   # 20k independent streams, log-uniform lengths 1e3..2e5
         return Workload("c3_uneven", 0, 50, 111, net_c3(), n_sub=20_000, lengths="loguniform")
     raise KeyError(name)

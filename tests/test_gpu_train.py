@@ -127,6 +127,30 @@ def test_train_gradients_match_oracle_f32(torch, sn, oracle_lib, B):
     pred.close()
 
 
+def test_train_gradients_bf16_form_match_oracle(torch, sn, oracle_lib):
+    """BF16 form against the oracle's FP64 evaluation of the same form (the
+    same values rounded to bfloat16 at the same points).  The GPU sums in
+    FP32, so a value whose FP32 sum lands on the other side of a bfloat16
+    rounding boundary moves by one bfloat16 unit (2^-8 relative) and carries
+    that into what it feeds; such values are a small fraction, so each
+    tensor's normwise relative error stays well under one unit: bar 2^-8.
+    The loss is held to 1e-4 relative."""
+    B = 40
+    layers, ws, bs, x, lat = inputs(B, 51)
+    pred = sn.Predictor(layers, sn.SIM_BF16)
+    pred.load_weights(layers, sn.flat_params(ws, bs))
+    loss, dz, dp, dx = gpu_grads(torch, sn, pred, x, lat)
+    ref = oracle_lib.train_step(oracle_lib.Model(layers, ws, bs, D, L, prec=1), x, lat,
+                                want_dlogits=True, want_dx=True)
+    assert abs(loss - ref["loss"]) <= 1e-4 * abs(ref["loss"]), (loss, ref["loss"])
+    errs = {"dlogits": normwise(dz, ref["dlogits"]), "dx": normwise(dx, ref["dx"])}
+    for (kind, lo, hi), li in zip(layer_slices(layers), np.repeat(np.arange(len(layers)), 2)):
+        errs[f"{li}{kind}"] = normwise(dp[lo:hi], ref["dparams"][lo:hi])
+    print("bf16 form gradient normwise errors", {k: f"{v:.2e}" for k, v in errs.items()})
+    assert max(errs.values()) <= 2.0 ** -8, errs
+    pred.close()
+
+
 def test_train_finite_differences_f32(torch, sn):
     """(L(p + h u) - L(p - h u)) / 2h along u = g_l / |g_l| for each layer's
     weight tensor, and along dx / |dx| for the windows; the GPU loss at the
