@@ -98,12 +98,19 @@ struct Geo {
   using T = typename P::T;
   static constexpr int NT = Net::WAVES * 64;
   static constexpr int NG = group_blocks<Net, P>();
-  static constexpr int PAD = 16 / sizeof(T);                       // 16 bytes of row padding
+  static constexpr int PAD = 16 / sizeof(T);                       // 16 bytes of padding
   static constexpr int DP = padded_feat(Net::D, P::ID);            // features per slot
-  static constexpr int SX = NG * Net::BS * DP + PAD;               // a group's window rows, per window
-  static constexpr int SA1 = NG * (Net::BS / 2) * Net::CH1 + PAD;  // conv1 output
-  static constexpr int SA2 = NG * (Net::BS / 4) * Net::CH2 + PAD;  // conv2 output
-  static constexpr int SA3 = (Net::NCONV == 3 ? NG * Net::CH3 : 0) + PAD;  // conv3 output
+  // A conv reads rows of two consecutive input positions; each such pair is
+  // followed by 16 bytes of padding, so the 16 rows of an MFMA tile (16
+  // positions) fall in different LDS banks.  R* = elements per pair.
+  static constexpr int RX = 2 * DP + PAD;                          // slot pair (conv1 row)
+  static constexpr int R1 = 2 * Net::CH1 + PAD;                    // conv1 output pair
+  static constexpr int R2 = 2 * Net::CH2 + PAD;                    // conv2 output pair (C3)
+  static constexpr int SX = (NG * Net::BS / 2) * RX + PAD;         // a group's window rows, per window
+  static constexpr int SA1 = (NG * Net::BS / 4) * R1 + PAD;        // conv1 output
+  static constexpr int SA2 = Net::NCONV == 3 ? (NG * Net::BS / 8) * R2 + PAD  // conv2 output
+                                             : NG * Net::CH2 + PAD;  // (last conv: flat)
+  static constexpr int SA3 = (Net::NCONV == 3 ? NG * Net::CH3 : 0) + PAD;  // conv3 output (flat)
   static constexpr int SAL = Net::NCONV == 3 ? SA3 : SA2;          // last conv output
   // three conv levels: X and conv2's output share memory (X is dead once
   // conv1 has read it), and so do conv1's and conv3's outputs
@@ -238,13 +245,15 @@ __device__ __forceinline__ void store_run(T* dst, const T (&e)[N]) {
 
 // One conv level as a GEMM: rows (s, q) = MT windows x POS output positions,
 // A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
-// 2q+1 at A + s*SA + q*K; output row (s, q) goes to O + s*SO + q*N.  The
+// 2q+1 at A + s*SA + q*IRS; output row (s, q) goes to O + s*SO + q*N, or,
+// OPAIR, to O + s*SO + (q/2)*(2N + 16 bytes) + (q%2)*N (the padded pair
+// layout the next conv reads).  The
 // waves split the N tiles first (each weight fragment is read by as few
 // waves as possible), then the M tiles; a wave runs MPW x NPW tiles.
 // SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
 // s < sv_rows only), the layer's activations kept for the backward pass.
-template <class P, int K, int N, int POS, int WAVES, int SA, int SO, bool CAL = false,
-          bool SAVE = false>
+template <class P, int K, int N, int POS, int WAVES, int SA, int IRS, int SO, bool OPAIR,
+          bool CAL = false, bool SAVE = false>
 __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
                                            typename P::T* __restrict__ O,
                                            const uint4* __restrict__ Bp,
@@ -269,7 +278,7 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
     const int row = (wm * MPW + i) * 16 + (lane & 15);
-    ap[i] = A + (row / POS) * SA + (row % POS) * K + (P::KG / 4) * (lane >> 4);
+    ap[i] = A + (row / POS) * SA + (row % POS) * IRS + (P::KG / 4) * (lane >> 4);
   }
   v4f acc[MPW][NPW];
 #pragma unroll
@@ -280,7 +289,9 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
     const int row = (wm * MPW + i) * 16 + (lane & 15);
-    T* orow = O + (row / POS) * SO + (row % POS) * N;
+    constexpr int ORS = 2 * N + 16 / (int)sizeof(T);
+    const int q = row % POS;
+    T* orow = O + (row / POS) * SO + (OPAIR ? (q >> 1) * ORS + (q & 1) * N : q * N);
     const bool live = !CAL || row_live[row / POS];
 #pragma unroll
     for (int j = 0; j < NPW; ++j) {
@@ -329,18 +340,20 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int P1 = NBG * Net::BS / 2, P2 = NBG * Net::BS / 4;
   constexpr int Q1 = Net::BS / 2, Q2 = Net::BS / 4;  // positions per block
-  conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::SA1, CAL, SAVE>(
+  conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::RX, G::SA1, true, CAL, SAVE>(
       sm.x(), sm.a1(), static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
       wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live,
       sv.a1 + (size_t)j0 * Q1 * Net::CH1, (int64_t)Net::NB * Q1 * Net::CH1, sv.rows);
   __syncthreads();
-  conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::SA2, CAL, SAVE>(
+  conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::R1, G::SA2, Net::NCONV == 3,
+             CAL, SAVE>(
       sm.a1(), sm.a2(), static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
       wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live,
       sv.a2 + (size_t)j0 * Q2 * Net::CH2, (int64_t)Net::NB * Q2 * Net::CH2, sv.rows);
   __syncthreads();
   if constexpr (Net::NCONV == 3) {
-    conv_stage<P, 2 * Net::CH2, Net::CH3, NBG, Net::WAVES, G::SA2, G::SA3, CAL, SAVE>(
+    conv_stage<P, 2 * Net::CH2, Net::CH3, NBG, Net::WAVES, G::SA2, G::R2, G::SA3, false, CAL,
+               SAVE>(
         sm.a2(), sm.a3(), static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
         wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2, row_live,
         sv.a3 + (size_t)j0 * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows);
@@ -383,7 +396,8 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
 // The whole predictor on one tile of MT windows.  The window arrives a group
 // of NG blocks (NG*BS slots) at a time: load(j0, nb) requests the rows of
 // blocks j0 .. j0+nb-1 into registers, commit(j0, nb, regs, X) writes them,
-// in storage precision, to X[s*SX + t*DP + c] (t = slot within the group).
+// in storage precision, to X at window s, slot t of the group, feature c
+// (slot pairs padded, see Geo).
 // The next group's rows are requested after the current group's conv levels
 // and committed before its FC, so their memory latency is hidden.  Both are
 // called by all threads; the raw outputs land in sm.logit.  CAL: also record
@@ -702,7 +716,8 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     T e[CPT];
     window_elems<P, CPT, D>(v, sm.net.x_inv, part * CPT, e);
-    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(X + gs * G::SX + gt * DP + part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(
+        X + gs * G::SX + (gt >> 1) * G::RX + (gt & 1) * DP + part * CPT, e);
   };
 
   int any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
@@ -858,7 +873,8 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     T e[CPT];
     window_elems<P, CPT, D>(v, sm.x_inv, part * CPT, e);
-    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(X + s * G::SX + t * DP + part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(
+        X + s * G::SX + (t >> 1) * G::RX + (t & 1) * DP + part * CPT, e);
   };
   predict_tile<Net, P>(wt, relu_mask, sm, load, commit);
   if (tid < MT * Net::NOUT) {
@@ -914,7 +930,8 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     T e[CPT];
     window_elems<P, CPT, D>(v, sm.x_inv, part * CPT, e);
-    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(X + s * G::SX + t * DP + part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(
+        X + s * G::SX + (t >> 1) * G::RX + (t & 1) * DP + part * CPT, e);
   };
   SavePtrs<T> sv;
   sv.a1 = static_cast<T*>(sb.a1) + b0 * (Net::NB * BS / 2) * Net::CH1;
