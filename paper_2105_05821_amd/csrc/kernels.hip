@@ -157,10 +157,10 @@ __device__ __forceinline__ void cal_max(unsigned* cal, int i, float v) {
   atomicMax(cal + i, __float_as_uint(fabsf(v)));
 }
 
-// k-groups per chunk when streaming B: two chunks of TPW fragments in flight
-// are at most 16 fragments (64 VGPRs) per lane; must divide the k-groups.
-constexpr int stream_chunk(int kgs, int tpw) {
-  int c = 8 / tpw;
+// k-groups per chunk when streaming B: a chunk is at most FRAGS fragments
+// (4 VGPRs each) and two chunks are in flight; must divide the k-groups.
+constexpr int stream_chunk(int kgs, int tpw, int frags = 8) {
+  int c = frags / tpw;
   if (c < 1) c = 1;
   if (c > kgs) c = kgs;
   while (kgs % c) --c;
@@ -182,11 +182,11 @@ __device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_of
 // weight fragment serves MPW m-tiles.  Weight fragments are requested one
 // chunk ahead of their use (double buffering) and the scheduler is kept
 // from sinking the requests.
-template <class P, int KGS, int NTILES, int NPW, int MPW>
+template <class P, int KGS, int NTILES, int NPW, int MPW, int FRAGS = 8>
 __device__ __forceinline__ void mma_stream(v4f (&acc)[MPW][NPW],
                                            const typename P::T* const (&ap)[MPW],
                                            const uint4* __restrict__ Bp, int nt0, int lane) {
-  constexpr int CH = stream_chunk(KGS, NPW), NCH = KGS / CH;
+  constexpr int CH = stream_chunk(KGS, NPW, FRAGS), NCH = KGS / CH;
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<uint4*>(Bp), (short)0, KGS * NTILES * 1024, 0x00020000);
   const int lo = lane * 16;
@@ -352,15 +352,19 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
       sv.a2 + (size_t)j0 * Q2 * Net::CH2, (int64_t)Net::NB * Q2 * Net::CH2, sv.rows);
   __syncthreads();
   if constexpr (Net::NCONV == 3) {
+    // the next group's rows are requested now, held through conv3 and
+    // written once conv3 has read conv2's output (X's region), so the FC's
+    // weight stream has the registers to itself
+    auto next_rows = issue();
     conv_stage<P, 2 * Net::CH2, Net::CH3, NBG, Net::WAVES, G::SA2, G::R2, G::SA3, false, CAL,
                SAVE>(
         sm.a2(), sm.a3(), static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
         wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2, row_live,
         sv.a3 + (size_t)j0 * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows);
     __syncthreads();
+    finish(next_rows);
   }
   const T* last = Net::NCONV == 3 ? sm.a3() : sm.a2();
-  auto next_rows = issue();
   if constexpr (Net::HID > 0) {
     // hidden FC over the group's NBG*CHL inputs per window (block-major, as
     // the packed per-block matrices are consecutive): a fresh accumulator
@@ -373,15 +377,17 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
     v4f bacc[1][HT];
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
-    mma_stream<P, KGS, Net::HID / 16, HT, 1>(bacc, ap, bj, wave * HT, lane);
+    mma_stream<P, KGS, Net::HID / 16, HT, 1, 8>(bacc, ap, bj, wave * HT, lane);
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
   } else {
-    // final FC on the VALU straight after the convs: (s, o) pairs, LPP lanes each
+    // final FC on the VALU straight after the convs: (s, o) pairs, LPP lanes
+    // each; the next group's rows are requested before it and written after
     constexpr int LPP = G::NT / (MT * Net::NOUT);
     constexpr int CPL = Net::CHL / LPP;
     const int fpair = tid / LPP, fsub = tid % LPP;
     const int fs = fpair / Net::NOUT, fo = fpair % Net::NOUT;
+    auto next_rows = issue();
 #pragma unroll
     for (int jb = 0; jb < NBG; ++jb) {
       const float* wrow = wt.last_w + ((size_t)(j0 + jb) * Net::NOUT + fo) * Net::CHL + fsub * CPL;
@@ -389,8 +395,8 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
 #pragma unroll
       for (int c = 0; c < CPL; ++c) fpart = fmaf(P::val(arow[c]), wrow[c], fpart);
     }
+    finish(next_rows);
   }
-  finish(next_rows);
 }
 
 // The whole predictor on one tile of MT windows.  The window arrives a group
