@@ -55,6 +55,8 @@ def lib():
         L.ol_forward.argtypes = [P, C.c_int64, f64p, f64p, P]
         L.ol_round.restype = C.c_int32
         L.ol_round.argtypes = [C.c_double, C.c_int32, C.POINTER(C.c_int32)]
+        L.ol_hybrid_select.restype = C.c_int32
+        L.ol_hybrid_select.argtypes = [f64p, C.c_int32, C.POINTER(C.c_int32)]
         L.ol_partition.restype = C.c_int
         L.ol_partition.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i64p, i32p]
         L.ol_simulate.restype = C.c_int
@@ -151,9 +153,28 @@ def default_threads() -> int:
     return max(1, min(16, n))
 
 
-def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=65535):
-    return np.array([n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max],
-                    dtype=np.int32)
+HYB_CLASSES = 10
+HYB_PER_TYPE = HYB_CLASSES + 1
+
+
+def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=65535,
+            head=0):
+    """head 0: regression head (n_out outputs); 1: hybrid head (Sec. 2.3),
+    HYB_PER_TYPE outputs per latency type."""
+    return np.array([n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max,
+                     head], dtype=np.int32)
+
+
+def n_logits(cfg) -> int:
+    return int(cfg[2]) * (HYB_PER_TYPE if int(cfg[8]) == 1 else 1)
+
+
+def hybrid_select(z, lat_max: int = 65535):
+    """Latency of one type from its HYB_PER_TYPE hybrid-head outputs."""
+    z = np.ascontiguousarray(z, np.float64)
+    fl = C.c_int32(0)
+    r = lib().ol_hybrid_select(z, int(lat_max), C.byref(fl))
+    return int(r), int(fl.value)
 
 
 def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
@@ -175,9 +196,10 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
     elif n_instr is None:
         n_instr = int(np.max(start + length))
     res = {k: np.zeros(K, np.int64) for k in ("fetch", "drain", "final", "warm_tick")}
-    logits = np.zeros((n_pred, n_out), np.float64) if want_logits else None
+    n_log = n_logits(cfg)
+    logits = np.zeros((n_pred, n_log), np.float64) if want_logits else None
     lat = np.zeros((n_pred, n_out), np.int32) if want_lat else None
-    scale = np.zeros((n_pred, n_out), np.float64) if want_scale else None
+    scale = np.zeros((n_pred, n_log), np.float64) if want_scale else None
     if lat_table is not None:
         lat_table = np.ascontiguousarray(lat_table, np.int32)
         assert lat_table.size >= n_pred * n_out

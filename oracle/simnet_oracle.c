@@ -51,7 +51,12 @@ enum { OL_CONV = 0, OL_FC = 1 };
 enum { OL_PREDICT = 0, OL_INJECT = 1 };
 
 /* cfg[] layout shared with the Python wrapper */
-enum { CF_NFEAT = 0, CF_NSLOT, CF_NOUT, CF_W, CF_COLRES, CF_COLEXE, CF_COLSTO, CF_LATMAX, CF_LEN };
+enum { CF_NFEAT = 0, CF_NSLOT, CF_NOUT, CF_W, CF_COLRES, CF_COLEXE, CF_COLSTO, CF_LATMAX, CF_HEAD,
+       CF_LEN };
+/* CF_HEAD: 0 = regression head (one output per latency type, rounded);
+ * 1 = hybrid head (Sec. 2.3): per latency type HYB_CLASSES class scores for
+ * latencies 0 .. HYB_CLASSES-2 and "larger", then one regression output. */
+enum { HYB_CLASSES = 10, HYB_PER_TYPE = HYB_CLASSES + 1 };
 
 typedef struct {
   int n_layers;
@@ -331,6 +336,21 @@ int32_t ol_round(double v, int32_t lat_max, int32_t* flags) {
   return (int32_t)r;
 }
 
+/* Hybrid head (Sec. 2.3, "From Output to Latency"): the latency of one type
+ * from its HYB_PER_TYPE outputs z.  The class with the largest score wins
+ * (the first of equal ones; a NaN score never wins); a class below the last
+ * one is its latency, the last class ("larger than HYB_CLASSES-2") takes the
+ * regression output z[HYB_CLASSES], rounded as ol_round.  flags as
+ * ol_round's (0 when a class decides). */
+int32_t ol_hybrid_select(const double* z, int32_t lat_max, int32_t* flags) {
+  int best = 0;
+  for (int c = 1; c < HYB_CLASSES; ++c)
+    if (z[c] > z[best]) best = c;
+  *flags = 0;
+  if (best < HYB_CLASSES - 1) return best;
+  return ol_round(z[HYB_CLASSES], lat_max, flags);
+}
+
 /* ----------------------------------------------------------- partition --- */
 
 /* Equal contiguous sub-traces (Sec. 3.3): the first n mod k get one extra
@@ -417,7 +437,9 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
   const int32_t lat_max = cfg[CF_LATMAX];
   const int C = L - 1;
   const int need_pred = (J->mode == OL_PREDICT) || (J->logits_out != NULL) || (amax != NULL);
-  double out[8], scl[8];
+  const int hybrid = cfg[CF_HEAD] == 1;
+  const int n_logit = hybrid ? HYB_PER_TYPE * n_out : n_out; /* model outputs */
+  double out[3 * HYB_PER_TYPE], scl[3 * HYB_PER_TYPE];
 
   Q->head = Q->tail = 0;
   int64_t cur = 0, t_w = 0;
@@ -448,15 +470,16 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
       }
       forward_cal(J->m, win, out, a, t, J->scale_out ? scl : NULL, amax);
       if (J->logits_out)
-        for (int o = 0; o < n_out; ++o) J->logits_out[g * n_out + o] = out[o];
+        for (int o = 0; o < n_logit; ++o) J->logits_out[g * n_logit + o] = out[o];
       if (J->scale_out)
-        for (int o = 0; o < n_out; ++o) J->scale_out[g * n_out + o] = scl[o];
+        for (int o = 0; o < n_logit; ++o) J->scale_out[g * n_logit + o] = scl[o];
     }
     int32_t lat[8];
     for (int o = 0; o < n_out; ++o) {
       if (J->mode == OL_PREDICT) {
         int32_t fl;
-        lat[o] = ol_round(out[o], lat_max, &fl);
+        lat[o] = hybrid ? ol_hybrid_select(out + o * HYB_PER_TYPE, lat_max, &fl)
+                        : ol_round(out[o], lat_max, &fl);
         if (fl & 2) cnt[0]++;
         if (fl & 1) cnt[1]++;
       } else {
@@ -530,8 +553,10 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
   const ol_model* m = (const ol_model*)model;
   if (cfg[CF_NOUT] < 2 || cfg[CF_NOUT] > 2) return -1; /* store latency not modelled */
   if (cfg[CF_W] < 1 || cfg[CF_NSLOT] < 1) return -1;
+  if (cfg[CF_HEAD] < 0 || cfg[CF_HEAD] > 1) return -1;
   if ((mode == OL_PREDICT || logits_out) && !m) return -1;
-  if (m && (m->n_feat != cfg[CF_NFEAT] || m->n_slot != cfg[CF_NSLOT] || m->n_out != cfg[CF_NOUT]))
+  const int n_logit = cfg[CF_HEAD] == 1 ? HYB_PER_TYPE * cfg[CF_NOUT] : cfg[CF_NOUT];
+  if (m && (m->n_feat != cfg[CF_NFEAT] || m->n_slot != cfg[CF_NSLOT] || m->n_out != n_logit))
     return -1;
   if (mode == OL_INJECT && !lat_table) return -1;
   int64_t* pred_off = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_sub + 1));

@@ -400,6 +400,22 @@ def net_c3() -> List[Layer]:
             Layer(FC, 256 * 13, 512, 1), Layer(FC, 512, 2, 0)]
 
 
+HYB_CLASSES = 10  # hybrid inference head: classes for latencies 0..8 and "larger"
+
+
+def net_c3_hybrid_infer() -> List[Layer]:
+    """The C3 trunk with the paper's hybrid inference head: per latency type
+    (fetch, execution) 10 class scores and one regression output, FC 512 ->
+    22."""
+    return net_c3()[:-1] + [Layer(FC, 512, 2 * (HYB_CLASSES + 1), 0)]
+
+
+# Output bias of the hybrid inference head under random init: fetch leans to
+# latencies 0 and 1, execution to the "larger" class whose regression output
+# sits near 12 cycles.
+HYB_BIAS = tuple([2.0, 1.0] + [0.0] * 8 + [2.0]) + tuple([0.0] * 9 + [2.0] + [12.0])
+
+
 def net_c3_hybrid() -> List[Layer]:
     """The C3 trunk with the training head: per latency type 400 class
     logits and one regression output, FC 512 -> 2 x 401."""
@@ -411,6 +427,9 @@ def workload(name: str) -> Workload:
         return Workload("tiny", 10_000, 32, 16, net_small())
     if name == "c3_1m":       # 1M instructions, 4,096 sub-traces, 256 warm-up, 111 x 50
         return Workload("c3_1m", 1_000_000, 50, 111, net_c3(), n_sub=4096, warmup=256)
+    if name == "c3hyb_1m":    # c3_1m with the hybrid inference head
+        return Workload("c3hyb_1m", 1_000_000, 50, 111, net_c3_hybrid_infer(), n_sub=4096,
+                        warmup=256, extra={"out_bias": HYB_BIAS, "head": 1})
     if name == "c3_train":    # 4,096 labelled contexts per step, hybrid head, BF16
         return Workload("c3_train", 200_000, 50, 111, net_c3_hybrid(), extra={"batch": 4096})
     if name == "c3_uneven":   # 20k independent streams, log-uniform lengths 1e3..2e5

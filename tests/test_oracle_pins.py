@@ -732,3 +732,58 @@ def test_uniform_logits_cross_entropy_is_log_bins(oracle_lib):
     want = np.mean([2 * np.log(400) + abs(0.25 - np.log1p(a)) + abs(-1.0 - np.log1p(b))
                     for a, b in lat])
     assert abs(oracle_lib.hybrid_loss(z, lat) - want) < 1e-12
+
+
+# ---------------------------------------------------- hybrid inference head ---
+
+def _hyb(classes, reg):
+    z = np.zeros(11)
+    z[:10] = classes
+    z[10] = reg
+    return z
+
+
+@pytest.mark.parametrize("classes,reg,want,flags", [
+    ([0, 0, 0, 5, 0, 0, 0, 0, 0, 0], 99.0, 3, 0),       # class 3 has the largest score
+    ([9, 0, 0, 0, 0, 0, 0, 0, 0, 0], 99.0, 0, 0),       # latency 0
+    ([0, 0, 0, 0, 0, 0, 0, 0, 7, 0], -5.0, 8, 0),       # latency 8, regression ignored
+    ([0, 0, 0, 0, 0, 0, 0, 0, 0, 1], 12.5, 12, 0),      # "larger": regression, ties to even
+    ([0, 0, 0, 0, 0, 0, 0, 0, 0, 1], 13.5, 14, 0),
+    ([0, 0, 0, 0, 0, 0, 0, 0, 0, 1], -3.0, 0, 2),       # clamped below
+    ([0, 0, 0, 0, 0, 0, 0, 0, 0, 1], float("nan"), 0, 1),
+    ([1, 0, 4, 0, 0, 4, 0, 0, 0, 4], 50.0, 2, 0),       # equal scores: the first wins
+    ([0, float("nan"), 0, 0, 0, 0, 0, 0, 0, 0], 9.0, 0, 0),  # a NaN score never wins
+])
+def test_hybrid_select_cases(oracle_lib, classes, reg, want, flags):
+    """Sec. 2.3, from output to latency: the most probable class gives the
+    latency, unless it is the "larger than 8" class, then the direct output
+    does (rounded like every other latency)."""
+    assert oracle_lib.hybrid_select(_hyb(classes, reg)) == (want, flags)
+
+
+@pytest.mark.parametrize("f,e_reg,N", [(4, 7.4, 300), (1, 30.6, 500), (2, 2.2, 200)])
+def test_hybrid_head_closed_form(oracle_lib, f, e_reg, N):
+    """A hybrid network whose outputs are its biases: fetch class f wins,
+    execution's "larger" class wins with a direct output of e_reg.  Every
+    instruction then has F = f and E = rint(e_reg), and one sub-trace takes
+    N*f + E + 1 cycles (the closed form of Sec. 3.2's clock pinned above)."""
+    layers = synth.net_small()[:-1] + [synth.Layer(synth.FC, 256, 22, 0)]
+    ws, bs = synth.init_weights(1, layers)
+    ws = [np.zeros_like(w) for w in ws]
+    bs = [np.zeros_like(b) for b in bs]
+    bias = np.zeros(22, np.float32)
+    bias[f] = 3.0                   # fetch: class f
+    bias[11 + 9] = 3.0              # execution: "larger"
+    bias[11 + 10] = e_reg           # execution's direct output
+    bias[10] = 1000.0               # fetch's direct output, unused
+    bs[-1] = bias
+    m = oracle_lib.Model(layers, ws, bs, 32, 16)
+    cfg = oracle_lib.sim_cfg(32, 16, 2, 8, synth.dynamic_columns(32), head=1)
+    feat = synth.trace_features(1, N, 32)
+    res = oracle_lib.simulate(cfg, feat, np.array([0]), np.array([N]), np.array([0]), model=m,
+                              want_lat=True, want_logits=True)
+    E = int(np.rint(e_reg))
+    assert res["final"][0] == N * f + E + 1
+    assert np.all(res["lat"] == [f, E])
+    assert res["logits"].shape == (N, 22)
+    assert np.all(res["logits"] == bias)
