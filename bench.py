@@ -15,6 +15,9 @@ Workloads (--workload):
                    1 % of the FP32 run, the others are reported beside it.
   tiny             10,000 instructions, one sub-trace, 16 x 32 windows, conv
                    32/64 + FC 2, FP32: bound by per-step latency (B = 1).
+  c3hyb_1m         c3_1m with the paper's hybrid inference head (FC 512 -> 22:
+                   per latency type 10 class scores + 1 direct output), FP32
+                   and BF16.
   c3_uneven        20,000 independent streams with log-uniform lengths in
                    [1e3, 2e5] (7.5e8 instructions), packed instruction codes,
                    BF16, slots refilled longest-first, run as one graph.
@@ -40,7 +43,7 @@ METRIC = "simulated MIPS on 1 MI355X, FP32 vs BF16/FP8 at ≤1% total-cycle erro
 # FLOP per prediction from the layer lists (multiply-adds x 2); the kernels
 # skip window slots and conv positions no output depends on, so they execute
 # slightly fewer (6,631,424 for the C3 network).
-FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560}
+FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560, "c3hyb": 6_723_072}
 # Training step per context: forward 3,760,896 MAC (trunk + FC 512 -> 802),
 # backward twice that less conv1's input gradient (352,000 MAC), x 2 FLOP.
 FLOP_PER_TRAIN_CTX = 21_861_376
@@ -74,7 +77,8 @@ def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0):
     import oracle
     oracle.build(force=not os.path.exists(oracle.LIB))
     model = oracle.Model(wl.layers, ws, bs, wl.n_feat, wl.n_slot)
-    cfg = oracle.sim_cfg(wl.n_feat, wl.n_slot, 2, wl.retire_width, wl.cols)
+    cfg = oracle.sim_cfg(wl.n_feat, wl.n_slot, 2, wl.retire_width, wl.cols,
+                         head=wl.extra.get("head", 0))
     threads = oracle.default_threads()
     K = len(start)
     if K == 1:
@@ -181,6 +185,9 @@ WORKLOAD_TEXT = {
              "random-init weights",
     "tiny": "tiny: 10,000-instruction synthetic trace, one sub-trace, 16x32 windows, "
             "conv 32/64 k2s2 + FC 2, random-init weights",
+    "c3hyb_1m": "c3hyb_1m: the c3_1m trace and partition with the hybrid inference head "
+                "(per latency type 10 class scores + 1 direct output, FC 512 -> 22), "
+                "random-init weights",
     "c3_uneven": "c3_uneven: 20,000 streams, log-uniform lengths 1e3..2e5, packed codes, "
                  "111x50 windows, C3 network, slots refilled longest-first",
     "c3_train": "c3_train: training step on 4,096 labelled 111x50 contexts (analytic "
@@ -253,8 +260,9 @@ def main():
         }
         print(json.dumps(out), flush=True)
         return
-    ws, bs = synth.init_weights(wl.weight_seed, wl.layers)
-    net = "small" if args.workload == "tiny" else "c3"
+    ws, bs = synth.init_weights(wl.weight_seed, wl.layers,
+                                out_bias=wl.extra.get("out_bias", synth.OUT_BIAS))
+    net = {"tiny": "small", "c3hyb_1m": "c3hyb"}.get(args.workload, "c3")
     n_feat = None
     feat = None
     if args.workload == "c3_uneven":
@@ -282,6 +290,8 @@ def main():
         dfeat = torch.from_numpy(feat).cuda()
         if args.workload == "tiny":
             forms = [args.prec or "f32"]
+        elif args.workload == "c3hyb_1m":
+            forms = [args.prec] if args.prec else ["f32", "bf16"]
         else:
             forms = [args.prec] if args.prec else ["f32", "bf16", "fp8"]
     n_pred = int(length.sum() + warm.sum())

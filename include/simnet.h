@@ -139,8 +139,14 @@ SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx**
  * [out][in]), float32, on the device if on_device != 0 else on the host.
  * The parameters are copied (and re-laid-out for the kernels), so the
  * caller may free them afterwards.  The layer list must map the window
- * [n_slot][n_feat] to n_out outputs; SIM_EUNSUPPORTED if no kernel exists for
- * the shape, SIM_ENONFINITE on NaN/Inf.  Resets the simulation state. */
+ * [n_slot][n_feat] to n_out outputs (regression head: each output, rounded,
+ * is a latency), or, for the 111x50 C3 network, to 22 outputs: the hybrid
+ * head of Sec. 2.3, per latency type 10 class scores (latencies 0..8 and
+ * "larger than 8") then one direct output; the latency is the most probable
+ * class (the first of equal scores), or the rounded direct output when the
+ * "larger" class wins (FP32 and BF16 forms).  SIM_EUNSUPPORTED if no kernel
+ * exists for the shape, SIM_ENONFINITE on NaN/Inf.  Resets the simulation
+ * state. */
 SIMNET_API int sim_load_weights(sim_ctx* ctx, const sim_layer* layers, int32_t n_layers,
                      const float* params, int32_t on_device);
 
@@ -169,8 +175,9 @@ SIMNET_API int sim_set_graph(sim_ctx* ctx, int32_t enable);
 SIMNET_API int sim_reset(sim_ctx* ctx);
 
 /* Record every prediction's raw float32 outputs into a DEVICE buffer of
- * [sum(warm+len)][n_out] float32, indexed like lat_table (NULL stops
- * recording).  Used for parity checks on identical windows. */
+ * [sum(warm+len)][network outputs] float32 (n_out, or 22 for the hybrid
+ * head), in prediction order like lat_table (NULL stops recording).  Used
+ * for parity checks on identical windows. */
 SIMNET_API int sim_record_logits(sim_ctx* ctx, float* logits);
 
 /* Calibrate the FP8 form (also allowed for FP32 contexts, to read the
@@ -192,8 +199,8 @@ SIMNET_API int sim_calibrate(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
 SIMNET_API int sim_act_scales(const sim_ctx* ctx, float* out, int32_t n);
 
 /* Predictor forward on explicit windows (Sec. 2.3): x is DEVICE
- * [B][n_slot][n_feat] float32, logits DEVICE [B][n_out] float32 (n_out = 2
- * for the regression head).  save_or_null must be NULL except for the
+ * [B][n_slot][n_feat] float32, logits DEVICE [B][network outputs] float32
+ * (n_out = 2 for the regression head, 22 for the hybrid head).  save_or_null must be NULL except for the
  * training head, where it is required.
  *
  * Training head (Sec. 2.3's hybrid output, Sec. 4's training set-up): a

@@ -185,6 +185,7 @@ class Simulator:
         order: w0, b0, w1, b1, ..."""
         arr = (sim_layer * len(layers))(*[sim_layer(l.kind, l.c_in, l.c_out, l.relu)
                                           for l in layers])
+        self.n_outputs = int(layers[-1].c_out)
         if isinstance(params, np.ndarray):
             params = np.ascontiguousarray(params, np.float32)
             self._check("sim_load_weights",
@@ -240,7 +241,8 @@ class Simulator:
             raise ValueError("x must be a contiguous float32 device tensor")
         B = x.shape[0]
         if logits is None:
-            logits = torch.empty((B, 2), dtype=torch.float32, device=x.device)
+            logits = torch.empty((B, getattr(self, "n_outputs", 2)), dtype=torch.float32,
+                                 device=x.device)
         self._check("predictor_fwd",
                     lib().predictor_fwd(self.ctx, x.data_ptr(), B, logits.data_ptr(), None))
         return logits

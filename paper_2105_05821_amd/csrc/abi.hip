@@ -39,7 +39,7 @@ struct sim_ctx {
   int32_t n_sub = 0;
   int64_t n_instr = 0;
   const float* feat = nullptr;
-  int net = -1;  // 0 NetSmall, 1 NetC3
+  int net = -1;  // 0 NetSmall, 1 NetC3, 2 C3 training head, 3 C3 hybrid inference head
   int C = 0;
   uint32_t relu = 0;
   bool weights = false;
@@ -225,7 +225,7 @@ std::vector<Expect> expected_layers() {
 // Offsets (bytes) of every array inside the packed weight block.
 struct Layout {
   size_t conv_w[3], conv_b[3], conv_ws[3], conv_ai[3], x_inv, hid_w, hid_b, hid_ws, hid_ai,
-      last_w, last_b;
+      last_w, last_b, last_p;
 };
 
 // Re-lay-out PyTorch-order FP32 parameters for one network and precision.
@@ -336,6 +336,15 @@ std::vector<uint8_t> relayout(int prec, const float* params,
     }
     L->last_w = put_floats(lw);
     L->last_b = put_floats(std::vector<float>(b[li + 1], b[li + 1] + Net::NOUT));
+    L->last_p = 0;
+    if (Net::HEAD == 1) {
+      // hybrid head: the same rounded weights packed for one MFMA tile row,
+      // outputs padded to whole 16-column tiles with zeros
+      constexpr int NOUTP = (Net::NOUT + 15) / 16 * 16;
+      L->last_p = reserve((size_t)N * NOUTP * es);
+      pack_b(prec, N, NOUTP, [&](int k, int n) { return n < Net::NOUT ? lw[(size_t)n * N + k] : 0.f; },
+             out.data() + L->last_p);
+    }
   } else {
     const int K = Net::CHL, NB = Net::NB;
     const float* Wf = w[li];
@@ -390,8 +399,9 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
                           const std::vector<std::vector<float>>* scales, void** dev,
                           DevWeights* w) {
   Layout lay{};
-  std::vector<uint8_t> packed = c->net == 0 ? relayout<NetSmall>(prec, params, scales, &lay)
-                                            : relayout<NetC3>(prec, params, scales, &lay);
+  std::vector<uint8_t> packed = c->net == 0   ? relayout<NetSmall>(prec, params, scales, &lay)
+                                : c->net == 3 ? relayout<NetC3Hyb>(prec, params, scales, &lay)
+                                              : relayout<NetC3>(prec, params, scales, &lay);
   void* dw = nullptr;
   hipError_t e = hipMalloc(&dw, packed.size());
   if (e != hipSuccess) return hip_fail(c, e, "hipMalloc weights");
@@ -417,7 +427,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
     w->conv_ai[l] = F(lay.conv_ai[l]);
   }
   w->x_inv = F(lay.x_inv);
-  if (c->net == 1) {
+  if (c->net == 1 || c->net == 3) {
     w->hid_w = base + lay.hid_w;
     w->hid_b = F(lay.hid_b);
     w->hid_ws = F(lay.hid_ws);
@@ -425,6 +435,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
   }
   w->last_w = F(lay.last_w);
   w->last_b = F(lay.last_b);
+  w->last_p = c->net == 3 ? base + lay.last_p : nullptr;
   return SIM_OK;
 }
 
@@ -793,13 +804,21 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
     c->net = 2;
     return load_train_weights(c, layers, n_layers, params, on_device);
   }
-  if (c->net == 2) c->net = 1;
-  const bool ok = c->net == 0 ? layers_match<NetSmall>(layers, n_layers)
-                              : layers_match<NetC3>(layers, n_layers);
+  if (c->net == 2 || c->net == 3) c->net = 1;
+  if (c->net == 1 && layers_match<NetC3Hyb>(layers, n_layers)) {
+    if (c->cfg.prec == SIM_FP8E4M3)
+      return fail(c, SIM_EUNSUPPORTED, "no FP8 form of the hybrid head");
+    c->net = 3;
+  }
+  const bool ok = c->net == 0   ? layers_match<NetSmall>(layers, n_layers)
+                  : c->net == 3 ? true
+                                : layers_match<NetC3>(layers, n_layers);
   if (!ok) return fail(c, SIM_EUNSUPPORTED, "no kernel for this layer list");
   if (layers[n_layers - 1].relu)
     return fail(c, SIM_EUNSUPPORTED, "the output layer must not have ReLU");
-  const size_t np = c->net == 0 ? param_count<NetSmall>() : param_count<NetC3>();
+  const size_t np = c->net == 0   ? param_count<NetSmall>()
+                    : c->net == 3 ? param_count<NetC3Hyb>()
+                                  : param_count<NetC3>();
   std::vector<float> host(np);
   if (on_device) {
     hipError_t e = hipMemcpy(host.data(), params, np * 4, hipMemcpyDeviceToHost);
@@ -843,6 +862,7 @@ int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* tabl
   if (!c) return SIM_EINVAL;
   if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
   if (c->net == 2) return fail(c, SIM_EUNSUPPORTED, "no FP8 training form");
+  if (c->net == 3) return fail(c, SIM_EUNSUPPORTED, "no FP8 form of the hybrid head");
   if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
   if (c->cfg.prec == SIM_BF16) return fail(c, SIM_EUNSUPPORTED, "calibration runs FP32 weights");
   if (n_steps < 1) return fail(c, SIM_EINVAL, "n_steps < 1");

@@ -123,16 +123,21 @@ struct Geo {
 template <class Net, class P>
 struct NetSmem {
   using G = Geo<Net, P>;
-  typename P::T xa2[G::NXA2];   // window rows of the group (X), then conv2's output
-  typename P::T a1a3[G::NA1A3]; // conv1's output, then conv3's output
-  typename P::T a2own[G::NA2];  // conv2's output when it does not alias X
-  float red[Net::WAVES][MT][Net::NOUT];
+  // window rows of the group (X), then conv2's output; after the last group
+  // also the final FC's cross-wave partial sums
+  alignas(16) typename P::T xa2[G::NXA2];
+  alignas(16) typename P::T a1a3[G::NA1A3]; // conv1's output, then conv3's output
+  alignas(16) typename P::T a2own[G::NA2];  // conv2's output when it does not alias X
   float logit[MT][Net::NOUT];
   float x_inv[Net::D];  // FP8: reciprocal input scale of each window feature
   __device__ typename P::T* x() { return xa2; }
   __device__ typename P::T* a1() { return a1a3; }
   __device__ typename P::T* a2() { return G::ALIAS ? xa2 : a2own; }
   __device__ typename P::T* a3() { return a1a3; }
+  // [WAVES][MT][NOUT] partial sums of the final FC (X is dead by then)
+  __device__ float* red() { return reinterpret_cast<float*>(xa2); }
+  static_assert(Net::HID == 0 || sizeof(xa2) >= sizeof(float) * Net::WAVES * MT * Net::NOUT,
+                "final-FC partial sums do not fit X's region");
 };
 
 // Epilogue of one accumulator element: bias, (FP8) dequantisation, ReLU.
@@ -462,6 +467,42 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
                              col0 + i, wt.hid_ai);
       if (row < sv.rows) store_run<4 * sizeof(T)>(sv.h + (size_t)row * Net::HID + col0, e);
     }
+  } else if constexpr (Net::HID > 0 && Net::HEAD == 1) {
+    // hybrid head (NOUT outputs): the hidden layer's outputs, rounded to the
+    // form, go to LDS (X's region, dead after the last group), then the
+    // final FC runs as one MFMA tile row on the first NOUTP/16 waves
+    constexpr int NOUTP = (Net::NOUT + 15) / 16 * 16, NTL = NOUTP / 16;
+    constexpr int SH = Net::HID + G::PAD;
+    static_assert(sizeof(T) * MT * SH <= sizeof(sm.xa2) && NTL <= Net::WAVES, "hybrid head");
+    T* hb = sm.x();
+    const bool hrelu = relu_mask & (1u << Net::NCONV);
+    const int row = lane & 15;
+    const bool live = !CAL || row_live[row];
+#pragma unroll
+    for (int jj = 0; jj < HT; ++jj) {
+      const int col0 = (wave * HT + jj) * 16 + 4 * (lane >> 4);
+      T e[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float hv = activation<P>(hacc[jj][i], col0 + i, wt.hid_b, wt.hid_ws, hrelu);
+        if constexpr (CAL)
+          if (live) cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col0 + i, hv);
+        e[i] = to_storage<P>(hv, col0 + i, wt.hid_ai);
+      }
+      store_run<4 * sizeof(T)>(hb + row * SH + col0, e);
+    }
+    __syncthreads();
+    if (wave < NTL) {
+      const T* const ap[1] = {hb + row * SH + (P::KG / 4) * (lane >> 4)};
+      v4f acc[1][1] = {{v4f{0.f, 0.f, 0.f, 0.f}}};
+      mma_stream<P, Net::HID / P::KG, NTL, 1, 1>(acc, ap, static_cast<const uint4*>(wt.last_p),
+                                                 wave, lane);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int col = wave * 16 + 4 * (lane >> 4) + i;
+        if (col < Net::NOUT) sm.logit[row][col] = acc[0][0][i] + wt.last_b[col];
+      }
+    }
   } else if constexpr (Net::HID > 0) {
     // bias + ReLU on the hidden layer, rounding to the form's precision, then
     // the final FC: lane l holds row l % 16 and 4 columns of each of its HT
@@ -490,14 +531,14 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
       float v = p[o];
       v += __shfl_xor(v, 16);
       v += __shfl_xor(v, 32);
-      if (lane < 16) sm.red[wave][row][o] = v;
+      if (lane < 16) sm.red()[(wave * MT + row) * Net::NOUT + o] = v;
     }
     __syncthreads();
     if (tid < MT * Net::NOUT) {
       const int s = tid / Net::NOUT, o = tid % Net::NOUT;
       float v = 0.f;
 #pragma unroll
-      for (int w = 0; w < Net::WAVES; ++w) v += sm.red[w][s][o];
+      for (int w = 0; w < Net::WAVES; ++w) v += sm.red()[(w * MT + s) * Net::NOUT + o];
       v += wt.last_b[o];
       if (relu_mask & (1u << (Net::NCONV + 1))) v = fmaxf(v, 0.f);
       sm.logit[s][o] = v;
@@ -559,6 +600,19 @@ __device__ __forceinline__ int32_t round_latency(float v, int32_t lat_max, uint3
     return lat_max;
   }
   return (int32_t)r;
+}
+
+// Hybrid head (Sec. 2.3): the most probable class (the first of equal
+// scores; a NaN score never wins) is the latency, unless it is the last
+// class ("larger"), which takes the direct output z[HYB_CLASSES], rounded.
+__device__ __forceinline__ int32_t hybrid_latency(const float* z, int32_t lat_max,
+                                                  uint32_t& clamped, uint32_t& nonfinite) {
+  int best = 0;
+#pragma unroll
+  for (int c = 1; c < HYB_CLASSES; ++c)
+    if (z[c] > z[best]) best = c;
+  if (best < HYB_CLASSES - 1) return best;
+  return round_latency(z[HYB_CLASSES], lat_max, clamped, nonfinite);
 }
 
 template <class Net, class P>
@@ -737,20 +791,24 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       const int s = tid, k = sm.kid[s];
       const int64_t pos = sm.pos[s];
       const int64_t g = sm.pred_off[s] + pos;
-      int32_t lat[Net::NOUT];
+      int32_t lat[Net::NLAT];
       if (RUN_NET) {
+        if (p.logits_out)
+          for (int o = 0; o < Net::NOUT; ++o) p.logits_out[g * Net::NOUT + o] = sm.net.logit[s][o];
 #pragma unroll
-        for (int o = 0; o < Net::NOUT; ++o) {
-          const float v = sm.net.logit[s][o];
-          if (p.logits_out) p.logits_out[g * Net::NOUT + o] = v;
-          lat[o] = round_latency(v, p.lat_max, n_clamped, n_nonfinite);
+        for (int o = 0; o < Net::NLAT; ++o) {
+          if constexpr (Net::HEAD == 1)
+            lat[o] = hybrid_latency(&sm.net.logit[s][o * HYB_PER_TYPE], p.lat_max, n_clamped,
+                                    n_nonfinite);
+          else
+            lat[o] = round_latency(sm.net.logit[s][o], p.lat_max, n_clamped, n_nonfinite);
         }
         ++n_pred;
       }
       if (p.lat_mode != 0) {
 #pragma unroll
-        for (int o = 0; o < Net::NOUT; ++o) {
-          const int32_t inj = p.lat_table[g * Net::NOUT + o];
+        for (int o = 0; o < Net::NLAT; ++o) {
+          const int32_t inj = p.lat_table[g * Net::NLAT + o];
           if (RUN_NET && inj != lat[o]) ++n_mismatch;
           lat[o] = inj;
         }
@@ -1020,6 +1078,11 @@ static hipError_t launch_step_n(int prec, const DevWeights& w, uint32_t relu, co
 
 hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, const DevState& s,
                        const StepParams& p, hipStream_t stream) {
+  if (net == 3) {  // hybrid head: FP32 and BF16 forms
+    if (prec == 0) return launch_step_t<NetC3Hyb, PF32>(w, relu, s, p, stream);
+    if (prec == 1) return launch_step_t<NetC3Hyb, PBF16>(w, relu, s, p, stream);
+    return hipErrorInvalidValue;
+  }
   return net == 0 ? launch_step_n<NetSmall>(prec, w, relu, s, p, stream)
                   : launch_step_n<NetC3>(prec, w, relu, s, p, stream);
 }
@@ -1058,6 +1121,11 @@ int calibration_size(int net) { return net == 0 ? n_cal<NetSmall>() : n_cal<NetC
 
 hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
                           int64_t B, float* logits, hipStream_t stream) {
+  if (net == 3) {
+    if (prec == 0) return launch_forward_t<NetC3Hyb, PF32>(w, relu, x, B, logits, stream);
+    if (prec == 1) return launch_forward_t<NetC3Hyb, PBF16>(w, relu, x, B, logits, stream);
+    return hipErrorInvalidValue;
+  }
   return net == 0 ? launch_forward_n<NetSmall>(prec, w, relu, x, B, logits, stream)
                   : launch_forward_n<NetC3>(prec, w, relu, x, B, logits, stream);
 }
@@ -1095,6 +1163,10 @@ hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu
     fn = prec == 0 ? step_fn<NetSmall, PF32>(run_net)
          : prec == 1 ? step_fn<NetSmall, PBF16>(run_net) : step_fn<NetSmall, PFP8>(run_net);
     nt = Geo<NetSmall, PF32>::NT;
+  } else if (net == 3) {
+    if (prec > 1) return hipErrorInvalidValue;
+    fn = prec == 0 ? step_fn<NetC3Hyb, PF32>(run_net) : step_fn<NetC3Hyb, PBF16>(run_net);
+    nt = Geo<NetC3Hyb, PF32>::NT;
   } else {
     fn = prec == 0 ? step_fn<NetC3, PF32>(run_net)
          : prec == 1 ? step_fn<NetC3, PBF16>(run_net) : step_fn<NetC3, PFP8>(run_net);

@@ -20,6 +20,7 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr int NCONV = 2, BS = 4, NB = 4;
   static constexpr int CH1 = 32, CH2 = 64, CH3 = 0;
   static constexpr int HID = 0, NOUT = 2;
+  static constexpr int NLAT = 2, HEAD = 0;   // latencies per instruction; regression head
   static constexpr int WAVES = 4;
   static constexpr int CHL = CH2;            // channels of the last conv
 };
@@ -28,8 +29,15 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
   static constexpr int NCONV = 3, BS = 8, NB = 13;
   static constexpr int CH1 = 64, CH2 = 128, CH3 = 256;
   static constexpr int HID = 512, NOUT = 2;
+  static constexpr int NLAT = 2, HEAD = 0;
   static constexpr int WAVES = 8;
   static constexpr int CHL = CH3;
+};
+// Hybrid inference head (Sec. 2.3): per latency type HYB_CLASSES class scores
+// (latencies 0 .. HYB_CLASSES-2 and "larger") and one direct output.
+constexpr int HYB_CLASSES = 10, HYB_PER_TYPE = HYB_CLASSES + 1;
+struct NetC3Hyb : NetC3 {  // C3 trunk -> FC 512 -> 2 x 11
+  static constexpr int NOUT = 2 * HYB_PER_TYPE, HEAD = 1;
 };
 
 // Contraction length covered by one 16-byte per-lane MFMA fragment group:
@@ -66,6 +74,7 @@ struct DevWeights {
   const float* hid_ai;
   const float* last_w;
   const float* last_b;
+  const void* last_p;  // hybrid head: the final FC packed like a hidden matrix
 };
 
 struct DevState {
