@@ -158,11 +158,13 @@ HYB_PER_TYPE = HYB_CLASSES + 1
 
 
 def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=65535,
-            head=0):
+            head=0, store_col=-1):
     """head 0: regression head (n_out outputs); 1: hybrid head (Sec. 2.3),
-    HYB_PER_TYPE outputs per latency type."""
+    HYB_PER_TYPE outputs per latency type.  n_out = 3 adds store latencies
+    and the memory write queue; store_col is then the trace column whose
+    nonzero value marks a store."""
     return np.array([n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max,
-                     head], dtype=np.int32)
+                     head, store_col], dtype=np.int32)
 
 
 def n_logits(cfg) -> int:

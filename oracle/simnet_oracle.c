@@ -52,7 +52,9 @@ enum { OL_PREDICT = 0, OL_INJECT = 1 };
 
 /* cfg[] layout shared with the Python wrapper */
 enum { CF_NFEAT = 0, CF_NSLOT, CF_NOUT, CF_W, CF_COLRES, CF_COLEXE, CF_COLSTO, CF_LATMAX, CF_HEAD,
-       CF_LEN };
+       CF_STCOL, CF_LEN };
+/* CF_STCOL: with n_out = 3 (fetch, execution, store latencies), the trace
+ * column whose nonzero value marks a store instruction. */
 /* CF_HEAD: 0 = regression head (one output per latency type, rounded);
  * 1 = hybrid head (Sec. 2.3): per latency type HYB_CLASSES class scores for
  * latencies 0 .. HYB_CLASSES-2 and "larger", then one regression output. */
@@ -370,7 +372,7 @@ int ol_partition(int64_t n_instr, int32_t n_sub, int32_t warm_max,
 
 /* ------------------------------------------------- literal queue model --- */
 
-typedef struct { int64_t idx, res; int32_t e, s; } qentry;
+typedef struct { int64_t idx, res; int32_t e, s, store; } qentry;
 
 typedef struct {
   qentry* q;
@@ -392,17 +394,26 @@ static void q_push(queue* Q, qentry e) {
   Q->q[Q->tail++] = e;
 }
 
-/* One clock cycle of the processor queue: the clock moves by one, every
- * queued instruction ages by one, then up to W ready instructions leave from
- * the head in program order. */
-static void tick(queue* Q, int64_t* cur, int W) {
+/* One clock cycle (Sec. 3.2, clock management): the clock moves by one and
+ * every instruction in either queue ages by one; up to W ready instructions
+ * (residence > execution latency) leave the processor queue from its head in
+ * program order, and a store among them enters the memory write queue (when
+ * M is given); then every ready instruction (residence > store latency) at
+ * the head of the memory write queue leaves it, in order, any number per
+ * cycle. */
+static void tick(queue* Q, queue* M, int64_t* cur, int W) {
   *cur += 1;
   for (int64_t j = Q->head; j < Q->tail; ++j) Q->q[j].res += 1;
+  if (M)
+    for (int64_t j = M->head; j < M->tail; ++j) M->q[j].res += 1;
   int n = 0;
   while (n < W && Q->head < Q->tail && Q->q[Q->head].res > Q->q[Q->head].e) {
-    Q->head++;
+    const qentry e = Q->q[Q->head++];
+    if (M && e.store) q_push(M, e);
     n++;
   }
+  if (M)
+    while (M->head < M->tail && M->q[M->head].res > M->q[M->head].s) M->head++;
 }
 
 typedef struct {
@@ -430,7 +441,7 @@ typedef struct {
 } sim_job;
 
 static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* t,
-                         queue* Q, int64_t* cnt, double* amax) {
+                         queue* Q, queue* MQ, int64_t* cnt, double* amax) {
   const int32_t* cfg = J->cfg;
   const int D = cfg[CF_NFEAT], L = cfg[CF_NSLOT], n_out = cfg[CF_NOUT], W = cfg[CF_W];
   const int cr = cfg[CF_COLRES], ce = cfg[CF_COLEXE], cs = cfg[CF_COLSTO];
@@ -441,7 +452,10 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
   const int n_logit = hybrid ? HYB_PER_TYPE * n_out : n_out; /* model outputs */
   double out[3 * HYB_PER_TYPE], scl[3 * HYB_PER_TYPE];
 
+  const int stcol = cfg[CF_STCOL];
+  queue* M = n_out >= 3 ? MQ : NULL; /* the memory write queue exists with store latencies */
   Q->head = Q->tail = 0;
+  MQ->head = MQ->tail = 0;
   int64_t cur = 0, t_w = 0;
   const int64_t w = J->warm[k];
   int64_t n_pos = J->warm[k] + J->len[k];
@@ -451,17 +465,18 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
     const int64_t i = first + p;
     const int64_t g = J->pred_off[k] + p; /* global prediction index */
     if (need_pred) {
-      /* Window (Sec. 2.2): slot 0 = this instruction with zero dynamic
-       * columns; slot j >= 1 = j-th newest queued instruction. */
+      /* Window (Sec. 2.2, Sec. 3.2): slot 0 = this instruction with zero
+       * dynamic columns; then the processor queue newest first, then the
+       * memory write queue newest first, C slots in all. */
       memset(win, 0, sizeof(double) * (size_t)L * D);
       for (int c = 0; c < D; ++c) win[c] = J->feat[i * D + c];
       if (cr >= 0) win[cr] = 0.0;
       if (ce >= 0) win[ce] = 0.0;
       if (cs >= 0) win[cs] = 0.0;
-      int64_t inq = Q->tail - Q->head;
-      int shown = (int)(inq < C ? inq : C);
+      const int64_t inq = Q->tail - Q->head, inm = M ? M->tail - M->head : 0;
+      const int shown = (int)(inq + inm < C ? inq + inm : C);
       for (int j = 1; j <= shown; ++j) {
-        const qentry* e = &Q->q[Q->tail - j];
+        const qentry* e = j <= inq ? &Q->q[Q->tail - j] : &M->q[M->tail - (j - inq)];
         double* row = win + (size_t)j * D;
         for (int c = 0; c < D; ++c) row[c] = J->feat[e->idx * D + c];
         if (cr >= 0) row[cr] = (double)e->res;
@@ -488,14 +503,15 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
       if (J->lat_out) J->lat_out[g * n_out + o] = lat[o];
     }
     /* Clock management (Sec. 3.2): F cycles pass, one at a time. */
-    for (int32_t f = 0; f < lat[0]; ++f) tick(Q, &cur, W);
-    qentry e = {i, 0, lat[1], n_out >= 3 ? lat[2] : 0};
+    for (int32_t f = 0; f < lat[0]; ++f) tick(Q, M, &cur, W);
+    qentry e = {i, 0, lat[1], n_out >= 3 ? lat[2] : 0,
+                n_out >= 3 && J->feat[i * D + stcol] != 0.0f};
     q_push(Q, e);
     if (p == w - 1) t_w = cur;
   }
   if (J->max_pos > 0) return; /* partial run (calibration): no results */
   const int64_t t_last = cur;
-  while (Q->tail > Q->head) tick(Q, &cur, W); /* drain */
+  while (Q->tail > Q->head || (M && M->tail > M->head)) tick(Q, M, &cur, W); /* drain */
   J->fetch[k] = t_last - t_w;
   J->drain[k] = cur - t_last;
   J->final_tick[k] = cur;
@@ -509,7 +525,7 @@ static void* sim_worker(void* arg) {
   double* win = (double*)malloc(sizeof(double) * (size_t)L * D);
   double* a = (double*)malloc(sizeof(double) * (size_t)width);
   double* t = (double*)malloc(sizeof(double) * (size_t)width);
-  queue Q = {NULL, 0, 0, 0};
+  queue Q = {NULL, 0, 0, 0}, MQ = {NULL, 0, 0, 0};
   int64_t cnt[2] = {0, 0};
   double* amax = J->amax ? (double*)calloc((size_t)J->n_amax, sizeof(double)) : NULL;
   for (;;) {
@@ -517,7 +533,7 @@ static void* sim_worker(void* arg) {
     int32_t k = J->next++;
     pthread_mutex_unlock(&J->mu);
     if (k >= J->n_sub) break;
-    simulate_one(J, k, win, a, t, &Q, cnt, amax);
+    simulate_one(J, k, win, a, t, &Q, &MQ, cnt, amax);
   }
   pthread_mutex_lock(&J->mu);
   J->counters[0] += cnt[0];
@@ -528,6 +544,7 @@ static void* sim_worker(void* arg) {
   pthread_mutex_unlock(&J->mu);
   free(amax);
   free(Q.q);
+  free(MQ.q);
   free(win);
   free(a);
   free(t);
@@ -551,7 +568,10 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
                 double* logits_out, double* scale_out, int32_t* lat_out, int64_t* counters,
                 int32_t n_threads, int64_t max_pos, double* amax) {
   const ol_model* m = (const ol_model*)model;
-  if (cfg[CF_NOUT] < 2 || cfg[CF_NOUT] > 2) return -1; /* store latency not modelled */
+  if (cfg[CF_NOUT] < 2 || cfg[CF_NOUT] > 3) return -1;
+  /* store latencies need the store flags of the trace */
+  if (cfg[CF_NOUT] == 3 && (!feat || cfg[CF_STCOL] < 0 || cfg[CF_STCOL] >= cfg[CF_NFEAT]))
+    return -1;
   if (cfg[CF_W] < 1 || cfg[CF_NSLOT] < 1) return -1;
   if (cfg[CF_HEAD] < 0 || cfg[CF_HEAD] > 1) return -1;
   if ((mode == OL_PREDICT || logits_out) && !m) return -1;

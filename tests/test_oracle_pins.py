@@ -787,3 +787,132 @@ def test_hybrid_head_closed_form(oracle_lib, f, e_reg, N):
     assert np.all(res["lat"] == [f, E])
     assert res["logits"].shape == (N, 22)
     assert np.all(res["logits"] == bias)
+
+
+# ----------------------------------------- store latency, memory write queue ---
+
+def recurrence_mwq(F, E, S, store, W):
+    """Timestamp form with the memory write queue (an independent
+    formulation of Sec. 3.2): r as in recurrence_final; a store leaves the
+    memory write queue at x_i = max(T_i + S_i + 1, r_i, x of the previous
+    store) (it enters when it leaves the processor queue, ages from its fetch
+    like every instruction, and the queue drains in order, any number per
+    cycle).  The run ends at the largest of r and x."""
+    T, r = recurrence_final(F, E, W)
+    x = [None] * len(F)
+    last = 0
+    for i in range(len(F)):
+        if store[i]:
+            last = max(T[i] + S[i] + 1, r[i], last)
+            x[i] = last
+    final = max([r[-1]] + [v for v in x if v is not None])
+    return T, r, x, final
+
+
+def mwq_run(oracle, F, E, S, store, W=8, model=None, want_logits=False, stcol=5):
+    n = len(F)
+    feat = np.zeros((n, 32), np.float32)
+    feat[:, stcol] = np.asarray(store, np.float32)
+    feat[:, 4] = np.arange(n, dtype=np.float32) + 1  # instruction id
+    cfg = oracle.sim_cfg(32, 16, 3, W, (29, 30, 31), store_col=stcol)
+    table = np.stack([F, E, S], axis=1).astype(np.int32)
+    return oracle.simulate(cfg, feat, [0], [n], [0], model=model, mode=oracle.INJECT,
+                           lat_table=table, want_logits=want_logits, threads=1)
+
+
+@pytest.mark.parametrize("N,f,e,s,st", [(1000, 2, 3, 10, 1), (1000, 2, 10, 3, 1),
+                                        (500, 1, 4, 40, 0), (300, 3, 0, 0, 1)])
+def test_mwq_closed_forms(oracle_lib, N, f, e, s, st):
+    """F = f >= 1, E = e, S = s for every instruction: with every instruction
+    a store the last leaves the memory write queue at N*f + max(e, s) + 1;
+    with none the store latency plays no part (N*f + e + 1)."""
+    res = mwq_run(oracle_lib, [f] * N, [e] * N, [s] * N, [st] * N)
+    want = N * f + (max(e, s) if st else e) + 1
+    assert int(res["final"][0]) == want
+    assert int(res["fetch"][0]) == N * f
+
+
+def test_mwq_brute_force_literal_vs_recurrence(oracle_lib):
+    """Every F, E, S in {0,1,2}^N and every store pattern for N <= 3, W in
+    {1, 2}: the two-queue cycle model equals the timestamp form (all cases of
+    one (W, N) as independent sub-traces of one oracle run)."""
+    n_cases = 0
+    for W in (1, 2):
+        for N in range(1, 4):
+            cases = list(itertools.product(itertools.product((0, 1, 2), repeat=N),
+                                           itertools.product((0, 1, 2), repeat=N),
+                                           itertools.product((0, 1, 2), repeat=N),
+                                           itertools.product((0, 1), repeat=N)))
+            K = len(cases)
+            table = np.array([[F[i], E[i], S[i]] for F, E, S, _ in cases for i in range(N)],
+                             np.int32)
+            feat = np.zeros((K * N, 32), np.float32)
+            feat[:, 5] = [st[i] for _, _, _, st in cases for i in range(N)]
+            cfg = oracle_lib.sim_cfg(32, 16, 3, W, (29, 30, 31), store_col=5)
+            start = np.arange(K, dtype=np.int64) * N
+            res = oracle_lib.simulate(cfg, feat, start, np.full(K, N, np.int64),
+                                      np.zeros(K, np.int32), mode=oracle_lib.INJECT,
+                                      lat_table=table)
+            want = [recurrence_mwq(F, E, S, st, W)[3] for F, E, S, st in cases]
+            np.testing.assert_array_equal(res["final"], want)
+            n_cases += K
+    assert n_cases == 2 * sum(27 ** n * 2 ** n for n in range(1, 4))
+
+
+def test_mwq_random_recurrence(oracle_lib):
+    rng = np.random.default_rng(11)
+    for trial in range(150):
+        N = int(rng.integers(1, 80))
+        W = int(rng.integers(1, 9))
+        F = rng.integers(0, 4, size=N)
+        E = rng.integers(0, 30, size=N)
+        S = rng.integers(0, 60, size=N)
+        st = rng.random(N) < 0.3
+        final = recurrence_mwq(F, E, S, st, W)[3]
+        res = mwq_run(oracle_lib, F, E, S, st, W=W)
+        assert int(res["final"][0]) == final
+        assert int(res["final"][0]) == int(res["fetch"][0]) + int(res["drain"][0])
+
+
+def probe_net3(slot, col):
+    """probe_net with three outputs (fetch, execution, store): the fetch
+    output is x[slot][col], the others 0."""
+    layers = synth.net_small()[:-1] + [synth.Layer(synth.FC, 256, 3, 0)]
+    ws = [np.zeros((32, 32, 2), np.float32), np.zeros((64, 32, 2), np.float32),
+          np.zeros((3, 256), np.float32)]
+    bs = [np.zeros(32, np.float32), np.zeros(64, np.float32), np.zeros(3, np.float32)]
+    ws[0][0, col, slot % 2] = 1.0
+    ws[1][0, 0, (slot // 2) % 2] = 1.0
+    ws[2][0, slot // 4] = 1.0
+    return layers, ws, bs
+
+
+@pytest.mark.parametrize("slot,col", [(1, 4), (3, 4), (7, 4), (15, 4), (2, 29), (6, 29),
+                                      (9, 30), (12, 31)])
+def test_mwq_window_order(oracle_lib, slot, col):
+    """With store latencies the context is the processor queue newest first,
+    then the memory write queue newest first (Sec. 3.2's two queues), C slots
+    in all; every slot carries residence, execution and store latency.
+    Read back through a selector model in inject mode and compared with the
+    queues implied by the timestamp form."""
+    layers, ws, bs = probe_net3(slot, col)
+    m = oracle_lib.Model(layers, ws, bs, 32, 16)
+    N = 300
+    rng = np.random.default_rng(slot * 31 + col)
+    F = rng.integers(0, 3, size=N)
+    E = rng.integers(0, 25, size=N)
+    S = rng.integers(0, 80, size=N)
+    st = (rng.random(N) < 0.4).astype(int)
+    res = mwq_run(oracle_lib, F, E, S, st, model=m, want_logits=True)
+    T, r, x, _ = recurrence_mwq(F, E, S, st, 8)
+    for i in range(N):
+        t = T[i - 1] if i > 0 else 0
+        pq = [j for j in range(i) if r[j] > t]                       # oldest -> newest
+        mq = [j for j in range(i) if st[j] and r[j] <= t < x[j]]
+        shown = (pq[::-1] + mq[::-1])[:15]
+        if slot <= len(shown):
+            j = shown[slot - 1]
+            want = {4: j + 1, 29: t - T[j], 30: E[j], 31: S[j]}[col]
+        else:
+            want = 0
+        assert res["logits"][i, 0] == want, (i, slot, col)
