@@ -15,6 +15,8 @@ Workloads (--workload):
                    1 % of the FP32 run, the others are reported beside it.
   tiny             10,000 instructions, one sub-trace, 16 x 32 windows, conv
                    32/64 + FC 2, FP32: bound by per-step latency (B = 1).
+  c3st_1m          c3_1m with store latencies (FC 512 -> 3) and the memory
+                   write queue that stores pass through, FP32 and BF16.
   c3hyb_1m         c3_1m with the paper's hybrid inference head (FC 512 -> 22:
                    per latency type 10 class scores + 1 direct output), FP32
                    and BF16.
@@ -43,7 +45,7 @@ METRIC = "simulated MIPS on 1 MI355X, FP32 vs BF16/FP8 at ≤1% total-cycle erro
 # FLOP per prediction from the layer lists (multiply-adds x 2); the kernels
 # skip window slots and conv positions no output depends on, so they execute
 # slightly fewer (6,631,424 for the C3 network).
-FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560, "c3hyb": 6_723_072}
+FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560, "c3hyb": 6_723_072, "c3st": 6_703_616}
 # Training step per context: forward 3,760,896 MAC (trunk + FC 512 -> 802),
 # backward twice that less conv1's input gradient (352,000 MAC), x 2 FLOP.
 FLOP_PER_TRAIN_CTX = 21_861_376
@@ -77,8 +79,8 @@ def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0):
     import oracle
     oracle.build(force=not os.path.exists(oracle.LIB))
     model = oracle.Model(wl.layers, ws, bs, wl.n_feat, wl.n_slot)
-    cfg = oracle.sim_cfg(wl.n_feat, wl.n_slot, 2, wl.retire_width, wl.cols,
-                         head=wl.extra.get("head", 0))
+    cfg = oracle.sim_cfg(wl.n_feat, wl.n_slot, wl.n_out, wl.retire_width, wl.cols,
+                         head=wl.extra.get("head", 0), store_col=wl.extra.get("store_col", -1))
     threads = oracle.default_threads()
     K = len(start)
     if K == 1:
@@ -110,7 +112,7 @@ def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, wa
     the whole runs (host clock) and of the step kernel (HIP events on the
     stream the library launches on)."""
     sim = sn.Simulator(dfeat, wl.n_slot, wl.cols, start, length, warm, prec=PREC[prec],
-                       n_feat=n_feat)
+                       n_feat=n_feat, n_out=wl.n_out, store_col=wl.extra.get("store_col", 0))
     sim.load_weights(wl.layers, sn.flat_params(ws, bs))
     if prec == "fp8":
         sim.calibrate(64)  # per-channel scales from the first 64 FP32 steps (set-up, untimed)
@@ -185,6 +187,8 @@ WORKLOAD_TEXT = {
              "random-init weights",
     "tiny": "tiny: 10,000-instruction synthetic trace, one sub-trace, 16x32 windows, "
             "conv 32/64 k2s2 + FC 2, random-init weights",
+    "c3st_1m": "c3st_1m: the c3_1m trace and partition with store latencies (FC 512 -> 3: "
+               "fetch, execution, store) and the memory write queue, random-init weights",
     "c3hyb_1m": "c3hyb_1m: the c3_1m trace and partition with the hybrid inference head "
                 "(per latency type 10 class scores + 1 direct output, FC 512 -> 22), "
                 "random-init weights",
@@ -262,7 +266,7 @@ def main():
         return
     ws, bs = synth.init_weights(wl.weight_seed, wl.layers,
                                 out_bias=wl.extra.get("out_bias", synth.OUT_BIAS))
-    net = {"tiny": "small", "c3hyb_1m": "c3hyb"}.get(args.workload, "c3")
+    net = {"tiny": "small", "c3hyb_1m": "c3hyb", "c3st_1m": "c3st"}.get(args.workload, "c3")
     n_feat = None
     feat = None
     if args.workload == "c3_uneven":
@@ -290,7 +294,7 @@ def main():
         dfeat = torch.from_numpy(feat).cuda()
         if args.workload == "tiny":
             forms = [args.prec or "f32"]
-        elif args.workload == "c3hyb_1m":
+        elif args.workload in ("c3hyb_1m", "c3st_1m"):
             forms = [args.prec] if args.prec else ["f32", "bf16"]
         else:
             forms = [args.prec] if args.prec else ["f32", "bf16", "fp8"]

@@ -81,14 +81,19 @@ typedef struct {
 typedef struct {
   int32_t n_feat;        /* D: features per instruction (window width) */
   int32_t n_slot;        /* L: window slots = 1 + context capacity C */
-  int32_t n_out;         /* predicted latencies per instruction: 2 (fetch, execution) */
+  int32_t n_out;         /* predicted latencies per instruction: 2 (fetch, execution),
+                            or 3 (and store: stores then pass through the memory
+                            write queue, Sec. 3.2; C3 window, FP32/BF16) */
   int32_t retire_width;  /* W: in-order retirements per cycle, 1..16 */
   int32_t col_res;       /* feature column receiving residence latency, -1 = none */
   int32_t col_exe;       /* feature column receiving execution latency, -1 = none */
-  int32_t col_sto;       /* feature column receiving store latency (written 0), -1 = none */
+  int32_t col_sto;       /* feature column receiving store latency (0 when n_out = 2), -1 = none */
   int32_t lat_max;       /* rounded latencies are clamped to [0, lat_max] */
   int32_t prec;          /* sim_precision of the predictor */
-  int32_t reserved;      /* must be 0 */
+  int32_t store_col;     /* n_out = 3: trace feature column whose nonzero value marks
+                            a store (packed codes: the expanded column; 2 is the
+                            store op class); n_out = 3 also needs lat_max <= 65535.
+                            Ignored when n_out = 2. */
   void* stream;          /* hipStream_t borrowed from the caller */
 } sim_config;
 

@@ -40,7 +40,7 @@ class sim_config(C.Structure):
     _fields_ = [("n_feat", C.c_int32), ("n_slot", C.c_int32), ("n_out", C.c_int32),
                 ("retire_width", C.c_int32), ("col_res", C.c_int32), ("col_exe", C.c_int32),
                 ("col_sto", C.c_int32), ("lat_max", C.c_int32), ("prec", C.c_int32),
-                ("reserved", C.c_int32), ("stream", C.c_void_p)]
+                ("store_col", C.c_int32), ("stream", C.c_void_p)]
 
 
 class sim_trace(C.Structure):
@@ -110,9 +110,9 @@ def _ptr(t) -> Optional[int]:
 
 def make_config(n_feat: int, n_slot: int, cols: Sequence[int], retire_width: int = 8,
                 lat_max: int = 65535, prec: int = SIM_FP32, n_out: int = 2,
-                stream=None) -> sim_config:
+                stream=None, store_col: int = 0) -> sim_config:
     return sim_config(n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max,
-                      prec, 0, stream)
+                      prec, store_col, stream)
 
 
 def make_trace(feat_ptr: Optional[int], n_instr: int, start, length, warm,
@@ -153,7 +153,8 @@ class Simulator:
 
     def __init__(self, feat, n_slot: int, cols: Sequence[int], start, length, warm,
                  retire_width: int = 8, lat_max: int = 65535, prec: int = SIM_FP32,
-                 stream=None, n_feat: Optional[int] = None):
+                 stream=None, n_feat: Optional[int] = None, n_out: int = 2,
+                 store_col: int = 0):
         import torch
         if not feat.is_cuda or not feat.is_contiguous():
             raise ValueError("feat must be a contiguous device tensor")
@@ -165,8 +166,9 @@ class Simulator:
             raise ValueError("feat must be float32 [n][D] rows or int32 [n] codes with n_feat")
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.feat = feat
-        self.cfg = make_config(width, n_slot, cols, retire_width, lat_max, prec,
-                               stream=self.stream.cuda_stream)
+        self.cfg = make_config(width, n_slot, cols, retire_width, lat_max, prec, n_out=n_out,
+                               stream=self.stream.cuda_stream, store_col=store_col)
+        self.n_out = n_out
         self.trace = make_trace(feat.data_ptr(), feat.shape[0], start, length, warm, kind)
         self.n_sub = int(self.trace.n_sub)
         self.n_pred = int(np.sum(self.trace._keep[1]) + np.sum(self.trace._keep[2]))

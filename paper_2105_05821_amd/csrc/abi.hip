@@ -39,7 +39,8 @@ struct sim_ctx {
   int32_t n_sub = 0;
   int64_t n_instr = 0;
   const float* feat = nullptr;
-  int net = -1;  // 0 NetSmall, 1 NetC3, 2 C3 training head, 3 C3 hybrid inference head
+  int net = -1;  // 0 NetSmall, 1 NetC3, 2 C3 training head, 3 C3 hybrid inference head,
+                 // 4 C3 with store latencies (memory write queue)
   int C = 0;
   uint32_t relu = 0;
   bool weights = false;
@@ -103,7 +104,8 @@ int check_cfg(const sim_config* cfg, const sim_trace* tr, std::string* why) {
   };
   if (!cfg || !tr) return bad("null config or trace");
   if (cfg->n_feat < 1 || cfg->n_slot < 2) return bad("n_feat must be >= 1 and n_slot >= 2");
-  if (cfg->n_out != 2) return bad("n_out must be 2 (fetch, execution)");
+  if (cfg->n_out != 2 && cfg->n_out != 3)
+    return bad("n_out must be 2 (fetch, execution) or 3 (and store)");
   if (cfg->retire_width < 1 || cfg->retire_width > WMAX) return bad("retire_width must be 1..16");
   const int32_t cols[3] = {cfg->col_res, cfg->col_exe, cfg->col_sto};
   for (int i = 0; i < 3; ++i) {
@@ -113,7 +115,10 @@ int check_cfg(const sim_config* cfg, const sim_trace* tr, std::string* why) {
   }
   if (cfg->lat_max < 1) return bad("lat_max must be >= 1");
   if (cfg->prec < SIM_FP32 || cfg->prec > SIM_FP8E4M3) return bad("unknown precision");
-  if (cfg->reserved != 0) return bad("reserved field must be 0");
+  if (cfg->n_out == 3) {
+    if (cfg->store_col < 0 || cfg->store_col >= cfg->n_feat) return bad("store_col out of range");
+    if (cfg->lat_max > 65535) return bad("lat_max must be <= 65535 with store latencies");
+  }
   if (tr->n_sub == 0 && !tr->feat) return SIM_OK;  // predictor-only context (no trace)
   if (!tr->feat) return bad("feat is NULL");
   if (tr->feat_dtype != SIM_FEAT_F32 && tr->feat_dtype != SIM_FEAT_CODE32)
@@ -401,6 +406,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
   Layout lay{};
   std::vector<uint8_t> packed = c->net == 0   ? relayout<NetSmall>(prec, params, scales, &lay)
                                 : c->net == 3 ? relayout<NetC3Hyb>(prec, params, scales, &lay)
+                                : c->net == 4 ? relayout<NetC3S>(prec, params, scales, &lay)
                                               : relayout<NetC3>(prec, params, scales, &lay);
   void* dw = nullptr;
   hipError_t e = hipMalloc(&dw, packed.size());
@@ -427,7 +433,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
     w->conv_ai[l] = F(lay.conv_ai[l]);
   }
   w->x_inv = F(lay.x_inv);
-  if (c->net == 1 || c->net == 3) {
+  if (c->net == 1 || c->net == 3 || c->net == 4) {
     w->hid_w = base + lay.hid_w;
     w->hid_b = F(lay.hid_b);
     w->hid_ws = F(lay.hid_ws);
@@ -673,6 +679,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
     return rc;
   }
   c->net = window_net(cfg->n_feat, cfg->n_slot);
+  if (cfg->n_out == 3) c->net = c->net == 1 ? 4 : -1;  // store latencies: the C3 window only
   if (c->net < 0) {
     fprintf(stderr, "sim_init: no kernel for window %dx%d at precision %d\n", cfg->n_slot,
             cfg->n_feat, cfg->prec);
@@ -744,6 +751,11 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
                o_fe = take(8 * K), o_dr = take(8 * K), o_fi = take(8 * K), o_wt = take(8 * K),
                o_ctr = take(8 * NCOUNTERS), o_tot = take(8), o_order = take(4 * K),
                o_slot = take(4 * (size_t)n_slots), o_next = take(4);
+  const bool mwq = cfg->n_out == 3;
+  const size_t KC = mwq ? (size_t)K * C : 0, KM = mwq ? (size_t)K : 0;
+  const size_t o_mi = take(4 * KC), o_mes = take(4 * KC), o_mt = take(8 * KC), o_mr = take(8 * KC),
+               o_mx = take(8 * KC), o_mh = take(4 * KM), o_mc = take(4 * KM), o_mq = take(4 * KM),
+               o_xp = take(8 * KM);
   hipError_t e = hipMalloc(&c->dev_block, off);
   if (e != hipSuccess) {
     fprintf(stderr, "sim_init: hipMalloc(%zu): %s\n", off, hipGetErrorString(e));
@@ -776,6 +788,17 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   s.order = reinterpret_cast<int32_t*>(base + o_order);
   s.slot_kid = reinterpret_cast<int32_t*>(base + o_slot);
   s.next = reinterpret_cast<unsigned*>(base + o_next);
+  if (mwq) {
+    s.m_idx = reinterpret_cast<int32_t*>(base + o_mi);
+    s.m_es = reinterpret_cast<int32_t*>(base + o_mes);
+    s.m_t = reinterpret_cast<int64_t*>(base + o_mt);
+    s.m_r = reinterpret_cast<int64_t*>(base + o_mr);
+    s.m_x = reinterpret_cast<int64_t*>(base + o_mx);
+    s.m_head = reinterpret_cast<int32_t*>(base + o_mh);
+    s.m_count = reinterpret_cast<int32_t*>(base + o_mc);
+    s.m_inpq = reinterpret_cast<int32_t*>(base + o_mq);
+    s.x_prev = reinterpret_cast<int64_t*>(base + o_xp);
+  }
 
   hipError_t e1 = hipMemcpyAsync(base + o_first, first.data(), 8 * K, hipMemcpyHostToDevice, c->stream);
   hipError_t e2 = hipMemcpyAsync(base + o_npos, npos.data(), 8 * K, hipMemcpyHostToDevice, c->stream);
@@ -804,6 +827,12 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
     c->net = 2;
     return load_train_weights(c, layers, n_layers, params, on_device);
   }
+  if (c->net == 4) {  // store latencies: the trunk with three outputs only
+    if (!layers_match<NetC3S>(layers, n_layers))
+      return fail(c, SIM_EUNSUPPORTED, "with n_out = 3 the layer list must end in FC 512 -> 3");
+    if (c->cfg.prec == SIM_FP8E4M3)
+      return fail(c, SIM_EUNSUPPORTED, "no FP8 form with store latencies");
+  }
   if (c->net == 2 || c->net == 3) c->net = 1;
   if (c->net == 1 && layers_match<NetC3Hyb>(layers, n_layers)) {
     if (c->cfg.prec == SIM_FP8E4M3)
@@ -811,13 +840,14 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
     c->net = 3;
   }
   const bool ok = c->net == 0   ? layers_match<NetSmall>(layers, n_layers)
-                  : c->net == 3 ? true
+                  : c->net >= 3 ? true
                                 : layers_match<NetC3>(layers, n_layers);
   if (!ok) return fail(c, SIM_EUNSUPPORTED, "no kernel for this layer list");
   if (layers[n_layers - 1].relu)
     return fail(c, SIM_EUNSUPPORTED, "the output layer must not have ReLU");
   const size_t np = c->net == 0   ? param_count<NetSmall>()
                     : c->net == 3 ? param_count<NetC3Hyb>()
+                    : c->net == 4 ? param_count<NetC3S>()
                                   : param_count<NetC3>();
   std::vector<float> host(np);
   if (on_device) {
@@ -862,7 +892,7 @@ int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* tabl
   if (!c) return SIM_EINVAL;
   if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
   if (c->net == 2) return fail(c, SIM_EUNSUPPORTED, "no FP8 training form");
-  if (c->net == 3) return fail(c, SIM_EUNSUPPORTED, "no FP8 form of the hybrid head");
+  if (c->net >= 3) return fail(c, SIM_EUNSUPPORTED, "no FP8 form of this network");
   if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
   if (c->cfg.prec == SIM_BF16) return fail(c, SIM_EUNSUPPORTED, "calibration runs FP32 weights");
   if (n_steps < 1) return fail(c, SIM_EINVAL, "n_steps < 1");
@@ -956,6 +986,7 @@ static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
   p.col_res = c->cfg.col_res;
   p.col_exe = c->cfg.col_exe;
   p.col_sto = c->cfg.col_sto;
+  p.store_col = c->cfg.n_out == 3 ? c->cfg.store_col : 0;
   p.lat_max = c->cfg.lat_max;
   p.lat_mode = mode;
   p.lat_table = table;

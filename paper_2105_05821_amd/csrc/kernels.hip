@@ -90,7 +90,8 @@ struct PFP8 {
 // the form's LDS budget allows beside the queue rings.
 template <class Net, class P>
 constexpr int group_blocks() {
-  return Net::NCONV == 2 ? Net::NB : (P::ID == 0 ? 2 : 4);
+  // (store latencies: the stores' ring takes LDS, so smaller groups)
+  return Net::NCONV == 2 ? Net::NB : Net::MWQ ? (P::ID == 0 ? 1 : 2) : (P::ID == 0 ? 2 : 4);
 }
 
 template <class Net, class P>
@@ -578,7 +579,7 @@ template <int CPT>
 struct RowRegs {
   float2 v[CPT / 2];
   uint32_t code;
-  float res, ex;
+  float res, ex, sto;
   int valid;
 };
 
@@ -602,6 +603,11 @@ __device__ __forceinline__ int32_t round_latency(float v, int32_t lat_max, uint3
   return (int32_t)r;
 }
 
+// Execution and store latency (each at most 65535) in one 32-bit word.
+__device__ __forceinline__ int32_t pack_es(int32_t e, int32_t s) {
+  return (int32_t)((uint32_t)e | ((uint32_t)s << 16));
+}
+
 // Hybrid head (Sec. 2.3): the most probable class (the first of equal
 // scores; a NaN score never wins) is the latency, unless it is the last
 // class ("larger"), which takes the direct output z[HYB_CLASSES], rounded.
@@ -617,6 +623,7 @@ __device__ __forceinline__ int32_t hybrid_latency(const float* z, int32_t lat_ma
 
 template <class Net, class P>
 struct StepSmem {
+  static constexpr int CM = Net::MWQ ? Net::C : 1;
   NetSmem<Net, P> net;
   int32_t q_idx[MT][Net::C];
   int32_t q_e[MT][Net::C];
@@ -625,6 +632,14 @@ struct StepSmem {
   int64_t rw[MT][WMAX];
   int64_t cur[MT], t_w[MT], r_prev[MT], pos[MT], first[MT], n_pos[MT], pred_off[MT];
   int32_t head[MT], count[MT], warm[MT], active[MT], kid[MT];
+  // stores (store latencies only), as in DevState
+  int32_t m_idx[MT][CM];
+  int32_t m_es[MT][CM];
+  int64_t m_t[MT][CM];
+  int64_t m_r[MT][CM];
+  int64_t m_x[MT][CM];
+  int32_t m_head[MT], m_count[MT], m_inpq[MT];
+  int64_t x_prev[MT];
 };
 
 // Slot s of the tile takes sub-trace k: its scalars come from the global
@@ -646,6 +661,12 @@ __device__ __forceinline__ void load_slot(SM& sm, int s, int k, const DevState& 
   sm.head[s] = st.head[k];
   sm.count[s] = st.count[k];
   sm.warm[s] = st.warm[k];
+  if (st.m_head) {
+    sm.m_head[s] = st.m_head[k];
+    sm.m_count[s] = st.m_count[k];
+    sm.m_inpq[s] = st.m_inpq[k];
+    sm.x_prev[s] = st.x_prev[k];
+  }
   for (int i = 0; i < W; ++i) sm.rw[s][i] = st.rw[(size_t)k * WMAX + i];
   sm.active[s] = sm.pos[s] < sm.n_pos[s];
 }
@@ -706,6 +727,13 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       sm.q_e[s][e] = st.q_e[g];
       sm.q_t[s][e] = st.q_t[g];
       sm.q_r[s][e] = st.q_r[g];
+      if constexpr (Net::MWQ) {
+        sm.m_idx[s][e] = st.m_idx[g];
+        sm.m_es[s][e] = st.m_es[g];
+        sm.m_t[s][e] = st.m_t[g];
+        sm.m_r[s][e] = st.m_r[g];
+        sm.m_x[s][e] = st.m_x[g];
+      }
     }
   }
   uint32_t n_clamped = 0, n_nonfinite = 0, n_mismatch = 0, n_pred = 0;
@@ -728,15 +756,27 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     int64_t idx = -1;
     r.res = 0.f;
     r.ex = 0.f;
+    r.sto = 0.f;
     if (gt < nb * BS && sm.active[gs]) {
       if (w == 0) {
         idx = sm.first[gs] + sm.pos[gs];
-      } else if (w <= sm.count[gs]) {
+      } else if (w <= sm.count[gs]) {  // processor queue, newest first
         int e = sm.head[gs] + sm.count[gs] - w;
         e = e >= C ? e - C : e;
         idx = sm.q_idx[gs][e];
         r.res = (float)(sm.cur[gs] - sm.q_t[gs][e]);
-        r.ex = (float)sm.q_e[gs][e];
+        const int32_t es = sm.q_e[gs][e];
+        r.ex = (float)(Net::MWQ ? es & 0xffff : es);
+        if (Net::MWQ) r.sto = (float)((uint32_t)es >> 16);
+      } else if (Net::MWQ && w <= sm.count[gs] + sm.m_count[gs] - sm.m_inpq[gs]) {
+        // then the memory write queue, newest first: the stores that have
+        // left the processor queue and not this one
+        int e = sm.m_head[gs] + sm.m_count[gs] - sm.m_inpq[gs] - (w - sm.count[gs]);
+        e = e >= C ? e - C : e;
+        idx = sm.m_idx[gs][e];
+        r.res = (float)(sm.cur[gs] - sm.m_t[gs][e]);
+        r.ex = (float)(sm.m_es[gs][e] & 0xffff);
+        r.sto = (float)((uint32_t)sm.m_es[gs][e] >> 16);
       }
     }
     r.valid = idx >= 0;
@@ -769,7 +809,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
         x = p.codes ? code_feature(r.code, c) : (cc & 1 ? r.v[cc / 2].y : r.v[cc / 2].x);
       if (c == p.col_res) x = r.res;
       if (c == p.col_exe) x = r.ex;
-      if (c == p.col_sto) x = 0.f;
+      if (c == p.col_sto) x = r.sto;
       if constexpr (CAL)
         if (c < D && r.valid) cal_max(cal, c, x);
       v[cc] = x;
@@ -834,20 +874,65 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       } else {
         ++count;
       }
-      sm.q_idx[s][slot] = (int32_t)(sm.first[s] + pos);
-      sm.q_e[s][slot] = lat[1];
+      const int64_t ii = sm.first[s] + pos;
+      sm.q_idx[s][slot] = (int32_t)ii;
+      // store latencies: E and S packed as 16-bit halves (lat_max <= 65535)
+      sm.q_e[s][slot] = Net::MWQ ? pack_es(lat[1], lat[Net::NLAT - 1]) : lat[1];
       sm.q_t[s][slot] = Tn;
       sm.q_r[s][slot] = r;
+      int64_t final_t = r;
+      if constexpr (Net::MWQ) {
+        // memory write queue (Sec. 3.2): a store enters it when it leaves
+        // the processor queue (r) and leaves, in order, once its residence
+        // exceeds its store latency: x = max(T + S + 1, r, previous x)
+        int mh = sm.m_head[s], mc = sm.m_count[s];
+        while (mc > 0 && sm.m_x[s][mh] <= Tn) {  // gone by Tn: a prefix (x is monotone)
+          mh = mh + 1 == C ? 0 : mh + 1;
+          --mc;
+        }
+        const bool is_store = p.codes ? code_feature(p.codes[ii], p.store_col) != 0.f
+                                      : p.feat[ii * Net::D + p.store_col] != 0.f;
+        if (is_store) {
+          int64_t x = Tn + lat[2] + 1;
+          x = x > r ? x : r;
+          x = x > sm.x_prev[s] ? x : sm.x_prev[s];
+          sm.x_prev[s] = x;
+          int ms = mh + mc;
+          ms = ms >= C ? ms - C : ms;
+          if (mc == C) {
+            mh = mh + 1 == C ? 0 : mh + 1;  // the newest C stores suffice for the window
+          } else {
+            ++mc;
+          }
+          sm.m_idx[s][ms] = (int32_t)ii;
+          sm.m_es[s][ms] = pack_es(lat[1], lat[2]);
+          sm.m_t[s][ms] = Tn;
+          sm.m_r[s][ms] = r;
+          sm.m_x[s][ms] = x;
+        }
+        // the newest stores still in the processor queue at Tn (r > Tn)
+        int q = 0;
+        while (q < mc) {
+          int e = mh + mc - 1 - q;
+          e = e >= C ? e - C : e;
+          if (sm.m_r[s][e] <= Tn) break;
+          ++q;
+        }
+        sm.m_head[s] = mh;
+        sm.m_count[s] = mc;
+        sm.m_inpq[s] = q;
+        final_t = r > sm.x_prev[s] ? r : sm.x_prev[s];
+      }
       sm.head[s] = head;
       sm.count[s] = count;
       sm.r_prev[s] = r;
       sm.cur[s] = Tn;
       sm.pos[s] = pos + 1;
       if (pos + 1 == sm.warm[s]) sm.t_w[s] = Tn;
-      if (pos + 1 == sm.n_pos[s]) {  // last instruction: drain ends at r (Eq. 1)
+      if (pos + 1 == sm.n_pos[s]) {  // last instruction: the drain ends (Eq. 1)
         st.fetch[k] = Tn - sm.t_w[s];
-        st.drain[k] = r - Tn;
-        st.final_tick[k] = r;
+        st.drain[k] = final_t - Tn;
+        st.final_tick[k] = final_t;
         st.warm_tick[k] = sm.t_w[s];
         st.pos[k] = pos + 1;
         st.cur[k] = Tn;
@@ -868,6 +953,12 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       st.pos[k] = sm.pos[tid];
       st.head[k] = sm.head[tid];
       st.count[k] = sm.count[tid];
+      if constexpr (Net::MWQ) {
+        st.m_head[k] = sm.m_head[tid];
+        st.m_count[k] = sm.m_count[tid];
+        st.m_inpq[k] = sm.m_inpq[tid];
+        st.x_prev[k] = sm.x_prev[tid];
+      }
       for (int i = 0; i < p.W; ++i) st.rw[(size_t)k * WMAX + i] = sm.rw[tid][i];
     }
     if (n_clamped) atomicAdd(&st.counters[0], (unsigned long long)n_clamped);
@@ -888,6 +979,13 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       st.q_e[g] = sm.q_e[s][e];
       st.q_t[g] = sm.q_t[s][e];
       st.q_r[g] = sm.q_r[s][e];
+      if constexpr (Net::MWQ) {
+        st.m_idx[g] = sm.m_idx[s][e];
+        st.m_es[g] = sm.m_es[s][e];
+        st.m_t[g] = sm.m_t[s][e];
+        st.m_r[g] = sm.m_r[s][e];
+        st.m_x[g] = sm.m_x[s][e];
+      }
     }
   }
 }
@@ -1036,6 +1134,12 @@ __global__ void reset_kernel(DevState st, int32_t n_sub, int32_t C, int32_t n_sl
     st.final_tick[i] = 0;
     st.warm_tick[i] = 0;
     for (int w = 0; w < WMAX; ++w) st.rw[i * WMAX + w] = 0;
+    if (st.m_head) {
+      st.m_head[i] = 0;
+      st.m_count[i] = 0;
+      st.m_inpq[i] = 0;
+      st.x_prev[i] = 0;
+    }
     for (int e = 0; e < C; ++e) {
       st.q_idx[i * C + e] = 0;
       st.q_e[i * C + e] = 0;
@@ -1078,6 +1182,11 @@ static hipError_t launch_step_n(int prec, const DevWeights& w, uint32_t relu, co
 
 hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, const DevState& s,
                        const StepParams& p, hipStream_t stream) {
+  if (net == 4) {  // store latencies: FP32 and BF16 forms
+    if (prec == 0) return launch_step_t<NetC3S, PF32>(w, relu, s, p, stream);
+    if (prec == 1) return launch_step_t<NetC3S, PBF16>(w, relu, s, p, stream);
+    return hipErrorInvalidValue;
+  }
   if (net == 3) {  // hybrid head: FP32 and BF16 forms
     if (prec == 0) return launch_step_t<NetC3Hyb, PF32>(w, relu, s, p, stream);
     if (prec == 1) return launch_step_t<NetC3Hyb, PBF16>(w, relu, s, p, stream);
@@ -1121,6 +1230,11 @@ int calibration_size(int net) { return net == 0 ? n_cal<NetSmall>() : n_cal<NetC
 
 hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
                           int64_t B, float* logits, hipStream_t stream) {
+  if (net == 4) {
+    if (prec == 0) return launch_forward_t<NetC3S, PF32>(w, relu, x, B, logits, stream);
+    if (prec == 1) return launch_forward_t<NetC3S, PBF16>(w, relu, x, B, logits, stream);
+    return hipErrorInvalidValue;
+  }
   if (net == 3) {
     if (prec == 0) return launch_forward_t<NetC3Hyb, PF32>(w, relu, x, B, logits, stream);
     if (prec == 1) return launch_forward_t<NetC3Hyb, PBF16>(w, relu, x, B, logits, stream);
@@ -1167,6 +1281,10 @@ hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu
     if (prec > 1) return hipErrorInvalidValue;
     fn = prec == 0 ? step_fn<NetC3Hyb, PF32>(run_net) : step_fn<NetC3Hyb, PBF16>(run_net);
     nt = Geo<NetC3Hyb, PF32>::NT;
+  } else if (net == 4) {
+    if (prec > 1) return hipErrorInvalidValue;
+    fn = prec == 0 ? step_fn<NetC3S, PF32>(run_net) : step_fn<NetC3S, PBF16>(run_net);
+    nt = Geo<NetC3S, PF32>::NT;
   } else {
     fn = prec == 0 ? step_fn<NetC3, PF32>(run_net)
          : prec == 1 ? step_fn<NetC3, PBF16>(run_net) : step_fn<NetC3, PFP8>(run_net);

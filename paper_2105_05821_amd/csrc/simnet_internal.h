@@ -21,6 +21,7 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr int CH1 = 32, CH2 = 64, CH3 = 0;
   static constexpr int HID = 0, NOUT = 2;
   static constexpr int NLAT = 2, HEAD = 0;   // latencies per instruction; regression head
+  static constexpr bool MWQ = false;         // store latency and memory write queue
   static constexpr int WAVES = 4;
   static constexpr int CHL = CH2;            // channels of the last conv
 };
@@ -30,6 +31,7 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
   static constexpr int CH1 = 64, CH2 = 128, CH3 = 256;
   static constexpr int HID = 512, NOUT = 2;
   static constexpr int NLAT = 2, HEAD = 0;
+  static constexpr bool MWQ = false;
   static constexpr int WAVES = 8;
   static constexpr int CHL = CH3;
 };
@@ -38,6 +40,12 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
 constexpr int HYB_CLASSES = 10, HYB_PER_TYPE = HYB_CLASSES + 1;
 struct NetC3Hyb : NetC3 {  // C3 trunk -> FC 512 -> 2 x 11
   static constexpr int NOUT = 2 * HYB_PER_TYPE, HEAD = 1;
+};
+// Store latency (Sec. 3.2): three outputs (fetch, execution, store) and the
+// memory write queue that stores enter on leaving the processor queue.
+struct NetC3S : NetC3 {  // C3 trunk -> FC 512 -> 3
+  static constexpr int NOUT = 3, NLAT = 3;
+  static constexpr bool MWQ = true;
 };
 
 // Contraction length covered by one 16-byte per-lane MFMA fragment group:
@@ -91,11 +99,26 @@ struct DevState {
   int32_t* head;
   int32_t* count;
   int64_t* rw;              // [K][WMAX] retire times of the last W pushes
-  // processor queue ring [K][C]
+  // processor queue ring [K][C]: the newest C instructions (q_e holds
+  // E | S << 16 when store latencies are modelled)
   int32_t* q_idx;
   int32_t* q_e;
   int64_t* q_t;
   int64_t* q_r;
+  // stores (store latencies only, else NULL): ring [K][C] of the newest C
+  // stores with fetch tick, processor-queue exit r and memory-write-queue
+  // exit x; the oldest m_count entries from m_head that have not left; the
+  // newest m_inpq of them are still in the processor queue; x_prev = the
+  // last store's x
+  int32_t* m_idx;
+  int32_t* m_es;
+  int64_t* m_t;
+  int64_t* m_r;
+  int64_t* m_x;
+  int32_t* m_head;
+  int32_t* m_count;
+  int32_t* m_inpq;
+  int64_t* x_prev;
   // results
   int64_t* fetch;
   int64_t* drain;
@@ -115,6 +138,7 @@ struct StepParams {
   int32_t n_sub;
   int32_t W;
   int32_t col_res, col_exe, col_sto;
+  int32_t store_col;        // store latencies: trace column flagging stores
   int32_t lat_max;
   int32_t lat_mode;
   const int32_t* lat_table;

@@ -416,6 +416,15 @@ def net_c3_hybrid_infer() -> List[Layer]:
 HYB_BIAS = tuple([2.0, 1.0] + [0.0] * 8 + [2.0]) + tuple([0.0] * 9 + [2.0] + [12.0])
 
 
+def net_c3_store() -> List[Layer]:
+    """The C3 network with three outputs: fetch, execution and store latency."""
+    return net_c3()[:-1] + [Layer(FC, 512, 3, 0)]
+
+
+OUT_BIAS_STORE = (-6.0, 8.0, 20.0)  # fetch, execution, store
+STORE_COL = 2                       # the store op class column of the feature layout
+
+
 def net_c3_hybrid() -> List[Layer]:
     """The C3 trunk with the training head: per latency type 400 class
     logits and one regression output, FC 512 -> 2 x 401."""
@@ -427,6 +436,9 @@ def workload(name: str) -> Workload:
         return Workload("tiny", 10_000, 32, 16, net_small())
     if name == "c3_1m":       # 1M instructions, 4,096 sub-traces, 256 warm-up, 111 x 50
         return Workload("c3_1m", 1_000_000, 50, 111, net_c3(), n_sub=4096, warmup=256)
+    if name == "c3st_1m":     # c3_1m with store latencies and the memory write queue
+        return Workload("c3st_1m", 1_000_000, 50, 111, net_c3_store(), n_sub=4096, warmup=256,
+                        n_out=3, extra={"out_bias": OUT_BIAS_STORE, "store_col": STORE_COL})
     if name == "c3hyb_1m":    # c3_1m with the hybrid inference head
         return Workload("c3hyb_1m", 1_000_000, 50, 111, net_c3_hybrid_infer(), n_sub=4096,
                         warmup=256, extra={"out_bias": HYB_BIAS, "head": 1})

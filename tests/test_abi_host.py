@@ -37,12 +37,26 @@ def test_validate_accepts_good_config():
     assert sn.sim_validate_config(cfg, tr) == sn.SIM_OK
 
 
-@pytest.mark.parametrize("field,value", [("n_out", 3), ("retire_width", 0), ("retire_width", 17),
-                                         ("col_res", 50), ("col_exe", 47), ("lat_max", 0),
-                                         ("prec", 7), ("reserved", 1), ("n_slot", 1)])
+@pytest.mark.parametrize("field,value", [("n_out", 4), ("n_out", 1), ("retire_width", 0),
+                                         ("retire_width", 17), ("col_res", 50), ("col_exe", 47),
+                                         ("lat_max", 0), ("prec", 7), ("n_slot", 1)])
 def test_validate_rejects_bad_config(field, value):
     cfg, tr = good()
     setattr(cfg, field, value)
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_EINVAL
+
+
+def test_validate_store_latency_config():
+    """n_out = 3 (store latencies) needs a store flag column in range and
+    lat_max <= 65535; with n_out = 2 store_col is ignored."""
+    cfg, tr = good()
+    cfg.store_col = 77
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_OK
+    cfg.n_out = 3
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_EINVAL
+    cfg.store_col = 2
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_OK
+    cfg.lat_max = 65536
     assert sn.sim_validate_config(cfg, tr) == sn.SIM_EINVAL
 
 
