@@ -15,6 +15,8 @@ Workloads (--workload):
                    1 % of the FP32 run, the others are reported beside it.
   tiny             10,000 instructions, one sub-trace, 16 x 32 windows, conv
                    32/64 + FC 2, FP32: bound by per-step latency (B = 1).
+  c3dep_1m         c3_1m with the 5 memory-dependency flags per context slot,
+                   from synthetic PCs and data addresses, FP32 and BF16.
   c3st_1m          c3_1m with store latencies (FC 512 -> 3) and the memory
                    write queue that stores pass through, FP32 and BF16.
   c3hyb_1m         c3_1m with the paper's hybrid inference head (FC 512 -> 22:
@@ -73,14 +75,15 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0):
+def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0, mem=None):
     """The FP64 oracle on the host cores over a bounded sample of the
     workload's sub-traces (every step-th), scaled to MIPS."""
     import oracle
     oracle.build(force=not os.path.exists(oracle.LIB))
     model = oracle.Model(wl.layers, ws, bs, wl.n_feat, wl.n_slot)
     cfg = oracle.sim_cfg(wl.n_feat, wl.n_slot, wl.n_out, wl.retire_width, wl.cols,
-                         head=wl.extra.get("head", 0), store_col=wl.extra.get("store_col", -1))
+                         head=wl.extra.get("head", 0), store_col=wl.extra.get("store_col", -1),
+                         dep_col=wl.extra.get("dep_col", -1))
     threads = oracle.default_threads()
     K = len(start)
     if K == 1:
@@ -90,14 +93,15 @@ def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0):
         probe = np.arange(0, K, max(1, K // 8))
         t0 = time.perf_counter()
         oracle.simulate(cfg, feat, start[probe], length[probe], warm[probe], model=model,
-                        threads=threads)
+                        threads=threads, mem=mem)
         dt = time.perf_counter() - t0
         per_sub = dt / len(probe) * min(threads, len(probe))
         n = int(max(threads, min(K // 8, budget_s / max(per_sub, 1e-6) * threads)))
         step = max(1, K // n)
         ks = np.arange(0, K, step)
     t0 = time.perf_counter()
-    oracle.simulate(cfg, feat, start[ks], length[ks], warm[ks], model=model, threads=threads)
+    oracle.simulate(cfg, feat, start[ks], length[ks], warm[ks], model=model, threads=threads,
+                    mem=mem)
     dt = time.perf_counter() - t0
     meas = int(length[ks].sum())
     return {"value": round(meas / dt / 1e6, 6), "unit": "MIPS", "cores": threads,
@@ -107,12 +111,13 @@ def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0):
 
 
 def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, warmup,
-              n_feat=None, graph=False):
+              n_feat=None, graph=False, dmem=None):
     """Run the workload `steps` times after `warmup` runs; returns the time of
     the whole runs (host clock) and of the step kernel (HIP events on the
     stream the library launches on)."""
     sim = sn.Simulator(dfeat, wl.n_slot, wl.cols, start, length, warm, prec=PREC[prec],
-                       n_feat=n_feat, n_out=wl.n_out, store_col=wl.extra.get("store_col", 0))
+                       n_feat=n_feat, n_out=wl.n_out, store_col=wl.extra.get("store_col", 0),
+                       mem=dmem, col_dep=wl.extra.get("dep_col", -1))
     sim.load_weights(wl.layers, sn.flat_params(ws, bs))
     if prec == "fp8":
         sim.calibrate(64)  # per-channel scales from the first 64 FP32 steps (set-up, untimed)
@@ -187,6 +192,8 @@ WORKLOAD_TEXT = {
              "random-init weights",
     "tiny": "tiny: 10,000-instruction synthetic trace, one sub-trace, 16x32 windows, "
             "conv 32/64 k2s2 + FC 2, random-init weights",
+    "c3dep_1m": "c3dep_1m: the c3_1m trace and partition with the 5 memory-dependency flags "
+                "of every context slot (synthetic PCs and data addresses), C3 network",
     "c3st_1m": "c3st_1m: the c3_1m trace and partition with store latencies (FC 512 -> 3: "
                "fetch, execution, store) and the memory write queue, random-init weights",
     "c3hyb_1m": "c3hyb_1m: the c3_1m trace and partition with the hybrid inference head "
@@ -269,6 +276,7 @@ def main():
     net = {"tiny": "small", "c3hyb_1m": "c3hyb", "c3st_1m": "c3st"}.get(args.workload, "c3")
     n_feat = None
     feat = None
+    mem = dmem = None
     if args.workload == "c3_uneven":
         steps = args.steps if args.steps is not None else 1
         warmup = args.warmup if args.warmup is not None else 0
@@ -292,9 +300,12 @@ def main():
         feat = synth.trace_features(wl.trace_seed, n_instr, wl.n_feat)
         start, length, warm = sn.partition(n_instr, wl.n_sub, wl.warmup)
         dfeat = torch.from_numpy(feat).cuda()
+        if "dep_col" in wl.extra:
+            mem = synth.trace_mem(wl.trace_seed, n_instr)
+            dmem = torch.from_numpy(mem.view(np.int32)).cuda()
         if args.workload == "tiny":
             forms = [args.prec or "f32"]
-        elif args.workload in ("c3hyb_1m", "c3st_1m"):
+        elif args.workload in ("c3hyb_1m", "c3st_1m", "c3dep_1m"):
             forms = [args.prec] if args.prec else ["f32", "bf16"]
         else:
             forms = [args.prec] if args.prec else ["f32", "bf16", "fp8"]
@@ -304,7 +315,7 @@ def main():
     results = {}
     for f in forms:
         r = time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, f, steps, warmup,
-                      n_feat=n_feat, graph=args.workload == "c3_uneven")
+                      n_feat=n_feat, graph=args.workload == "c3_uneven", dmem=dmem)
         r["mips"] = measured * steps / r["elapsed"] / 1e6
         r["tflops"] = FLOP_PER_PRED[net] * n_pred / (r["kernel_ms"] / 1e3) / 1e12
         results[f] = r
@@ -343,7 +354,7 @@ def main():
         out["steps_per_s"] = round(n_pred * steps / b["elapsed"], 1)
     if not args.no_cpu_baseline and feat is not None:
         log("[bench] timing the FP64 oracle on the host cores")
-        out["cpu_baseline"] = cpu_baseline(wl, feat, start, length, warm, ws, bs)
+        out["cpu_baseline"] = cpu_baseline(wl, feat, start, length, warm, ws, bs, mem=mem)
     print(json.dumps(out), flush=True)
 
 

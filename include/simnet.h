@@ -94,6 +94,13 @@ typedef struct {
                             a store (packed codes: the expanded column; 2 is the
                             store op class); n_out = 3 also needs lat_max <= 65535.
                             Ignored when n_out = 2. */
+  int32_t col_dep;       /* first of 5 consecutive feature columns receiving each
+                            context instruction's memory dependency flags (Sec. 2.1):
+                            same instruction cache line, same instruction page, same
+                            data address, same data cache line, same data page as the
+                            current instruction (64-byte lines, 4 KB pages; data flags
+                            need both data addresses nonzero); 0 in slot 0 and empty
+                            slots.  -1 = none; needs sim_trace.mem. */
   void* stream;          /* hipStream_t borrowed from the caller */
 } sim_config;
 
@@ -113,6 +120,10 @@ typedef struct {
   const int64_t* start;  /* HOST [n_sub] */
   const int64_t* len;    /* HOST [n_sub], each >= 1 */
   const int32_t* warm;   /* HOST [n_sub], each >= 0 and <= start[k] */
+  const void* mem;       /* DEVICE uint32 [n_instr][2]: program counter and data
+                            address (0 = no data access) of every instruction, for
+                            the dependency flags; NULL when col_dep = -1.
+                            Borrowed like feat. */
 } sim_trace;
 
 /* Results of sim_run.  Scalars are always written; each per-sub-trace array

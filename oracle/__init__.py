@@ -60,7 +60,7 @@ def lib():
         L.ol_partition.restype = C.c_int
         L.ol_partition.argtypes = [C.c_int64, C.c_int32, C.c_int32, i64p, i64p, i32p]
         L.ol_simulate.restype = C.c_int
-        L.ol_simulate.argtypes = [P, i32p, P, C.c_int64, C.c_int32, i64p, i64p, i32p,
+        L.ol_simulate.argtypes = [P, i32p, P, P, C.c_int64, C.c_int32, i64p, i64p, i32p,
                                   C.c_int32, P, i64p, i64p, i64p, i64p, P, P, P, i64p, C.c_int32,
                                   C.c_int64, P]
         L.ol_model_new_fp8.restype = P
@@ -158,13 +158,14 @@ HYB_PER_TYPE = HYB_CLASSES + 1
 
 
 def sim_cfg(n_feat, n_slot, n_out=2, retire_width=8, cols=(-1, -1, -1), lat_max=65535,
-            head=0, store_col=-1):
+            head=0, store_col=-1, dep_col=-1):
     """head 0: regression head (n_out outputs); 1: hybrid head (Sec. 2.3),
     HYB_PER_TYPE outputs per latency type.  n_out = 3 adds store latencies
     and the memory write queue; store_col is then the trace column whose
-    nonzero value marks a store."""
+    nonzero value marks a store.  dep_col >= 0: the 5 memory-dependency flag
+    columns start there (needs the trace's addresses, `mem`)."""
     return np.array([n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max,
-                     head, store_col], dtype=np.int32)
+                     head, store_col, dep_col], dtype=np.int32)
 
 
 def n_logits(cfg) -> int:
@@ -183,9 +184,14 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
              model: Optional[Model] = None, mode: int = PREDICT,
              lat_table: Optional[np.ndarray] = None, want_logits: bool = False,
              want_lat: bool = False, n_instr: Optional[int] = None, threads: int = 0,
-             want_scale: bool = False, max_pos: int = 0, want_amax: bool = False) -> dict:
+             want_scale: bool = False, max_pos: int = 0, want_amax: bool = False,
+             mem: Optional[np.ndarray] = None) -> dict:
     """Run the oracle over every sub-trace; returns per-sub-trace int64 arrays
-    and optionally the per-prediction logits (float64) and latencies."""
+    and optionally the per-prediction logits (float64) and latencies.  mem:
+    uint32 [n_instr][2] program counters and data addresses (needed with
+    dependency flags)."""
+    if mem is not None:
+        mem = np.ascontiguousarray(mem, np.uint32)
     start = np.ascontiguousarray(start, np.int64)
     length = np.ascontiguousarray(length, np.int64)
     warm = np.ascontiguousarray(warm, np.int32)
@@ -213,7 +219,8 @@ def simulate(cfg: np.ndarray, feat: Optional[np.ndarray], start, length, warm,
     if threads <= 0:
         threads = default_threads()
     rc = lib().ol_simulate(model.ptr if model else None, cfg,
-                           feat.ctypes.data if feat is not None else None, n_instr, K,
+                           feat.ctypes.data if feat is not None else None,
+                           mem.ctypes.data if mem is not None else None, n_instr, K,
                            start, length, warm, mode,
                            lat_table.ctypes.data if lat_table is not None else None,
                            res["fetch"], res["drain"], res["final"], res["warm_tick"],

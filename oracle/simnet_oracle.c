@@ -52,7 +52,10 @@ enum { OL_PREDICT = 0, OL_INJECT = 1 };
 
 /* cfg[] layout shared with the Python wrapper */
 enum { CF_NFEAT = 0, CF_NSLOT, CF_NOUT, CF_W, CF_COLRES, CF_COLEXE, CF_COLSTO, CF_LATMAX, CF_HEAD,
-       CF_STCOL, CF_LEN };
+       CF_STCOL, CF_COLDEP, CF_LEN };
+/* CF_COLDEP: first of 5 consecutive window columns receiving the memory
+ * dependency flags of each context instruction (-1 = none). */
+enum { LINE_SHIFT = 6, PAGE_SHIFT = 12 }; /* 64-byte cache lines, 4 KB pages */
 /* CF_STCOL: with n_out = 3 (fetch, execution, store latencies), the trace
  * column whose nonzero value marks a store instruction. */
 /* CF_HEAD: 0 = regression head (one output per latency type, rounded);
@@ -420,6 +423,7 @@ typedef struct {
   const ol_model* m;
   const int32_t* cfg;
   const float* feat;
+  const uint32_t* mem; /* [n_instr][2] program counter, data address (0 = none) */
   int32_t n_sub;
   const int64_t* start;
   const int64_t* len;
@@ -445,6 +449,7 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
   const int32_t* cfg = J->cfg;
   const int D = cfg[CF_NFEAT], L = cfg[CF_NSLOT], n_out = cfg[CF_NOUT], W = cfg[CF_W];
   const int cr = cfg[CF_COLRES], ce = cfg[CF_COLEXE], cs = cfg[CF_COLSTO];
+  const int cd = cfg[CF_COLDEP];
   const int32_t lat_max = cfg[CF_LATMAX];
   const int C = L - 1;
   const int need_pred = (J->mode == OL_PREDICT) || (J->logits_out != NULL) || (amax != NULL);
@@ -473,6 +478,8 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
       if (cr >= 0) win[cr] = 0.0;
       if (ce >= 0) win[ce] = 0.0;
       if (cs >= 0) win[cs] = 0.0;
+      if (cd >= 0)
+        for (int f = 0; f < 5; ++f) win[cd + f] = 0.0;
       const int64_t inq = Q->tail - Q->head, inm = M ? M->tail - M->head : 0;
       const int shown = (int)(inq + inm < C ? inq + inm : C);
       for (int j = 1; j <= shown; ++j) {
@@ -482,6 +489,19 @@ static void simulate_one(sim_job* J, int32_t k, double* win, double* a, double* 
         if (cr >= 0) row[cr] = (double)e->res;
         if (ce >= 0) row[ce] = (double)e->e;
         if (cs >= 0) row[cs] = (n_out >= 3) ? (double)e->s : 0.0;
+        if (cd >= 0) {
+          /* memory dependency flags (Sec. 2.1): does the context
+           * instruction share this one's instruction cache line, its
+           * instruction page, its data address, data cache line, data page */
+          const uint32_t pci = J->mem[2 * i], dai = J->mem[2 * i + 1];
+          const uint32_t pcj = J->mem[2 * e->idx], daj = J->mem[2 * e->idx + 1];
+          const int both = dai != 0 && daj != 0;
+          row[cd + 0] = (pci >> LINE_SHIFT) == (pcj >> LINE_SHIFT);
+          row[cd + 1] = (pci >> PAGE_SHIFT) == (pcj >> PAGE_SHIFT);
+          row[cd + 2] = both && dai == daj;
+          row[cd + 3] = both && (dai >> LINE_SHIFT) == (daj >> LINE_SHIFT);
+          row[cd + 4] = both && (dai >> PAGE_SHIFT) == (daj >> PAGE_SHIFT);
+        }
       }
       forward_cal(J->m, win, out, a, t, J->scale_out ? scl : NULL, amax);
       if (J->logits_out)
@@ -561,7 +581,8 @@ static void* sim_worker(void* arg) {
  * depends on (window features, then every hidden layer).  Per-sub-trace results: fetch = T_last - T_w,
  * drain = final - T_last, final tick, T_w.  counters[0] = clamped, [1] =
  * non-finite.  Returns 0, or -1 on invalid arguments. */
-int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_t n_instr,
+int ol_simulate(const void* model, const int32_t* cfg, const float* feat, const uint32_t* mem,
+                int64_t n_instr,
                 int32_t n_sub, const int64_t* start, const int64_t* len, const int32_t* warm,
                 int32_t mode, const int32_t* lat_table,
                 int64_t* fetch, int64_t* drain, int64_t* final_tick, int64_t* warm_tick,
@@ -574,6 +595,7 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
     return -1;
   if (cfg[CF_W] < 1 || cfg[CF_NSLOT] < 1) return -1;
   if (cfg[CF_HEAD] < 0 || cfg[CF_HEAD] > 1) return -1;
+  if (cfg[CF_COLDEP] >= 0 && (!mem || cfg[CF_COLDEP] + 5 > cfg[CF_NFEAT])) return -1;
   if ((mode == OL_PREDICT || logits_out) && !m) return -1;
   const int n_logit = cfg[CF_HEAD] == 1 ? HYB_PER_TYPE * cfg[CF_NOUT] : cfg[CF_NOUT];
   if (m && (m->n_feat != cfg[CF_NFEAT] || m->n_slot != cfg[CF_NSLOT] || m->n_out != n_logit))
@@ -590,7 +612,7 @@ int ol_simulate(const void* model, const int32_t* cfg, const float* feat, int64_
   }
   sim_job J;
   memset(&J, 0, sizeof(J));
-  J.m = m; J.cfg = cfg; J.feat = feat; J.n_sub = n_sub;
+  J.m = m; J.cfg = cfg; J.feat = feat; J.mem = mem; J.n_sub = n_sub;
   J.start = start; J.len = len; J.warm = warm; J.pred_off = pred_off;
   J.mode = mode; J.lat_table = lat_table;
   J.fetch = fetch; J.drain = drain; J.final_tick = final_tick; J.warm_tick = warm_tick;

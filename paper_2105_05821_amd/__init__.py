@@ -40,13 +40,14 @@ class sim_config(C.Structure):
     _fields_ = [("n_feat", C.c_int32), ("n_slot", C.c_int32), ("n_out", C.c_int32),
                 ("retire_width", C.c_int32), ("col_res", C.c_int32), ("col_exe", C.c_int32),
                 ("col_sto", C.c_int32), ("lat_max", C.c_int32), ("prec", C.c_int32),
-                ("store_col", C.c_int32), ("stream", C.c_void_p)]
+                ("store_col", C.c_int32), ("col_dep", C.c_int32), ("stream", C.c_void_p)]
 
 
 class sim_trace(C.Structure):
     _fields_ = [("feat", C.c_void_p), ("feat_dtype", C.c_int32), ("n_sub", C.c_int32),
                 ("n_instr", C.c_int64), ("start", C.POINTER(C.c_int64)),
-                ("len", C.POINTER(C.c_int64)), ("warm", C.POINTER(C.c_int32))]
+                ("len", C.POINTER(C.c_int64)), ("warm", C.POINTER(C.c_int32)),
+                ("mem", C.c_void_p)]
 
 
 class sim_result(C.Structure):
@@ -110,20 +111,20 @@ def _ptr(t) -> Optional[int]:
 
 def make_config(n_feat: int, n_slot: int, cols: Sequence[int], retire_width: int = 8,
                 lat_max: int = 65535, prec: int = SIM_FP32, n_out: int = 2,
-                stream=None, store_col: int = 0) -> sim_config:
+                stream=None, store_col: int = 0, col_dep: int = -1) -> sim_config:
     return sim_config(n_feat, n_slot, n_out, retire_width, cols[0], cols[1], cols[2], lat_max,
-                      prec, store_col, stream)
+                      prec, store_col, col_dep, stream)
 
 
 def make_trace(feat_ptr: Optional[int], n_instr: int, start, length, warm,
-               feat_dtype: int = SIM_FEAT_F32):
+               feat_dtype: int = SIM_FEAT_F32, mem_ptr: Optional[int] = None):
     start = np.ascontiguousarray(start, np.int64)
     length = np.ascontiguousarray(length, np.int64)
     warm = np.ascontiguousarray(warm, np.int32)
     tr = sim_trace(feat_ptr, feat_dtype, start.shape[0], n_instr,
                    start.ctypes.data_as(C.POINTER(C.c_int64)),
                    length.ctypes.data_as(C.POINTER(C.c_int64)),
-                   warm.ctypes.data_as(C.POINTER(C.c_int32)))
+                   warm.ctypes.data_as(C.POINTER(C.c_int32)), mem_ptr)
     tr._keep = (start, length, warm)
     return tr
 
@@ -154,7 +155,7 @@ class Simulator:
     def __init__(self, feat, n_slot: int, cols: Sequence[int], start, length, warm,
                  retire_width: int = 8, lat_max: int = 65535, prec: int = SIM_FP32,
                  stream=None, n_feat: Optional[int] = None, n_out: int = 2,
-                 store_col: int = 0):
+                 store_col: int = 0, mem=None, col_dep: int = -1):
         import torch
         if not feat.is_cuda or not feat.is_contiguous():
             raise ValueError("feat must be a contiguous device tensor")
@@ -167,9 +168,15 @@ class Simulator:
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.feat = feat
         self.cfg = make_config(width, n_slot, cols, retire_width, lat_max, prec, n_out=n_out,
-                               stream=self.stream.cuda_stream, store_col=store_col)
+                               stream=self.stream.cuda_stream, store_col=store_col,
+                               col_dep=col_dep)
+        if mem is not None and (not mem.is_cuda or not mem.is_contiguous() or mem.dim() != 2
+                                or mem.shape[1] != 2 or mem.element_size() != 4):
+            raise ValueError("mem must be a contiguous 32-bit device tensor [n_instr][2]")
+        self.mem = mem
         self.n_out = n_out
-        self.trace = make_trace(feat.data_ptr(), feat.shape[0], start, length, warm, kind)
+        self.trace = make_trace(feat.data_ptr(), feat.shape[0], start, length, warm, kind,
+                                mem.data_ptr() if mem is not None else None)
         self.n_sub = int(self.trace.n_sub)
         self.n_pred = int(np.sum(self.trace._keep[1]) + np.sum(self.trace._keep[2]))
         h = C.c_void_p()

@@ -48,6 +48,7 @@ struct sim_ctx {
   int64_t max_pos = 0, n_pred = 0, n_meas = 0;
   int32_t n_wg = 0;                 // persistent workgroups; slots = n_wg * MT
   const uint32_t* codes = nullptr;  // packed trace (SIM_FEAT_CODE32)
+  const uint2* mem = nullptr;       // addresses for the dependency flags
   float* logits_out = nullptr;
   hipStream_t stream = nullptr;
   void* dev_block = nullptr;  // state + table
@@ -115,12 +116,18 @@ int check_cfg(const sim_config* cfg, const sim_trace* tr, std::string* why) {
   }
   if (cfg->lat_max < 1) return bad("lat_max must be >= 1");
   if (cfg->prec < SIM_FP32 || cfg->prec > SIM_FP8E4M3) return bad("unknown precision");
+  if (cfg->col_dep < -1 || cfg->col_dep + 5 > cfg->n_feat) return bad("col_dep out of range");
+  if (cfg->col_dep >= 0)
+    for (int i = 0; i < 3; ++i)
+      if (cols[i] >= cfg->col_dep && cols[i] < cfg->col_dep + 5)
+        return bad("dependency-flag columns overlap a dynamic column");
   if (cfg->n_out == 3) {
     if (cfg->store_col < 0 || cfg->store_col >= cfg->n_feat) return bad("store_col out of range");
     if (cfg->lat_max > 65535) return bad("lat_max must be <= 65535 with store latencies");
   }
   if (tr->n_sub == 0 && !tr->feat) return SIM_OK;  // predictor-only context (no trace)
   if (!tr->feat) return bad("feat is NULL");
+  if (cfg->col_dep >= 0 && !tr->mem) return bad("dependency flags need the trace's addresses");
   if (tr->feat_dtype != SIM_FEAT_F32 && tr->feat_dtype != SIM_FEAT_CODE32)
     return bad("unknown feat_dtype");
   if (tr->feat_dtype == SIM_FEAT_CODE32 && cfg->n_feat < 30)
@@ -700,6 +707,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
     c->codes = static_cast<const uint32_t*>(tr->feat);
   else
     c->feat = static_cast<const float*>(tr->feat);
+  c->mem = static_cast<const uint2*>(tr->mem);
   c->stream = static_cast<hipStream_t>(cfg->stream);
 
   const int32_t K = tr->n_sub, C = c->C;
@@ -910,6 +918,8 @@ int sim_calibrate(sim_ctx* c, int32_t n_steps, int32_t mode, const int32_t* tabl
     StepParams p{};
     p.feat = c->feat;
     p.codes = c->codes;
+    p.mem = c->mem;
+    p.col_dep = c->cfg.col_dep;
     p.n_wg = c->n_wg;
     p.n_sub = c->n_sub;
     p.W = c->cfg.retire_width;
@@ -980,6 +990,8 @@ static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
   StepParams p{};
   p.feat = c->feat;
   p.codes = c->codes;
+  p.mem = c->mem;
+  p.col_dep = c->cfg.col_dep;
   p.n_wg = c->n_wg;
   p.n_sub = c->n_sub;
   p.W = c->cfg.retire_width;

@@ -581,7 +581,23 @@ struct RowRegs {
   uint32_t code;
   float res, ex, sto;
   int valid;
+  uint2 mem, cur_mem;  // dependency flags: this row's and slot 0's addresses
 };
+
+// The five memory dependency flags of a context instruction with addresses
+// m against the current instruction's c (Sec. 2.1): same instruction cache
+// line, same instruction page, same data address, data cache line, data
+// page (64-byte lines, 4 KB pages; data flags need both addresses).
+__device__ __forceinline__ float dep_flag(uint2 m, uint2 c, int f) {
+  const bool both = m.y != 0u && c.y != 0u;
+  switch (f) {
+    case 0: return (m.x >> 6) == (c.x >> 6) ? 1.f : 0.f;
+    case 1: return (m.x >> 12) == (c.x >> 12) ? 1.f : 0.f;
+    case 2: return both && m.y == c.y ? 1.f : 0.f;
+    case 3: return both && (m.y >> 6) == (c.y >> 6) ? 1.f : 0.f;
+    default: return both && (m.y >> 12) == (c.y >> 12) ? 1.f : 0.f;
+  }
+}
 
 // Rounded latency in cycles: nearest, ties to even; non-finite -> 0;
 // clamped to [0, lat_max].
@@ -781,6 +797,11 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     r.valid = idx >= 0;
     r.code = 0;
+    if (p.col_dep >= 0) {  // addresses of this row and of slot 0 (broadcast)
+      r.mem = p.mem[idx < 0 ? 0 : idx];
+      r.cur_mem = p.mem[sm.active[gs] ? sm.first[gs] + sm.pos[gs] : 0];
+      if (w == 0) r.valid = idx >= 0 ? 2 : 0;  // slot 0: no flags
+    }
     if (p.codes) {
       r.code = p.codes[idx < 0 ? 0 : idx];
     } else {
@@ -810,6 +831,8 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       if (c == p.col_res) x = r.res;
       if (c == p.col_exe) x = r.ex;
       if (c == p.col_sto) x = r.sto;
+      if (p.col_dep >= 0 && c >= p.col_dep && c < p.col_dep + 5)
+        x = r.valid == 1 ? dep_flag(r.mem, r.cur_mem, c - p.col_dep) : 0.f;
       if constexpr (CAL)
         if (c < D && r.valid) cal_max(cal, c, x);
       v[cc] = x;

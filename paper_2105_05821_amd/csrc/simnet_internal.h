@@ -139,6 +139,8 @@ struct StepParams {
   int32_t W;
   int32_t col_res, col_exe, col_sto;
   int32_t store_col;        // store latencies: trace column flagging stores
+  int32_t col_dep;          // first dependency-flag column, -1 = none
+  const uint2* mem;         // [n_instr] (program counter, data address)
   int32_t lat_max;
   int32_t lat_mode;
   const int32_t* lat_table;

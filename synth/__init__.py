@@ -182,6 +182,63 @@ def trace_features(seed: int, n_instr: int, n_feat: int, lo: int = 0,
     return expand_codes(trace_codes(seed, n_instr, lo, hi), n_feat)
 
 
+# ------------------------------------------------- instruction/data addresses ---
+
+MEM_STREAM = 501
+CODE_BASE, CODE_SPAN = 0x400000, 1 << 16      # 64 KB of code
+HEAP_BASE, HEAP_SPAN = 0x10000000, 1 << 20    # 1 MB of data
+TAKEN_RATE, DATA_JUMP_RATE = 0.5, 0.4
+DEP_COLS = 42                                  # first of the 5 dependency-flag columns (D = 50)
+
+
+def trace_mem(seed: int, n_instr: int) -> np.ndarray:
+    """Program counter and data address of every instruction, uint32 [n][2]
+    (data address 0 for instructions without a data access).
+
+    PCs advance by 4 and jump to a uniform 4-aligned target in a 64 KB code
+    region after a taken branch (half of the branches).  Loads and stores
+    walk the 1 MB heap in 8-byte steps and jump on 40 % of accesses: half of
+    the jumps go back to where the previous run started (reuse), the others
+    to a uniform 8-aligned address."""
+    op = trace_fields(seed, 0, n_instr)["op"]
+    ctr = np.arange(n_instr, dtype=np.uint64) * np.uint64(4)
+    u_take = uniform(seed, MEM_STREAM, ctr)
+    u_tgt = u64(seed, MEM_STREAM, ctr + np.uint64(1))
+    u_jump = uniform(seed, MEM_STREAM, ctr + np.uint64(2))
+    u_addr = u64(seed, MEM_STREAM, ctr + np.uint64(3))
+    idx = np.arange(n_instr, dtype=np.int64)
+    # PC: segments start at 0 and after every taken branch
+    taken = (op == OP_BRANCH) & (u_take < TAKEN_RATE)
+    seg_start = np.zeros(n_instr, np.int64)
+    seg_start[1:] = np.where(taken[:-1], idx[1:], 0)
+    seg_start = np.maximum.accumulate(seg_start)
+    target = CODE_BASE + ((u_tgt >> np.uint64(40)).astype(np.int64) % (CODE_SPAN // 4)) * 4
+    target[0] = CODE_BASE
+    pc = target[seg_start] + 4 * (idx - seg_start)
+    pc = CODE_BASE + (pc - CODE_BASE) % CODE_SPAN
+    # data addresses: over memory instructions only, runs of 8-byte steps
+    mem = (op == OP_LOAD) | (op == OP_STORE)
+    m_idx = np.nonzero(mem)[0]
+    addr = np.zeros(n_instr, np.int64)
+    if m_idx.size:
+        k = np.arange(m_idx.size, dtype=np.int64)
+        jump = u_jump[m_idx] < DATA_JUMP_RATE
+        jump[0] = True
+        run_start = np.maximum.accumulate(np.where(jump, k, 0))
+        fresh = HEAP_BASE + ((u_addr[m_idx] >> np.uint64(40)).astype(np.int64) % (HEAP_SPAN // 8)) * 8
+        # runs in order; a reusing run starts where the previous run started
+        starts = np.nonzero(jump)[0]
+        reuse = (u_addr[m_idx][starts] & np.uint64(1)).astype(bool)
+        reuse[0] = False
+        r = np.arange(starts.size)
+        src = np.maximum.accumulate(np.where(reuse, 0, r))
+        run_base = np.zeros(m_idx.size, np.int64)
+        run_base[starts] = fresh[starts[src]]
+        a = run_base[run_start] + 8 * (k - run_start)
+        addr[m_idx] = HEAP_BASE + (a - HEAP_BASE) % HEAP_SPAN
+    return np.stack([pc, addr], axis=1).astype(np.uint32)
+
+
 def dynamic_columns(n_feat: int) -> Tuple[int, int, int]:
     """(residence, execution, store) column of each layout; -1 = absent."""
     return (30, 31, -1) if n_feat == 32 else (47, 48, 49)
@@ -436,6 +493,9 @@ def workload(name: str) -> Workload:
         return Workload("tiny", 10_000, 32, 16, net_small())
     if name == "c3_1m":       # 1M instructions, 4,096 sub-traces, 256 warm-up, 111 x 50
         return Workload("c3_1m", 1_000_000, 50, 111, net_c3(), n_sub=4096, warmup=256)
+    if name == "c3dep_1m":    # c3_1m with the 5 memory-dependency flags in the window
+        return Workload("c3dep_1m", 1_000_000, 50, 111, net_c3(), n_sub=4096, warmup=256,
+                        extra={"dep_col": DEP_COLS})
     if name == "c3st_1m":     # c3_1m with store latencies and the memory write queue
         return Workload("c3st_1m", 1_000_000, 50, 111, net_c3_store(), n_sub=4096, warmup=256,
                         n_out=3, extra={"out_bias": OUT_BIAS_STORE, "store_col": STORE_COL})

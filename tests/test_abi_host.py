@@ -90,3 +90,18 @@ def test_product_does_not_import_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "simnet_oracle" not in text, f
+
+
+def test_validate_dependency_flag_config():
+    """col_dep: 5 columns inside the window, not over a dynamic column, and
+    the trace's addresses given."""
+    cfg, tr = good()
+    cfg.col_dep = 42
+    assert sn.sim_validate_config(cfg, tr) == sn.SIM_EINVAL  # no addresses
+    s, l, w = sn.partition(100_000, 64, 256)
+    tr2 = sn.make_trace(0x1000, 100_000, s, l, w, mem_ptr=0x2000)
+    assert sn.sim_validate_config(cfg, tr2) == sn.SIM_OK
+    cfg.col_dep = 46                                     # 46..50: past the window
+    assert sn.sim_validate_config(cfg, tr2) == sn.SIM_EINVAL
+    cfg.col_dep = 44                                     # 44..48 covers residence (47)
+    assert sn.sim_validate_config(cfg, tr2) == sn.SIM_EINVAL

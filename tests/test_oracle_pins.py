@@ -916,3 +916,64 @@ def test_mwq_window_order(oracle_lib, slot, col):
         else:
             want = 0
         assert res["logits"][i, 0] == want, (i, slot, col)
+
+
+# ------------------------------------------------ memory dependency flags ---
+
+def test_dependency_flags_hand_example(oracle_lib):
+    """Sec. 2.1's memory dependency flags, worked by hand: I2 against its
+    context I1 and I0 (same instruction line / instruction page / data
+    address / data line / data page; 64-byte lines, 4 KB pages; data flags
+    only when both access data)."""
+    mem = np.array([[0x1000, 0x2000],    # I0
+                    [0x1004, 0x2008],    # I1: I0's line; data 8 bytes on
+                    [0x1040, 0x2000],    # I2: next line, same page; I0's data address
+                    [0x3000, 0x0000]],   # I3: another page, no data access
+                   np.uint32)
+    want = {  # (instruction, slot) -> flags
+        (1, 1): [1, 1, 0, 1, 1],
+        (2, 1): [0, 1, 0, 1, 1],
+        (2, 2): [0, 1, 1, 1, 1],
+        (3, 1): [0, 0, 0, 0, 0],
+        (3, 3): [0, 0, 0, 0, 0],
+    }
+    N = 4
+    feat = np.zeros((N, 32), np.float32)
+    cfg = oracle_lib.sim_cfg(32, 16, 2, 8, (30, 31, -1), dep_col=25)
+    table = np.array([[1, 100]] * N, np.int32)   # everything stays in flight
+    for (i, slot), flags in want.items():
+        for f in range(5):
+            layers, ws, bs = probe_net(slot, 25 + f)
+            m = oracle_lib.Model(layers, ws, bs, 32, 16)
+            res = oracle_lib.simulate(cfg, feat, [0], [N], [0], model=m, mode=oracle_lib.INJECT,
+                                      lat_table=table, want_logits=True, mem=mem)
+            assert res["logits"][i, 0] == flags[f], (i, slot, f)
+    # slot 0 carries no flags
+    layers, ws, bs = probe_net(0, 27)
+    m = oracle_lib.Model(layers, ws, bs, 32, 16)
+    res = oracle_lib.simulate(cfg, feat, [0], [N], [0], model=m, mode=oracle_lib.INJECT,
+                              lat_table=table, want_logits=True, mem=mem)
+    assert np.all(res["logits"][:, 0] == 0)
+
+
+def test_dependency_flags_need_addresses(oracle_lib):
+    cfg = oracle_lib.sim_cfg(32, 16, 2, 8, (30, 31, -1), dep_col=25)
+    with pytest.raises(ValueError):
+        oracle_lib.simulate(cfg, np.zeros((4, 32), np.float32), [0], [4], [0],
+                            mode=oracle_lib.INJECT, lat_table=np.ones((4, 2), np.int32))
+
+
+def test_trace_addresses_recipe():
+    """The synthetic address stream: PCs advance by 4 and stay in the code
+    region; only loads and stores have data addresses, 8-byte aligned in the
+    heap; a fraction of consecutive PCs share a cache line."""
+    mem = synth.trace_mem(1, 20000).astype(np.int64)
+    op = synth.trace_fields(1, 0, 20000)["op"]
+    pc, da = mem[:, 0], mem[:, 1]
+    assert np.all((pc >= synth.CODE_BASE) & (pc < synth.CODE_BASE + synth.CODE_SPAN))
+    assert np.all(pc % 4 == 0)
+    is_mem = (op == synth.OP_LOAD) | (op == synth.OP_STORE)
+    assert np.all((da != 0) == is_mem)
+    assert np.all(da[is_mem] % 8 == 0)
+    step = np.diff(pc) == 4
+    assert 0.8 < step.mean() < 0.95
