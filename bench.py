@@ -121,7 +121,12 @@ def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, wa
     sim.load_weights(wl.layers, sn.flat_params(ws, bs))
     if prec == "fp8":
         sim.calibrate(64)  # per-channel scales from the first 64 FP32 steps (set-up, untimed)
+    tuning = None
     if graph:
+        # launch shape chosen on the first 300 steps (set-up, untimed)
+        tuning = sim.autotune(300)
+        log(f"[bench] autotune: variant {tuning['variant']}, {tuning['n_wg']} workgroups; "
+            f"trials {tuning['trials']}")
         sim.use_graph(True)
     stream = sim.stream
 
@@ -151,7 +156,7 @@ def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, wa
     elapsed = time.perf_counter() - t0
     k_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     sim.close()
-    return {"elapsed": elapsed, "kernel_ms": k_ms, "res": res}
+    return {"elapsed": elapsed, "kernel_ms": k_ms, "res": res, "tuning": tuning}
 
 
 def train_bench(sn, torch, wl, steps, warmup, prec):
@@ -352,6 +357,8 @@ def main():
                         for f, r in results.items()}
     if args.workload == "tiny":
         out["steps_per_s"] = round(n_pred * steps / b["elapsed"], 1)
+    if b.get("tuning"):
+        out["config"]["launch_shape"] = {k: b["tuning"][k] for k in ("variant", "n_wg")}
     if not args.no_cpu_baseline and feat is not None:
         log("[bench] timing the FP64 oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(wl, feat, start, length, warm, ws, bs, mem=mem)

@@ -187,6 +187,31 @@ SIMNET_API int sim_run(sim_ctx* ctx, int32_t lat_mode, const int32_t* lat_table,
  * logits buffer or the weights change.  The graph holds kernel nodes only. */
 SIMNET_API int sim_set_graph(sim_ctx* ctx, int32_t enable);
 
+/* Launch shape of the step kernel as chosen by sim_autotune. */
+typedef struct {
+  int32_t variant;            /* kernel variant (hidden-FC weight prefetch depth) */
+  int32_t n_wg;               /* persistent workgroups (16 sub-trace slots each) */
+  float ms;                   /* its time per million positions advanced in the trial */
+  int32_t n_tried;            /* candidates timed (at most 16 listed) */
+  int32_t tried_variant[16], tried_n_wg[16];
+  float tried_ms[16];
+} sim_tuning;
+
+/* Time n_steps steps (lat_mode/lat_table as in sim_step) from the reset
+ * state under each candidate launch shape: every kernel variant (the C3
+ * network with the predictor running) x 4/4, 3/4 and 1/2 of the slots
+ * sim_init allocated; keep the one with the least time per position
+ * advanced and reset the simulation.  The
+ * variants differ only in how far ahead weights are fetched, so results do
+ * not depend on the choice.  Synchronises.  *out receives the choice and
+ * the trials. */
+SIMNET_API int sim_autotune(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
+                            const int32_t* lat_table, sim_tuning* out);
+
+/* Apply a launch shape (a cached sim_autotune result): variant in [0, 3),
+ * n_wg in [1, slots allocated / 16].  Resets the simulation. */
+SIMNET_API int sim_set_tuning(sim_ctx* ctx, int32_t variant, int32_t n_wg);
+
 /* Return every sub-trace to its first instruction (asynchronous). */
 SIMNET_API int sim_reset(sim_ctx* ctx);
 

@@ -27,6 +27,7 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVIC
 
 EXPORTED = ("sim_validate_config", "sim_init", "sim_load_weights", "sim_step", "sim_run",
             "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
+            "sim_autotune", "sim_set_tuning",
             "predictor_fwd", "predictor_save_bytes", "sim_loss", "predictor_bwd", "sim_adam",
             "sim_destroy", "sim_last_error")
 
@@ -48,6 +49,12 @@ class sim_trace(C.Structure):
                 ("n_instr", C.c_int64), ("start", C.POINTER(C.c_int64)),
                 ("len", C.POINTER(C.c_int64)), ("warm", C.POINTER(C.c_int32)),
                 ("mem", C.c_void_p)]
+
+
+class sim_tuning(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("n_wg", C.c_int32), ("ms", C.c_float),
+                ("n_tried", C.c_int32), ("tried_variant", C.c_int32 * 16),
+                ("tried_n_wg", C.c_int32 * 16), ("tried_ms", C.c_float * 16)]
 
 
 class sim_result(C.Structure):
@@ -82,6 +89,8 @@ def lib():
         L.sim_act_scales.argtypes = [P, P, C.c_int32]
         L.sim_set_graph.argtypes = [P, C.c_int32]
         L.predictor_save_bytes.argtypes = [P, C.c_int64]
+        L.sim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, C.POINTER(sim_tuning)]
+        L.sim_set_tuning.argtypes = [P, C.c_int32, C.c_int32]
         L.sim_loss.argtypes = [P, P, P, C.c_int64, P, P]
         L.predictor_bwd.argtypes = [P, P, P, P, C.c_int64, P, P, C.c_int32]
         L.sim_adam.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float,
@@ -228,6 +237,40 @@ class Simulator:
 
     def reset(self) -> None:
         self._check("sim_reset", lib().sim_reset(self.ctx))
+
+    def autotune(self, n_steps: int = 200, lat_mode: int = SIM_LAT_PREDICT, lat_table=None,
+                 cache: Optional[str] = None) -> dict:
+        """Choose the step kernel's launch shape (sim_autotune).  With a cache
+        file (JSON), a choice recorded for the same device, window, network,
+        precision and sub-trace count is applied instead of timing again."""
+        import json
+        import torch
+        key = "|".join(str(v) for v in (torch.cuda.get_device_name(), self.cfg.n_feat,
+                                         self.cfg.n_slot, getattr(self, "n_outputs", 0),
+                                         self.cfg.prec, self.n_sub, self.trace.feat_dtype,
+                                         lat_mode))
+        table = {}
+        if cache and os.path.exists(cache):
+            with open(cache) as fh:
+                table = json.load(fh)
+        if key in table:
+            t = table[key]
+            self._check("sim_set_tuning", lib().sim_set_tuning(self.ctx, t["variant"], t["n_wg"]))
+            return dict(t, cached=True)
+        out = sim_tuning()
+        self._check("sim_autotune", lib().sim_autotune(self.ctx, n_steps, lat_mode,
+                                                       _ptr(lat_table), C.byref(out)))
+        t = {"variant": out.variant, "n_wg": out.n_wg, "ms": out.ms,
+             "trials": [(out.tried_variant[i], out.tried_n_wg[i], out.tried_ms[i])
+                        for i in range(out.n_tried)]}
+        if cache:
+            table[key] = t
+            with open(cache, "w") as fh:
+                json.dump(table, fh, indent=1)
+        return dict(t, cached=False)
+
+    def set_tuning(self, variant: int, n_wg: int) -> None:
+        self._check("sim_set_tuning", lib().sim_set_tuning(self.ctx, variant, n_wg))
 
     def calibrate(self, n_steps: int = 64, lat_mode: int = SIM_LAT_PREDICT, lat_table=None):
         self._check("sim_calibrate",

@@ -47,6 +47,8 @@ struct sim_ctx {
   bool completed = false;
   int64_t max_pos = 0, n_pred = 0, n_meas = 0;
   int32_t n_wg = 0;                 // persistent workgroups; slots = n_wg * MT
+  int32_t n_wg_max = 0;             // slots allocated at init
+  int32_t variant = 0;              // tuning variant of the step kernel
   const uint32_t* codes = nullptr;  // packed trace (SIM_FEAT_CODE32)
   const uint2* mem = nullptr;       // addresses for the dependency flags
   float* logits_out = nullptr;
@@ -741,6 +743,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   // per CU for the small one
   const int per_cu = c->net == 0 ? 4 : 1;
   c->n_wg = (int32_t)std::min<int64_t>((K + MT - 1) / MT, (int64_t)n_cu * per_cu);
+  c->n_wg_max = c->n_wg;
   const int32_t n_slots = c->n_wg * MT;
 
   // one device block: table + state + results + counters + total
@@ -889,7 +892,7 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
 int sim_reset(sim_ctx* c) {
   if (!c) return SIM_EINVAL;
   if (!c->has_trace) return SIM_OK;
-  hipError_t e = launch_reset(c->st, c->n_sub, c->C, c->n_wg * MT, c->stream);
+  hipError_t e = launch_reset(c->st, c->n_sub, c->C, c->n_wg_max * MT, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "reset");
   c->completed = false;
   c->ran_to_end = false;
@@ -1010,6 +1013,8 @@ static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
 
 static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t* table) {
   if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
+  if (c->cfg.col_dep >= 0 && c->net != 1 && mode != SIM_LAT_INJECT)
+    return fail(c, SIM_EUNSUPPORTED, "dependency flags need the C3 regression network");
   if (c->net == 2) return fail(c, SIM_EUNSUPPORTED, "the training head does not drive the simulation");
   if (mode < SIM_LAT_PREDICT || mode > SIM_LAT_SHADOW) return fail(c, SIM_EINVAL, "bad lat_mode");
   if (mode != SIM_LAT_PREDICT && !table) return fail(c, SIM_EINVAL, "lat_table required");
@@ -1021,7 +1026,7 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   if (n_steps == 0) return SIM_OK;   // checks only
   if (n_steps >= INT32_MAX) c->ran_to_end = true;
   const StepParams p = step_params(c, n_steps, mode, table);
-  hipError_t e = launch_step(c->net, c->cfg.prec, c->w, c->relu, c->st, p, c->stream);
+  hipError_t e = launch_step(c->net, c->cfg.prec, c->variant, c->w, c->relu, c->st, p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   return SIM_OK;
 }
@@ -1045,7 +1050,7 @@ int sim_run(sim_ctx* c, int32_t mode, const int32_t* table, sim_result* res) {
         c->graph_logits != c->logits_out) {
       drop_graph(c);
       hipGraph_t g = nullptr;
-      e = build_run_graph(c->net, c->cfg.prec, c->w, c->relu, c->st,
+      e = build_run_graph(c->net, c->cfg.prec, c->variant, c->w, c->relu, c->st,
                           step_params(c, INT32_MAX, mode, table), c->dev_total, &g);
       if (e == hipSuccess) e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
       if (g) (void)hipGraphDestroy(g);
@@ -1116,6 +1121,78 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
                                 B, logits, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "forward launch");
   return SIM_OK;
+}
+
+int sim_set_tuning(sim_ctx* c, int32_t variant, int32_t n_wg) {
+  if (!c) return SIM_EINVAL;
+  if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
+  if (variant < 0 || variant >= N_VARIANTS) return fail(c, SIM_EINVAL, "unknown variant");
+  if (variant != 0 && c->cfg.col_dep >= 0)
+    return fail(c, SIM_EUNSUPPORTED, "with dependency flags only variant 0 exists");
+  if (n_wg < 1 || n_wg > c->n_wg_max) return fail(c, SIM_EINVAL, "n_wg out of range");
+  drop_graph(c);
+  c->variant = variant;
+  c->n_wg = n_wg;
+  return sim_reset(c);
+}
+
+int sim_autotune(sim_ctx* c, int32_t n_steps, int32_t lat_mode, const int32_t* lat_table,
+                 sim_tuning* out) {
+  if (!c) return SIM_EINVAL;
+  if (!c->has_trace) return fail(c, SIM_ESTATE, "context has no trace");
+  if (n_steps < 1 || !out) return fail(c, SIM_EINVAL, "bad arguments");
+  // candidates: every kernel variant (C3 with the predictor running) x
+  // 4/4, 3/4 and 1/2 of the slots
+  const int nv = (c->net == 1 && lat_mode != SIM_LAT_INJECT && c->cfg.col_dep < 0) ? N_VARIANTS : 1;
+  std::vector<int32_t> shapes;
+  for (int q : {4, 3, 2}) {
+    const int32_t n = std::max<int32_t>(1, c->n_wg_max * q / 4);
+    if (std::find(shapes.begin(), shapes.end(), n) == shapes.end()) shapes.push_back(n);
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  if (e != hipSuccess) return hip_fail(c, e, "events");
+  *out = sim_tuning{};
+  float best = -1.f;
+  int rc = SIM_OK;
+  for (int v = 0; v < nv && rc == SIM_OK; ++v)
+    for (int32_t nw : shapes) {
+      if ((rc = sim_set_tuning(c, v, nw)) != SIM_OK) break;
+      // one untimed launch (first use of a kernel), then the timed one
+      if ((rc = step_launch(c, n_steps, lat_mode, lat_table)) != SIM_OK) break;
+      if ((rc = sim_reset(c)) != SIM_OK) break;
+      float ms = 0.f;
+      unsigned long long ctr[NCOUNTERS] = {0, 0, 0, 0};
+      e = hipEventRecord(e0, c->stream);
+      if (e == hipSuccess) rc = step_launch(c, n_steps, lat_mode, lat_table);
+      if (e == hipSuccess && rc == SIM_OK) e = hipEventRecord(e1, c->stream);
+      if (e == hipSuccess && rc == SIM_OK)
+        e = hipMemcpyAsync(ctr, c->st.counters, sizeof ctr, hipMemcpyDeviceToHost, c->stream);
+      if (e == hipSuccess && rc == SIM_OK) e = hipStreamSynchronize(c->stream);
+      if (e == hipSuccess && rc == SIM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+      if (e != hipSuccess) rc = hip_fail(c, e, "timing");
+      if (rc != SIM_OK) break;
+      // the objective is time per position advanced: fewer slots do less
+      // work per step
+      ms = ctr[3] ? ms * 1e6f / (float)ctr[3] : ms * 1e6f;
+      if (out->n_tried < 16) {
+        out->tried_variant[out->n_tried] = v;
+        out->tried_n_wg[out->n_tried] = nw;
+        out->tried_ms[out->n_tried] = ms;
+        ++out->n_tried;
+      }
+      if (best < 0.f || ms < best) {
+        best = ms;
+        out->variant = v;
+        out->n_wg = nw;
+        out->ms = ms;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SIM_OK) return rc;
+  return sim_set_tuning(c, out->variant, out->n_wg);
 }
 
 int64_t predictor_save_bytes(const sim_ctx* c, int64_t B) {

@@ -21,6 +21,8 @@
 // Precision forms: weights and activations in FP32, BF16 or FP8 (OCP e4m3,
 // per-channel power-of-two scales), products accumulated in FP32 in every
 // form; biases and the final logits are FP32.
+#include <type_traits>
+
 #include "simnet_internal.h"
 
 namespace simnet {
@@ -383,7 +385,7 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
     v4f bacc[1][HT];
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
-    mma_stream<P, KGS, Net::HID / 16, HT, 1, 8>(bacc, ap, bj, wave * HT, lane);
+    mma_stream<P, KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS>(bacc, ap, bj, wave * HT, lane);
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
   } else {
@@ -713,7 +715,9 @@ constexpr int n_cal() {
   return Net::D + Net::CH1 + Net::CH2 + Net::CH3 + Net::HID;
 }
 
-template <class Net, class P, bool RUN_NET, bool CAL = false>
+// DEP: the window carries the memory dependency flags (a separate
+// instantiation, so that runs without them pay no registers for them).
+template <class Net, class P, bool RUN_NET, bool CAL = false, bool DEP = false>
 __global__ void __launch_bounds__(Net::WAVES * 64)
     step_kernel(DevWeights wt, uint32_t relu_mask, DevState st, StepParams p) {
   using G = Geo<Net, P>;
@@ -797,7 +801,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     r.valid = idx >= 0;
     r.code = 0;
-    if (p.col_dep >= 0) {  // addresses of this row and of slot 0 (broadcast)
+    if constexpr (DEP) {  // addresses of this row and of slot 0 (broadcast)
       r.mem = p.mem[idx < 0 ? 0 : idx];
       r.cur_mem = p.mem[sm.active[gs] ? sm.first[gs] + sm.pos[gs] : 0];
       if (w == 0) r.valid = idx >= 0 ? 2 : 0;  // slot 0: no flags
@@ -831,8 +835,9 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       if (c == p.col_res) x = r.res;
       if (c == p.col_exe) x = r.ex;
       if (c == p.col_sto) x = r.sto;
-      if (p.col_dep >= 0 && c >= p.col_dep && c < p.col_dep + 5)
-        x = r.valid == 1 ? dep_flag(r.mem, r.cur_mem, c - p.col_dep) : 0.f;
+      if constexpr (DEP)
+        if (c >= p.col_dep && c < p.col_dep + 5)
+          x = r.valid == 1 ? dep_flag(r.mem, r.cur_mem, c - p.col_dep) : 0.f;
       if constexpr (CAL)
         if (c < D && r.valid) cal_max(cal, c, x);
       v[cc] = x;
@@ -866,8 +871,8 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
           else
             lat[o] = round_latency(sm.net.logit[s][o], p.lat_max, n_clamped, n_nonfinite);
         }
-        ++n_pred;
       }
+      ++n_pred;  // positions advanced (the work a launch did)
       if (p.lat_mode != 0) {
 #pragma unroll
         for (int o = 0; o < Net::NLAT; ++o) {
@@ -1188,6 +1193,13 @@ template <class Net, class P>
 static hipError_t launch_step_t(const DevWeights& w, uint32_t relu, const DevState& s,
                                 const StepParams& p, hipStream_t stream) {
   const dim3 grid(p.n_wg), block(Geo<Net, P>::NT);
+  if constexpr (std::is_same<Net, NetC3>::value) {
+    if (p.lat_mode != 1 && p.col_dep >= 0) {
+      hipLaunchKernelGGL((step_kernel<Net, P, true, false, true>), grid, block, 0, stream, w,
+                         relu, s, p);
+      return hipGetLastError();
+    }
+  }
   if (p.lat_mode == 1)
     hipLaunchKernelGGL((step_kernel<Net, P, false>), grid, block, 0, stream, w, relu, s, p);
   else
@@ -1203,8 +1215,12 @@ static hipError_t launch_step_n(int prec, const DevWeights& w, uint32_t relu, co
   return launch_step_t<Net, PFP8>(w, relu, s, p, stream);
 }
 
-hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, const DevState& s,
-                       const StepParams& p, hipStream_t stream) {
+hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
+                       const DevState& s, const StepParams& p, hipStream_t stream) {
+  if (net == 1 && p.lat_mode != 1 && variant == 1)
+    return launch_step_n<NetC3V1>(prec, w, relu, s, p, stream);
+  if (net == 1 && p.lat_mode != 1 && variant == 2)
+    return launch_step_n<NetC3V2>(prec, w, relu, s, p, stream);
   if (net == 4) {  // store latencies: FP32 and BF16 forms
     if (prec == 0) return launch_step_t<NetC3S, PF32>(w, relu, s, p, stream);
     if (prec == 1) return launch_step_t<NetC3S, PBF16>(w, relu, s, p, stream);
@@ -1239,6 +1255,13 @@ template <class Net>
 static hipError_t launch_cal_t(const DevWeights& w, uint32_t relu, const DevState& s,
                                const StepParams& p, hipStream_t stream) {
   const dim3 grid(p.n_wg), block(Geo<Net, PF32>::NT);
+  if constexpr (std::is_same<Net, NetC3>::value) {
+    if (p.col_dep >= 0) {
+      hipLaunchKernelGGL((step_kernel<Net, PF32, true, true, true>), grid, block, 0, stream, w,
+                         relu, s, p);
+      return hipGetLastError();
+    }
+  }
   hipLaunchKernelGGL((step_kernel<Net, PF32, true, true>), grid, block, 0, stream, w, relu, s, p);
   return hipGetLastError();
 }
@@ -1285,18 +1308,28 @@ hipError_t launch_total(const DevState& s, int32_t n_sub, int64_t* total, hipStr
 // The run as a graph of kernel nodes (no memset nodes): the persistent step
 // kernel until every slot is empty, then the total.
 template <class Net, class P>
-static void* step_fn(bool run_net) {
+static void* step_fn(bool run_net, bool dep = false) {
+  if constexpr (std::is_same<Net, NetC3>::value)
+    if (run_net && dep) return reinterpret_cast<void*>(&step_kernel<Net, P, true, false, true>);
   return run_net ? reinterpret_cast<void*>(&step_kernel<Net, P, true>)
                  : reinterpret_cast<void*>(&step_kernel<Net, P, false>);
 }
 
-hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu,
+hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
                            const DevState& s, const StepParams& p, int64_t* total,
                            hipGraph_t* out) {
   const bool run_net = p.lat_mode != 1;
   void* fn;
   int nt;
-  if (net == 0) {
+  if (net == 1 && run_net && variant == 1) {
+    fn = prec == 0 ? step_fn<NetC3V1, PF32>(run_net)
+         : prec == 1 ? step_fn<NetC3V1, PBF16>(run_net) : step_fn<NetC3V1, PFP8>(run_net);
+    nt = Geo<NetC3V1, PF32>::NT;
+  } else if (net == 1 && run_net && variant == 2) {
+    fn = prec == 0 ? step_fn<NetC3V2, PF32>(run_net)
+         : prec == 1 ? step_fn<NetC3V2, PBF16>(run_net) : step_fn<NetC3V2, PFP8>(run_net);
+    nt = Geo<NetC3V2, PF32>::NT;
+  } else if (net == 0) {
     fn = prec == 0 ? step_fn<NetSmall, PF32>(run_net)
          : prec == 1 ? step_fn<NetSmall, PBF16>(run_net) : step_fn<NetSmall, PFP8>(run_net);
     nt = Geo<NetSmall, PF32>::NT;
@@ -1309,8 +1342,9 @@ hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu
     fn = prec == 0 ? step_fn<NetC3S, PF32>(run_net) : step_fn<NetC3S, PBF16>(run_net);
     nt = Geo<NetC3S, PF32>::NT;
   } else {
-    fn = prec == 0 ? step_fn<NetC3, PF32>(run_net)
-         : prec == 1 ? step_fn<NetC3, PBF16>(run_net) : step_fn<NetC3, PFP8>(run_net);
+    const bool dep = p.col_dep >= 0;
+    fn = prec == 0 ? step_fn<NetC3, PF32>(run_net, dep)
+         : prec == 1 ? step_fn<NetC3, PBF16>(run_net, dep) : step_fn<NetC3, PFP8>(run_net, dep);
     nt = Geo<NetC3, PF32>::NT;
   }
   hipGraph_t g = nullptr;

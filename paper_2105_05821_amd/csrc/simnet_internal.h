@@ -8,7 +8,7 @@ namespace simnet {
 
 constexpr int MT = 16;       // sub-traces (windows) per workgroup tile: one MFMA row block
 constexpr int WMAX = 16;     // largest supported retire width
-constexpr int NCOUNTERS = 4; // clamped, non-finite, shadow mismatches, predictions
+constexpr int NCOUNTERS = 4; // clamped, non-finite, shadow mismatches, positions advanced
 
 // Compile-time shape of a supported predictor.  A kernel-2 stride-2 stack is
 // a tree: output position p of conv level l depends on input slots
@@ -22,6 +22,7 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr int HID = 0, NOUT = 2;
   static constexpr int NLAT = 2, HEAD = 0;   // latencies per instruction; regression head
   static constexpr bool MWQ = false;         // store latency and memory write queue
+  static constexpr int FC1_FRAGS = 8;
   static constexpr int WAVES = 4;
   static constexpr int CHL = CH2;            // channels of the last conv
 };
@@ -32,6 +33,7 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
   static constexpr int HID = 512, NOUT = 2;
   static constexpr int NLAT = 2, HEAD = 0;
   static constexpr bool MWQ = false;
+  static constexpr int FC1_FRAGS = 8;        // hidden-FC weight fragments per prefetch chunk
   static constexpr int WAVES = 8;
   static constexpr int CHL = CH3;
 };
@@ -41,6 +43,12 @@ constexpr int HYB_CLASSES = 10, HYB_PER_TYPE = HYB_CLASSES + 1;
 struct NetC3Hyb : NetC3 {  // C3 trunk -> FC 512 -> 2 x 11
   static constexpr int NOUT = 2 * HYB_PER_TYPE, HEAD = 1;
 };
+// Tuning variants of the C3 step kernel (chosen by sim_autotune): a deeper
+// or a shallower hidden-FC weight prefetch.  The products and their
+// summation order are the same in every variant, so results are identical.
+struct NetC3V1 : NetC3 { static constexpr int FC1_FRAGS = 16; };
+struct NetC3V2 : NetC3 { static constexpr int FC1_FRAGS = 4; };
+constexpr int N_VARIANTS = 3;
 // Store latency (Sec. 3.2): three outputs (fetch, execution, store) and the
 // memory write queue that stores enter on leaving the processor queue.
 struct NetC3S : NetC3 {  // C3 trunk -> FC 512 -> 3
@@ -151,7 +159,10 @@ struct StepParams {
 
 // Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3; prec: 0 FP32,
 // 1 BF16, 2 FP8 (e4m3).  relu: bit l = ReLU after layer l.
-hipError_t launch_step(int net, int prec, const DevWeights& w, uint32_t relu, const DevState& s,
+// variant (0 .. N_VARIANTS-1) selects a tuning variant of the C3 network
+// (net 1) when the predictor runs; other networks ignore it.
+hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
+                       const DevState& s,
                        const StepParams& p, hipStream_t stream);
 hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
                           int64_t B, float* logits, hipStream_t stream);
@@ -213,7 +224,7 @@ hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, 
                        float b2, float eps, int32_t t, hipStream_t stream);
 
 // Graph of the run: step kernel until every slot is empty, then the total.
-hipError_t build_run_graph(int net, int prec, const DevWeights& w, uint32_t relu,
+hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
                            const DevState& s, const StepParams& p, int64_t* total,
                            hipGraph_t* out);
 

@@ -173,3 +173,30 @@ def test_graph_replay_equals_direct_run(torch, sn):
     sim.reset()
     d = sim.run(sn.SIM_LAT_INJECT, table)
     assert_same(c, d)
+
+
+def test_autotune_choice_does_not_change_results(torch, sn, tmp_path):
+    """sim_autotune tries every kernel variant and slot count; the chosen
+    shape, any other shape and the cached choice all give the same cycles."""
+    layers = synth.net_c3()
+    ws, bs = synth.init_weights(2, layers)
+    start, length, warm, N = independent_streams(600, 20, 900)
+    codes = synth.trace_codes(1, N)
+    sim = sn.Simulator(torch.from_numpy(codes.view(np.int32)).cuda(), 111,
+                       synth.dynamic_columns(50), start, length, warm, prec=sn.SIM_BF16, n_feat=50)
+    sim.load_weights(layers, sn.flat_params(ws, bs))
+    ref = sim.run()
+    cache = str(tmp_path / "tune.json")
+    t = sim.autotune(50, cache=cache)
+    assert not t["cached"] and len(t["trials"]) >= 3
+    assert (t["variant"], t["n_wg"]) in [(v, n) for v, n, _ in t["trials"]]
+    assert_same(sim.run(), ref)
+    for v, n, _ in t["trials"]:
+        sim.set_tuning(v, n)
+        assert_same(sim.run(), ref)
+    t2 = sim.autotune(50, cache=cache)
+    assert t2["cached"] and (t2["variant"], t2["n_wg"]) == (t["variant"], t["n_wg"])
+    assert_same(sim.run(), ref)
+    with pytest.raises(sn.SimError):
+        sim.set_tuning(3, 1)
+    sim.close()
