@@ -47,7 +47,13 @@
 #include <string.h>
 #include <unistd.h>
 
-enum { OL_CONV = 0, OL_FC = 1 };
+/* Layer kinds: kernel-2 stride-2 convolution, fully connected, and the two
+ * halves of a residual block (Sec. 2.3 names residual blocks as the
+ * alternative to plain convolution layers; RB7 stacks seven): a pointwise
+ * (kernel 1) convolution, and a pointwise convolution whose output has the
+ * input of the preceding pointwise layer added before its activation. */
+enum { OL_CONV = 0, OL_FC = 1, OL_PW = 2, OL_PWRES = 3 };
+enum { OL_MAXL = 32 };
 enum { OL_PREDICT = 0, OL_INJECT = 1 };
 
 /* cfg[] layout shared with the Python wrapper */
@@ -65,12 +71,12 @@ enum { HYB_CLASSES = 10, HYB_PER_TYPE = HYB_CLASSES + 1 };
 
 typedef struct {
   int n_layers;
-  int32_t desc[16][4];      /* kind, c_in, c_out, relu */
-  double* w[16];
-  double* b[16];
+  int32_t desc[OL_MAXL][4]; /* kind, c_in, c_out, relu */
+  double* w[OL_MAXL];
+  double* b[OL_MAXL];
   int n_feat, n_slot, n_out, max_width;
   int prec;                 /* 0: plain FP64; 1: BF16 form; 2: FP8 form */
-  double* in_scale[17];     /* FP8 form: scale of each input channel of layer l */
+  double* in_scale[OL_MAXL + 1];     /* FP8 form: scale of each input channel of layer l */
 } ol_model;
 
 /* Nearest bfloat16 value (8 significant bits, ties to even), from the
@@ -135,7 +141,7 @@ static double qform(const ol_model* m, double v) { return m->prec == 1 ? round_b
  * last layer's output is not rounded. */
 void* ol_model_new_prec(int n_layers, const int32_t* desc, const float* params,
                         int n_feat, int n_slot, int prec) {
-  if (n_layers < 1 || n_layers > 16 || prec < 0 || prec > 1) return NULL;
+  if (n_layers < 1 || n_layers > OL_MAXL || prec < 0 || prec > 1) return NULL;
   ol_model* m = (ol_model*)calloc(1, sizeof(ol_model));
   m->prec = prec;
   m->n_layers = n_layers;
@@ -151,6 +157,17 @@ void* ol_model_new_prec(int n_layers, const int32_t* desc, const float* params,
       if (ci != ch || len < 2) { free(m); return NULL; }
       nw = (size_t)co * ci * 2;
       len = len / 2;
+    } else if (kind == OL_PW || kind == OL_PWRES) {
+      /* the residual half adds the preceding pointwise layer's input, so
+       * it must follow one and give back that layer's input channels */
+      const int ok = ci == ch && (kind == OL_PW || (l > 0 && desc[4 * (l - 1)] == OL_PW &&
+                                                    co == desc[4 * (l - 1) + 1]));
+      if (!ok) {
+        for (int j = 0; j < l; ++j) { free(m->w[j]); free(m->b[j]); }
+        free(m);
+        return NULL;
+      }
+      nw = (size_t)co * ci;
     } else {
       if (ci != ch * len) { free(m); return NULL; }
       nw = (size_t)co * ci;
@@ -171,7 +188,8 @@ void* ol_model_new_prec(int n_layers, const int32_t* desc, const float* params,
     return NULL;
   }
   m->n_out = ch;
-  m->max_width = width;
+  /* scratch: the layer output, then the residual block's saved input */
+  m->max_width = 2 * width;
   return m;
 }
 
@@ -188,6 +206,8 @@ void* ol_model_new(int n_layers, const int32_t* desc, const float* params,
  * e4m3(W s_c / w_n) * w_n / s_c.  Biases as given, sums exact. */
 void* ol_model_new_fp8(int n_layers, const int32_t* desc, const float* params,
                        int n_feat, int n_slot, const float* scales) {
+  for (int l = 0; l < n_layers; ++l)
+    if (desc[4 * l] != OL_CONV && desc[4 * l] != OL_FC) return NULL; /* no FP8 residual form */
   ol_model* m = (ol_model*)ol_model_new_prec(n_layers, desc, params, n_feat, n_slot, 0);
   if (!m) return NULL;
   m->prec = 2;
@@ -246,10 +266,10 @@ static void forward_one(const ol_model* m, const double* x, double* out,
 /* Number of leading positions of conv level li's output that some final
  * output depends on (the rest are the unpaired tails dropped later). */
 static int live_len(const ol_model* m, int li, int len_out) {
-  int n = len_out;
-  for (int l = li + 1; l < m->n_layers && m->desc[l][0] == OL_CONV; ++l) n /= 2;
-  for (int l = li + 1; l < m->n_layers && m->desc[l][0] == OL_CONV; ++l) n *= 2;
-  return n;
+  int halvings = 0; /* pointwise layers keep the length */
+  for (int l = li + 1; l < m->n_layers && m->desc[l][0] != OL_FC; ++l)
+    if (m->desc[l][0] == OL_CONV) ++halvings;
+  return (len_out >> halvings) << halvings;
 }
 
 /* forward_one, optionally recording into amax the largest |input| of every
@@ -284,6 +304,19 @@ static void forward_cal(const ol_model* m, const double* x, double* out, double*
           t[o * lout + p] = (d[3] && s < 0.0) ? 0.0 : s;
         }
       len = lout;
+    } else if (d[0] == OL_PW || d[0] == OL_PWRES) {
+      /* kernel-1 convolution at every position; the residual half adds the
+       * block input saved by the preceding pointwise layer (as stored, i.e.
+       * rounded to the form), then the activation */
+      double* skip = t + m->max_width / 2;
+      if (d[0] == OL_PW) memcpy(skip, a, sizeof(double) * (size_t)ch * len);
+      for (int o = 0; o < co; ++o)
+        for (int p = 0; p < len; ++p) {
+          double s = b[o];
+          for (int ci = 0; ci < ch; ++ci) s += w[(size_t)o * ch + ci] * a[ci * len + p];
+          if (d[0] == OL_PWRES) s += skip[o * len + p];
+          t[o * len + p] = (d[3] && s < 0.0) ? 0.0 : s;
+        }
     } else {
       int n_in = ch * len; /* flatten: index c*len + p, already the layout of a */
       const int is_last = (li == m->n_layers - 1);
@@ -302,7 +335,7 @@ static void forward_cal(const ol_model* m, const double* x, double* out, double*
     ch = co;
     const int last = (li == m->n_layers - 1);
     if (amax && !last) {
-      const int live = d[0] == OL_CONV ? live_len(m, li, len) : len;
+      const int live = d[0] != OL_FC ? live_len(m, li, len) : len;
       for (int c = 0; c < ch; ++c)
         for (int p = 0; p < live; ++p)
           if (fabs(t[c * len + p]) > amax[c]) amax[c] = fabs(t[c * len + p]);
@@ -728,18 +761,18 @@ static void* train_worker(void* arg) {
   J->next += (int64_t)1 << 40;
   pthread_mutex_unlock(&J->mu);
   double* dp = J->dparams + (size_t)tid * J->n_params;
-  size_t woff[16], boff[16], tot;
+  size_t woff[OL_MAXL], boff[OL_MAXL], tot;
   param_offsets(m, woff, boff, &tot);
   /* activations: a[0] = input (channel-major), a[l+1] = output of layer l */
-  int ch[17], len[17];
+  int ch[OL_MAXL + 1], len[OL_MAXL + 1];
   ch[0] = D;
   len[0] = L;
   for (int l = 0; l < NL; ++l) {
     ch[l + 1] = m->desc[l][2];
     len[l + 1] = m->desc[l][0] == OL_CONV ? len[l] / 2 : 1;
   }
-  double* a[17];
-  double* g[17];
+  double* a[OL_MAXL + 1];
+  double* g[OL_MAXL + 1];
   for (int l = 0; l <= NL; ++l) {
     a[l] = (double*)calloc((size_t)ch[l] * len[l], sizeof(double));
     g[l] = (double*)calloc((size_t)ch[l] * len[l], sizeof(double));
@@ -833,7 +866,9 @@ int ol_train(const void* p, int64_t B, const double* x, const int32_t* lat, int3
              double* loss, double* dparams, double* dlogits, double* dx, int32_t n_threads) {
   const ol_model* m = (const ol_model*)p;
   if (!m || m->prec > 1 || m->n_out != 2 * (n_bins + 1) || B < 1) return -1;
-  size_t woff[16], boff[16], tot;
+  for (int l = 0; l < m->n_layers; ++l)
+    if (m->desc[l][0] != OL_CONV && m->desc[l][0] != OL_FC) return -1; /* convs and FCs only */
+  size_t woff[OL_MAXL], boff[OL_MAXL], tot;
   param_offsets(m, woff, boff, &tot);
   if (n_threads <= 0) n_threads = 1;
   if (n_threads > B) n_threads = (int32_t)B;

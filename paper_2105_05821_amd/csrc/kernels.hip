@@ -251,13 +251,23 @@ __device__ __forceinline__ void store_run(T* dst, const T (&e)[N]) {
   }
 }
 
+// Waves along N for a conv level: two N tiles per wave where there are
+// enough (each A fragment read from LDS then serves two MFMAs, each B
+// fragment from L2 serves the wave's M tiles), and never more waves along M
+// than there are M tiles.
+constexpr int conv_wave_split(int ntiles, int mtiles, int waves) {
+  int wn = ntiles / 2 < 1 ? 1 : ntiles / 2 < waves ? ntiles / 2 : waves;
+  while (waves / wn > mtiles || waves % wn) wn *= 2;
+  return wn;
+}
+
 // One conv level as a GEMM: rows (s, q) = MT windows x POS output positions,
 // A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
 // 2q+1 at A + s*SA + q*IRS; output row (s, q) goes to O + s*SO + q*N, or,
 // OPAIR, to O + s*SO + (q/2)*(2N + 16 bytes) + (q%2)*N (the padded pair
 // layout the next conv reads).  The
-// waves split the N tiles first (each weight fragment is read by as few
-// waves as possible), then the M tiles; a wave runs MPW x NPW tiles.
+// waves split the N tiles (conv_wave_split), then the M tiles; a wave runs
+// MPW x NPW tiles.
 // SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
 // s < sv_rows only), the layer's activations kept for the backward pass.
 template <class P, int K, int N, int POS, int WAVES, int SA, int IRS, int SO, bool OPAIR,
@@ -275,7 +285,7 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
   using T = typename P::T;
   constexpr int ROWS = MT * POS;
   constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
-  constexpr int WN = NTILES < WAVES ? NTILES : WAVES, WM = WAVES / WN;
+  constexpr int WN = conv_wave_split(NTILES, MTILES, WAVES), WM = WAVES / WN;
   constexpr int MPW = MTILES / WM, NPW = NTILES / WN;
   static_assert(ROWS % 16 == 0 && N % 16 == 0 && K % P::KG == 0, "tile shape");
   static_assert(WAVES % WN == 0 && MTILES % WM == 0 && NTILES % WN == 0 && MPW >= 1,

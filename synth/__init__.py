@@ -248,21 +248,24 @@ def dynamic_columns(n_feat: int) -> Tuple[int, int, int]:
 
 @dataclass(frozen=True)
 class Layer:
-    kind: int      # 0 = conv (kernel 2, stride 2), 1 = fully connected
-    c_in: int
-    c_out: int
+    kind: int      # 0 = conv (kernel 2, stride 2), 1 = fully connected,
+    c_in: int      # 2 = pointwise conv (kernel 1), 3 = pointwise conv plus the
+    c_out: int     #     input of the preceding pointwise layer (residual)
     relu: int
 
 
-CONV, FC = 0, 1
+CONV, FC, PW, PWRES = 0, 1, 2, 3
 
 
 def layer_param_shapes(layers: Sequence[Layer]) -> List[Tuple[Tuple[int, ...], Tuple[int]]]:
-    """PyTorch parameter shapes: conv weight [co][ci][2], fc weight [out][in]."""
+    """PyTorch parameter shapes: conv weight [co][ci][2], pointwise conv
+    weight [co][ci][1], fc weight [out][in]."""
     out = []
     for ly in layers:
         if ly.kind == CONV:
             out.append(((ly.c_out, ly.c_in, 2), (ly.c_out,)))
+        elif ly.kind in (PW, PWRES):
+            out.append(((ly.c_out, ly.c_in, 1), (ly.c_out,)))
         else:
             out.append(((ly.c_out, ly.c_in), (ly.c_out,)))
     return out
@@ -271,6 +274,7 @@ def layer_param_shapes(layers: Sequence[Layer]) -> List[Tuple[Tuple[int, ...], T
 WEIGHT_STREAM = 101
 OUT_GAIN = 8.0
 OUT_BIAS = (-6.0, 8.0)
+RES_GAIN = 0.25  # residual branches start small, so seven blocks keep the scale
 
 
 def init_weights(seed: int, layers: Sequence[Layer], out_bias: Optional[Sequence[float]] = OUT_BIAS,
@@ -279,7 +283,9 @@ def init_weights(seed: int, layers: Sequence[Layer], out_bias: Optional[Sequence
 
     Hidden layers: weights U(+-sqrt(6/fan_in)) (He et al. 2015 uniform, which
     keeps activation scale through ReLU), biases U(+-1/sqrt(fan_in)).
-    Output layer: weights U(+-out_gain/sqrt(fan_in)) and bias ``out_bias``
+    The second half of a residual block (PWRES) scales its weight bound
+    by RES_GAIN.  Output layer: weights U(+-out_gain/sqrt(fan_in)) and bias
+    ``out_bias``
     (fetch, execution), chosen so that rounded latencies are spread out
     (fetch mostly 0-3, execution ~4-40 cycles) instead of all rounding to the
     bias.  Returns lists of float32 arrays in PyTorch layouts."""
@@ -287,7 +293,8 @@ def init_weights(seed: int, layers: Sequence[Layer], out_bias: Optional[Sequence
     last = len(layers) - 1
     for li, (ly, (wshape, bshape)) in enumerate(zip(layers, layer_param_shapes(layers))):
         fan_in = ly.c_in * (2 if ly.kind == CONV else 1)
-        wbound = (out_gain if li == last else math.sqrt(6.0)) / math.sqrt(fan_in)
+        gain = out_gain if li == last else math.sqrt(6.0) * (RES_GAIN if ly.kind == PWRES else 1.0)
+        wbound = gain / math.sqrt(fan_in)
         bbound = 1.0 / math.sqrt(fan_in)
         nw = int(np.prod(wshape))
         w = (2.0 * uniform(seed, WEIGHT_STREAM + 2 * li, np.arange(nw)) - 1.0) * wbound
@@ -471,6 +478,21 @@ def net_c3_hybrid_infer() -> List[Layer]:
 # latencies 0 and 1, execution to the "larger" class whose regression output
 # sits near 12 cycles.
 HYB_BIAS = tuple([2.0, 1.0] + [0.0] * 8 + [2.0]) + tuple([0.0] * 9 + [2.0] + [12.0])
+
+
+RB7_BLOCKS, RB7_EXPAND = 7, 1920
+
+
+def net_rb7() -> List[Layer]:
+    """RB7 with the hybrid head: the C3 convolutions (50 -> 64 -> 128 -> 256
+    over 111 -> 55 -> 27 -> 13 positions), seven residual blocks at the 13
+    positions (pointwise 256 -> 1920 with ReLU, pointwise 1920 -> 256, plus
+    the block input, ReLU), FC 3328 -> 512 -> 2 x 11.  92,818,176
+    multiply-adds per prediction."""
+    blocks = []
+    for _ in range(RB7_BLOCKS):
+        blocks += [Layer(PW, 256, RB7_EXPAND, 1), Layer(PWRES, RB7_EXPAND, 256, 1)]
+    return net_c3()[:3] + blocks + net_c3_hybrid_infer()[3:]
 
 
 def net_c3_store() -> List[Layer]:
