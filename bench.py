@@ -47,7 +47,8 @@ METRIC = "simulated MIPS on 1 MI355X, FP32 vs BF16/FP8 at ≤1% total-cycle erro
 # FLOP per prediction from the layer lists (multiply-adds x 2); the kernels
 # skip window slots and conv positions no output depends on, so they execute
 # slightly fewer (6,631,424 for the C3 network).
-FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560, "c3hyb": 6_723_072, "c3st": 6_703_616}
+FLOP_PER_PRED = {"c3": 6_702_592, "small": 66_560, "c3hyb": 6_723_072, "c3st": 6_703_616,
+                 "rb7": 185_636_352}
 # Training step per context: forward 3,760,896 MAC (trunk + FC 512 -> 802),
 # backward twice that less conv1's input gradient (352,000 MAC), x 2 FLOP.
 FLOP_PER_TRAIN_CTX = 21_861_376
@@ -206,6 +207,9 @@ WORKLOAD_TEXT = {
                 "random-init weights",
     "c3_uneven": "c3_uneven: 20,000 streams, log-uniform lengths 1e3..2e5, packed codes, "
                  "111x50 windows, C3 network, slots refilled longest-first",
+    "rb7_1m": "rb7_1m: the c3_1m trace and partition with RB7 (conv 64/128/256 k2s2, seven "
+              "residual blocks 256 -> 1920 -> 256 at 13 positions, FC 512, hybrid head FC "
+              "512 -> 22), random-init weights",
     "c3_train": "c3_train: training step on 4,096 labelled 111x50 contexts (analytic "
                 "latencies 0..400), conv 64/128/256 k2s2 + FC 512 + FC 802 hybrid head, "
                 "400-bin CE + L1 log1p loss, Adam, FP32 master weights",
@@ -278,7 +282,8 @@ def main():
         return
     ws, bs = synth.init_weights(wl.weight_seed, wl.layers,
                                 out_bias=wl.extra.get("out_bias", synth.OUT_BIAS))
-    net = {"tiny": "small", "c3hyb_1m": "c3hyb", "c3st_1m": "c3st"}.get(args.workload, "c3")
+    net = {"tiny": "small", "c3hyb_1m": "c3hyb", "c3st_1m": "c3st",
+           "rb7_1m": "rb7"}.get(args.workload, "c3")
     n_feat = None
     feat = None
     mem = dmem = None
@@ -310,7 +315,7 @@ def main():
             dmem = torch.from_numpy(mem.view(np.int32)).cuda()
         if args.workload == "tiny":
             forms = [args.prec or "f32"]
-        elif args.workload in ("c3hyb_1m", "c3st_1m", "c3dep_1m"):
+        elif args.workload in ("c3hyb_1m", "c3st_1m", "c3dep_1m", "rb7_1m"):
             forms = [args.prec] if args.prec else ["f32", "bf16"]
         else:
             forms = [args.prec] if args.prec else ["f32", "bf16", "fp8"]
@@ -344,7 +349,10 @@ def main():
         "roofline": {"bound": "mfma", "achieved": round(b["tflops"], 3), "peak": PEAK[best],
                      "unit": "TFLOP/s", "frac": round(b["tflops"] / PEAK[best], 4),
                      "traffic": measured_traffic(args.workload, best),
-                     "kernel": "step_kernel (persistent: gather + CNN + round + queue update)",
+                     "kernel": ("RB7 step: gather + convolutions, residual blocks, FC 512 + "
+                                "head, update (four launches per step, all timed)"
+                                if net == "rb7" else
+                                "step_kernel (persistent: gather + CNN + round + queue update)"),
                      "kernel_ms": round(b["kernel_ms"], 3)},
     }
     if len(results) > 1:

@@ -40,7 +40,7 @@ struct sim_ctx {
   int64_t n_instr = 0;
   const float* feat = nullptr;
   int net = -1;  // 0 NetSmall, 1 NetC3, 2 C3 training head, 3 C3 hybrid inference head,
-                 // 4 C3 with store latencies (memory write queue)
+                 // 4 C3 with store latencies (memory write queue), 5 RB7 (staged step)
   int C = 0;
   uint32_t relu = 0;
   bool weights = false;
@@ -69,6 +69,13 @@ struct sim_ctx {
   bool has_trace = true;
   TrainState tr;
   int64_t* dev_total = nullptr;
+  // RB7: per slot the last conv's output [NB][CH3], activity, raw outputs;
+  // predictor_fwd's workspace for B windows
+  void* rb_trunk = nullptr;
+  int32_t* rb_active = nullptr;
+  float* rb_logits = nullptr;
+  void* rb_ws = nullptr;
+  int64_t rb_ws_B = 0;
   DevState st{};
   DevWeights w{};
   std::string err;
@@ -227,6 +234,10 @@ std::vector<Expect> expected_layers() {
   v.push_back({0, Net::D, Net::CH1});
   v.push_back({0, Net::CH1, Net::CH2});
   if (Net::NCONV == 3) v.push_back({0, Net::CH2, Net::CH3});
+  for (int i = 0; i < Net::NRES; ++i) {  // residual blocks: expansion, projection
+    v.push_back({2, Net::CH3, Net::EXPAND});
+    v.push_back({3, Net::EXPAND, Net::CH3});
+  }
   if (Net::HID > 0) {
     v.push_back({1, Net::CHL * Net::NB, Net::HID});
     v.push_back({1, Net::HID, Net::NOUT});
@@ -239,7 +250,7 @@ std::vector<Expect> expected_layers() {
 // Offsets (bytes) of every array inside the packed weight block.
 struct Layout {
   size_t conv_w[3], conv_b[3], conv_ws[3], conv_ai[3], x_inv, hid_w, hid_b, hid_ws, hid_ai,
-      last_w, last_b, last_p;
+      last_w, last_b, last_p, res_w, res_stride, res_b;
 };
 
 // Re-lay-out PyTorch-order FP32 parameters for one network and precision.
@@ -319,7 +330,27 @@ std::vector<uint8_t> relayout(int prec, const float* params,
       for (int c = 0; c < Net::D; ++c) xi[c] = 1.f / (*in_scale)[0][c];
     L->x_inv = put_floats(xi);
   }
-  const int li = Net::NCONV;
+  if (Net::NRES > 0) {
+    // residual blocks (no FP8 form): per block the expansion B[c][e] =
+    // E[e][c] (PyTorch [EXPAND][CH3][1]) then the projection B[e][c] =
+    // P[c][e] ([CH3][EXPAND][1]), packed like a conv level
+    const int C3 = Net::CH3, E = Net::EXPAND;
+    const size_t half = (size_t)C3 * E * es;
+    L->res_stride = (2 * half + 255) / 256 * 256;
+    L->res_w = reserve(L->res_stride * Net::NRES);
+    std::vector<float> rb;
+    for (int i = 0; i < Net::NRES; ++i) {
+      const float* We = w[Net::NCONV + 2 * i];
+      const float* Wp = w[Net::NCONV + 2 * i + 1];
+      uint8_t* dst = out.data() + L->res_w + L->res_stride * i;
+      pack_b(prec, C3, E, [&](int k, int n) { return We[(size_t)n * C3 + k]; }, dst);
+      pack_b(prec, E, C3, [&](int k, int n) { return Wp[(size_t)n * E + k]; }, dst + half);
+      rb.insert(rb.end(), b[Net::NCONV + 2 * i], b[Net::NCONV + 2 * i] + E);
+      rb.insert(rb.end(), b[Net::NCONV + 2 * i + 1], b[Net::NCONV + 2 * i + 1] + C3);
+    }
+    L->res_b = put_floats(rb);
+  }
+  const int li = Net::NCONV + 2 * Net::NRES;
   if (Net::HID > 0) {
     const int K = Net::CHL, N = Net::HID, NB = Net::NB;
     const float* W1 = w[li];
@@ -415,6 +446,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
   Layout lay{};
   std::vector<uint8_t> packed = c->net == 0   ? relayout<NetSmall>(prec, params, scales, &lay)
                                 : c->net == 3 ? relayout<NetC3Hyb>(prec, params, scales, &lay)
+                                : c->net == 5 ? relayout<NetRB7>(prec, params, scales, &lay)
                                 : c->net == 4 ? relayout<NetC3S>(prec, params, scales, &lay)
                                               : relayout<NetC3>(prec, params, scales, &lay);
   void* dw = nullptr;
@@ -442,7 +474,7 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
     w->conv_ai[l] = F(lay.conv_ai[l]);
   }
   w->x_inv = F(lay.x_inv);
-  if (c->net == 1 || c->net == 3 || c->net == 4) {
+  if (c->net == 1 || c->net == 3 || c->net == 4 || c->net == 5) {
     w->hid_w = base + lay.hid_w;
     w->hid_b = F(lay.hid_b);
     w->hid_ws = F(lay.hid_ws);
@@ -450,7 +482,12 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
   }
   w->last_w = F(lay.last_w);
   w->last_b = F(lay.last_b);
-  w->last_p = c->net == 3 ? base + lay.last_p : nullptr;
+  w->last_p = c->net == 3 || c->net == 5 ? base + lay.last_p : nullptr;
+  if (c->net == 5) {
+    w->res_w = base + lay.res_w;
+    w->res_stride = (int64_t)lay.res_stride;
+    w->res_b = F(lay.res_b);
+  }
   return SIM_OK;
 }
 
@@ -844,7 +881,13 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
     if (c->cfg.prec == SIM_FP8E4M3)
       return fail(c, SIM_EUNSUPPORTED, "no FP8 form with store latencies");
   }
-  if (c->net == 2 || c->net == 3) c->net = 1;
+  if (c->net == 2 || c->net == 3 || c->net == 5) c->net = 1;
+  if (c->net == 1 && layers_match<NetRB7>(layers, n_layers)) {
+    if (c->cfg.prec == SIM_FP8E4M3) return fail(c, SIM_EUNSUPPORTED, "no FP8 form of RB7");
+    if (c->cfg.col_dep >= 0)
+      return fail(c, SIM_EUNSUPPORTED, "dependency flags need the C3 regression network");
+    c->net = 5;
+  }
   if (c->net == 1 && layers_match<NetC3Hyb>(layers, n_layers)) {
     if (c->cfg.prec == SIM_FP8E4M3)
       return fail(c, SIM_EUNSUPPORTED, "no FP8 form of the hybrid head");
@@ -858,6 +901,7 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
     return fail(c, SIM_EUNSUPPORTED, "the output layer must not have ReLU");
   const size_t np = c->net == 0   ? param_count<NetSmall>()
                     : c->net == 3 ? param_count<NetC3Hyb>()
+                    : c->net == 5 ? param_count<NetRB7>()
                     : c->net == 4 ? param_count<NetC3S>()
                                   : param_count<NetC3>();
   std::vector<float> host(np);
@@ -885,6 +929,14 @@ int sim_load_weights(sim_ctx* c, const sim_layer* layers, int32_t n_layers, cons
   }
   int rc = upload_weights(c, c->cfg.prec, host.data(), nullptr, &c->dev_weights, &c->w);
   if (rc != SIM_OK) return rc;
+  if (c->net == 5 && c->has_trace && !c->rb_trunk) {
+    const int64_t slots = (int64_t)c->n_wg_max * MT;
+    const size_t es = elem_size(c->cfg.prec);
+    hipError_t e = hipMalloc(&c->rb_trunk, (size_t)slots * NetRB7::NB * NetRB7::CH3 * es);
+    if (e == hipSuccess) e = hipMalloc(&c->rb_active, sizeof(int32_t) * slots);
+    if (e == hipSuccess) e = hipMalloc(&c->rb_logits, sizeof(float) * slots * NetRB7::NOUT);
+    if (e != hipSuccess) return hip_fail(c, e, "hipMalloc RB7 step buffers");
+  }
   c->weights = true;
   return sim_reset(c);
 }
@@ -1008,7 +1060,52 @@ static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
   p.logits_out = c->logits_out;
   p.n_steps = (int32_t)std::min<int64_t>(n_steps, INT32_MAX);
   p.cal_out = nullptr;
+  p.trunk_out = c->rb_trunk;
+  p.active_out = c->rb_active;
+  p.ext_logits = c->rb_logits;
   return p;
+}
+
+// RB7: one step = gather and convolutions (stage 1), the residual blocks
+// over every slot's 13 positions, FC 512 and the head, then the update
+// (stage 2).  Slots with nothing left to simulate are skipped by every part.
+static hipError_t rb_step(sim_ctx* c, int32_t mode, const int32_t* table) {
+  StepParams p = step_params(c, 1, mode, table);
+  const int64_t slots = (int64_t)p.n_wg * MT;
+  hipError_t e = launch_rb_stage(c->cfg.prec, 1, c->w, c->relu, c->st, p, c->stream);
+  if (e == hipSuccess)
+    e = launch_resblocks(c->cfg.prec, c->w, c->relu, c->rb_trunk, slots * NetRB7::NB,
+                         c->rb_active, c->stream);
+  if (e == hipSuccess)
+    e = launch_rb_head(c->cfg.prec, c->w, c->relu, c->rb_trunk, slots, c->rb_active,
+                       c->rb_logits, c->stream);
+  if (e == hipSuccess) e = launch_rb_stage(c->cfg.prec, 2, c->w, c->relu, c->st, p, c->stream);
+  return e;
+}
+
+// RB7 steps; n_steps = INT32_MAX runs until every position has been
+// advanced (checked on the host every RB_CHECK steps).
+constexpr int RB_CHECK = 16;
+static int rb_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t* table) {
+  const bool to_end = n_steps >= INT32_MAX;
+  for (int64_t done = 0; to_end || done < n_steps;) {
+    const int64_t chunk = to_end ? RB_CHECK : std::min<int64_t>(RB_CHECK, n_steps - done);
+    for (int64_t i = 0; i < chunk; ++i) {
+      hipError_t e = rb_step(c, mode, table);
+      if (e != hipSuccess) return hip_fail(c, e, "RB7 step launch");
+    }
+    done += chunk;
+    if (!to_end) continue;
+    unsigned long long adv = 0;
+    hipError_t e = hipMemcpyAsync(&adv, c->st.counters + 3, sizeof adv, hipMemcpyDeviceToHost,
+                                  c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "RB7 progress");
+    if ((int64_t)adv >= c->n_pred) break;
+    if (done > c->n_pred + RB_CHECK)  // every step advances at least one position
+      return fail(c, SIM_EDEVICE, "RB7 run did not finish");
+  }
+  return SIM_OK;
 }
 
 static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t* table) {
@@ -1025,8 +1122,11 @@ static int step_launch(sim_ctx* c, int64_t n_steps, int32_t mode, const int32_t*
   if (c->ran_to_end) return SIM_OK;  // every sub-trace has already finished
   if (n_steps == 0) return SIM_OK;   // checks only
   if (n_steps >= INT32_MAX) c->ran_to_end = true;
+  if (c->net == 5 && mode != SIM_LAT_INJECT) return rb_launch(c, n_steps, mode, table);
   const StepParams p = step_params(c, n_steps, mode, table);
-  hipError_t e = launch_step(c->net, c->cfg.prec, c->variant, c->w, c->relu, c->st, p, c->stream);
+  // (injected latencies need no predictor: RB7 shares the hybrid head's step)
+  hipError_t e = launch_step(c->net == 5 ? 3 : c->net, c->cfg.prec, c->variant, c->w, c->relu,
+                             c->st, p, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "step launch");
   return SIM_OK;
 }
@@ -1042,7 +1142,7 @@ int sim_run(sim_ctx* c, int32_t mode, const int32_t* table, sim_result* res) {
   if (!c) return SIM_EINVAL;
   if (!res) return fail(c, SIM_EINVAL, "null result");
   hipError_t e = hipSuccess;
-  if (c->use_graph && !c->ran_to_end) {
+  if (c->use_graph && !c->ran_to_end && c->net != 5) {  // (RB7 runs its steps eagerly)
     // same checks as a step launch, then replay (rebuilt when its inputs change)
     int rc = step_launch(c, 0, mode, table);
     if (rc != SIM_OK) return rc;
@@ -1117,6 +1217,30 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
     return SIM_OK;
   }
   if (save_or_null) return fail(c, SIM_EUNSUPPORTED, "save buffer not supported");
+  if (c->net == 5) {  // convolutions, residual blocks, FC 512 and head over a workspace
+    if (B > INT64_MAX / (NetRB7::NB * NetRB7::CH3 * 4)) return fail(c, SIM_EINVAL, "batch too large");
+    if (B > c->rb_ws_B) {
+      if (c->rb_ws) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(c->rb_ws);
+        c->rb_ws = nullptr;
+        c->rb_ws_B = 0;
+      }
+      hipError_t e = hipMalloc(&c->rb_ws, (size_t)B * NetRB7::NB * NetRB7::CH3 *
+                                              elem_size(c->cfg.prec));
+      if (e != hipSuccess) return hip_fail(c, e, "hipMalloc RB7 workspace");
+      c->rb_ws_B = B;
+    }
+    hipError_t e = launch_rb_trunk(c->cfg.prec, c->w, c->relu, static_cast<const float*>(x), B,
+                                   c->rb_ws, c->stream);
+    if (e == hipSuccess)
+      e = launch_resblocks(c->cfg.prec, c->w, c->relu, c->rb_ws, B * NetRB7::NB, nullptr,
+                           c->stream);
+    if (e == hipSuccess)
+      e = launch_rb_head(c->cfg.prec, c->w, c->relu, c->rb_ws, B, nullptr, logits, c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "RB7 forward");
+    return SIM_OK;
+  }
   hipError_t e = launch_forward(c->net, c->cfg.prec, c->w, c->relu, static_cast<const float*>(x),
                                 B, logits, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "forward launch");
@@ -1316,6 +1440,10 @@ void sim_destroy(sim_ctx* c) {
   if (c->tr.perm) (void)hipFree(c->tr.perm);
   if (c->tr.work) (void)hipFree(c->tr.work);
   if (c->dev_block) (void)hipFree(c->dev_block);
+  if (c->rb_trunk) (void)hipFree(c->rb_trunk);
+  if (c->rb_active) (void)hipFree(c->rb_active);
+  if (c->rb_logits) (void)hipFree(c->rb_logits);
+  if (c->rb_ws) (void)hipFree(c->rb_ws);
   delete c;
 }
 

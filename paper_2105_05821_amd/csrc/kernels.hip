@@ -340,6 +340,35 @@ struct SavePtrs {
   int rows;
 };
 
+// Index of the hidden FC in the layer list (after the convs and the
+// residual blocks' two pointwise layers each): its ReLU bit.
+template <class Net>
+constexpr int hidden_layer() {
+  return Net::NCONV + 2 * Net::NRES;
+}
+
+// Hidden-FC contribution of NBG blocks from block j0: last = the blocks'
+// last-conv output in LDS (window s at s * SAL, block-major), hacc += it
+// times the per-block packed weights.  A fresh accumulator per group, then
+// added, so the FP32 chain is per group.
+template <class Net, class P, int NBG>
+__device__ __forceinline__ void hidden_fc(const DevWeights& wt, const typename P::T* last, int j0,
+                                          v4f* hacc, int wave, int lane) {
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  constexpr int HT = (Net::HID / 16) / Net::WAVES;
+  constexpr int KGS = NBG * Net::CHL / P::KG;
+  const uint4* bj = static_cast<const uint4*>(wt.hid_w) +
+                    (size_t)j0 * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
+  const T* const ap[1] = {last + (lane & 15) * G::SAL + (P::KG / 4) * (lane >> 4)};
+  v4f bacc[1][HT];
+#pragma unroll
+  for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
+  mma_stream<P, KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS>(bacc, ap, bj, wave * HT, lane);
+#pragma unroll
+  for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
+}
+
 // The conv levels and the hidden-FC (or final-FC) contribution of one group
 // of NBG blocks starting at block j0, for the tile of MT windows whose
 // window rows are in sm.x().  relu_mask bit l = ReLU after layer l.  Ends
@@ -347,7 +376,9 @@ struct SavePtrs {
 // conv levels (it requests the next group's rows into registers) and
 // finish(regs) after the FC (it writes them into sm.x(), the region conv2's
 // output used, dead by then): the FC's weight stream hides the gather.
-template <class Net, class P, int NBG, bool CAL, bool SAVE, class Issue, class Finish>
+// TRUNK: the convolutions only, the last conv's output going to sv.a3 (a1
+// and a2 are not written).
+template <class Net, class P, int NBG, bool CAL, bool SAVE, bool TRUNK, class Issue, class Finish>
 __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_mask,
                                           NetSmem<Net, P>& sm, int j0, unsigned* cal,
                                           const int* row_live, SavePtrs<typename P::T> sv,
@@ -358,13 +389,14 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int P1 = NBG * Net::BS / 2, P2 = NBG * Net::BS / 4;
   constexpr int Q1 = Net::BS / 2, Q2 = Net::BS / 4;  // positions per block
-  conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::RX, G::SA1, true, CAL, SAVE>(
+  conv_stage<P, 2 * G::DP, Net::CH1, P1, Net::WAVES, G::SX, G::RX, G::SA1, true, CAL,
+             SAVE && !TRUNK>(
       sm.x(), sm.a1(), static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
       wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live,
       sv.a1 + (size_t)j0 * Q1 * Net::CH1, (int64_t)Net::NB * Q1 * Net::CH1, sv.rows);
   __syncthreads();
   conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::R1, G::SA2, Net::NCONV == 3,
-             CAL, SAVE>(
+             CAL, SAVE && !TRUNK>(
       sm.a1(), sm.a2(), static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
       wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live,
       sv.a2 + (size_t)j0 * Q2 * Net::CH2, (int64_t)Net::NB * Q2 * Net::CH2, sv.rows);
@@ -383,21 +415,12 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
     finish(next_rows);
   }
   const T* last = Net::NCONV == 3 ? sm.a3() : sm.a2();
-  if constexpr (Net::HID > 0) {
+  if constexpr (TRUNK) {
+    (void)last;
+  } else if constexpr (Net::HID > 0) {
     // hidden FC over the group's NBG*CHL inputs per window (block-major, as
-    // the packed per-block matrices are consecutive): a fresh accumulator
-    // per group, then added, so the FP32 chain is per group
-    constexpr int HT = (Net::HID / 16) / Net::WAVES;
-    constexpr int KGS = NBG * Net::CHL / P::KG;
-    const uint4* bj = static_cast<const uint4*>(wt.hid_w) +
-                      (size_t)j0 * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
-    const T* const ap[1] = {last + (lane & 15) * G::SAL + (P::KG / 4) * (lane >> 4)};
-    v4f bacc[1][HT];
-#pragma unroll
-    for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
-    mma_stream<P, KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS>(bacc, ap, bj, wave * HT, lane);
-#pragma unroll
-    for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
+    // the packed per-block matrices are consecutive)
+    hidden_fc<Net, P, NBG>(wt, last, j0, hacc, wave, lane);
   } else {
     // final FC on the VALU straight after the convs: (s, o) pairs, LPP lanes
     // each; the next group's rows are requested before it and written after
@@ -417,6 +440,53 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
   }
 }
 
+// Hybrid head (NOUT outputs) after the hidden FC: the hidden layer's
+// outputs (bias, ReLU, rounded to the form) go to LDS (X's region, dead
+// after the last group), then the final FC runs as one MFMA tile row on the
+// first NOUTP/16 waves; raw outputs to sm.logit.
+template <class Net, class P, bool CAL>
+__device__ __forceinline__ void hybrid_head(const DevWeights& wt, uint32_t relu_mask,
+                                            NetSmem<Net, P>& sm, const v4f* hacc, unsigned* cal,
+                                            const int* row_live) {
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  constexpr int HT = (Net::HID / 16) / Net::WAVES;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  (void)tid;
+  constexpr int NOUTP = (Net::NOUT + 15) / 16 * 16, NTL = NOUTP / 16;
+  constexpr int SH = Net::HID + G::PAD;
+  static_assert(sizeof(T) * MT * SH <= sizeof(sm.xa2) && NTL <= Net::WAVES, "hybrid head");
+  T* hb = sm.x();
+  const bool hrelu = relu_mask & (1u << hidden_layer<Net>());
+  const int row = lane & 15;
+  const bool live = !CAL || row_live[row];
+#pragma unroll
+  for (int jj = 0; jj < HT; ++jj) {
+    const int col0 = (wave * HT + jj) * 16 + 4 * (lane >> 4);
+    T e[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float hv = activation<P>(hacc[jj][i], col0 + i, wt.hid_b, wt.hid_ws, hrelu);
+      if constexpr (CAL)
+        if (live) cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col0 + i, hv);
+      e[i] = to_storage<P>(hv, col0 + i, wt.hid_ai);
+    }
+    store_run<4 * sizeof(T)>(hb + row * SH + col0, e);
+  }
+  __syncthreads();
+  if (wave < NTL) {
+    const T* const ap[1] = {hb + row * SH + (P::KG / 4) * (lane >> 4)};
+    v4f acc[1][1] = {{v4f{0.f, 0.f, 0.f, 0.f}}};
+    mma_stream<P, Net::HID / P::KG, NTL, 1, 1>(acc, ap, static_cast<const uint4*>(wt.last_p),
+                                               wave, lane);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int col = wave * 16 + 4 * (lane >> 4) + i;
+      if (col < Net::NOUT) sm.logit[row][col] = acc[0][0][i] + wt.last_b[col];
+    }
+  }
+}
+
 // The whole predictor on one tile of MT windows.  The window arrives a group
 // of NG blocks (NG*BS slots) at a time: load(j0, nb) requests the rows of
 // blocks j0 .. j0+nb-1 into registers, commit(j0, nb, regs, X) writes them,
@@ -427,8 +497,10 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
 // called by all threads; the raw outputs land in sm.logit.  CAL: also record
 // per-channel max |input| of every layer into cal (offsets: window D, conv1
 // out, conv2 out[, conv3 out, hidden out]), counting only tile rows whose
-// row_live[s] is set.
-template <class Net, class P, bool CAL = false, bool SAVE = false, class Load, class Commit>
+// row_live[s] is set.  TRUNK: the convolutions only, the last conv's
+// output written to sv.a3 (nothing in sm.logit).
+template <class Net, class P, bool CAL = false, bool SAVE = false, bool TRUNK = false, class Load,
+          class Commit>
 __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu_mask,
                                              NetSmem<Net, P>& sm, Load&& load, Commit&& commit,
                                              unsigned* cal = nullptr,
@@ -452,7 +524,7 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
     __syncthreads();
     const int j0 = g * NG;
     const int nj = j0 + NG, nnb = g + 1 < NFULL ? NG : TAIL;
-    run_group<Net, P, NG, CAL, SAVE>(
+    run_group<Net, P, NG, CAL, SAVE, TRUNK>(
         wt, relu_mask, sm, j0, cal, row_live, sv, hacc, fpart, [&]() { return load(nj, nnb); },
         [&](const auto& regs) {
           if (nnb > 0) commit(nj, nnb, regs, sm.x());
@@ -460,15 +532,19 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
   }
   if constexpr (TAIL > 0) {
     __syncthreads();
-    run_group<Net, P, TAIL, CAL, SAVE>(
+    run_group<Net, P, TAIL, CAL, SAVE, TRUNK>(
         wt, relu_mask, sm, NFULL * NG, cal, row_live, sv, hacc, fpart, []() { return 0; },
         [](int) {});
+  }
+  if constexpr (TRUNK) {
+    __syncthreads();
+    return;
   }
 
   if constexpr (SAVE && Net::HID > 0) {
     // training form: the hidden layer's output is kept, the head runs as a
     // separate GEMM over the whole batch
-    const bool hrelu = relu_mask & (1u << Net::NCONV);
+    const bool hrelu = relu_mask & (1u << hidden_layer<Net>());
     const int row = lane & 15;
 #pragma unroll
     for (int jj = 0; jj < HT; ++jj) {
@@ -481,46 +557,12 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
       if (row < sv.rows) store_run<4 * sizeof(T)>(sv.h + (size_t)row * Net::HID + col0, e);
     }
   } else if constexpr (Net::HID > 0 && Net::HEAD == 1) {
-    // hybrid head (NOUT outputs): the hidden layer's outputs, rounded to the
-    // form, go to LDS (X's region, dead after the last group), then the
-    // final FC runs as one MFMA tile row on the first NOUTP/16 waves
-    constexpr int NOUTP = (Net::NOUT + 15) / 16 * 16, NTL = NOUTP / 16;
-    constexpr int SH = Net::HID + G::PAD;
-    static_assert(sizeof(T) * MT * SH <= sizeof(sm.xa2) && NTL <= Net::WAVES, "hybrid head");
-    T* hb = sm.x();
-    const bool hrelu = relu_mask & (1u << Net::NCONV);
-    const int row = lane & 15;
-    const bool live = !CAL || row_live[row];
-#pragma unroll
-    for (int jj = 0; jj < HT; ++jj) {
-      const int col0 = (wave * HT + jj) * 16 + 4 * (lane >> 4);
-      T e[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float hv = activation<P>(hacc[jj][i], col0 + i, wt.hid_b, wt.hid_ws, hrelu);
-        if constexpr (CAL)
-          if (live) cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col0 + i, hv);
-        e[i] = to_storage<P>(hv, col0 + i, wt.hid_ai);
-      }
-      store_run<4 * sizeof(T)>(hb + row * SH + col0, e);
-    }
-    __syncthreads();
-    if (wave < NTL) {
-      const T* const ap[1] = {hb + row * SH + (P::KG / 4) * (lane >> 4)};
-      v4f acc[1][1] = {{v4f{0.f, 0.f, 0.f, 0.f}}};
-      mma_stream<P, Net::HID / P::KG, NTL, 1, 1>(acc, ap, static_cast<const uint4*>(wt.last_p),
-                                                 wave, lane);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int col = wave * 16 + 4 * (lane >> 4) + i;
-        if (col < Net::NOUT) sm.logit[row][col] = acc[0][0][i] + wt.last_b[col];
-      }
-    }
+    hybrid_head<Net, P, CAL>(wt, relu_mask, sm, hacc, cal, row_live);
   } else if constexpr (Net::HID > 0) {
     // bias + ReLU on the hidden layer, rounding to the form's precision, then
     // the final FC: lane l holds row l % 16 and 4 columns of each of its HT
     // tiles; reduce over the 4 lanes sharing the row, then over waves.
-    const bool hrelu = relu_mask & (1u << Net::NCONV);
+    const bool hrelu = relu_mask & (1u << hidden_layer<Net>());
     const int row = lane & 15;
     const bool live = !CAL || row_live[row];
     float p[Net::NOUT];
@@ -553,7 +595,7 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
 #pragma unroll
       for (int w = 0; w < Net::WAVES; ++w) v += sm.red()[(w * MT + s) * Net::NOUT + o];
       v += wt.last_b[o];
-      if (relu_mask & (1u << (Net::NCONV + 1))) v = fmaxf(v, 0.f);
+      if (relu_mask & (1u << (hidden_layer<Net>() + 1))) v = fmaxf(v, 0.f);
       sm.logit[s][o] = v;
     }
   } else {
@@ -727,7 +769,11 @@ constexpr int n_cal() {
 
 // DEP: the window carries the memory dependency flags (a separate
 // instantiation, so that runs without them pay no registers for them).
-template <class Net, class P, bool RUN_NET, bool CAL = false, bool DEP = false>
+// STAGE (networks run as separate kernels per step, one step per launch):
+// 1 = gather and convolutions only, the last conv's output to p.trunk_out
+// and each slot's activity to p.active_out, the state not advanced;
+// 2 = the update from the raw outputs in p.ext_logits, no gather.
+template <class Net, class P, bool RUN_NET, bool CAL = false, bool DEP = false, int STAGE = 0>
 __global__ void __launch_bounds__(Net::WAVES * 64)
     step_kernel(DevWeights wt, uint32_t relu_mask, DevState st, StepParams p) {
   using G = Geo<Net, P>;
@@ -858,10 +904,19 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
         X + gs * G::SX + (gt >> 1) * G::RX + (gt & 1) * DP + part * CPT, e);
   };
 
+  if constexpr (STAGE == 1)
+    if (tid < MT) p.active_out[slot0 + tid] = sm.active[tid];
   int any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
 
   for (int it = 0; it < p.n_steps && any; ++it) {
-    if (RUN_NET) {
+    if constexpr (RUN_NET && STAGE == 1) {
+      SavePtrs<T> sv{};
+      sv.a3 = static_cast<T*>(p.trunk_out) + (size_t)slot0 * Net::NB * Net::CH3;
+      sv.rows = MT;
+      predict_tile<Net, P, false, true, true>(wt, relu_mask, sm.net, load, commit, nullptr,
+                                              nullptr, sv);
+      break;  // the update is a separate launch
+    } else if constexpr (RUN_NET && STAGE == 0) {
       predict_tile<Net, P, CAL>(wt, relu_mask, sm.net, load, commit, cal, sm.active);
     }
 
@@ -871,15 +926,16 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
       const int64_t g = sm.pred_off[s] + pos;
       int32_t lat[Net::NLAT];
       if (RUN_NET) {
+        const float* z = STAGE == 2 ? p.ext_logits + (size_t)(slot0 + s) * Net::NOUT
+                                    : sm.net.logit[s];
         if (p.logits_out)
-          for (int o = 0; o < Net::NOUT; ++o) p.logits_out[g * Net::NOUT + o] = sm.net.logit[s][o];
+          for (int o = 0; o < Net::NOUT; ++o) p.logits_out[g * Net::NOUT + o] = z[o];
 #pragma unroll
         for (int o = 0; o < Net::NLAT; ++o) {
           if constexpr (Net::HEAD == 1)
-            lat[o] = hybrid_latency(&sm.net.logit[s][o * HYB_PER_TYPE], p.lat_max, n_clamped,
-                                    n_nonfinite);
+            lat[o] = hybrid_latency(z + o * HYB_PER_TYPE, p.lat_max, n_clamped, n_nonfinite);
           else
-            lat[o] = round_latency(sm.net.logit[s][o], p.lat_max, n_clamped, n_nonfinite);
+            lat[o] = round_latency(z[o], p.lat_max, n_clamped, n_nonfinite);
         }
       }
       ++n_pred;  // positions advanced (the work a launch did)
@@ -981,10 +1037,11 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     any = __syncthreads_or(tid < MT ? sm.active[tid] : 0);
   }
 
+  // (stage 1 leaves the state as it found it, apart from the slots' claims)
   if (tid < MT) {
     const int k = sm.kid[tid];
     st.slot_kid[slot0 + tid] = k;
-    if (k >= 0) {
+    if (STAGE != 1 && k >= 0) {
       st.cur[k] = sm.cur[tid];
       st.t_w[k] = sm.t_w[tid];
       st.r_prev[k] = sm.r_prev[tid];
@@ -1009,7 +1066,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     for (int i = tid; i < n_cal<Net>(); i += NT)
       if (cal[i]) atomicMax(p.cal_out + i, cal[i]);
   }
-  for (int i = tid; i < MT * C; i += NT) {
+  for (int i = tid; i < MT * C && STAGE != 1; i += NT) {
     const int s = i / C, e = i % C, k = sm.kid[s];
     if (k >= 0) {
       const size_t g = (size_t)k * C + e;
@@ -1028,10 +1085,12 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   }
 }
 
-template <class Net, class P>
+// Predictor over explicit windows x [B][L][D] -> logits [B][NOUT]; TRUNK:
+// the convolutions only, the last conv's output to trunk_out [B][NB][CH3].
+template <class Net, class P, bool TRUNK = false>
 __global__ void __launch_bounds__(Net::WAVES * 64)
     forward_kernel(DevWeights wt, uint32_t relu_mask, const float* __restrict__ x, int64_t B,
-                   float* __restrict__ logits) {
+                   float* __restrict__ logits, void* __restrict__ trunk_out) {
   using G = Geo<Net, P>;
   using T = typename P::T;
   constexpr int NT = G::NT, D = Net::D, DP = G::DP, BS = Net::BS, L = Net::L;
@@ -1076,7 +1135,178 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(
         X + s * G::SX + (t >> 1) * G::RX + (t & 1) * DP + part * CPT, e);
   };
-  predict_tile<Net, P>(wt, relu_mask, sm, load, commit);
+  if constexpr (TRUNK) {
+    SavePtrs<T> sv{};
+    sv.a3 = static_cast<T*>(trunk_out) + b0 * Net::NB * Net::CH3;
+    sv.rows = (int)(B - b0 < MT ? B - b0 : MT);
+    predict_tile<Net, P, false, true, true>(wt, relu_mask, sm, load, commit, nullptr, nullptr, sv);
+  } else {
+    predict_tile<Net, P>(wt, relu_mask, sm, load, commit);
+    if (tid < MT * Net::NOUT) {
+      const int ss = tid / Net::NOUT, o = tid % Net::NOUT;
+      if (b0 + ss < B) logits[(b0 + ss) * Net::NOUT + o] = sm.logit[ss][o];
+    }
+  }
+}
+
+// ------------------------------------------------------ residual blocks ---
+// A tile of TM rows (window positions at the last conv level, CH3 channels
+// each) stays in LDS through all NRES blocks.  Per block the expansion is
+// produced EC channels at a time (bias, ReLU, rounded to the form, into
+// LDS) and consumed at once by the projection, whose TM x CH3 accumulators
+// stay in registers for the whole block; then bias, the block input and the
+// ReLU, rounded to the form, replace the tile.  Expansion: each wave one
+// 16-channel tile of the chunk for all the tile's rows (a weight fragment
+// is fetched once per workgroup); projection: each wave two output tiles.
+template <class P>
+struct ResGeo {
+  using T = typename P::T;
+  static constexpr int C = NetRB7::CH3, E = NetRB7::EXPAND, EC = 128;
+  static constexpr int TM = P::ID == 0 ? 64 : 128, MTL = TM / 16;
+  static constexpr int PAD = 16 / sizeof(T);
+  static constexpr int SXR = C + PAD, SHR = EC + PAD;  // padded LDS rows
+  static constexpr int WAVES = 8, NT = WAVES * 64, NPWP = (C / 16) / WAVES;
+  static_assert(E % EC == 0 && EC / 16 == WAVES && NPWP * WAVES * 16 == C, "wave split");
+};
+
+template <class P>
+__global__ void __launch_bounds__(ResGeo<P>::NT)
+    resblock_kernel(DevWeights wt, uint32_t relu_mask, typename P::T* __restrict__ x, int64_t rows,
+                    const int32_t* __restrict__ active) {
+  using RG = ResGeo<P>;
+  using T = typename P::T;
+  using Net = NetRB7;
+  constexpr int C = RG::C, E = RG::E, EC = RG::EC, TM = RG::TM, MTL = RG::MTL, NPWP = RG::NPWP;
+  constexpr int CV = C * (int)sizeof(T) / 16, EPV = 16 / (int)sizeof(T);
+  __shared__ alignas(16) T xs[TM * RG::SXR];
+  __shared__ alignas(16) T hs[TM * RG::SHR];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * TM;
+  const int64_t r1 = r0 + TM < rows ? r0 + TM : rows;  // rows [r0, r1) exist
+  if (active) {  // windows none of whose rows is live are skipped
+    int a = 0;
+    for (int64_t w = r0 / Net::NB + tid; w <= (r1 - 1) / Net::NB; w += RG::NT) a |= active[w];
+    if (!__syncthreads_or(a)) return;
+  }
+  for (int i = tid; i < TM * CV; i += RG::NT) {
+    const int r = i / CV, v = i % CV;
+    uint4 val = make_uint4(0u, 0u, 0u, 0u);
+    if (r0 + r < r1) val = reinterpret_cast<const uint4*>(x + (r0 + r) * C)[v];
+    *reinterpret_cast<uint4*>(xs + r * RG::SXR + v * EPV) = val;
+  }
+  __syncthreads();
+  const T* apx[MTL];
+  const T* aph[MTL];
+#pragma unroll
+  for (int i = 0; i < MTL; ++i) {
+    apx[i] = xs + (i * 16 + (lane & 15)) * RG::SXR + (P::KG / 4) * (lane >> 4);
+    aph[i] = hs + (i * 16 + (lane & 15)) * RG::SHR + (P::KG / 4) * (lane >> 4);
+  }
+  const int row = lane & 15, q4 = 4 * (lane >> 4);
+  for (int blk = 0; blk < Net::NRES; ++blk) {
+    const char* wb = static_cast<const char*>(wt.res_w) + (size_t)blk * wt.res_stride;
+    const uint4* We = reinterpret_cast<const uint4*>(wb);
+    const uint4* Wp = reinterpret_cast<const uint4*>(wb + (size_t)C * E * sizeof(T));
+    const float* be = wt.res_b + (size_t)blk * (E + C);
+    const float* bp = be + E;
+    const bool erelu = relu_mask & (1u << (Net::NCONV + 2 * blk));
+    const bool orelu = relu_mask & (1u << (Net::NCONV + 2 * blk + 1));
+    v4f yacc[MTL][NPWP];
+#pragma unroll
+    for (int i = 0; i < MTL; ++i)
+#pragma unroll
+      for (int j = 0; j < NPWP; ++j) yacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int ch = 0; ch < E / EC; ++ch) {
+      v4f hacc[MTL][1];
+#pragma unroll
+      for (int i = 0; i < MTL; ++i) hacc[i][0] = v4f{0.f, 0.f, 0.f, 0.f};
+      mma_stream<P, C / P::KG, E / 16, 1, MTL>(hacc, apx, We, ch * (EC / 16) + wave, lane);
+      const int hc0 = wave * 16 + q4;  // this lane's 4 channels of the chunk
+#pragma unroll
+      for (int i = 0; i < MTL; ++i) {
+        T e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          e[q] = to_storage<P>(activation<P>(hacc[i][0][q], ch * EC + hc0 + q, be, nullptr, erelu),
+                               0, nullptr);
+        store_run<4 * sizeof(T)>(hs + (i * 16 + row) * RG::SHR + hc0, e);
+      }
+      __syncthreads();
+      mma_stream<P, EC / P::KG, C / 16, NPWP, MTL>(
+          yacc, aph, Wp + (size_t)ch * (EC / P::KG) * (C / 16) * 64, wave * NPWP, lane);
+      __syncthreads();
+    }
+    // bias, the block input (as stored) and the activation replace the tile
+#pragma unroll
+    for (int i = 0; i < MTL; ++i)
+#pragma unroll
+      for (int j = 0; j < NPWP; ++j) {
+        const int col0 = (wave * NPWP + j) * 16 + q4;
+        T* xr = xs + (i * 16 + row) * RG::SXR + col0;
+        T e[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v = yacc[i][j][q] + bp[col0 + q] + P::val(xr[q]);
+          if (orelu) v = fmaxf(v, 0.f);
+          e[q] = to_storage<P>(v, 0, nullptr);
+        }
+        store_run<4 * sizeof(T)>(xr, e);
+      }
+    __syncthreads();
+  }
+  for (int i = tid; i < TM * CV; i += RG::NT) {
+    const int r = i / CV, v = i % CV;
+    if (r0 + r < r1)
+      reinterpret_cast<uint4*>(x + (r0 + r) * C)[v] =
+          *reinterpret_cast<const uint4*>(xs + r * RG::SXR + v * EPV);
+  }
+}
+
+// FC 512 and the hybrid head over x [B][NB][CH3] (the blocks' output):
+// each group of the tile's blocks is staged into LDS where the fused step
+// keeps its last conv output, then the same hidden-FC and head code runs.
+template <class P>
+__global__ void __launch_bounds__(NetRB7::WAVES * 64)
+    rb_head_kernel(DevWeights wt, uint32_t relu_mask, const typename P::T* __restrict__ x,
+                   int64_t B, const int32_t* __restrict__ active, float* __restrict__ logits) {
+  using Net = NetRB7;
+  using G = Geo<Net, P>;
+  using T = typename P::T;
+  constexpr int NG = G::NG, NFULL = Net::NB / NG, TAIL = Net::NB % NG;
+  constexpr int HT = (Net::HID / 16) / Net::WAVES, V = Net::CH3 * (int)sizeof(T) / 16;
+  __shared__ NetSmem<Net, P> sm;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t b0 = (int64_t)blockIdx.x * MT;
+  if (active) {
+    const int a = tid < MT && b0 + tid < B ? active[b0 + tid] : 0;
+    if (!__syncthreads_or(a)) return;
+  }
+  v4f hacc[HT];
+#pragma unroll
+  for (int j = 0; j < HT; ++j) hacc[j] = v4f{0.f, 0.f, 0.f, 0.f};
+  auto stage = [&](int j0, int nb) {
+    for (int i = tid; i < MT * nb * V; i += G::NT) {
+      const int s = i / (nb * V), r = i % (nb * V), jb = r / V, v = r % V;
+      uint4 val = make_uint4(0u, 0u, 0u, 0u);
+      if (b0 + s < B)
+        val = reinterpret_cast<const uint4*>(x + ((b0 + s) * Net::NB + j0 + jb) * Net::CH3)[v];
+      *reinterpret_cast<uint4*>(sm.a3() + s * G::SAL + jb * Net::CH3 + v * (16 / (int)sizeof(T))) =
+          val;
+    }
+    __syncthreads();
+  };
+  for (int g = 0; g < NFULL; ++g) {
+    stage(g * NG, NG);
+    hidden_fc<Net, P, NG>(wt, sm.a3(), g * NG, hacc, wave, lane);
+    __syncthreads();
+  }
+  if constexpr (TAIL > 0) {
+    stage(NFULL * NG, TAIL);
+    hidden_fc<Net, P, TAIL>(wt, sm.a3(), NFULL * NG, hacc, wave, lane);
+    __syncthreads();
+  }
+  hybrid_head<Net, P, false>(wt, relu_mask, sm, hacc, nullptr, nullptr);
+  __syncthreads();
   if (tid < MT * Net::NOUT) {
     const int ss = tid / Net::NOUT, o = tid % Net::NOUT;
     if (b0 + ss < B) logits[(b0 + ss) * Net::NOUT + o] = sm.logit[ss][o];
@@ -1249,7 +1479,8 @@ template <class Net, class P>
 static hipError_t launch_forward_t(const DevWeights& w, uint32_t relu, const float* x, int64_t B,
                                    float* logits, hipStream_t stream) {
   const dim3 grid((unsigned)((B + MT - 1) / MT)), block(Geo<Net, P>::NT);
-  hipLaunchKernelGGL((forward_kernel<Net, P>), grid, block, 0, stream, w, relu, x, B, logits);
+  hipLaunchKernelGGL((forward_kernel<Net, P>), grid, block, 0, stream, w, relu, x, B, logits,
+                     nullptr);
   return hipGetLastError();
 }
 
@@ -1391,6 +1622,77 @@ hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, 
   }
   *out = g;
   return hipSuccess;
+}
+
+// ------------------------------------------------------------------ RB7 ---
+
+template <class P>
+static hipError_t launch_rb_stage_t(int stage, const DevWeights& w, uint32_t relu,
+                                    const DevState& s, const StepParams& p, hipStream_t stream) {
+  const dim3 grid(p.n_wg), block(Geo<NetRB7, P>::NT);
+  if (stage == 1)
+    hipLaunchKernelGGL((step_kernel<NetRB7, P, true, false, false, 1>), grid, block, 0, stream, w,
+                       relu, s, p);
+  else
+    hipLaunchKernelGGL((step_kernel<NetRB7, P, true, false, false, 2>), grid, block, 0, stream, w,
+                       relu, s, p);
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_stage(int prec, int stage, const DevWeights& w, uint32_t relu,
+                           const DevState& s, const StepParams& p, hipStream_t stream) {
+  if ((stage != 1 && stage != 2) || p.n_steps != 1) return hipErrorInvalidValue;
+  if (prec == 0) return launch_rb_stage_t<PF32>(stage, w, relu, s, p, stream);
+  if (prec == 1) return launch_rb_stage_t<PBF16>(stage, w, relu, s, p, stream);
+  return hipErrorInvalidValue;
+}
+
+template <class P>
+static hipError_t launch_resblocks_t(const DevWeights& w, uint32_t relu, void* x, int64_t rows,
+                                     const int32_t* active, hipStream_t stream) {
+  const int64_t tiles = (rows + ResGeo<P>::TM - 1) / ResGeo<P>::TM;
+  if (tiles > INT32_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((resblock_kernel<P>), dim3((unsigned)tiles), dim3(ResGeo<P>::NT), 0, stream,
+                     w, relu, static_cast<typename P::T*>(x), rows, active);
+  return hipGetLastError();
+}
+
+hipError_t launch_resblocks(int prec, const DevWeights& w, uint32_t relu, void* x, int64_t rows,
+                            const int32_t* active, hipStream_t stream) {
+  if (rows <= 0) return hipSuccess;
+  if (prec == 0) return launch_resblocks_t<PF32>(w, relu, x, rows, active, stream);
+  if (prec == 1) return launch_resblocks_t<PBF16>(w, relu, x, rows, active, stream);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_rb_head(int prec, const DevWeights& w, uint32_t relu, const void* x, int64_t B,
+                          const int32_t* active, float* logits, hipStream_t stream) {
+  if (B <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((B + MT - 1) / MT)), block(NetRB7::WAVES * 64);
+  if (prec == 0)
+    hipLaunchKernelGGL((rb_head_kernel<PF32>), grid, block, 0, stream, w, relu,
+                       static_cast<const float*>(x), B, active, logits);
+  else if (prec == 1)
+    hipLaunchKernelGGL((rb_head_kernel<PBF16>), grid, block, 0, stream, w, relu,
+                       static_cast<const PBF16::T*>(x), B, active, logits);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_rb_trunk(int prec, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
+                           void* out, hipStream_t stream) {
+  if (B <= 0) return hipSuccess;
+  const dim3 grid((unsigned)((B + MT - 1) / MT)), block(NetRB7::WAVES * 64);
+  if (prec == 0)
+    hipLaunchKernelGGL((forward_kernel<NetRB7, PF32, true>), grid, block, 0, stream, w, relu, x, B,
+                       nullptr, out);
+  else if (prec == 1)
+    hipLaunchKernelGGL((forward_kernel<NetRB7, PBF16, true>), grid, block, 0, stream, w, relu, x,
+                       B, nullptr, out);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
 }
 
 }  // namespace simnet

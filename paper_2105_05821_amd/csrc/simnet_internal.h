@@ -25,6 +25,7 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr int FC1_FRAGS = 8;
   static constexpr int WAVES = 4;
   static constexpr int CHL = CH2;            // channels of the last conv
+  static constexpr int NRES = 0, EXPAND = 0; // residual blocks after the convs
 };
 struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -> FC 512 -> FC 2
   static constexpr int D = 50, L = 111, C = 110;
@@ -36,6 +37,7 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
   static constexpr int FC1_FRAGS = 8;        // hidden-FC weight fragments per prefetch chunk
   static constexpr int WAVES = 8;
   static constexpr int CHL = CH3;
+  static constexpr int NRES = 0, EXPAND = 0;
 };
 // Hybrid inference head (Sec. 2.3): per latency type HYB_CLASSES class scores
 // (latencies 0 .. HYB_CLASSES-2 and "larger") and one direct output.
@@ -54,6 +56,15 @@ constexpr int N_VARIANTS = 3;
 struct NetC3S : NetC3 {  // C3 trunk -> FC 512 -> 3
   static constexpr int NOUT = 3, NLAT = 3;
   static constexpr bool MWQ = true;
+};
+// RB7 (Sec. 2.3, residual blocks; the model table's deepest CNN): the C3
+// convolutions, then NRES residual blocks at the last conv's 13 positions,
+// each y = ReLU(x + P ReLU(E x + e) + p) with E: 256 -> EXPAND and P:
+// EXPAND -> 256 pointwise, then FC 3328 -> 512 and the hybrid head.  Runs
+// as separate kernels per step: the convolutions inside the gather, the
+// blocks over all windows' positions at once, FC 512 and the head.
+struct NetRB7 : NetC3Hyb {
+  static constexpr int NRES = 7, EXPAND = 1920;
 };
 
 // Contraction length covered by one 16-byte per-lane MFMA fragment group:
@@ -91,6 +102,13 @@ struct DevWeights {
   const float* last_w;
   const float* last_b;
   const void* last_p;  // hybrid head: the final FC packed like a hidden matrix
+  // residual blocks (RB7): block i's expansion B[c][e] = E[e][c] (K = CH3,
+  // N = EXPAND) then its projection B[e][c] = P[c][e] (K = EXPAND, N = CH3),
+  // both packed like a conv level, at res_w + i * res_stride bytes; biases
+  // res_b + i * (EXPAND + CH3): expansion's, then projection's
+  const void* res_w;
+  int64_t res_stride;
+  const float* res_b;
 };
 
 struct DevState {
@@ -155,6 +173,13 @@ struct StepParams {
   float* logits_out;
   int32_t n_steps;
   unsigned* cal_out;  // calibration launches: per-channel max |input| (float bits)
+  // staged step (RB7): the trunk stage writes each slot's last-conv output
+  // [NB][CH3] (storage precision) to trunk_out + slot * NB * CH3 and the
+  // slot's activity to active_out[slot]; the update stage reads the slot's
+  // raw outputs from ext_logits + slot * NOUT
+  void* trunk_out;
+  int32_t* active_out;
+  const float* ext_logits;
 };
 
 // Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3; prec: 0 FP32,
@@ -222,6 +247,23 @@ hipError_t launch_map_scatter(const float* src, const int32_t* map, int64_t n, f
 hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int32_t t, hipStream_t stream);
+
+// RB7, one step in three parts (n_steps = 1 each): stage 1 = gather and
+// convolutions into p.trunk_out; then launch_resblocks and launch_rb_head
+// on the slots' rows; stage 2 = round and update from p.ext_logits.
+hipError_t launch_rb_stage(int prec, int stage, const DevWeights& w, uint32_t relu,
+                           const DevState& s, const StepParams& p, hipStream_t stream);
+// Residual blocks in place on x [rows][CH3] (storage precision); a tile of
+// rows whose windows (row / NB) all have active[window] == 0 is skipped
+// (active may be NULL: every row).
+hipError_t launch_resblocks(int prec, const DevWeights& w, uint32_t relu, void* x, int64_t rows,
+                            const int32_t* active, hipStream_t stream);
+// FC 512 and the hybrid head on x [B][NB][CH3] -> logits [B][NOUT].
+hipError_t launch_rb_head(int prec, const DevWeights& w, uint32_t relu, const void* x, int64_t B,
+                          const int32_t* active, float* logits, hipStream_t stream);
+// Convolutions of explicit windows x [B][L][D] (FP32) -> out [B][NB][CH3].
+hipError_t launch_rb_trunk(int prec, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
+                           void* out, hipStream_t stream);
 
 // Graph of the run: step kernel until every slot is empty, then the total.
 hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, uint32_t relu,

@@ -524,6 +524,9 @@ def workload(name: str) -> Workload:
     if name == "c3hyb_1m":    # c3_1m with the hybrid inference head
         return Workload("c3hyb_1m", 1_000_000, 50, 111, net_c3_hybrid_infer(), n_sub=4096,
                         warmup=256, extra={"out_bias": HYB_BIAS, "head": 1})
+    if name == "rb7_1m":      # c3_1m with the RB7 network (seven residual blocks, hybrid head)
+        return Workload("rb7_1m", 1_000_000, 50, 111, net_rb7(), n_sub=4096, warmup=256,
+                        extra={"out_bias": HYB_BIAS, "head": 1})
     if name == "c3_train":    # 4,096 labelled contexts per step, hybrid head, BF16
         return Workload("c3_train", 200_000, 50, 111, net_c3_hybrid(), extra={"batch": 4096})
     if name == "c3_uneven":   # 20k independent streams, log-uniform lengths 1e3..2e5
