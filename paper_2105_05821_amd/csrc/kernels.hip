@@ -1150,14 +1150,20 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
 }
 
 // ------------------------------------------------------ residual blocks ---
+// Workgroup barrier ordering LDS only: global loads in flight (weight
+// prefetches) stay in flight across it (__syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // A tile of TM rows (window positions at the last conv level, CH3 channels
 // each) stays in LDS through all NRES blocks.  Per block the expansion is
 // produced EC channels at a time (bias, ReLU, rounded to the form, into
 // LDS) and consumed at once by the projection, whose TM x CH3 accumulators
 // stay in registers for the whole block; then bias, the block input and the
-// ReLU, rounded to the form, replace the tile.  Expansion: each wave one
-// 16-channel tile of the chunk for all the tile's rows (a weight fragment
-// is fetched once per workgroup); projection: each wave two output tiles.
+// ReLU, rounded to the form, replace the tile.
 template <class P>
 struct ResGeo {
   using T = typename P::T;
@@ -1165,8 +1171,8 @@ struct ResGeo {
   static constexpr int TM = P::ID == 0 ? 64 : 128, MTL = TM / 16;
   static constexpr int PAD = 16 / sizeof(T);
   static constexpr int SXR = C + PAD, SHR = EC + PAD;  // padded LDS rows
-  static constexpr int WAVES = 8, NT = WAVES * 64, NPWP = (C / 16) / WAVES;
-  static_assert(E % EC == 0 && EC / 16 == WAVES && NPWP * WAVES * 16 == C, "wave split");
+  static constexpr int WAVES = 8, NT = WAVES * 64;
+  static_assert(E % EC == 0, "chunks");
 };
 
 template <class P>
@@ -1176,7 +1182,7 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
   using RG = ResGeo<P>;
   using T = typename P::T;
   using Net = NetRB7;
-  constexpr int C = RG::C, E = RG::E, EC = RG::EC, TM = RG::TM, MTL = RG::MTL, NPWP = RG::NPWP;
+  constexpr int C = RG::C, E = RG::E, EC = RG::EC, TM = RG::TM, MTL = RG::MTL;
   constexpr int CV = C * (int)sizeof(T) / 16, EPV = 16 / (int)sizeof(T);
   __shared__ alignas(16) T xs[TM * RG::SXR];
   __shared__ alignas(16) T hs[TM * RG::SHR];
@@ -1195,64 +1201,95 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
     *reinterpret_cast<uint4*>(xs + r * RG::SXR + v * EPV) = val;
   }
   __syncthreads();
-  const T* apx[MTL];
-  const T* aph[MTL];
+  // waves: 4 along N x 2 along M in both products; a wave's A fragments
+  // (LDS) serve its 2 (expansion) or 4 (projection) N tiles, its weight
+  // fragments its MTL/2 M tiles
+  constexpr int WNW = 4, WMW = RG::WAVES / WNW, MPW = MTL / WMW;
+  constexpr int NPE = EC / 16 / WNW, NPP = C / 16 / WNW;
+  constexpr int KGE = C / P::KG, KGP = EC / P::KG, NCH = E / EC, NTE = E / 16, NTP = C / 16;
+  static_assert(MTL % WMW == 0 && NPE * WNW * 16 == EC && NPP * WNW * 16 == C, "wave split");
+  const int wn = wave % WNW, wm = wave / WNW;
+  const T* apx[MPW];
+  const T* aph[MPW];
 #pragma unroll
-  for (int i = 0; i < MTL; ++i) {
-    apx[i] = xs + (i * 16 + (lane & 15)) * RG::SXR + (P::KG / 4) * (lane >> 4);
-    aph[i] = hs + (i * 16 + (lane & 15)) * RG::SHR + (P::KG / 4) * (lane >> 4);
+  for (int i = 0; i < MPW; ++i) {
+    const int r = (wm * MPW + i) * 16 + (lane & 15);
+    apx[i] = xs + r * RG::SXR + (P::KG / 4) * (lane >> 4);
+    aph[i] = hs + r * RG::SHR + (P::KG / 4) * (lane >> 4);
   }
-  const int row = lane & 15, q4 = 4 * (lane >> 4);
-  for (int blk = 0; blk < Net::NRES; ++blk) {
+  const int q4 = 4 * (lane >> 4);
+  const size_t half = (size_t)C * E * sizeof(T);
+  v4f yacc[MPW][NPP];
+#pragma unroll
+  for (int i = 0; i < MPW; ++i)
+#pragma unroll
+    for (int j = 0; j < NPP; ++j) yacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < Net::NRES * NCH; ++t) {
+    const int blk = t / NCH, ch = t % NCH;
     const char* wb = static_cast<const char*>(wt.res_w) + (size_t)blk * wt.res_stride;
     const uint4* We = reinterpret_cast<const uint4*>(wb);
-    const uint4* Wp = reinterpret_cast<const uint4*>(wb + (size_t)C * E * sizeof(T));
+    const uint4* Wp = reinterpret_cast<const uint4*>(wb + half) + (size_t)ch * KGP * NTP * 64;
     const float* be = wt.res_b + (size_t)blk * (E + C);
     const float* bp = be + E;
     const bool erelu = relu_mask & (1u << (Net::NCONV + 2 * blk));
     const bool orelu = relu_mask & (1u << (Net::NCONV + 2 * blk + 1));
-    v4f yacc[MTL][NPWP];
+    float4 bev[NPE], bpv[NPP];
 #pragma unroll
-    for (int i = 0; i < MTL; ++i)
+    for (int j = 0; j < NPE; ++j)
+      bev[j] = *reinterpret_cast<const float4*>(be + ch * EC + (wn * NPE + j) * 16 + q4);
+    if (ch == NCH - 1)
 #pragma unroll
-      for (int j = 0; j < NPWP; ++j) yacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    for (int ch = 0; ch < E / EC; ++ch) {
-      v4f hacc[MTL][1];
+      for (int j = 0; j < NPP; ++j)
+        bpv[j] = *reinterpret_cast<const float4*>(bp + (wn * NPP + j) * 16 + q4);
+    // expansion: this wave's NPE 16-channel tiles of the chunk x its rows
+    v4f hacc[MPW][NPE];
 #pragma unroll
-      for (int i = 0; i < MTL; ++i) hacc[i][0] = v4f{0.f, 0.f, 0.f, 0.f};
-      mma_stream<P, C / P::KG, E / 16, 1, MTL>(hacc, apx, We, ch * (EC / 16) + wave, lane);
-      const int hc0 = wave * 16 + q4;  // this lane's 4 channels of the chunk
+    for (int i = 0; i < MPW; ++i)
 #pragma unroll
-      for (int i = 0; i < MTL; ++i) {
-        T e[4];
+      for (int j = 0; j < NPE; ++j) hacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    mma_stream<P, KGE, NTE, NPE, MPW>(hacc, apx, We, ch * (EC / 16) + wn * NPE, lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          e[q] = to_storage<P>(activation<P>(hacc[i][0][q], ch * EC + hc0 + q, be, nullptr, erelu),
-                               0, nullptr);
-        store_run<4 * sizeof(T)>(hs + (i * 16 + row) * RG::SHR + hc0, e);
-      }
-      __syncthreads();
-      mma_stream<P, EC / P::KG, C / 16, NPWP, MTL>(
-          yacc, aph, Wp + (size_t)ch * (EC / P::KG) * (C / 16) * 64, wave * NPWP, lane);
-      __syncthreads();
-    }
-    // bias, the block input (as stored) and the activation replace the tile
+    for (int j = 0; j < NPE; ++j) {
+      const int hc0 = (wn * NPE + j) * 16 + q4;  // 4 channels of the chunk
+      const float bq[4] = {bev[j].x, bev[j].y, bev[j].z, bev[j].w};
 #pragma unroll
-    for (int i = 0; i < MTL; ++i)
-#pragma unroll
-      for (int j = 0; j < NPWP; ++j) {
-        const int col0 = (wave * NPWP + j) * 16 + q4;
-        T* xr = xs + (i * 16 + row) * RG::SXR + col0;
+      for (int i = 0; i < MPW; ++i) {
         T e[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          float v = yacc[i][j][q] + bp[col0 + q] + P::val(xr[q]);
-          if (orelu) v = fmaxf(v, 0.f);
+          float v = hacc[i][j][q] + bq[q];
+          if (erelu) v = fmaxf(v, 0.f);
           e[q] = to_storage<P>(v, 0, nullptr);
         }
-        store_run<4 * sizeof(T)>(xr, e);
+        store_run<4 * sizeof(T)>(hs + ((wm * MPW + i) * 16 + (lane & 15)) * RG::SHR + hc0, e);
       }
-    __syncthreads();
+    }
+    lds_barrier();
+    // projection: this wave's NPP output tiles += the chunk x its rows of P
+    mma_stream<P, KGP, NTP, NPP, MPW>(yacc, aph, Wp, wn * NPP, lane);
+    lds_barrier();
+    if (ch == NCH - 1) {
+      // bias, the block input (as stored) and the activation replace the tile
+#pragma unroll
+      for (int j = 0; j < NPP; ++j) {
+        const int col0 = (wn * NPP + j) * 16 + q4;
+        const float bq[4] = {bpv[j].x, bpv[j].y, bpv[j].z, bpv[j].w};
+#pragma unroll
+        for (int i = 0; i < MPW; ++i) {
+          T* xr = xs + ((wm * MPW + i) * 16 + (lane & 15)) * RG::SXR + col0;
+          T e[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float v = yacc[i][j][q] + bq[q] + P::val(xr[q]);
+            if (orelu) v = fmaxf(v, 0.f);
+            e[q] = to_storage<P>(v, 0, nullptr);
+          }
+          store_run<4 * sizeof(T)>(xr, e);
+          yacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+        }
+      }
+      lds_barrier();
+    }
   }
   for (int i = tid; i < TM * CV; i += RG::NT) {
     const int r = i / CV, v = i % CV;
