@@ -72,7 +72,11 @@ typedef enum { SIM_FEAT_F32 = 0, SIM_FEAT_CODE32 = 1 } sim_feat_dtype;
 /* One predictor layer.  kind 0: 1-D convolution over instructions, kernel 2,
  * stride 2, no padding, output length floor(L/2) (Sec. 2.3: non-overlapping
  * kernel-2 convolutions; odd lengths drop the unpaired last slot);
- * kind 1: fully connected on the channel-major flattening (index c*L + p).
+ * kind 1: fully connected on the channel-major flattening (index c*L + p);
+ * kind 2: pointwise (kernel 1) convolution, the length unchanged;
+ * kind 3: pointwise convolution plus the input of the preceding kind-2
+ * layer, added before the ReLU (a residual block, Sec. 2.3, is a kind-2
+ * expansion followed by a kind-3 projection back to its input width).
  * relu != 0 applies ReLU after the layer. */
 typedef struct {
   int32_t kind, c_in, c_out, relu;
@@ -151,8 +155,9 @@ SIMNET_API int sim_validate_config(const sim_config* cfg, const sim_trace* trace
 SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx** out);
 
 /* Load predictor parameters.  params is the concatenation, layer by layer,
- * of weight then bias in PyTorch layouts (conv [c_out][c_in][2], fc
- * [out][in]), float32, on the device if on_device != 0 else on the host.
+ * of weight then bias in PyTorch layouts (conv [c_out][c_in][2], pointwise
+ * conv [c_out][c_in][1], fc [out][in]), float32, on the device if
+ * on_device != 0 else on the host.
  * The parameters are copied (and re-laid-out for the kernels), so the
  * caller may free them afterwards.  The layer list must map the window
  * [n_slot][n_feat] to n_out outputs (regression head: each output, rounded,
@@ -160,9 +165,14 @@ SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx**
  * head of Sec. 2.3, per latency type 10 class scores (latencies 0..8 and
  * "larger than 8") then one direct output; the latency is the most probable
  * class (the first of equal scores), or the rounded direct output when the
- * "larger" class wins (FP32 and BF16 forms).  SIM_EUNSUPPORTED if no kernel
- * exists for the shape, SIM_ENONFINITE on NaN/Inf.  Resets the simulation
- * state. */
+ * "larger" class wins (FP32 and BF16 forms).  RB7 (the model table's
+ * residual network, FP32 and BF16 forms): the three C3 convolutions, seven
+ * residual blocks (kind 2: 256 -> 1920 with ReLU, kind 3: 1920 -> 256 with
+ * ReLU), fc 3328 -> 512 (ReLU), fc 512 -> 22 (the hybrid head); its steps
+ * run as four launches each (sim_step stays asynchronous; sim_run checks
+ * progress between batches of steps, and with a graph requested still runs
+ * them eagerly).  SIM_EUNSUPPORTED if no kernel exists for the shape,
+ * SIM_ENONFINITE on NaN/Inf.  Resets the simulation state. */
 SIMNET_API int sim_load_weights(sim_ctx* ctx, const sim_layer* layers, int32_t n_layers,
                      const float* params, int32_t on_device);
 
@@ -241,7 +251,9 @@ SIMNET_API int sim_act_scales(const sim_ctx* ctx, float* out, int32_t n);
 
 /* Predictor forward on explicit windows (Sec. 2.3): x is DEVICE
  * [B][n_slot][n_feat] float32, logits DEVICE [B][network outputs] float32
- * (n_out = 2 for the regression head, 22 for the hybrid head).  save_or_null must be NULL except for the
+ * (n_out = 2 for the regression head, 22 for the hybrid head and RB7).
+ * RB7 uses a workspace of B * 13 * 256 elements of the form, kept by the
+ * context and grown as needed.  save_or_null must be NULL except for the
  * training head, where it is required.
  *
  * Training head (Sec. 2.3's hybrid output, Sec. 4's training set-up): a
