@@ -58,8 +58,8 @@ PREC = {"f32": 0, "bf16": 1, "fp8": 2}
 # rocprofv3 passes (FETCH_SIZE, WRITE_SIZE) scaled by the same counters over a
 # 1 GiB copy.  They hold for the kernel source they were measured on only:
 # reported while csrc/kernels.hip hashes to KERNEL_SHA, else null.
-KERNEL_SHA = "9e4b3f0a4554fa19"
-TRAFFIC = {"c3_1m": {"bf16": 30_896_644_260, "f32": 51_526_236_908, "fp8": 44_089_748_610}}
+KERNEL_SHA = "1d8d005f7711b491"
+TRAFFIC = {"c3_1m": {"bf16": 30_872_539_422, "f32": 54_363_036_828, "fp8": 44_100_724_422}}
 
 
 def measured_traffic(workload, form):
@@ -70,6 +70,48 @@ def measured_traffic(workload, form):
     if sha != KERNEL_SHA:
         return None
     return TRAFFIC.get(workload, {}).get(form)
+
+
+def measure_peaks():
+    """Project-written probes on this GPU: MFMA issue rate of the three
+    matrix instructions the kernels use, HBM read and copy bandwidth."""
+    import ctypes as C
+    import torch
+    lib = C.CDLL(os.path.join(ROOT, "paper_2105_05821_amd", "libsimnet_peaks.so"))
+    stream = torch.cuda.current_stream().cuda_stream
+    seed = torch.randint(1, 2 ** 30, (64,), dtype=torch.int32, device="cuda")
+    blocks = 2048  # 8 workgroups of 4 waves per CU
+    out = torch.empty(blocks * 256, dtype=torch.float32, device="cuda")
+    res = {}
+    for prec, name, n_iter, flop in [(0, "f32", 10000, 2048), (1, "bf16", 20000, 16384),
+                                     (2, "fp8", 20000, 16384)]:
+        best = None
+        for _ in range(4):  # the first launch warms up
+            ms = C.c_float(0.0)
+            rc = lib.peaks_mfma(prec, blocks, n_iter, C.c_void_p(seed.data_ptr()),
+                                C.c_void_p(out.data_ptr()), C.c_void_p(stream), C.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"peaks_mfma rc {rc}")
+            best = ms.value if best is None else min(best, ms.value)
+        tflops = blocks * 4 * n_iter * 8 * flop / (best / 1e3) / 1e12
+        res[f"mfma_{name}"] = {"tflops": round(tflops, 1), "published": PEAK[name],
+                               "ratio": round(tflops / PEAK[name], 3)}
+    nbytes = 1 << 31
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for mode, name, moved in [(0, "read", nbytes), (1, "copy", 2 * nbytes)]:
+        best = None
+        for _ in range(4):
+            ms = C.c_float(0.0)
+            rc = lib.peaks_hbm(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                               C.c_int64(nbytes), mode, 256 * 16, C.c_void_p(stream), C.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"peaks_hbm rc {rc}")
+            best = ms.value if best is None else min(best, ms.value)
+        gbs = moved / (best / 1e3) / 1e9
+        res[f"hbm_{name}"] = {"gb_s": round(gbs, 1), "published": 8000.0,
+                              "ratio": round(gbs / 8000.0, 3)}
+    return res
 
 
 def log(msg):
@@ -239,10 +281,17 @@ def main():
     ap.add_argument("--prec", default=None, choices=sorted(PREC),
                     help="run one form only (c3_1m default: all three)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--peaks", action="store_true",
+                    help="only measure this GPU's MFMA and HBM peaks with the project's probes")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES, 3 times (the "
                          "reference kernel that scales HBM byte counters)")
     args = ap.parse_args()
+    if args.peaks:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"peaks": measure_peaks()}), flush=True)
+        return
     if args.copy_probe:
         import torch
         n = args.copy_probe // 4

@@ -1,4 +1,5 @@
-"""Build libsimnet.so in-tree with hipcc for gfx950."""
+"""Build libsimnet.so (and the peak probes, libsimnet_peaks.so) in-tree
+with hipcc for gfx950."""
 from __future__ import annotations
 
 import os
@@ -9,6 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsimnet.so")
 SOURCES = ["kernels.hip", "train.hip", "abi.hip"]
+PEAKS_LIB = os.path.join(HERE, "libsimnet_peaks.so")
+PEAKS_SOURCES = ["peaks.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -20,8 +23,14 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+    _build(LIB, SOURCES, verbose)
+    _build(PEAKS_LIB, PEAKS_SOURCES, verbose)
+    return LIB
+
+
+def _build(lib: str, sources, verbose: bool) -> None:
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = lib + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
@@ -32,8 +41,7 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + msgs)
     if verbose and msgs.strip():
         print(msgs, file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
 
 
 if __name__ == "__main__":

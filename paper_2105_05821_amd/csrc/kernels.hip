@@ -270,6 +270,10 @@ constexpr int conv_wave_split(int ntiles, int mtiles, int waves) {
 // MPW x NPW tiles.
 // SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
 // s < sv_rows only), the layer's activations kept for the backward pass.
+// Rows are numbered position-major, row = q * MT + s: an MFMA tile's 16
+// rows are 16 windows at one position, whose window strides spread them
+// over the LDS banks (the position stride of a wide level is a multiple of
+// the bank count, so window-major tiles would collide).
 template <class P, int K, int N, int POS, int WAVES, int SA, int IRS, int SO, bool OPAIR,
           bool CAL = false, bool SAVE = false>
 __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
@@ -296,7 +300,7 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
     const int row = (wm * MPW + i) * 16 + (lane & 15);
-    ap[i] = A + (row / POS) * SA + (row % POS) * IRS + (P::KG / 4) * (lane >> 4);
+    ap[i] = A + (row % MT) * SA + (row / MT) * IRS + (P::KG / 4) * (lane >> 4);
   }
   v4f acc[MPW][NPW];
 #pragma unroll
@@ -308,9 +312,9 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
   for (int i = 0; i < MPW; ++i) {
     const int row = (wm * MPW + i) * 16 + (lane & 15);
     constexpr int ORS = 2 * N + 16 / (int)sizeof(T);
-    const int q = row % POS;
-    T* orow = O + (row / POS) * SO + (OPAIR ? (q >> 1) * ORS + (q & 1) * N : q * N);
-    const bool live = !CAL || row_live[row / POS];
+    const int q = row / MT, s = row % MT;
+    T* orow = O + s * SO + (OPAIR ? (q >> 1) * ORS + (q & 1) * N : q * N);
+    const bool live = !CAL || row_live[s];
 #pragma unroll
     for (int j = 0; j < NPW; ++j) {
       const int col0 = (nt0 + j) * 16 + 4 * (lane >> 4);
@@ -324,8 +328,7 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
       }
       store_run<4 * sizeof(T)>(orow + col0, e);
       if constexpr (SAVE)
-        if (row / POS < sv_rows)
-          store_run<4 * sizeof(T)>(sv + (row / POS) * sv_s + (row % POS) * N + col0, e);
+        if (s < sv_rows) store_run<4 * sizeof(T)>(sv + s * sv_s + q * N + col0, e);
     }
   }
 }
