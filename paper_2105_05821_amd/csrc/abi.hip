@@ -210,18 +210,23 @@ float round_to(int prec, float v) {
   return prec == 0 ? v : prec == 1 ? bf16_value(bf16_bits(v)) : e4m3_value(e4m3_bits(v));
 }
 
-// B[k][n] packed per (k-group of KG, n-tile of 16) as 64 lanes x 16 bytes:
-// lane holds B[kg*KG + (KG/4)*(lane/16) + e][nt*16 + lane%16], e < KG/4.
+// B[k][n] packed per (k-group of KG, n-tile of TILE) as 64 lanes x 16
+// bytes: lane holds B[kg*KG + E*(lane/TILE) + e][nt*TILE + lane%TILE],
+// e < E = KG*TILE/64 (16x16 tiles: KG/4 k per lane; 32x32 tiles: KG/2).
 template <class F>
-void pack_b(int prec, int K, int N, F&& B, uint8_t* out) {
-  const int KG = kgroup(prec), KGS = K / KG, NTL = N / 16, E = KG / 4;
+void pack_b_tile(int prec, int K, int N, int KG, int TILE, F&& B, uint8_t* out) {
+  const int KGS = K / KG, NTL = N / TILE, E = KG * TILE / 64;
   const size_t es = elem_size(prec);
   for (int kg = 0; kg < KGS; ++kg)
     for (int nt = 0; nt < NTL; ++nt)
       for (int lane = 0; lane < 64; ++lane)
         for (int e = 0; e < E; ++e)
-          store_elem(prec, B(kg * KG + E * (lane / 16) + e, nt * 16 + lane % 16),
+          store_elem(prec, B(kg * KG + E * (lane / TILE) + e, nt * TILE + lane % TILE),
                      out + ((((size_t)kg * NTL + nt) * 64 + lane) * E + e) * es);
+}
+template <class F>
+void pack_b(int prec, int K, int N, F&& B, uint8_t* out) {
+  pack_b_tile(prec, K, N, kgroup(prec), 16, B, out);
 }
 
 struct Expect {
@@ -333,7 +338,7 @@ std::vector<uint8_t> relayout(int prec, const float* params,
   if (Net::NRES > 0) {
     // residual blocks (no FP8 form): per block the expansion B[c][e] =
     // E[e][c] (PyTorch [EXPAND][CH3][1]) then the projection B[e][c] =
-    // P[c][e] ([CH3][EXPAND][1]), packed like a conv level
+    // P[c][e] ([CH3][EXPAND][1]), packed for the form's residual MFMA
     const int C3 = Net::CH3, E = Net::EXPAND;
     const size_t half = (size_t)C3 * E * es;
     L->res_stride = (2 * half + 255) / 256 * 256;
@@ -343,8 +348,12 @@ std::vector<uint8_t> relayout(int prec, const float* params,
       const float* We = w[Net::NCONV + 2 * i];
       const float* Wp = w[Net::NCONV + 2 * i + 1];
       uint8_t* dst = out.data() + L->res_w + L->res_stride * i;
-      pack_b(prec, C3, E, [&](int k, int n) { return We[(size_t)n * C3 + k]; }, dst);
-      pack_b(prec, E, C3, [&](int k, int n) { return Wp[(size_t)n * E + k]; }, dst + half);
+      // BF16 on 32x32x16 tiles (k-groups of 16), FP32 on 16x16 ones
+      const int KG = prec == 1 ? 16 : kgroup(prec), TILE = prec == 1 ? 32 : 16;
+      pack_b_tile(prec, C3, E, KG, TILE, [&](int k, int n) { return We[(size_t)n * C3 + k]; },
+                  dst);
+      pack_b_tile(prec, E, C3, KG, TILE, [&](int k, int n) { return Wp[(size_t)n * E + k]; },
+                  dst + half);
       rb.insert(rb.end(), b[Net::NCONV + 2 * i], b[Net::NCONV + 2 * i] + E);
       rb.insert(rb.end(), b[Net::NCONV + 2 * i + 1], b[Net::NCONV + 2 * i + 1] + C3);
     }

@@ -29,6 +29,7 @@ namespace simnet {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 // ------------------------------------------------------ precision forms ---
 // Each form stores activations and weights as T and multiplies one 16-byte
@@ -36,9 +37,15 @@ typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 // consecutive k of its row (A) or column (B); A and B use the same
 // assignment, so every call adds the full KG-long partial dot products.
 
+// Acc: the accumulator of one MFMA tile; TILE: its side; col4(g, lane):
+// the first of the 4 consecutive output columns (weight-first operand
+// order: the weights' N) that accumulator elements 4g .. 4g+3 of the lane
+// hold, for the activation row lane % TILE.
 struct PF32 {
   using T = float;
-  static constexpr int ID = 0, KG = 16;
+  using Acc = v4f;
+  static constexpr int ID = 0, KG = 16, TILE = 16;
+  __device__ static int col4(int, int lane) { return 4 * (lane >> 4); }
   static constexpr bool SCALED = false;
   __device__ static v4f mma(v4f c, uint4 a, uint4 b) {
     c = __builtin_amdgcn_mfma_f32_16x16x4f32(__uint_as_float(a.x), __uint_as_float(b.x), c, 0, 0, 0);
@@ -53,7 +60,9 @@ struct PF32 {
 
 struct PBF16 {
   using T = uint16_t;  // bfloat16 bits
-  static constexpr int ID = 1, KG = 32;
+  using Acc = v4f;
+  static constexpr int ID = 1, KG = 32, TILE = 16;
+  __device__ static int col4(int, int lane) { return 4 * (lane >> 4); }
   static constexpr bool SCALED = false;
   __device__ static v4f mma(v4f c, uint4 a, uint4 b) {
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a),
@@ -69,7 +78,9 @@ struct PBF16 {
 
 struct PFP8 {
   using T = uint8_t;  // OCP e4m3 (max 448)
-  static constexpr int ID = 2, KG = 64;
+  using Acc = v4f;
+  static constexpr int ID = 2, KG = 64, TILE = 16;
+  __device__ static int col4(int, int lane) { return 4 * (lane >> 4); }
   static constexpr bool SCALED = true;
   __device__ static v4f mma(v4f c, uint4 a, uint4 b) {
     const long a0 = ((long)a.y << 32) | a.x, a1 = ((long)a.w << 32) | a.z;
@@ -84,6 +95,21 @@ struct PFP8 {
     return (T)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.f, 0, false) & 0xff);
   }
   __device__ static float val(T x) { return __builtin_amdgcn_cvt_f32_fp8((int)x, 0); }
+};
+
+// BF16 on 32x32x16 tiles: the same storage, twice the FLOP per MFMA
+// (32,768).  Lane l holds 8 consecutive k (8 * (l / 32) ..) of row l % 32 of
+// either operand; the 16 accumulators of lane l are output columns
+// 8 * (i / 4) + 4 * (l / 32) + i % 4 of row l % 32.  On gfx950 this
+// instruction issues back to back where the 16x16x32 one leaves gaps.
+struct PBF16W : PBF16 {
+  using Acc = v16f;
+  static constexpr int KG = 16, TILE = 32;
+  __device__ static int col4(int g, int lane) { return 8 * g + 4 * (lane >> 5); }
+  __device__ static v16f mma(v16f c, uint4 a, uint4 b) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(v8bf, a),
+                                                   __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+  }
 };
 
 // Blocks per group: the window is processed a group of NG consecutive
@@ -191,7 +217,7 @@ __device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_of
 // chunk ahead of their use (double buffering) and the scheduler is kept
 // from sinking the requests.
 template <class P, int KGS, int NTILES, int NPW, int MPW, int FRAGS = 8>
-__device__ __forceinline__ void mma_stream(v4f (&acc)[MPW][NPW],
+__device__ __forceinline__ void mma_stream(typename P::Acc (&acc)[MPW][NPW],
                                            const typename P::T* const (&ap)[MPW],
                                            const uint4* __restrict__ Bp, int nt0, int lane) {
   constexpr int CH = stream_chunk(KGS, NPW, FRAGS), NCH = KGS / CH;
@@ -1167,15 +1193,31 @@ __device__ __forceinline__ void lds_barrier() {
 // LDS) and consumed at once by the projection, whose TM x CH3 accumulators
 // stay in registers for the whole block; then bias, the block input and the
 // ReLU, rounded to the form, replace the tile.
+// The matrix instruction of a form in the residual blocks: BF16 on
+// 32x32x16 tiles, FP32 on 16x16x4.
+template <class P>
+struct ResMma {
+  using M = P;
+};
+template <>
+struct ResMma<PBF16> {
+  using M = PBF16W;
+};
+
 template <class P>
 struct ResGeo {
   using T = typename P::T;
+  using M = typename ResMma<P>::M;
   static constexpr int C = NetRB7::CH3, E = NetRB7::EXPAND, EC = 128;
-  static constexpr int TM = P::ID == 0 ? 64 : 128, MTL = TM / 16;
+  static constexpr int TM = P::ID == 0 ? 64 : 128, TILE = M::TILE, MTL = TM / TILE;
   static constexpr int PAD = 16 / sizeof(T);
   static constexpr int SXR = C + PAD, SHR = EC + PAD;  // padded LDS rows
-  static constexpr int WAVES = 8, NT = WAVES * 64;
-  static_assert(E % EC == 0, "chunks");
+  // waves 4 along N x 2 along M in both products
+  static constexpr int WAVES = 8, NT = WAVES * 64, WNW = 4, WMW = WAVES / WNW;
+  static constexpr int MPW = MTL / WMW, NPE = EC / TILE / WNW, NPP = C / TILE / WNW;
+  static_assert(E % EC == 0 && MTL % WMW == 0 && NPE * WNW * TILE == EC &&
+                    NPP * WNW * TILE == C,
+                "wave split");
 };
 
 template <class P>
@@ -1183,10 +1225,15 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
     resblock_kernel(DevWeights wt, uint32_t relu_mask, typename P::T* __restrict__ x, int64_t rows,
                     const int32_t* __restrict__ active) {
   using RG = ResGeo<P>;
+  using M = typename RG::M;
   using T = typename P::T;
+  using Acc = typename M::Acc;
   using Net = NetRB7;
-  constexpr int C = RG::C, E = RG::E, EC = RG::EC, TM = RG::TM, MTL = RG::MTL;
+  constexpr int C = RG::C, E = RG::E, EC = RG::EC, TM = RG::TM, TILE = RG::TILE;
+  constexpr int MPW = RG::MPW, NPE = RG::NPE, NPP = RG::NPP;
+  constexpr int NG4 = TILE * TILE / 256;  // 4-column groups per lane and tile
   constexpr int CV = C * (int)sizeof(T) / 16, EPV = 16 / (int)sizeof(T);
+  constexpr int KGE = C / M::KG, KGP = EC / M::KG, NCH = E / EC, NTE = E / TILE, NTP = C / TILE;
   __shared__ alignas(16) T xs[TM * RG::SXR];
   __shared__ alignas(16) T hs[TM * RG::SHR];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -1204,29 +1251,24 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
     *reinterpret_cast<uint4*>(xs + r * RG::SXR + v * EPV) = val;
   }
   __syncthreads();
-  // waves: 4 along N x 2 along M in both products; a wave's A fragments
-  // (LDS) serve its 2 (expansion) or 4 (projection) N tiles, its weight
-  // fragments its MTL/2 M tiles
-  constexpr int WNW = 4, WMW = RG::WAVES / WNW, MPW = MTL / WMW;
-  constexpr int NPE = EC / 16 / WNW, NPP = C / 16 / WNW;
-  constexpr int KGE = C / P::KG, KGP = EC / P::KG, NCH = E / EC, NTE = E / 16, NTP = C / 16;
-  static_assert(MTL % WMW == 0 && NPE * WNW * 16 == EC && NPP * WNW * 16 == C, "wave split");
-  const int wn = wave % WNW, wm = wave / WNW;
+  // a wave's A fragments (LDS) serve its NPE or NPP N tiles, its weight
+  // fragments its MPW M tiles
+  const int wn = wave % RG::WNW, wm = wave / RG::WNW;
+  const int row = lane % TILE, ko = (lane / TILE) * (M::KG * TILE / 64);
   const T* apx[MPW];
   const T* aph[MPW];
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
-    const int r = (wm * MPW + i) * 16 + (lane & 15);
-    apx[i] = xs + r * RG::SXR + (P::KG / 4) * (lane >> 4);
-    aph[i] = hs + r * RG::SHR + (P::KG / 4) * (lane >> 4);
+    const int r = (wm * MPW + i) * TILE + row;
+    apx[i] = xs + r * RG::SXR + ko;
+    aph[i] = hs + r * RG::SHR + ko;
   }
-  const int q4 = 4 * (lane >> 4);
   const size_t half = (size_t)C * E * sizeof(T);
-  v4f yacc[MPW][NPP];
+  Acc yacc[MPW][NPP];
 #pragma unroll
   for (int i = 0; i < MPW; ++i)
 #pragma unroll
-    for (int j = 0; j < NPP; ++j) yacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < NPP; ++j) yacc[i][j] = Acc{};
   for (int t = 0; t < Net::NRES * NCH; ++t) {
     const int blk = t / NCH, ch = t % NCH;
     const char* wb = static_cast<const char*>(wt.res_w) + (size_t)blk * wt.res_stride;
@@ -1236,61 +1278,76 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
     const float* bp = be + E;
     const bool erelu = relu_mask & (1u << (Net::NCONV + 2 * blk));
     const bool orelu = relu_mask & (1u << (Net::NCONV + 2 * blk + 1));
-    float4 bev[NPE], bpv[NPP];
+    // biases first: loads complete in order, so a bias requested after the
+    // weight stream would make the epilogue wait for all of it
+    float4 bev[NPE][NG4], bpv[NPP][NG4];
 #pragma unroll
     for (int j = 0; j < NPE; ++j)
-      bev[j] = *reinterpret_cast<const float4*>(be + ch * EC + (wn * NPE + j) * 16 + q4);
+#pragma unroll
+      for (int g = 0; g < NG4; ++g)
+        bev[j][g] = *reinterpret_cast<const float4*>(be + ch * EC + (wn * NPE + j) * TILE +
+                                                     M::col4(g, lane));
     if (ch == NCH - 1)
 #pragma unroll
       for (int j = 0; j < NPP; ++j)
-        bpv[j] = *reinterpret_cast<const float4*>(bp + (wn * NPP + j) * 16 + q4);
-    // expansion: this wave's NPE 16-channel tiles of the chunk x its rows
-    v4f hacc[MPW][NPE];
+#pragma unroll
+        for (int g = 0; g < NG4; ++g)
+          bpv[j][g] = *reinterpret_cast<const float4*>(bp + (wn * NPP + j) * TILE +
+                                                       M::col4(g, lane));
+    // expansion: the wave's MPW x NPE tiles of the chunk, K = C
+    Acc hacc[MPW][NPE];
 #pragma unroll
     for (int i = 0; i < MPW; ++i)
 #pragma unroll
-      for (int j = 0; j < NPE; ++j) hacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-    mma_stream<P, KGE, NTE, NPE, MPW>(hacc, apx, We, ch * (EC / 16) + wn * NPE, lane);
+      for (int j = 0; j < NPE; ++j) hacc[i][j] = Acc{};
+    mma_stream<M, KGE, NTE, NPE, MPW>(hacc, apx, We, ch * (EC / TILE) + wn * NPE, lane);
 #pragma unroll
-    for (int j = 0; j < NPE; ++j) {
-      const int hc0 = (wn * NPE + j) * 16 + q4;  // 4 channels of the chunk
-      const float bq[4] = {bev[j].x, bev[j].y, bev[j].z, bev[j].w};
+    for (int j = 0; j < NPE; ++j)
 #pragma unroll
-      for (int i = 0; i < MPW; ++i) {
-        T e[4];
+      for (int g = 0; g < NG4; ++g) {
+        const int hc0 = (wn * NPE + j) * TILE + M::col4(g, lane);  // 4 channels of the chunk
+        const float bq[4] = {bev[j][g].x, bev[j][g].y, bev[j][g].z, bev[j][g].w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float v = hacc[i][j][q] + bq[q];
-          if (erelu) v = fmaxf(v, 0.f);
-          e[q] = to_storage<P>(v, 0, nullptr);
+        for (int i = 0; i < MPW; ++i) {
+          T e[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float v = hacc[i][j][4 * g + q] + bq[q];
+            if (erelu) v = fmaxf(v, 0.f);
+            e[q] = to_storage<P>(v, 0, nullptr);
+          }
+          store_run<4 * sizeof(T)>(hs + ((wm * MPW + i) * TILE + row) * RG::SHR + hc0, e);
         }
-        store_run<4 * sizeof(T)>(hs + ((wm * MPW + i) * 16 + (lane & 15)) * RG::SHR + hc0, e);
       }
-    }
     lds_barrier();
-    // projection: this wave's NPP output tiles += the chunk x its rows of P
-    mma_stream<P, KGP, NTP, NPP, MPW>(yacc, aph, Wp, wn * NPP, lane);
+    // projection: the wave's MPW x NPP output tiles += the chunk x its rows of P
+    mma_stream<M, KGP, NTP, NPP, MPW>(yacc, aph, Wp, wn * NPP, lane);
     lds_barrier();
     if (ch == NCH - 1) {
       // bias, the block input (as stored) and the activation replace the tile
 #pragma unroll
-      for (int j = 0; j < NPP; ++j) {
-        const int col0 = (wn * NPP + j) * 16 + q4;
-        const float bq[4] = {bpv[j].x, bpv[j].y, bpv[j].z, bpv[j].w};
+      for (int j = 0; j < NPP; ++j)
 #pragma unroll
-        for (int i = 0; i < MPW; ++i) {
-          T* xr = xs + ((wm * MPW + i) * 16 + (lane & 15)) * RG::SXR + col0;
-          T e[4];
+        for (int g = 0; g < NG4; ++g) {
+          const int col0 = (wn * NPP + j) * TILE + M::col4(g, lane);
+          const float bq[4] = {bpv[j][g].x, bpv[j][g].y, bpv[j][g].z, bpv[j][g].w};
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            float v = yacc[i][j][q] + bq[q] + P::val(xr[q]);
-            if (orelu) v = fmaxf(v, 0.f);
-            e[q] = to_storage<P>(v, 0, nullptr);
+          for (int i = 0; i < MPW; ++i) {
+            T* xr = xs + ((wm * MPW + i) * TILE + row) * RG::SXR + col0;
+            T e[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              float v = yacc[i][j][4 * g + q] + bq[q] + P::val(xr[q]);
+              if (orelu) v = fmaxf(v, 0.f);
+              e[q] = to_storage<P>(v, 0, nullptr);
+            }
+            store_run<4 * sizeof(T)>(xr, e);
           }
-          store_run<4 * sizeof(T)>(xr, e);
-          yacc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
         }
-      }
+#pragma unroll
+      for (int i = 0; i < MPW; ++i)
+#pragma unroll
+        for (int j = 0; j < NPP; ++j) yacc[i][j] = Acc{};
       lds_barrier();
     }
   }

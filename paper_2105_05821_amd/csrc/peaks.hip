@@ -7,12 +7,14 @@
 namespace {
 
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 constexpr int CHAINS = 8;  // independent accumulators per wave
 
 // prec 0: 16x16x4 FP32 (2,048 FLOP), 1: 16x16x32 BF16 (16,384), 2: 16x16x32
-// FP8 e4m3 (16,384).  Operands come from the input so nothing folds.
+// FP8 e4m3 (16,384), 3: 32x32x16 BF16 (32,768; 4 chains of 16 registers).
+// Operands come from the input so nothing folds.
 template <int PREC>
 __global__ void __launch_bounds__(256) mfma_probe(const uint32_t* __restrict__ seed, int n_iter,
                                                   float* __restrict__ out) {
@@ -32,6 +34,22 @@ __global__ void __launch_bounds__(256) mfma_probe(const uint32_t* __restrict__ s
 #pragma unroll
       for (int j = 0; j < CHAINS; ++j)
         acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, a, acc[j], 0, 0, 0);
+  } else if constexpr (PREC == 3) {
+    const uint4 u = make_uint4(s, s ^ 0x1234u, s + 7u, s * 3u);
+    const v8bf a = __builtin_bit_cast(v8bf, u);
+    v16f big[CHAINS / 2];
+#pragma unroll
+    for (int j = 0; j < CHAINS / 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) big[j][e] = 0.f;
+    for (int it = 0; it < n_iter; ++it)
+#pragma unroll
+      for (int j = 0; j < CHAINS / 2; ++j)
+        big[j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, a, big[j], 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < CHAINS / 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[j][e] = big[j][e] + big[j][e + 4] + big[j][e + 8] + big[j][e + 12];
   } else {
     const long a = (long)(((uint64_t)s << 32) | (s ^ 0x5555u));
     for (int it = 0; it < n_iter; ++it)
@@ -98,15 +116,15 @@ struct HbmArg {
 
 extern "C" {
 
-// Matrix-core probe: blocks x 256 threads, each wave n_iter x 8 dependent-free
-// MFMAs of the form prec (0 FP32, 1 BF16, 2 FP8).  seed: DEVICE >= 64
-// uint32; out: DEVICE >= blocks * 256 floats.  *ms = kernel time; FLOP =
-// blocks * 4 * n_iter * 8 * (2,048 for FP32, else 16,384).  0 or -1 (bad
-// arguments) / -3 (device error).
+// Matrix-core probe: blocks x 256 threads, each wave n_iter x 8 independent
+// MFMAs of the form prec (0 FP32, 1 BF16, 2 FP8; 3: n_iter x 4 of the
+// 32x32x16 BF16 one).  seed: DEVICE >= 64 uint32; out: DEVICE >= blocks *
+// 256 floats.  *ms = kernel time; FLOP = blocks * 4 * n_iter * 8 * (2,048
+// for FP32, else 16,384).  0 or -1 (bad arguments) / -3 (device error).
 __attribute__((visibility("default"))) int peaks_mfma(int prec, int blocks, int n_iter,
                                                       const uint32_t* seed, float* out,
                                                       void* stream, float* ms) {
-  if (prec < 0 || prec > 2 || blocks < 1 || n_iter < 1 || !seed || !out || !ms) return -1;
+  if (prec < 0 || prec > 3 || blocks < 1 || n_iter < 1 || !seed || !out || !ms) return -1;
   MfmaArg a{prec, blocks, n_iter, seed, out};
   return timed(static_cast<hipStream_t>(stream), ms,
                [](hipStream_t st, void* p) {
@@ -116,6 +134,9 @@ __attribute__((visibility("default"))) int peaks_mfma(int prec, int blocks, int 
                                       m.n_iter, m.out);
                  else if (m.prec == 1)
                    hipLaunchKernelGGL(mfma_probe<1>, dim3(m.blocks), dim3(256), 0, st, m.seed,
+                                      m.n_iter, m.out);
+                 else if (m.prec == 3)
+                   hipLaunchKernelGGL(mfma_probe<3>, dim3(m.blocks), dim3(256), 0, st, m.seed,
                                       m.n_iter, m.out);
                  else
                    hipLaunchKernelGGL(mfma_probe<2>, dim3(m.blocks), dim3(256), 0, st, m.seed,

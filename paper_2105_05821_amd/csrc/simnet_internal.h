@@ -104,7 +104,8 @@ struct DevWeights {
   const void* last_p;  // hybrid head: the final FC packed like a hidden matrix
   // residual blocks (RB7): block i's expansion B[c][e] = E[e][c] (K = CH3,
   // N = EXPAND) then its projection B[e][c] = P[c][e] (K = EXPAND, N = CH3),
-  // both packed like a conv level, at res_w + i * res_stride bytes; biases
+  // both packed for the form's residual MFMA tiles (BF16 32x32x16 with k-groups
+  // of 16, FP32 16x16), at res_w + i * res_stride bytes; biases
   // res_b + i * (EXPAND + CH3): expansion's, then projection's
   const void* res_w;
   int64_t res_stride;
