@@ -1189,10 +1189,12 @@ __device__ __forceinline__ void lds_barrier() {
 
 // A tile of TM rows (window positions at the last conv level, CH3 channels
 // each) stays in LDS through all NRES blocks.  Per block the expansion is
-// produced EC channels at a time (bias, ReLU, rounded to the form, into
-// LDS) and consumed at once by the projection, whose TM x CH3 accumulators
-// stay in registers for the whole block; then bias, the block input and the
-// ReLU, rounded to the form, replace the tile.
+// produced EC channels at a time (bias, ReLU, rounded to the form, into one
+// of two LDS buffers) and consumed by the projection in the next phase,
+// while the following chunk is expanded; the projection's TM x CH3
+// accumulators stay in registers for the whole block; then bias, the block
+// input and the ReLU, rounded to the form, replace the tile.
+
 // The matrix instruction of a form in the residual blocks: BF16 on
 // 32x32x16 tiles, FP32 on 16x16x4.
 template <class P>
@@ -1235,7 +1237,7 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
   constexpr int CV = C * (int)sizeof(T) / 16, EPV = 16 / (int)sizeof(T);
   constexpr int KGE = C / M::KG, KGP = EC / M::KG, NCH = E / EC, NTE = E / TILE, NTP = C / TILE;
   __shared__ alignas(16) T xs[TM * RG::SXR];
-  __shared__ alignas(16) T hs[TM * RG::SHR];
+  __shared__ alignas(16) T hs[2 * TM * RG::SHR];  // two expansion chunks
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int64_t r0 = (int64_t)blockIdx.x * TM;
   const int64_t r1 = r0 + TM < rows ? r0 + TM : rows;  // rows [r0, r1) exist
@@ -1269,38 +1271,27 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
   for (int i = 0; i < MPW; ++i)
 #pragma unroll
     for (int j = 0; j < NPP; ++j) yacc[i][j] = Acc{};
-  for (int t = 0; t < Net::NRES * NCH; ++t) {
-    const int blk = t / NCH, ch = t % NCH;
-    const char* wb = static_cast<const char*>(wt.res_w) + (size_t)blk * wt.res_stride;
-    const uint4* We = reinterpret_cast<const uint4*>(wb);
-    const uint4* Wp = reinterpret_cast<const uint4*>(wb + half) + (size_t)ch * KGP * NTP * 64;
+  // Expansion of chunk u into hs buffer u & 1: bias, ReLU, rounded to the form.
+  auto expand = [&](int u) {
+    const int blk = u / NCH, ch = u % NCH;
+    const uint4* We = reinterpret_cast<const uint4*>(static_cast<const char*>(wt.res_w) +
+                                                     (size_t)blk * wt.res_stride);
     const float* be = wt.res_b + (size_t)blk * (E + C);
-    const float* bp = be + E;
     const bool erelu = relu_mask & (1u << (Net::NCONV + 2 * blk));
-    const bool orelu = relu_mask & (1u << (Net::NCONV + 2 * blk + 1));
-    // biases first: loads complete in order, so a bias requested after the
-    // weight stream would make the epilogue wait for all of it
-    float4 bev[NPE][NG4], bpv[NPP][NG4];
+    float4 bev[NPE][NG4];  // requested before the weights (loads complete in order)
 #pragma unroll
     for (int j = 0; j < NPE; ++j)
 #pragma unroll
       for (int g = 0; g < NG4; ++g)
         bev[j][g] = *reinterpret_cast<const float4*>(be + ch * EC + (wn * NPE + j) * TILE +
                                                      M::col4(g, lane));
-    if (ch == NCH - 1)
-#pragma unroll
-      for (int j = 0; j < NPP; ++j)
-#pragma unroll
-        for (int g = 0; g < NG4; ++g)
-          bpv[j][g] = *reinterpret_cast<const float4*>(bp + (wn * NPP + j) * TILE +
-                                                       M::col4(g, lane));
-    // expansion: the wave's MPW x NPE tiles of the chunk, K = C
     Acc hacc[MPW][NPE];
 #pragma unroll
     for (int i = 0; i < MPW; ++i)
 #pragma unroll
       for (int j = 0; j < NPE; ++j) hacc[i][j] = Acc{};
     mma_stream<M, KGE, NTE, NPE, MPW>(hacc, apx, We, ch * (EC / TILE) + wn * NPE, lane);
+    T* hb = hs + (u & 1) * TM * RG::SHR;
 #pragma unroll
     for (int j = 0; j < NPE; ++j)
 #pragma unroll
@@ -1316,15 +1307,47 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
             if (erelu) v = fmaxf(v, 0.f);
             e[q] = to_storage<P>(v, 0, nullptr);
           }
-          store_run<4 * sizeof(T)>(hs + ((wm * MPW + i) * TILE + row) * RG::SHR + hc0, e);
+          store_run<4 * sizeof(T)>(hb + ((wm * MPW + i) * TILE + row) * RG::SHR + hc0, e);
         }
       }
-    lds_barrier();
-    // projection: the wave's MPW x NPP output tiles += the chunk x its rows of P
-    mma_stream<M, KGP, NTP, NPP, MPW>(yacc, aph, Wp, wn * NPP, lane);
+  };
+  // Projection of chunk u from hs buffer u & 1 into yacc.
+  auto project = [&](int u) {
+    const int blk = u / NCH, ch = u % NCH;
+    const uint4* Wp = reinterpret_cast<const uint4*>(static_cast<const char*>(wt.res_w) +
+                                                     (size_t)blk * wt.res_stride + half) +
+                      (size_t)ch * KGP * NTP * 64;
+    const int ho = (u & 1) * TM * RG::SHR;
+    const T* aphu[MPW];
+#pragma unroll
+    for (int i = 0; i < MPW; ++i) aphu[i] = aph[i] + ho;
+    mma_stream<M, KGP, NTP, NPP, MPW>(yacc, aphu, Wp, wn * NPP, lane);
+  };
+  // Chunk u+1's expansion and chunk u's projection share a phase (one
+  // barrier per chunk; the two products' chains interleave); a block's first
+  // expansion waits for the previous block's output.
+  constexpr int TT = Net::NRES * NCH;
+  expand(0);
+  lds_barrier();
+  for (int t = 0; t < TT; ++t) {
+    const int blk = t / NCH, ch = t % NCH;
+    float4 bpv[NPP][NG4];
+    if (ch == NCH - 1) {
+      const float* bp = wt.res_b + (size_t)blk * (E + C) + E;
+#pragma unroll
+      for (int j = 0; j < NPP; ++j)
+#pragma unroll
+        for (int g = 0; g < NG4; ++g)
+          bpv[j][g] = *reinterpret_cast<const float4*>(bp + (wn * NPP + j) * TILE +
+                                                       M::col4(g, lane));
+    } else {
+      expand(t + 1);
+    }
+    project(t);
     lds_barrier();
     if (ch == NCH - 1) {
       // bias, the block input (as stored) and the activation replace the tile
+      const bool orelu = relu_mask & (1u << (Net::NCONV + 2 * blk + 1));
 #pragma unroll
       for (int j = 0; j < NPP; ++j)
 #pragma unroll
@@ -1349,6 +1372,10 @@ __global__ void __launch_bounds__(ResGeo<P>::NT)
 #pragma unroll
         for (int j = 0; j < NPP; ++j) yacc[i][j] = Acc{};
       lds_barrier();
+      if (t + 1 < TT) {
+        expand(t + 1);
+        lds_barrier();
+      }
     }
   }
   for (int i = tid; i < TM * CV; i += RG::NT) {
