@@ -26,6 +26,16 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(L, name), name
 
 
+def test_peak_probe_library_loads():
+    """The measurement probes (bench.py --peaks) are a library of their own
+    with the two documented entry points; argument checks run on the host."""
+    import ctypes as C
+    L = C.CDLL(os.path.join(ROOT, "paper_2105_05821_amd", "libsimnet_peaks.so"))
+    ms = C.c_float(0.0)
+    assert L.peaks_mfma(7, 1, 1, None, None, None, C.byref(ms)) == -1  # bad form
+    assert L.peaks_hbm(None, None, C.c_int64(16), 0, 1, None, C.byref(ms)) == -1
+
+
 def good(n_sub=4, n_instr=1000, feat_ptr=0x1000):
     cfg = sn.make_config(50, 111, (47, 48, 49))
     s, l, w = sn.partition(n_instr, n_sub, 256)
