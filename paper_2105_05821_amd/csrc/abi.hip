@@ -39,6 +39,7 @@ struct sim_ctx {
   int32_t n_sub = 0;
   int64_t n_instr = 0;
   const float* feat = nullptr;
+  uint16_t* feat16 = nullptr;  // BF16 form: BF16 copy of feat (owned)
   int net = -1;  // 0 NetSmall, 1 NetC3, 2 C3 training head, 3 C3 hybrid inference head,
                  // 4 C3 with store latencies (memory write queue), 5 RB7 (staged step)
   int C = 0;
@@ -757,6 +758,20 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
     c->feat = static_cast<const float*>(tr->feat);
   c->mem = static_cast<const uint2*>(tr->mem);
   c->stream = static_cast<hipStream_t>(cfg->stream);
+  if (c->feat && cfg->prec == SIM_BF16) {
+    // the BF16 form gathers from a BF16 copy of the rows (the values its
+    // windows hold anyway), half the bytes per row
+    const size_t bytes = sizeof(uint16_t) * (size_t)tr->n_instr * staged_feat(cfg->n_feat);
+    hipError_t e = hipMalloc(&c->feat16, bytes);
+    if (e == hipSuccess)
+      e = launch_stage_bf16(c->feat, tr->n_instr, cfg->n_feat, c->feat16, c->stream);
+    if (e != hipSuccess) {
+      fprintf(stderr, "sim_init: %s\n", hipGetErrorString(e));
+      if (c->feat16) (void)hipFree(c->feat16);
+      delete c;
+      return SIM_ENOMEM;
+    }
+  }
 
   const int32_t K = tr->n_sub, C = c->C;
   std::vector<int64_t> first(K), npos(K), poff(K);
@@ -816,6 +831,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   hipError_t e = hipMalloc(&c->dev_block, off);
   if (e != hipSuccess) {
     fprintf(stderr, "sim_init: hipMalloc(%zu): %s\n", off, hipGetErrorString(e));
+    if (c->feat16) (void)hipFree(c->feat16);
     delete c;
     return e == hipErrorOutOfMemory ? SIM_ENOMEM : SIM_EDEVICE;
   }
@@ -868,6 +884,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
     if (x != hipSuccess) {
       fprintf(stderr, "sim_init: %s\n", hipGetErrorString(x));
       (void)hipFree(c->dev_block);
+      if (c->feat16) (void)hipFree(c->feat16);
       delete c;
       return SIM_EDEVICE;
     }
@@ -1053,6 +1070,7 @@ static StepParams step_params(const sim_ctx* c, int64_t n_steps, int32_t mode,
                               const int32_t* table) {
   StepParams p{};
   p.feat = c->feat;
+  p.feat16 = c->feat16;
   p.codes = c->codes;
   p.mem = c->mem;
   p.col_dep = c->cfg.col_dep;
@@ -1453,6 +1471,7 @@ void sim_destroy(sim_ctx* c) {
   if (c->rb_active) (void)hipFree(c->rb_active);
   if (c->rb_logits) (void)hipFree(c->rb_logits);
   if (c->rb_ws) (void)hipFree(c->rb_ws);
+  if (c->feat16) (void)hipFree(c->feat16);
   delete c;
 }
 

@@ -657,10 +657,10 @@ __device__ __forceinline__ void window_elems(const float (&v)[CPT], const float*
 }
 
 // Registers carrying one thread's share of one window row between load and
-// commit.
-template <int CPT>
+// commit: FP32 feature pairs, or (H) BF16 feature pairs in one word each.
+template <int CPT, bool H = false>
 struct RowRegs {
-  float2 v[CPT / 2];
+  typename std::conditional<H, uint32_t, float2>::type v[CPT / 2];
   uint32_t code;
   float res, ex, sto;
   int valid;
@@ -796,6 +796,27 @@ constexpr int n_cal() {
   return Net::D + Net::CH1 + Net::CH2 + Net::CH3 + Net::HID;
 }
 
+// BF16 copy of an FP32 trace for the BF16 form: row i's D features rounded
+// to BF16 (nearest even, as the window conversion does), then zeros to DS.
+__global__ void stage_bf16_kernel(const float* __restrict__ feat, int64_t n, int D, int DS,
+                                  uint16_t* __restrict__ out) {
+  const int64_t total = n * DS;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / DS;
+    const int c = (int)(i - r * DS);
+    out[i] = c < D ? PBF16::cvt(feat[r * D + c]) : (uint16_t)0;
+  }
+}
+
+hipError_t launch_stage_bf16(const float* feat, int64_t n, int D, uint16_t* out,
+                             hipStream_t stream) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(stage_bf16_kernel, dim3(2048), dim3(256), 0, stream, feat, n, D,
+                     staged_feat(D), out);
+  return hipGetLastError();
+}
+
 // DEP: the window carries the memory dependency flags (a separate
 // instantiation, so that runs without them pay no registers for them).
 // STAGE (networks run as separate kernels per step, one step per launch):
@@ -848,6 +869,10 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   constexpr int GSL = G::NG * BS;
   constexpr int ROWS = MT * GSL, TPR = NT / ROWS, CPT = DP / TPR;
   static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
+  // the BF16 form reads rows of a BF16 copy of the trace (DS features each)
+  constexpr bool H16 = P::ID == 1;
+  constexpr int DS = staged_feat(D);
+  static_assert(!H16 || (CPT % 8 == 0 && DS % 8 == 0), "BF16 rows");
   const int grow = tid / TPR, part = tid % TPR;
   const int gs = grow / GSL, gt = grow % GSL;
   if constexpr (P::SCALED)
@@ -856,7 +881,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   // features requested (every address in bounds, so all are in flight
   // together); commit: dynamic columns, conversion, one vector store.
   auto load = [&](int j0, int nb) {
-    RowRegs<CPT> r;
+    RowRegs<CPT, H16> r;
     const int w = j0 * BS + gt;
     int64_t idx = -1;
     r.res = 0.f;
@@ -893,6 +918,18 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     if (p.codes) {
       r.code = p.codes[idx < 0 ? 0 : idx];
+    } else if constexpr (H16) {
+      // BF16 rows of DS features (16-byte aligned): whole 16-byte chunks
+      const uint4* src = reinterpret_cast<const uint4*>(p.feat16 + (idx < 0 ? 0 : idx) * DS);
+#pragma unroll
+      for (int q = 0; q < CPT / 8; ++q) {
+        const int c = part * CPT + 8 * q;
+        const uint4 w = c < DS ? src[c / 8] : make_uint4(0u, 0u, 0u, 0u);
+        r.v[4 * q] = w.x;
+        r.v[4 * q + 1] = w.y;
+        r.v[4 * q + 2] = w.z;
+        r.v[4 * q + 3] = w.w;
+      }
     } else {
       const float* src = p.feat + (idx < 0 ? 0 : idx) * D;
 #pragma unroll
@@ -907,7 +944,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     return r;
   };
-  auto commit = [&](int j0, int nb, const RowRegs<CPT>& r, T* X) {
+  auto commit = [&](int j0, int nb, const RowRegs<CPT, H16>& r, T* X) {
     (void)j0;
     if (gt >= nb * BS) return;  // slots past a short group's blocks are never read
     float v[CPT];
@@ -915,8 +952,14 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     for (int cc = 0; cc < CPT; ++cc) {
       const int c = part * CPT + cc;
       float x = 0.f;
-      if (r.valid && c < D)
-        x = p.codes ? code_feature(r.code, c) : (cc & 1 ? r.v[cc / 2].y : r.v[cc / 2].x);
+      if (r.valid && c < D) {
+        if (p.codes)
+          x = code_feature(r.code, c);
+        else if constexpr (H16)
+          x = __uint_as_float(cc & 1 ? r.v[cc / 2] & 0xffff0000u : r.v[cc / 2] << 16);
+        else
+          x = cc & 1 ? r.v[cc / 2].y : r.v[cc / 2].x;
+      }
       if (c == p.col_res) x = r.res;
       if (c == p.col_exe) x = r.ex;
       if (c == p.col_sto) x = r.sto;

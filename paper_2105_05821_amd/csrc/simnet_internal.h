@@ -76,6 +76,10 @@ constexpr int padded_feat(int D, int prec) {
   return (D + kgroup(prec) / 2 - 1) / (kgroup(prec) / 2) * (kgroup(prec) / 2);
 }
 
+// Features per row of the BF16 copy of an FP32 trace that the BF16 form
+// reads: D rounded up to whole 16-byte chunks.
+constexpr int staged_feat(int D) { return (D + 7) / 8 * 8; }
+
 // Weights re-laid-out for the kernels (device pointers, owned by the context).
 // conv level l: B_l[k][n] with k = t*CH_l + c (t = pair member, c = input
 // channel, zero for padded channels), packed per (k-group of KG, n-tile of
@@ -160,6 +164,7 @@ struct DevState {
 
 struct StepParams {
   const float* feat;        // dense rows [n_instr][D], or
+  const uint16_t* feat16;   // (BF16 form) their BF16 copy [n_instr][staged_feat(D)], or
   const uint32_t* codes;    // packed instruction codes [n_instr] (one of the two)
   int32_t n_wg;             // persistent workgroups (slots = n_wg * MT)
   int32_t n_sub;
@@ -265,6 +270,10 @@ hipError_t launch_rb_head(int prec, const DevWeights& w, uint32_t relu, const vo
 // Convolutions of explicit windows x [B][L][D] (FP32) -> out [B][NB][CH3].
 hipError_t launch_rb_trunk(int prec, const DevWeights& w, uint32_t relu, const float* x, int64_t B,
                            void* out, hipStream_t stream);
+
+// BF16 copy of an FP32 trace [n][D] into out [n][staged_feat(D)].
+hipError_t launch_stage_bf16(const float* feat, int64_t n, int D, uint16_t* out,
+                             hipStream_t stream);
 
 // Graph of the run: step kernel until every slot is empty, then the total.
 hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
