@@ -105,13 +105,31 @@ def measure_peaks():
         for _ in range(4):
             ms = C.c_float(0.0)
             rc = lib.peaks_hbm(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
-                               C.c_int64(nbytes), mode, 256 * 16, C.c_void_p(stream), C.byref(ms))
+                               C.c_int64(nbytes), mode, 256 * 16, 1, C.c_void_p(stream),
+                               C.byref(ms))
             if rc != 0:
                 raise RuntimeError(f"peaks_hbm rc {rc}")
             best = ms.value if best is None else min(best, ms.value)
         gbs = moved / (best / 1e3) / 1e9
         res[f"hbm_{name}"] = {"gb_s": round(gbs, 1), "published": 8000.0,
                               "ratio": round(gbs / 8000.0, 3)}
+    # L2 -> CU: every workgroup (one per CU, and four per CU) re-reads the
+    # same 1 MiB
+    for per_cu in (1, 4):
+        blocks, reps, region = 256 * per_cu, 64, 1 << 20
+        best = None
+        for _ in range(4):
+            ms = C.c_float(0.0)
+            rc = lib.peaks_hbm(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()),
+                               C.c_int64(region), 2, blocks, reps, C.c_void_p(stream),
+                               C.byref(ms))
+            if rc != 0:
+                raise RuntimeError(f"peaks_hbm rc {rc}")
+            best = ms.value if best is None else min(best, ms.value)
+        gbs = blocks * reps * region / (best / 1e3) / 1e9
+        res[f"l2_read_{per_cu}wg_per_cu"] = {"gb_s": round(gbs, 1),
+                                             "per_cu_bytes_per_clk_at_2.4GHz":
+                                                 round(gbs / 256 / 2.4, 1)}
     return res
 
 
@@ -169,7 +187,7 @@ def cpu_baseline(wl, feat, start, length, warm, ws, bs, budget_s=15.0, mem=None)
 
 
 def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, warmup,
-              n_feat=None, graph=False, dmem=None):
+              n_feat=None, graph=False, dmem=None, tune=False):
     """Run the workload `steps` times after `warmup` runs; returns the time of
     the whole runs (host clock) and of the step kernel (HIP events on the
     stream the library launches on)."""
@@ -180,11 +198,12 @@ def time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, prec, steps, wa
     if prec == "fp8":
         sim.calibrate(64)  # per-channel scales from the first 64 FP32 steps (set-up, untimed)
     tuning = None
-    if graph:
+    if graph or tune:
         # launch shape chosen on the first 300 steps (set-up, untimed)
         tuning = sim.autotune(300)
         log(f"[bench] autotune: variant {tuning['variant']}, {tuning['n_wg']} workgroups; "
             f"trials {tuning['trials']}")
+    if graph:
         sim.use_graph(True)
     stream = sim.stream
 
@@ -389,7 +408,8 @@ def main():
     results = {}
     for f in forms:
         r = time_form(sn, torch, dfeat, wl, start, length, warm, ws, bs, f, steps, warmup,
-                      n_feat=n_feat, graph=args.workload == "c3_uneven", dmem=dmem)
+                      n_feat=n_feat, graph=args.workload == "c3_uneven", dmem=dmem,
+                      tune=args.workload == "c3_1m")
         r["mips"] = measured * steps / r["elapsed"] / 1e6
         r["tflops"] = FLOP_PER_PRED[net] * n_pred / (r["kernel_ms"] / 1e3) / 1e12
         results[f] = r
@@ -431,6 +451,10 @@ def main():
         out["steps_per_s"] = round(n_pred * steps / b["elapsed"], 1)
     if b.get("tuning"):
         out["config"]["launch_shape"] = {k: b["tuning"][k] for k in ("variant", "n_wg")}
+    if len(results) > 1 and any(r.get("tuning") for r in results.values()):
+        for f, r in results.items():
+            if r.get("tuning"):
+                out["forms"][f]["launch_shape"] = {k: r["tuning"][k] for k in ("variant", "n_wg")}
     if not args.no_cpu_baseline and feat is not None:
         log("[bench] timing the FP64 oracle on the host cores")
         out["cpu_baseline"] = cpu_baseline(wl, feat, start, length, warm, ws, bs, mem=mem)

@@ -64,11 +64,27 @@ __global__ void __launch_bounds__(256) mfma_probe(const uint32_t* __restrict__ s
 }
 
 // mode 0: read n16 16-byte words and fold them into one word per thread;
-// mode 1: copy them to dst.
+// mode 1: copy them to dst; mode 2: every workgroup reads the same first
+// n16 words (L2-resident when small) `reps` times (the per-CU read rate
+// from L2).
 __global__ void __launch_bounds__(256) hbm_probe(const uint4* __restrict__ src,
-                                                 uint4* __restrict__ dst, int64_t n16, int mode) {
+                                                 uint4* __restrict__ dst, int64_t n16, int mode,
+                                                 int reps) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (mode == 2) {
+    uint4 f = make_uint4(0u, 0u, 0u, 0u);
+    for (int r = 0; r < reps; ++r)
+      for (int64_t i = threadIdx.x; i < n16; i += blockDim.x) {
+        const uint4 v = src[i];
+        f.x ^= v.x + (uint32_t)r;
+        f.y ^= v.y;
+        f.z ^= v.z;
+        f.w ^= v.w;
+      }
+    dst[i0] = f;
+    return;
+  }
   if (mode == 1) {
     for (int64_t i = i0; i < n16; i += stride) dst[i] = src[i];
     return;
@@ -109,7 +125,7 @@ struct HbmArg {
   const uint4* src;
   uint4* dst;
   int64_t n16;
-  int mode, blocks;
+  int mode, blocks, reps;
 };
 
 }  // namespace
@@ -147,18 +163,22 @@ __attribute__((visibility("default"))) int peaks_mfma(int prec, int blocks, int 
 
 // HBM probe: mode 0 reads bytes from src (dst: DEVICE >= blocks * 256 * 16
 // bytes receives one folded word per thread), mode 1 copies bytes from src
-// to dst.  bytes a multiple of 16.  *ms = kernel time.
+// to dst, mode 2 has every workgroup read the first bytes of src reps times
+// (bytes read = blocks * reps * bytes).  bytes a multiple of 16.  *ms =
+// kernel time.
 __attribute__((visibility("default"))) int peaks_hbm(const void* src, void* dst, int64_t bytes,
-                                                     int mode, int blocks, void* stream,
+                                                     int mode, int blocks, int reps, void* stream,
                                                      float* ms) {
-  if (!src || !dst || bytes <= 0 || bytes % 16 || (mode != 0 && mode != 1) || blocks < 1 || !ms)
+  if (!src || !dst || bytes <= 0 || bytes % 16 || mode < 0 || mode > 2 || blocks < 1 ||
+      reps < 1 || !ms)
     return -1;
-  HbmArg a{static_cast<const uint4*>(src), static_cast<uint4*>(dst), bytes / 16, mode, blocks};
+  HbmArg a{static_cast<const uint4*>(src), static_cast<uint4*>(dst), bytes / 16, mode, blocks,
+           reps};
   return timed(static_cast<hipStream_t>(stream), ms,
                [](hipStream_t st, void* p) {
                  const HbmArg& h = *static_cast<HbmArg*>(p);
                  hipLaunchKernelGGL(hbm_probe, dim3(h.blocks), dim3(256), 0, st, h.src, h.dst,
-                                    h.n16, h.mode);
+                                    h.n16, h.mode, h.reps);
                },
                &a);
 }

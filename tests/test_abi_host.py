@@ -33,7 +33,7 @@ def test_peak_probe_library_loads():
     L = C.CDLL(os.path.join(ROOT, "paper_2105_05821_amd", "libsimnet_peaks.so"))
     ms = C.c_float(0.0)
     assert L.peaks_mfma(7, 1, 1, None, None, None, C.byref(ms)) == -1  # bad form
-    assert L.peaks_hbm(None, None, C.c_int64(16), 0, 1, None, C.byref(ms)) == -1
+    assert L.peaks_hbm(None, None, C.c_int64(16), 0, 1, 1, None, C.byref(ms)) == -1
 
 
 def good(n_sub=4, n_instr=1000, feat_ptr=0x1000):
