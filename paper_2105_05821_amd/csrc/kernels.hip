@@ -4,19 +4,26 @@
 // loop for them inside one launch (persistent: sub-traces are independent,
 // Sec. 3.3, so no grid-wide synchronisation is needed).  Each step:
 //   gather   - builds the tile's windows block by block straight into LDS
-//              from the trace rows and the sub-trace's processor queue
-//              (Sec. 2.2: current instruction with zero dynamic columns, then
-//              the in-flight instructions newest first with residence and
-//              execution latency);
+//              from the trace rows (FP32, their BF16 copy in the BF16 form, or
+//              packed codes) and the sub-trace's processor queue (Sec. 2.2:
+//              current instruction with zero dynamic columns, then the
+//              in-flight instructions newest first with residence and
+//              execution latency; with store latencies, then the memory
+//              write queue);
 //   predict  - conv levels as MFMA GEMMs on LDS tiles (Sec. 2.3: kernel 2,
 //              stride 2, ReLU), the hidden FC accumulated block by block in
-//              MFMA accumulators, the final FC on the VALU;
-//   update   - rounding and the clock / queue update of Sec. 3.2 in its
-//              timestamp form: instruction i enters at T_i = T_{i-1} + F_i and
-//              leaves at r_i = max(T_i + E_i + 1, r_{i-1}, r_{i-W} + 1); the
-//              queue after the advance is the suffix with r > T_i.
+//              MFMA accumulators, the final FC on the VALU (the hybrid head
+//              as one MFMA tile row);
+//   update   - rounding (or the hybrid head's class choice) and the clock /
+//              queue update of Sec. 3.2 in its timestamp form: instruction i
+//              enters at T_i = T_{i-1} + F_i and leaves at r_i = max(T_i +
+//              E_i + 1, r_{i-1}, r_{i-W} + 1); the queue after the advance is
+//              the suffix with r > T_i.
 // The queue ring and the per-sub-trace scalars stay in LDS for the whole
-// launch and are written back to HBM when the launch ends.
+// launch and are written back to HBM when the launch ends.  RB7, whose
+// residual blocks do not fit this loop, runs each step as four launches
+// (the step kernel's stages 1 and 2 around resblock_kernel and
+// rb_head_kernel).
 //
 // Precision forms: weights and activations in FP32, BF16 or FP8 (OCP e4m3,
 // per-channel power-of-two scales), products accumulated in FP32 in every
