@@ -216,27 +216,69 @@ __device__ __forceinline__ uint4 load_frag(__amdgpu_buffer_rsrc_t r, int lane_of
   return __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(r, lane_off, frag_off, 0));
 }
 
+// Workgroup barrier ordering LDS only: global loads in flight (weight
+// prefetches) stay in flight across it (__syncthreads waits for them).
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t frag_rsrc(const uint4* Bp, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint4*>(Bp), (short)0, bytes, 0x00020000);
+}
+
+// The first chunk of a weight stream (see mma_stream), requested ahead of
+// the stream: before the barrier that precedes it, so that its L2 latency
+// passes during the barrier and the previous phase's tail instead of
+// stalling every wave at the start of the phase.
+template <int CH, int NPW>
+struct StreamHead {
+  uint4 b[CH][NPW];
+};
+
+template <int KGS, int NTILES, int NPW, int FRAGS = 8>
+__device__ __forceinline__ StreamHead<stream_chunk(KGS, NPW, FRAGS), NPW> stream_head(
+    const uint4* __restrict__ Bp, int nt0, int lane) {
+  constexpr int CH = stream_chunk(KGS, NPW, FRAGS);
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(Bp, KGS * NTILES * 1024);
+  const int lo = lane * 16;
+  const int wn = __builtin_amdgcn_readfirstlane(nt0) * 1024;
+  StreamHead<CH, NPW> h;
+#pragma unroll
+  for (int kg = 0; kg < CH; ++kg)
+#pragma unroll
+    for (int j = 0; j < NPW; ++j) h.b[kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
+  return h;
+}
+
 // acc[i][j] += W(tile nt0 + j) x A(m-tile i: this lane's row of it), all K.
 // The weight fragment is the MFMA's first operand, so lane l ends up
 // holding row l % 16 of the activations and output columns 4*(l/16) .. +3
 // of the tile: consecutive columns, stored with one vector write.  Each
 // weight fragment serves MPW m-tiles.  Weight fragments are requested one
 // chunk ahead of their use (double buffering) and the scheduler is kept
-// from sinking the requests.
-template <class P, int KGS, int NTILES, int NPW, int MPW, int FRAGS = 8>
-__device__ __forceinline__ void mma_stream(typename P::Acc (&acc)[MPW][NPW],
-                                           const typename P::T* const (&ap)[MPW],
-                                           const uint4* __restrict__ Bp, int nt0, int lane) {
+// from sinking the requests.  HEAD: the first chunk was requested by
+// stream_head (same KGS, NTILES, NPW, FRAGS, Bp and nt0) and is passed in.
+template <class P, int KGS, int NTILES, int NPW, int MPW, int FRAGS = 8, bool HEAD = false>
+__device__ __forceinline__ void mma_stream(
+    typename P::Acc (&acc)[MPW][NPW], const typename P::T* const (&ap)[MPW],
+    const uint4* __restrict__ Bp, int nt0, int lane,
+    const StreamHead<stream_chunk(KGS, NPW, FRAGS), NPW>* head = nullptr) {
   constexpr int CH = stream_chunk(KGS, NPW, FRAGS), NCH = KGS / CH;
-  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<uint4*>(Bp), (short)0, KGS * NTILES * 1024, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rs = frag_rsrc(Bp, KGS * NTILES * 1024);
   const int lo = lane * 16;
   const int wn = __builtin_amdgcn_readfirstlane(nt0) * 1024;
   uint4 b[2][CH][NPW];
 #pragma unroll
   for (int kg = 0; kg < CH; ++kg)
 #pragma unroll
-    for (int j = 0; j < NPW; ++j) b[0][kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
+    for (int j = 0; j < NPW; ++j) {
+      if constexpr (HEAD)
+        b[0][kg][j] = head->b[kg][j];
+      else
+        b[0][kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
+    }
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
     if (c + 1 < NCH) {
@@ -307,26 +349,41 @@ constexpr int conv_wave_split(int ntiles, int mtiles, int waves) {
 // rows are 16 windows at one position, whose window strides spread them
 // over the LDS banks (the position stride of a wide level is a multiple of
 // the bank count, so window-major tiles would collide).
-template <class P, int K, int N, int POS, int WAVES, int SA, int IRS, int SO, bool OPAIR,
-          bool CAL = false, bool SAVE = false>
-__device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
-                                           typename P::T* __restrict__ O,
-                                           const uint4* __restrict__ Bp,
-                                           const float* __restrict__ bias,
-                                           const float* __restrict__ ws,
-                                           const float* __restrict__ ai, bool relu, int wave,
-                                           int lane, unsigned* cal = nullptr,
-                                           const int* row_live = nullptr,
-                                           typename P::T* sv = nullptr, int64_t sv_s = 0,
-                                           int sv_rows = 0) {
-  using T = typename P::T;
-  constexpr int ROWS = MT * POS;
-  constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
-  constexpr int WN = conv_wave_split(NTILES, MTILES, WAVES), WM = WAVES / WN;
-  constexpr int MPW = MTILES / WM, NPW = NTILES / WN;
+template <class P, int K, int N, int POS, int WAVES>
+struct ConvShape {
+  static constexpr int ROWS = MT * POS;
+  static constexpr int MTILES = ROWS / 16, NTILES = N / 16, KGS = K / P::KG;
+  static constexpr int WN = conv_wave_split(NTILES, MTILES, WAVES), WM = WAVES / WN;
+  static constexpr int MPW = MTILES / WM, NPW = NTILES / WN;
   static_assert(ROWS % 16 == 0 && N % 16 == 0 && K % P::KG == 0, "tile shape");
   static_assert(WAVES % WN == 0 && MTILES % WM == 0 && NTILES % WN == 0 && MPW >= 1,
                 "wave split");
+  using Head = StreamHead<stream_chunk(KGS, NPW), NPW>;
+};
+
+// The first chunk of a conv level's weight stream for this wave (see
+// StreamHead), requested ahead of conv_stage<..., HEAD = true>.
+template <class P, int K, int N, int POS, int WAVES>
+__device__ __forceinline__ typename ConvShape<P, K, N, POS, WAVES>::Head conv_head(
+    const void* Bp, int wave, int lane) {
+  using S = ConvShape<P, K, N, POS, WAVES>;
+  return stream_head<S::KGS, S::NTILES, S::NPW>(static_cast<const uint4*>(Bp),
+                                                (wave % S::WN) * S::NPW, lane);
+}
+
+template <class P, int K, int N, int POS, int WAVES, int SA, int IRS, int SO, bool OPAIR,
+          bool CAL = false, bool SAVE = false, bool HEAD = false>
+__device__ __forceinline__ void conv_stage(
+    const typename P::T* __restrict__ A, typename P::T* __restrict__ O,
+    const uint4* __restrict__ Bp, const float* __restrict__ bias, const float* __restrict__ ws,
+    const float* __restrict__ ai, bool relu, int wave, int lane, unsigned* cal = nullptr,
+    const int* row_live = nullptr, typename P::T* sv = nullptr, int64_t sv_s = 0,
+    int sv_rows = 0, const typename ConvShape<P, K, N, POS, WAVES>::Head* head = nullptr) {
+  using T = typename P::T;
+  using S = ConvShape<P, K, N, POS, WAVES>;
+  constexpr int MTILES = S::MTILES, NTILES = S::NTILES, KGS = S::KGS;
+  constexpr int WN = S::WN, MPW = S::MPW, NPW = S::NPW;
+  (void)MTILES;
   const int wm = wave / WN, wn = wave % WN;
   const int nt0 = wn * NPW;
   const T* ap[MPW];
@@ -340,7 +397,7 @@ __device__ __forceinline__ void conv_stage(const typename P::T* __restrict__ A,
   for (int i = 0; i < MPW; ++i)
 #pragma unroll
     for (int j = 0; j < NPW; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  mma_stream<P, KGS, NTILES, NPW, MPW>(acc, ap, Bp, nt0, lane);
+  mma_stream<P, KGS, NTILES, NPW, MPW, 8, HEAD>(acc, ap, Bp, nt0, lane, head);
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
     const int row = (wm * MPW + i) * 16 + (lane & 15);
@@ -383,24 +440,46 @@ constexpr int hidden_layer() {
   return Net::NCONV + 2 * Net::NRES;
 }
 
+template <class Net, class P, int NBG>
+struct FcShape {
+  static constexpr int HT = (Net::HID / 16) / Net::WAVES;
+  static constexpr int KGS = NBG * Net::CHL / P::KG;
+  using Head = StreamHead<stream_chunk(KGS, HT, Net::FC1_FRAGS), HT>;
+  // the packed weights of blocks j0 .. j0 + NBG - 1
+  static __device__ __forceinline__ const uint4* weights(const DevWeights& wt, int j0) {
+    return static_cast<const uint4*>(wt.hid_w) +
+           (size_t)j0 * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
+  }
+};
+
+// The first chunk of hidden_fc<..., HEAD = true>'s weight stream (see
+// StreamHead).
+template <class Net, class P, int NBG>
+__device__ __forceinline__ typename FcShape<Net, P, NBG>::Head fc_head(const DevWeights& wt,
+                                                                      int j0, int wave, int lane) {
+  using S = FcShape<Net, P, NBG>;
+  return stream_head<S::KGS, Net::HID / 16, S::HT, Net::FC1_FRAGS>(S::weights(wt, j0),
+                                                                  wave * S::HT, lane);
+}
+
 // Hidden-FC contribution of NBG blocks from block j0: last = the blocks'
 // last-conv output in LDS (window s at s * SAL, block-major), hacc += it
 // times the per-block packed weights.  A fresh accumulator per group, then
 // added, so the FP32 chain is per group.
-template <class Net, class P, int NBG>
+template <class Net, class P, int NBG, bool HEAD = false>
 __device__ __forceinline__ void hidden_fc(const DevWeights& wt, const typename P::T* last, int j0,
-                                          v4f* hacc, int wave, int lane) {
+                                          v4f* hacc, int wave, int lane,
+                                          const typename FcShape<Net, P, NBG>::Head* head = nullptr) {
   using G = Geo<Net, P>;
   using T = typename P::T;
-  constexpr int HT = (Net::HID / 16) / Net::WAVES;
-  constexpr int KGS = NBG * Net::CHL / P::KG;
-  const uint4* bj = static_cast<const uint4*>(wt.hid_w) +
-                    (size_t)j0 * (Net::CHL / P::KG) * (Net::HID / 16) * 64;
+  using S = FcShape<Net, P, NBG>;
+  constexpr int HT = S::HT;
   const T* const ap[1] = {last + (lane & 15) * G::SAL + (P::KG / 4) * (lane >> 4)};
   v4f bacc[1][HT];
 #pragma unroll
   for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
-  mma_stream<P, KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS>(bacc, ap, bj, wave * HT, lane);
+  mma_stream<P, S::KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS, HEAD>(
+      bacc, ap, S::weights(wt, j0), wave * HT, lane, head);
 #pragma unroll
   for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
 }
@@ -408,20 +487,24 @@ __device__ __forceinline__ void hidden_fc(const DevWeights& wt, const typename P
 // The conv levels and the hidden-FC (or final-FC) contribution of one group
 // of NBG blocks starting at block j0, for the tile of MT windows whose
 // window rows are in sm.x().  relu_mask bit l = ReLU after layer l.  Ends
-// with the group's last-conv output consumed.  issue() is called after the
-// conv levels (it requests the next group's rows into registers) and
-// finish(regs) after the FC (it writes them into sm.x(), the region conv2's
-// output used, dead by then): the FC's weight stream hides the gather.
+// with the group's last-conv output consumed.  issue() requests the next
+// group's rows into registers before the last conv level and finish(regs)
+// writes them into sm.x() (the region conv2's output used, dead once the
+// last level has read it) before the FC.  With three conv levels the first
+// weight chunk of conv2, conv3 and the FC is requested before the barrier
+// that precedes it (StreamHead) and the barriers order LDS only, so the
+// requests stay in flight across them.  (Requesting conv1's across the
+// group boundary as well made the hidden-FC stream spill registers.)
 // TRUNK: the convolutions only, the last conv's output going to sv.a3 (a1
 // and a2 are not written).
 template <class Net, class P, int NBG, bool CAL, bool SAVE, bool TRUNK, class Issue, class Finish>
-__device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_mask,
-                                          NetSmem<Net, P>& sm, int j0, unsigned* cal,
-                                          const int* row_live, SavePtrs<typename P::T> sv,
-                                          v4f* hacc, float& fpart, Issue&& issue,
-                                          Finish&& finish) {
+__device__ __forceinline__ void run_group(
+    const DevWeights& wt, uint32_t relu_mask, NetSmem<Net, P>& sm, int j0, unsigned* cal,
+    const int* row_live, SavePtrs<typename P::T> sv, v4f* hacc, float& fpart, Issue&& issue,
+    Finish&& finish) {
   using G = Geo<Net, P>;
   using T = typename P::T;
+  constexpr bool XPF = Net::NCONV == 3;  // weight streams requested across the barriers
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   constexpr int P1 = NBG * Net::BS / 2, P2 = NBG * Net::BS / 4;
   constexpr int Q1 = Net::BS / 2, Q2 = Net::BS / 4;  // positions per block
@@ -430,32 +513,48 @@ __device__ __forceinline__ void run_group(const DevWeights& wt, uint32_t relu_ma
       sm.x(), sm.a1(), static_cast<const uint4*>(wt.conv_w[0]), wt.conv_b[0], wt.conv_ws[0],
       wt.conv_ai[0], relu_mask & 1u, wave, lane, cal + Net::D, row_live,
       sv.a1 + (size_t)j0 * Q1 * Net::CH1, (int64_t)Net::NB * Q1 * Net::CH1, sv.rows);
-  __syncthreads();
+  typename ConvShape<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES>::Head h2;
+  if constexpr (XPF) {
+    h2 = conv_head<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES>(wt.conv_w[1], wave, lane);
+    lds_barrier();
+  } else {
+    __syncthreads();
+  }
   conv_stage<P, 2 * Net::CH1, Net::CH2, P2, Net::WAVES, G::SA1, G::R1, G::SA2, Net::NCONV == 3,
-             CAL, SAVE && !TRUNK>(
+             CAL, SAVE && !TRUNK, XPF>(
       sm.a1(), sm.a2(), static_cast<const uint4*>(wt.conv_w[1]), wt.conv_b[1], wt.conv_ws[1],
       wt.conv_ai[1], relu_mask & 2u, wave, lane, cal + Net::D + Net::CH1, row_live,
-      sv.a2 + (size_t)j0 * Q2 * Net::CH2, (int64_t)Net::NB * Q2 * Net::CH2, sv.rows);
-  __syncthreads();
+      sv.a2 + (size_t)j0 * Q2 * Net::CH2, (int64_t)Net::NB * Q2 * Net::CH2, sv.rows, &h2);
   if constexpr (Net::NCONV == 3) {
+    auto h3 = conv_head<P, 2 * Net::CH2, Net::CH3, NBG, Net::WAVES>(wt.conv_w[2], wave, lane);
+    lds_barrier();
     // the next group's rows are requested now, held through conv3 and
     // written once conv3 has read conv2's output (X's region), so the FC's
     // weight stream has the registers to itself
     auto next_rows = issue();
     conv_stage<P, 2 * Net::CH2, Net::CH3, NBG, Net::WAVES, G::SA2, G::R2, G::SA3, false, CAL,
-               SAVE>(
+               SAVE, true>(
         sm.a2(), sm.a3(), static_cast<const uint4*>(wt.conv_w[2]), wt.conv_b[2], wt.conv_ws[2],
         wt.conv_ai[2], relu_mask & 4u, wave, lane, cal + Net::D + Net::CH1 + Net::CH2, row_live,
-        sv.a3 + (size_t)j0 * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows);
-    __syncthreads();
+        sv.a3 + (size_t)j0 * Net::CH3, (int64_t)Net::NB * Net::CH3, sv.rows, &h3);
+    if constexpr (!TRUNK && Net::HID > 0) {
+      // hidden FC over the group's NBG*CHL inputs per window (block-major,
+      // as the packed per-block matrices are consecutive)
+      auto hf = fc_head<Net, P, NBG>(wt, j0, wave, lane);
+      lds_barrier();
+      finish(next_rows);
+      hidden_fc<Net, P, NBG, true>(wt, sm.a3(), j0, hacc, wave, lane, &hf);
+      return;
+    }
+    lds_barrier();
     finish(next_rows);
+  } else {
+    __syncthreads();
   }
   const T* last = Net::NCONV == 3 ? sm.a3() : sm.a2();
   if constexpr (TRUNK) {
     (void)last;
   } else if constexpr (Net::HID > 0) {
-    // hidden FC over the group's NBG*CHL inputs per window (block-major, as
-    // the packed per-block matrices are consecutive)
     hidden_fc<Net, P, NBG>(wt, last, j0, hacc, wave, lane);
   } else {
     // final FC on the VALU straight after the convs: (s, o) pairs, LPP lanes
@@ -556,8 +655,12 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
     auto regs = load(0, NFULL > 0 ? NG : TAIL);
     commit(0, NFULL > 0 ? NG : TAIL, regs, sm.x());
   }
+  constexpr bool XPF = Net::NCONV == 3;  // LDS-only barriers (see run_group)
   for (int g = 0; g < NFULL; ++g) {
-    __syncthreads();
+    if constexpr (XPF)
+      lds_barrier();
+    else
+      __syncthreads();
     const int j0 = g * NG;
     const int nj = j0 + NG, nnb = g + 1 < NFULL ? NG : TAIL;
     run_group<Net, P, NG, CAL, SAVE, TRUNK>(
@@ -567,7 +670,10 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
         });
   }
   if constexpr (TAIL > 0) {
-    __syncthreads();
+    if constexpr (XPF)
+      lds_barrier();
+    else
+      __syncthreads();
     run_group<Net, P, TAIL, CAL, SAVE, TRUNK>(
         wt, relu_mask, sm, NFULL * NG, cal, row_live, sv, hacc, fpart, []() { return 0; },
         [](int) {});
@@ -1229,14 +1335,6 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
 }
 
 // ------------------------------------------------------ residual blocks ---
-// Workgroup barrier ordering LDS only: global loads in flight (weight
-// prefetches) stay in flight across it (__syncthreads waits for them).
-__device__ __forceinline__ void lds_barrier() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
-  __builtin_amdgcn_s_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
-}
-
 // A tile of TM rows (window positions at the last conv level, CH3 channels
 // each) stays in LDS through all NRES blocks.  Per block the expansion is
 // produced EC channels at a time (bias, ReLU, rounded to the form, into one
