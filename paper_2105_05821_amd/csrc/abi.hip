@@ -504,6 +504,8 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
 // ------------------------------------------------------------ training ---
 
 constexpr int TRAIN_BINS = 400, TRAIN_OUT = 2 * (TRAIN_BINS + 1);
+// the head's operand rows padded to whole 16-byte vectors (BF16 and FP32)
+constexpr int TRAIN_LD = (TRAIN_OUT + 7) / 8 * 8;
 
 static bool train_layers_match(const sim_layer* l, int32_t n) {
   const int32_t want[5][4] = {{0, 50, 64, 1}, {0, 64, 128, 1}, {0, 128, 256, 1},
@@ -557,7 +559,7 @@ static void build_train_maps(sim_ctx* c, std::vector<int32_t>* maps) {
   T.n_pack[3] = maps->size() - T.map_pack[3];
   // FP32 row-major copies for the backward: conv l as [c_out][2*c_in] with
   // column t*c_in + c, the hidden layer with column p*256 + c, the head
-  // transposed [512][802]
+  // transposed [512][802] with rows padded to TRAIN_LD
   for (int l = 0; l < 3; ++l) {
     T.map_perm[l] = maps->size();
     const int ci = chs[l], co = chs[l + 1];
@@ -573,7 +575,8 @@ static void build_train_maps(sim_ctx* c, std::vector<int32_t>* maps) {
   T.n_perm[3] = maps->size() - T.map_perm[3];
   T.map_perm[4] = maps->size();
   for (int j = 0; j < 512; ++j)
-    for (int o = 0; o < TRAIN_OUT; ++o) maps->push_back((int32_t)(T.woff[4] + (size_t)o * 512 + j));
+    for (int o = 0; o < TRAIN_LD; ++o)
+      maps->push_back(o < TRAIN_OUT ? (int32_t)(T.woff[4] + (size_t)o * 512 + j) : -1);
   T.n_perm[4] = maps->size() - T.map_perm[4];
 }
 
@@ -1236,7 +1239,7 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
                                        B, sb, c->stream);
     TrainState& T = c->tr;
     const int bf = c->cfg.prec == SIM_BF16;
-    GemmArgs g = gemm(opnd(sb.h, bf, 512, 1), opnd(T.perm + T.perm_off[4], bf, TRAIN_OUT, 1),
+    GemmArgs g = gemm(opnd(sb.h, bf, 512, 1), opnd(T.perm + T.perm_off[4], bf, TRAIN_LD, 1),
                       logits, TRAIN_OUT, B, TRAIN_OUT, 512, 0);
     g.bias = T.master + T.boff[4];
     if (e == hipSuccess) e = launch_gemm(g, bf, nullptr, 0, c->stream);
@@ -1396,12 +1399,16 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
       e = launch_map_scatter(dWt, T.maps + T.map_perm[l], (int64_t)T.n_perm[l], dst, beta,
                              c->stream);
   };
-  // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H
-  GemmArgs g = gemm(opnd(dlogits, 0, TRAIN_OUT, 1), opnd(P + T.woff[4], 0, 512, 1), dH, 512, B,
+  // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H.
+  // dZ is read from a copy with rows padded to TRAIN_LD (dY1's space, free
+  // until conv2's input gradient), so both products read it in vectors.
+  float* dZp = dY1;
+  e = launch_pad_rows(dlogits, B, TRAIN_OUT, TRAIN_LD, dZp, c->stream);
+  GemmArgs g = gemm(opnd(dZp, 0, TRAIN_LD, 1), opnd(P + T.woff[4], 0, 512, 1), dH, 512, B,
                     512, TRAIN_OUT, 0);
   g.mask = opnd(sb.h, bf, 512, 1);
   run(g);
-  run(gemm(opnd(dlogits, 0, 1, TRAIN_OUT), opnd(sb.h, bf, 512, 1), dparams + T.woff[4], 512,
+  run(gemm(opnd(dZp, 0, 1, TRAIN_LD), opnd(sb.h, bf, 512, 1), dparams + T.woff[4], 512,
            TRAIN_OUT, 512, B, beta));
   colsum(dlogits, B, TRAIN_OUT, dparams + T.boff[4]);
   // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU

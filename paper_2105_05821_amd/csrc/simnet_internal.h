@@ -246,6 +246,8 @@ hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_
 size_t colsum_workspace(int64_t N);
 hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float* out, int beta,
                          float* work, hipStream_t stream);
+hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
+                           hipStream_t stream);
 hipError_t launch_map_gather(const float* src, const int32_t* map, int64_t n, void* dst, int bf16,
                              hipStream_t stream);
 hipError_t launch_map_scatter(const float* src, const int32_t* map, int64_t n, float* dst,

@@ -15,6 +15,7 @@
 //                    w.r.t. the head outputs.
 //   colsum kernels   bias gradients, summed in a fixed order.
 //   map kernels      weight re-layouts and gradient scatters by index maps.
+//   pad_rows         a row-major matrix copied with its rows padded.
 //   adam_kernel      Adam on FP32 master weights.
 #include "simnet_internal.h"
 
@@ -197,7 +198,7 @@ __device__ __forceinline__ int64_t elem_addr(const GemmOperand& o, bool is_b, in
   return is_b ? op_index(o, k, outer) : op_index(o, outer, k);
 }
 
-__device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int mode, bool vec,
+__device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int mode, int vec,
                                            int64_t outer0, int64_t k0, int64_t outer_lim,
                                            int64_t k_lim, int tid, Stage& st) {
   int64_t outer, k;
@@ -213,7 +214,30 @@ __device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int 
     const int64_t left = k_lim - k;
     cnt = outer < outer_lim ? (left > 16 ? 16 : (left > 0 ? (int)left : 0)) : 0;
   }
-  if (mode != 0 && vec && cnt == 16) {
+  if (mode != 0 && vec == 1 && cnt == 16) {  // 8-byte vectors
+    const int64_t a = elem_addr(o, is_b, outer, k);
+    if (o.bf16) {
+      const uint2* p = reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(o.p) + a);
+#pragma unroll
+      for (int h = 0; h < 4; ++h) {
+        const uint2 w = p[h];
+        st.v[4 * h] = __uint_as_float(w.x << 16);
+        st.v[4 * h + 1] = __uint_as_float(w.x & 0xffff0000u);
+        st.v[4 * h + 2] = __uint_as_float(w.y << 16);
+        st.v[4 * h + 3] = __uint_as_float(w.y & 0xffff0000u);
+      }
+    } else {
+      const float2* p = reinterpret_cast<const float2*>(static_cast<const float*>(o.p) + a);
+#pragma unroll
+      for (int h = 0; h < 8; ++h) {
+        const float2 w = p[h];
+        st.v[2 * h] = w.x;
+        st.v[2 * h + 1] = w.y;
+      }
+    }
+    return;
+  }
+  if (mode != 0 && vec == 2 && cnt == 16) {  // 16-byte vectors
     const int64_t a = elem_addr(o, is_b, outer, k);
     if (o.bf16) {
       const uint4* p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(o.p) + a);
@@ -378,8 +402,10 @@ __global__ void __launch_bounds__(256) strided_reduce(const float* __restrict__ 
   }
 }
 
-// Operand access mode for the BF16 kernel (see gemm_bf16_kernel) and whether
-// 16-byte vector reads are aligned.
+// Operand access mode for the BF16 kernel (see gemm_bf16_kernel) and the
+// vector reads a run of 16 elements allows: 2 = 16-byte, 1 = 8-byte (rows
+// of an odd multiple of 8 bytes apart, e.g. windows of 111 x 50 FP32
+// features), 0 = none.
 static void operand_mode(const GemmOperand& o, bool is_b, int32_t* mode, int32_t* vec) {
   const bool grouped = o.grp < NO_GROUP;
   const int64_t k_stride = is_b ? o.rs : o.cs, outer_stride = is_b ? o.cs : o.rs;
@@ -390,10 +416,13 @@ static void operand_mode(const GemmOperand& o, bool is_b, int32_t* mode, int32_t
     *mode = 2;
   else
     *mode = 0;
-  const int64_t q = o.bf16 ? 8 : 4;  // elements per 16 bytes
   const int64_t other = *mode == 1 ? outer_stride : k_stride;
-  *vec = *mode != 0 && (reinterpret_cast<uintptr_t>(o.p) % 16 == 0) && other % q == 0 &&
-         (!grouped || o.gs % q == 0);
+  auto fits = [&](int64_t bytes) {
+    const int64_t q = bytes / (o.bf16 ? 2 : 4);  // elements per vector
+    return *mode != 0 && (reinterpret_cast<uintptr_t>(o.p) % bytes == 0) && other % q == 0 &&
+           (!grouped || o.gs % q == 0);
+  };
+  *vec = fits(16) ? 2 : fits(8) ? 1 : 0;
 }
 
 hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
@@ -564,6 +593,23 @@ __global__ void map_scatter(const float* __restrict__ src, const int32_t* __rest
   if (i >= n) return;
   const int32_t k = map[i];
   if (k >= 0) dst[k] = beta ? dst[k] + src[i] : src[i];
+}
+
+// dst[r][c] = src[r][c] for c < cols, 0 for cols <= c < ld: rows padded to
+// a stride whose 16-byte vectors the GEMM operand reads can use.
+__global__ void pad_rows(const float* __restrict__ src, int64_t rows, int64_t cols, int64_t ld,
+                         float* __restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= rows * ld) return;
+  const int64_t r = i / ld, c = i % ld;
+  dst[i] = c < cols ? src[r * cols + c] : 0.f;
+}
+
+hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
+                           hipStream_t stream) {
+  hipLaunchKernelGGL(pad_rows, dim3((unsigned)((rows * ld + 255) / 256)), dim3(256), 0, stream,
+                     src, rows, cols, ld, dst);
+  return hipGetLastError();
 }
 
 hipError_t launch_map_gather(const float* src, const int32_t* map, int64_t n, void* dst, int bf16,
