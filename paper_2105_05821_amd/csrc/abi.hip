@@ -585,15 +585,17 @@ static void build_train_maps(sim_ctx* c, std::vector<int32_t>* maps) {
 static int relayout_train(sim_ctx* c) {
   TrainState& T = c->tr;
   const int bf16 = c->cfg.prec == SIM_BF16;
-  hipError_t e = hipSuccess;
-  for (int l = 0; l < 4 && e == hipSuccess; ++l)
-    e = launch_map_gather(T.master, T.maps + T.map_pack[l], (int64_t)T.n_pack[l],
-                          static_cast<char*>(T.packed) + T.pack_off[l], bf16, c->stream);
+  // one launch for the nine re-layouts
+  GatherSegs segs{};
+  for (int l = 0; l < 4; ++l)
+    segs.seg[segs.count++] = GatherSeg{T.maps + T.map_pack[l], (int64_t)T.n_pack[l],
+                                       static_cast<char*>(T.packed) + T.pack_off[l], bf16};
   // the head's transposed copy is the forward's operand: in the form's
   // precision; the others serve the backward products in FP32
-  for (int l = 0; l < 5 && e == hipSuccess; ++l)
-    e = launch_map_gather(T.master, T.maps + T.map_perm[l], (int64_t)T.n_perm[l],
-                          T.perm + T.perm_off[l], l == 4 ? bf16 : 0, c->stream);
+  for (int l = 0; l < 5; ++l)
+    segs.seg[segs.count++] = GatherSeg{T.maps + T.map_perm[l], (int64_t)T.n_perm[l],
+                                       T.perm + T.perm_off[l], l == 4 ? bf16 : 0};
+  const hipError_t e = launch_map_gather_multi(T.master, segs, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "training re-layout");
   DevWeights& w = c->w;
   w = DevWeights{};

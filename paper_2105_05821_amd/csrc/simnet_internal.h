@@ -248,8 +248,20 @@ hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float
                          float* work, hipStream_t stream);
 hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
                            hipStream_t stream);
-hipError_t launch_map_gather(const float* src, const int32_t* map, int64_t n, void* dst, int bf16,
-                             hipStream_t stream);
+// dst[i] = src[map[i]] (0 where map[i] < 0) for i < n, in FP32 or rounded
+// to BF16, for up to MAX (map, n, dst) segments in one launch.
+struct GatherSeg {
+  const int32_t* map;
+  int64_t n;
+  void* dst;
+  int32_t bf16;
+};
+struct GatherSegs {
+  static constexpr int MAX = 10;
+  GatherSeg seg[MAX];
+  int32_t count;
+};
+hipError_t launch_map_gather_multi(const float* src, const GatherSegs& segs, hipStream_t stream);
 hipError_t launch_map_scatter(const float* src, const int32_t* map, int64_t n, float* dst,
                               int beta, hipStream_t stream);
 hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);

@@ -571,21 +571,6 @@ hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float
   return hipGetLastError();
 }
 
-// dst[i] = src[map[i]] (0 where map < 0), stored as FP32 or BF16 (nearest even).
-__global__ void map_gather(const float* __restrict__ src, const int32_t* __restrict__ map,
-                           int64_t n, void* __restrict__ dst, int bf16) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int32_t k = map[i];
-  const float v = k < 0 ? 0.f : src[k];
-  if (bf16) {
-    const uint32_t u = __float_as_uint(v);
-    static_cast<uint16_t*>(dst)[i] = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-  } else {
-    static_cast<float*>(dst)[i] = v;
-  }
-}
-
 // dst[map[i]] (=|+=) src[i] for map[i] >= 0 (the map is one-to-one).
 __global__ void map_scatter(const float* __restrict__ src, const int32_t* __restrict__ map,
                             int64_t n, float* __restrict__ dst, int beta) {
@@ -612,10 +597,36 @@ hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t
   return hipGetLastError();
 }
 
-hipError_t launch_map_gather(const float* src, const int32_t* map, int64_t n, void* dst, int bf16,
-                             hipStream_t stream) {
-  hipLaunchKernelGGL(map_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src,
-                     map, n, dst, bf16);
+// dst[i] = src[map[i]] (0 where map < 0), stored as FP32 or BF16 (nearest
+// even), for several (map, n, dst) segments from one source in one launch:
+// workgroup b serves the segment whose block range holds b (segments in
+// order, each rounded up to whole workgroups).
+__global__ void map_gather_multi(const float* __restrict__ src, GatherSegs segs) {
+  int s = 0;
+  int64_t b = blockIdx.x;
+  while (s + 1 < segs.count && b >= (segs.seg[s].n + 255) / 256) {
+    b -= (segs.seg[s].n + 255) / 256;
+    ++s;
+  }
+  const GatherSeg& g = segs.seg[s];
+  const int64_t i = b * 256 + threadIdx.x;
+  if (i >= g.n) return;
+  const int32_t k = g.map[i];
+  const float v = k < 0 ? 0.f : src[k];
+  if (g.bf16) {
+    const uint32_t u = __float_as_uint(v);
+    static_cast<uint16_t*>(g.dst)[i] = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  } else {
+    static_cast<float*>(g.dst)[i] = v;
+  }
+}
+
+hipError_t launch_map_gather_multi(const float* src, const GatherSegs& segs, hipStream_t stream) {
+  if (segs.count < 1 || segs.count > GatherSegs::MAX) return hipErrorInvalidValue;
+  int64_t blocks = 0;
+  for (int s = 0; s < segs.count; ++s) blocks += (segs.seg[s].n + 255) / 256;
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(map_gather_multi, dim3((unsigned)blocks), dim3(256), 0, stream, src, segs);
   return hipGetLastError();
 }
 
