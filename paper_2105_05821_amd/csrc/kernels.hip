@@ -336,19 +336,9 @@ constexpr int conv_wave_split(int ntiles, int mtiles, int waves) {
   return wn;
 }
 
-// One conv level as a GEMM: rows (s, q) = MT windows x POS output positions,
-// A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
-// 2q+1 at A + s*SA + q*IRS; output row (s, q) goes to O + s*SO + q*N, or,
-// OPAIR, to O + s*SO + (q/2)*(2N + 16 bytes) + (q%2)*N (the padded pair
-// layout the next conv reads).  The
-// waves split the N tiles (conv_wave_split), then the M tiles; a wave runs
-// MPW x NPW tiles.
-// SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
-// s < sv_rows only), the layer's activations kept for the backward pass.
-// Rows are numbered position-major, row = q * MT + s: an MFMA tile's 16
-// rows are 16 windows at one position, whose window strides spread them
-// over the LDS banks (the position stride of a wide level is a multiple of
-// the bank count, so window-major tiles would collide).
+// The tiling of one conv level as a GEMM (see conv_stage): MT windows x POS
+// output positions of rows, N output channels, contraction K; the waves'
+// split over N and M tiles and the type of the stream's first chunk.
 template <class P, int K, int N, int POS, int WAVES>
 struct ConvShape {
   static constexpr int ROWS = MT * POS;
@@ -371,6 +361,21 @@ __device__ __forceinline__ typename ConvShape<P, K, N, POS, WAVES>::Head conv_he
                                                 (wave % S::WN) * S::NPW, lane);
 }
 
+// One conv level as a GEMM: rows (s, q) = MT windows x POS output positions,
+// A row (s, q) is the K = 2*C_in contiguous elements of input positions 2q,
+// 2q+1 at A + s*SA + q*IRS; output row (s, q) goes to O + s*SO + q*N, or,
+// OPAIR, to O + s*SO + (q/2)*(2N + 16 bytes) + (q%2)*N (the padded pair
+// layout the next conv reads).  The
+// waves split the N tiles (conv_wave_split), then the M tiles; a wave runs
+// MPW x NPW tiles.
+// SAVE: also store each output row (s, q) to sv + s*sv_s + q*N (rows with
+// s < sv_rows only), the layer's activations kept for the backward pass.
+// Rows are numbered position-major, row = q * MT + s: an MFMA tile's 16
+// rows are 16 windows at one position, whose window strides spread them
+// over the LDS banks (the position stride of a wide level is a multiple of
+// the bank count, so window-major tiles would collide).
+// HEAD: the weight stream's first chunk was requested by conv_head and is
+// passed in (head).
 template <class P, int K, int N, int POS, int WAVES, int SA, int IRS, int SO, bool OPAIR,
           bool CAL = false, bool SAVE = false, bool HEAD = false>
 __device__ __forceinline__ void conv_stage(
@@ -440,6 +445,8 @@ constexpr int hidden_layer() {
   return Net::NCONV + 2 * Net::NRES;
 }
 
+// The hidden FC's weight stream for a group of NBG blocks (see hidden_fc):
+// HT output tiles per wave, KGS k-groups, the packed weights' address.
 template <class Net, class P, int NBG>
 struct FcShape {
   static constexpr int HT = (Net::HID / 16) / Net::WAVES;
@@ -465,7 +472,8 @@ __device__ __forceinline__ typename FcShape<Net, P, NBG>::Head fc_head(const Dev
 // Hidden-FC contribution of NBG blocks from block j0: last = the blocks'
 // last-conv output in LDS (window s at s * SAL, block-major), hacc += it
 // times the per-block packed weights.  A fresh accumulator per group, then
-// added, so the FP32 chain is per group.
+// added, so the FP32 chain is per group.  HEAD: the stream's first chunk
+// was requested by fc_head and is passed in (head).
 template <class Net, class P, int NBG, bool HEAD = false>
 __device__ __forceinline__ void hidden_fc(const DevWeights& wt, const typename P::T* last, int j0,
                                           v4f* hacc, int wave, int lane,
