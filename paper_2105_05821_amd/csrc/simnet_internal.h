@@ -234,7 +234,7 @@ struct GemmArgs {
   const float* bias;
   int32_t beta;
   // set by launch_gemm
-  int32_t ksplit, amode, avec, bmode, bvec;
+  int32_t ksplit, amode, avec, bmode, bvec, evec;
   float* part;
 };
 // bf16_mma: BF16 MFMA with operands rounded to BF16 (else FP32 MFMA).  part

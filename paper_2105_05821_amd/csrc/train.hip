@@ -349,6 +349,80 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
     __syncthreads();
     cur ^= 1;
   }
+  if (g.evec) {
+    // whole 16-byte rows: the tile goes through LDS a quarter at a time (32
+    // rows x 128 columns), and each thread finishes 16 consecutive columns
+    // of one row with vector reads of the mask and previous C and vector
+    // stores (full cache lines per row instead of 64-byte pieces)
+    constexpr int ES = HB + 4;  // row stride of the staged quarter, in floats
+    static_assert(32 * ES * sizeof(float) <= sizeof(As), "epilogue staging");
+    float* E = reinterpret_cast<float*>(&As[0][0][0]);
+    const int er = tid / 8, ec = (tid % 8) * 16;
+    const int64_t m = m0 + (er / 16) * 64 + (er % 16);  // + i * 16
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          E[(wm * 16 + 4 * (lane >> 4) + r) * ES + wn * 64 + j * 16 + (lane & 15)] = acc[i][j][r];
+      __syncthreads();
+      const int64_t mi = m + i * 16, n = n0 + ec;
+      if (mi < g.M && n < g.N) {
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float4 t = *reinterpret_cast<const float4*>(&E[er * ES + ec + 4 * q]);
+          v[4 * q] = t.x;
+          v[4 * q + 1] = t.y;
+          v[4 * q + 2] = t.z;
+          v[4 * q + 3] = t.w;
+        }
+        if (g.mask.p) {
+          const int64_t a = grouped_row(mi, g.mask.grp, g.mask.gs, g.mask.rs) + n;
+          float mk[16];
+          if (g.mask.bf16) {
+            const uint4* mp = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(g.mask.p) + a);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const uint4 w = mp[h];
+              const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+              for (int q = 0; q < 4; ++q) {
+                mk[8 * h + 2 * q] = __uint_as_float(ws[q] << 16);
+                mk[8 * h + 2 * q + 1] = __uint_as_float(ws[q] & 0xffff0000u);
+              }
+            }
+          } else {
+            const float4* mp = reinterpret_cast<const float4*>(static_cast<const float*>(g.mask.p) + a);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const float4 w = mp[q];
+              mk[4 * q] = w.x;
+              mk[4 * q + 1] = w.y;
+              mk[4 * q + 2] = w.z;
+              mk[4 * q + 3] = w.w;
+            }
+          }
+#pragma unroll
+          for (int e = 0; e < 16; ++e)
+            if (!(mk[e] > 0.f)) v[e] = 0.f;
+        }
+        float4* cp = reinterpret_cast<float4*>(g.C + grouped_row(mi, g.cgrp, g.cgs, g.ldc) + n);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float4 o = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+          if (g.beta) {
+            const float4 c = cp[q];
+            o = make_float4(c.x + o.x, c.y + o.y, c.z + o.z, c.w + o.w);
+          }
+          cp[q] = o;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
   const int64_t nb = n0 + wn * 64 + (lane & 15);
 #pragma unroll
   for (int i = 0; i < 4; ++i)
@@ -450,6 +524,16 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   g.part = part;
   operand_mode(g.A, false, &g.amode, &g.avec);
   operand_mode(g.B, true, &g.bmode, &g.bvec);
+  // the BF16 kernel's vector epilogue: no split, no bias, N whole 16-column
+  // runs, C and the mask in 16-byte aligned rows contiguous along n
+  {
+    const int64_t mq = g.mask.bf16 ? 8 : 4;
+    const bool c_ok = reinterpret_cast<uintptr_t>(g.C) % 16 == 0 && g.ldc % 4 == 0 &&
+                      (g.cgrp >= NO_GROUP || g.cgs % 4 == 0);
+    const bool m_ok = !g.mask.p || (g.mask.cs == 1 && reinterpret_cast<uintptr_t>(g.mask.p) % 16 == 0 &&
+                                    g.mask.rs % mq == 0 && (g.mask.grp >= NO_GROUP || g.mask.gs % mq == 0));
+    g.evec = bf16_mma && ks == 1 && !g.bias && g.N % 16 == 0 && c_ok && m_ok;
+  }
   const dim3 grid((unsigned)((g.N + TB - 1) / TB), (unsigned)((g.M + TB - 1) / TB), (unsigned)ks);
   if (bf16_mma)
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
