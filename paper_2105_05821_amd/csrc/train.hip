@@ -382,7 +382,8 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
           const int64_t a = grouped_row(mi, g.mask.grp, g.mask.gs, g.mask.rs) + n;
           float mk[16];
           if (g.mask.bf16) {
-            const uint4* mp = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(g.mask.p) + a);
+            const uint4* mp =
+                reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(g.mask.p) + a);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
               const uint4 w = mp[h];
@@ -394,7 +395,8 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
               }
             }
           } else {
-            const float4* mp = reinterpret_cast<const float4*>(static_cast<const float*>(g.mask.p) + a);
+            const float4* mp =
+                reinterpret_cast<const float4*>(static_cast<const float*>(g.mask.p) + a);
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
               const float4 w = mp[q];
@@ -530,8 +532,10 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
     const int64_t mq = g.mask.bf16 ? 8 : 4;
     const bool c_ok = reinterpret_cast<uintptr_t>(g.C) % 16 == 0 && g.ldc % 4 == 0 &&
                       (g.cgrp >= NO_GROUP || g.cgs % 4 == 0);
-    const bool m_ok = !g.mask.p || (g.mask.cs == 1 && reinterpret_cast<uintptr_t>(g.mask.p) % 16 == 0 &&
-                                    g.mask.rs % mq == 0 && (g.mask.grp >= NO_GROUP || g.mask.gs % mq == 0));
+    const bool m_ok = !g.mask.p || (g.mask.cs == 1 &&
+                                    reinterpret_cast<uintptr_t>(g.mask.p) % 16 == 0 &&
+                                    g.mask.rs % mq == 0 &&
+                                    (g.mask.grp >= NO_GROUP || g.mask.gs % mq == 0));
     g.evec = bf16_mma && ks == 1 && !g.bias && g.N % 16 == 0 && c_ok && m_ok;
   }
   const dim3 grid((unsigned)((g.N + TB - 1) / TB), (unsigned)((g.M + TB - 1) / TB), (unsigned)ks);
