@@ -670,18 +670,21 @@ __global__ void map_scatter(const float* __restrict__ src, const int32_t* __rest
 
 // dst[r][c] = src[r][c] for c < cols, 0 for cols <= c < ld: rows padded to
 // a stride whose 16-byte vectors the GEMM operand reads can use.
-__global__ void pad_rows(const float* __restrict__ src, int64_t rows, int64_t cols, int64_t ld,
+// One workgroup row per matrix row (grid x), 256 columns per workgroup
+// (grid y).
+__global__ void pad_rows(const float* __restrict__ src, int64_t cols, int64_t ld,
                          float* __restrict__ dst) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= rows * ld) return;
-  const int64_t r = i / ld, c = i % ld;
-  dst[i] = c < cols ? src[r * cols + c] : 0.f;
+  const int64_t r = blockIdx.x, c = (int64_t)blockIdx.y * 256 + threadIdx.x;
+  if (c >= ld) return;
+  dst[r * ld + c] = c < cols ? src[r * cols + c] : 0.f;
 }
 
 hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(pad_rows, dim3((unsigned)((rows * ld + 255) / 256)), dim3(256), 0, stream,
-                     src, rows, cols, ld, dst);
+  if (rows <= 0) return hipSuccess;
+  if (rows > INT32_MAX || (ld + 255) / 256 > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(pad_rows, dim3((unsigned)rows, (unsigned)((ld + 255) / 256)), dim3(256), 0,
+                     stream, src, cols, ld, dst);
   return hipGetLastError();
 }
 
