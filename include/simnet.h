@@ -149,7 +149,22 @@ typedef struct {
  * device memory (feat is only checked for non-NULL).  SIM_OK or SIM_EINVAL. */
 SIMNET_API int sim_validate_config(const sim_config* cfg, const sim_trace* trace);
 
-/* Create a context: validates, copies the sub-trace table to the device and
+/* Partition of a trace for parallel simulation (Sec. 3.3, parallel
+ * simulation: the trace is split into sub-traces simulated independently,
+ * each after a warm-up over the instructions that precede it).  Pure host,
+ * no device use.  Writes n_sub entries of each HOST array, caller-owned:
+ * sub-trace k covers trace rows [start[k], start[k] + len[k]); the rows are
+ * cut into equal contiguous pieces, the first n_instr mod n_sub one
+ * instruction longer; warm[k] = min(warm_max, start[k]) instructions before
+ * start[k] are simulated as warm-up.  SIM_EINVAL unless
+ * 1 <= n_sub <= n_instr, warm_max >= 0 and every pointer is non-NULL
+ * (nothing is written then). */
+SIMNET_API int sim_partition(int64_t n_instr, int32_t n_sub, int32_t warm_max, int64_t* start,
+                             int64_t* len, int32_t* warm);
+
+/* Create a context (Sec. 3.3: the partitioned trace and each sub-trace's
+ * simulation state, processor queue and clock of Sec. 3.2, stay on the
+ * device for the whole run): validates, copies the sub-trace table to the device and
  * allocates the per-sub-trace state (processor queue of n_slot-1 entries,
  * clock, retire history).  *out is NULL on failure. */
 SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx** out);
@@ -176,7 +191,13 @@ SIMNET_API int sim_init(const sim_config* cfg, const sim_trace* trace, sim_ctx**
 SIMNET_API int sim_load_weights(sim_ctx* ctx, const sim_layer* layers, int32_t n_layers,
                      const float* params, int32_t on_device);
 
-/* Advance the simulation by up to n_steps steps (asynchronous).  The
+/* Advance the simulation by up to n_steps steps (asynchronous).  One step
+ * is one iteration of the parallel simulation loop of Sec. 3.3 over every
+ * sub-trace in a slot: the model input of its next instruction (Sec. 2.2),
+ * the predictor (Sec. 2.3), then the clock and queue update of Sec. 3.2
+ * (fetch latency advances the clock; in-flight instructions leave in order,
+ * at most retire_width per cycle, once their residence exceeds their
+ * execution latency).  The
  * library runs a fixed number of sub-trace slots (a multiple of 16, at most
  * a few per compute unit); a slot whose sub-trace finishes takes the next
  * unstarted one, longest first, so with more sub-traces than slots one step
@@ -187,7 +208,9 @@ SIMNET_API int sim_load_weights(sim_ctx* ctx, const sim_layer* layers, int32_t n
 SIMNET_API int sim_step(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode, const int32_t* lat_table);
 
 /* Run every sub-trace to completion (one launch that ends when every slot
- * is empty), synchronise, and fill *res.  A context
+ * is empty), synchronise, and fill *res: per sub-trace the fetch cycles and
+ * the drain after the last fetch (Sec. 3.1, Eq. 1), and their sum over the
+ * sub-traces as the simulated time of the whole trace (Sec. 3.3).  A context
  * that has completed must be sim_reset before it runs again. */
 SIMNET_API int sim_run(sim_ctx* ctx, int32_t lat_mode, const int32_t* lat_table, sim_result* res);
 
@@ -283,7 +306,8 @@ SIMNET_API int64_t predictor_save_bytes(const sim_ctx* ctx, int64_t B);
 SIMNET_API int sim_loss(sim_ctx* ctx, const float* logits, const int32_t* labels, int64_t B,
                         float* loss, float* dlogits);
 
-/* Backward of predictor_fwd (training head), the chain rule through the
+/* Backward of predictor_fwd (training head; the predictor of Sec. 2.3 trained
+ * on the hybrid loss as Sec. 4 sets up), the chain rule through the
  * head, the hidden layer, the three convolutions and their ReLUs: x and save
  * as passed to the forward, dlogits DEVICE [B][802].  dparams (DEVICE,
  * float32) has the layout of sim_load_weights's params and receives the

@@ -25,7 +25,8 @@ CONV, FC = 0, 1
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVICE",
                 -4: "SIM_ESTATE", -5: "SIM_ENONFINITE", -6: "SIM_EUNSUPPORTED"}
 
-EXPORTED = ("sim_validate_config", "sim_init", "sim_load_weights", "sim_step", "sim_run",
+EXPORTED = ("sim_validate_config", "sim_partition", "sim_init", "sim_load_weights", "sim_step",
+            "sim_run",
             "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
             "sim_autotune", "sim_set_tuning",
             "predictor_fwd", "predictor_save_bytes", "sim_loss", "predictor_bwd", "sim_adam",
@@ -78,6 +79,7 @@ def lib():
         L = C.CDLL(LIB_PATH)
         P = C.c_void_p
         L.sim_validate_config.argtypes = [C.POINTER(sim_config), C.POINTER(sim_trace)]
+        L.sim_partition.argtypes = [C.c_int64, C.c_int32, C.c_int32, P, P, P]
         L.sim_init.argtypes = [C.POINTER(sim_config), C.POINTER(sim_trace), C.POINTER(P)]
         L.sim_load_weights.argtypes = [P, C.POINTER(sim_layer), C.c_int32, P, C.c_int32]
         L.sim_step.argtypes = [P, C.c_int32, C.c_int32, P]
@@ -143,16 +145,15 @@ def sim_validate_config(cfg: sim_config, trace: sim_trace) -> int:
 
 
 def partition(n_instr: int, n_sub: int, warm_max: int = 0):
-    """Equal contiguous sub-traces (the first n_instr mod n_sub get one more
-    instruction) with warm-up min(warm_max, start)."""
-    if n_sub < 1 or n_instr < n_sub:
-        raise ValueError("need 1 <= n_sub <= n_instr")
-    q, r = divmod(n_instr, n_sub)
-    length = np.full(n_sub, q, np.int64)
-    length[:r] += 1
-    start = np.zeros(n_sub, np.int64)
-    start[1:] = np.cumsum(length)[:-1]
-    warm = np.minimum(start, warm_max).astype(np.int32)
+    """(start, len, warm) of the library's partition (sim_partition)."""
+    start = np.zeros(max(n_sub, 0), np.int64)
+    length = np.zeros(max(n_sub, 0), np.int64)
+    warm = np.zeros(max(n_sub, 0), np.int32)
+    rc = lib().sim_partition(n_instr, n_sub, warm_max, start.ctypes.data, length.ctypes.data,
+                             warm.ctypes.data)
+    if rc != SIM_OK:
+        raise ValueError(f"sim_partition({n_instr}, {n_sub}, {warm_max}) -> "
+                         f"{STATUS_NAMES.get(rc, rc)}")
     return start, length, warm
 
 

@@ -727,6 +727,24 @@ int sim_validate_config(const sim_config* cfg, const sim_trace* trace) {
   return check_cfg(cfg, trace, nullptr);
 }
 
+// Sec. 3.3: the trace is cut into n_sub contiguous sub-traces of equal
+// length, the first n_instr mod n_sub of them one instruction longer; each
+// also simulates the min(warm_max, start) instructions before its start.
+int sim_partition(int64_t n_instr, int32_t n_sub, int32_t warm_max, int64_t* start, int64_t* len,
+                  int32_t* warm) {
+  if (n_sub < 1 || n_instr < n_sub || warm_max < 0 || !start || !len || !warm)
+    return SIM_EINVAL;
+  const int64_t q = n_instr / n_sub, r = n_instr % n_sub;
+  int64_t at = 0;
+  for (int32_t k = 0; k < n_sub; ++k) {
+    start[k] = at;
+    len[k] = q + (k < r ? 1 : 0);
+    warm[k] = (int32_t)(at < warm_max ? at : warm_max);
+    at += len[k];
+  }
+  return SIM_OK;
+}
+
 int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   if (!out) return SIM_EINVAL;
   *out = nullptr;

@@ -84,11 +84,21 @@ def test_validate_rejects_bad_trace():
 
 
 def test_partition_matches_oracle(oracle_lib):
-    for N, K, wm in [(1_000_000, 4096, 256), (10, 3, 0), (1000, 7, 300), (5, 5, 2)]:
+    """sim_partition (library, host) against the oracle's partition."""
+    for N, K, wm in [(1_000_000, 4096, 256), (10, 3, 0), (1000, 7, 300), (5, 5, 2),
+                     (748_000_123, 20_000, 256), (1, 1, 9)]:
         a = sn.partition(N, K, wm)
         b = oracle_lib.partition(N, K, wm)
         for x, y in zip(a, b):
             np.testing.assert_array_equal(x, y)
+
+
+def test_partition_rejects_bad_arguments():
+    for N, K, wm in [(10, 0, 0), (3, 4, 0), (10, 2, -1), (0, 1, 0)]:
+        with pytest.raises(ValueError):
+            sn.partition(N, K, wm)
+    z = np.zeros(2, np.int64)
+    assert sn.lib().sim_partition(10, 2, 0, None, z.ctypes.data, z.ctypes.data) == sn.SIM_EINVAL
 
 
 def test_product_does_not_import_oracle():
