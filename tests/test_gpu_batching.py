@@ -200,3 +200,64 @@ def test_autotune_choice_does_not_change_results(torch, sn, tmp_path):
     with pytest.raises(sn.SimError):
         sim.set_tuning(3, 1)
     sim.close()
+
+
+def test_c3_uneven_full_run_sampled_replay(torch, sn, oracle_lib):
+    """The uneven-streams workload at its full size (20,000 streams of
+    log-uniform length in [1e3, 2e5], packed codes, BF16), run as one graph
+    in the autotuned launch shape, as the benchmark runs it.  The 32 shortest
+    streams and 4 seeded-random ones (among those of at most 4,000
+    instructions, so that the FP64 oracle finishes in seconds) are replayed
+    by the oracle's BF16 form from the GPU's own latencies: identical cycles,
+    outputs within one BF16 unit at the output's magnitude, and the oracle's
+    own rounding decisions equal outside that tie band."""
+    wl = synth.workload("c3_uneven")
+    length = synth.loguniform_lengths(wl.length_seed, wl.n_sub, *wl.len_range)
+    start = np.concatenate([[0], np.cumsum(length)[:-1]]).astype(np.int64)
+    warm = np.zeros(wl.n_sub, np.int32)
+    n_instr = int(length.sum())
+    dcodes = torch.empty(n_instr, dtype=torch.int32, device="cuda")
+    for lo in range(0, n_instr, 1 << 26):
+        hi = min(n_instr, lo + (1 << 26))
+        dcodes[lo:hi] = synth.trace_codes_torch(wl.trace_seed, lo, hi, device="cuda")
+    ws, bs = synth.init_weights(wl.weight_seed, wl.layers,
+                                out_bias=wl.extra.get("out_bias", synth.OUT_BIAS))
+    sim = sn.Simulator(dcodes, wl.n_slot, wl.cols, start, length, warm, prec=sn.SIM_BF16,
+                       n_feat=wl.n_feat)
+    sim.load_weights(wl.layers, sn.flat_params(ws, bs))
+    sim.autotune(300)
+    logits = torch.zeros((n_instr, 2), dtype=torch.float32, device="cuda")
+    sim.record_logits(logits)
+    sim.use_graph(True)
+    g = sim.run()
+    assert g["measured"] == n_instr and g["n_nonfinite"] == 0
+    assert g["total"] == int((g["final"] - g["warm_tick"]).sum())
+    assert np.array_equal(g["final"], g["warm_tick"] + g["fetch"] + g["drain"])
+    assert np.all(g["fetch"] >= 0) and np.all(g["drain"] >= 0)
+
+    rng = np.random.default_rng(17)
+    short = np.argsort(length, kind="stable")[:32]
+    pool = np.setdiff1d(np.flatnonzero(length <= 4000), short)
+    ks = np.sort(np.concatenate([short, rng.choice(pool, 4, replace=False)]))
+    gl = np.concatenate([logits[start[k]:start[k] + length[k]].cpu().numpy() for k in ks])
+    sim.close()
+    del logits
+    gl = gl.astype(np.float64)
+    lat = np.clip(np.rint(gl), 0, 65535).astype(np.int32)
+    feat = np.concatenate([synth.expand_codes(synth.trace_codes(wl.trace_seed, n_instr,
+                                                                int(start[k]),
+                                                                int(start[k] + length[k])),
+                                              wl.n_feat) for k in ks])
+    s_len = length[ks].astype(np.int64)
+    s_start = np.concatenate([[0], np.cumsum(s_len)[:-1]]).astype(np.int64)
+    cfg = oracle_lib.sim_cfg(wl.n_feat, wl.n_slot, 2, wl.retire_width, wl.cols)
+    form = oracle_lib.Model(wl.layers, ws, bs, wl.n_feat, wl.n_slot, prec=1)
+    rep = oracle_lib.simulate(cfg, feat, s_start, s_len, np.zeros(len(ks), np.int32), model=form,
+                              mode=oracle_lib.INJECT, lat_table=lat, want_logits=True,
+                              want_scale=True)
+    for key in ("fetch", "drain", "final", "warm_tick"):
+        np.testing.assert_array_equal(rep[key], g[key][ks], err_msg=key)
+    tol = 2.0 ** -8
+    assert rel_err(gl, rep["logits"], rep["scale"]).max() <= tol
+    lat_o = np.clip(np.rint(rep["logits"]), 0, 65535).astype(np.int32)
+    assert not np.any((lat_o != lat) & ~near_half(rep["logits"], rep["scale"], tol))
