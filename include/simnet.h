@@ -306,6 +306,22 @@ SIMNET_API int64_t predictor_save_bytes(const sim_ctx* ctx, int64_t B);
 SIMNET_API int sim_loss(sim_ctx* ctx, const float* logits, const int32_t* labels, int64_t B,
                         float* loss, float* dlogits);
 
+/* Largest batch of sim_loss_noalloc. */
+#define SIM_NOALLOC_MAX_B 65536
+
+/* sim_loss for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving or training loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results, bit for bit, but
+ * the per-window losses go to a static device buffer of SIM_NOALLOC_MAX_B
+ * floats (256 KB per GPU, held until the process ends) instead of the
+ * context's workspace, and nothing is allocated or freed.  Every call on a
+ * GPU shares that GPU's buffer: calls that overlap on one GPU (other
+ * streams, other contexts, other threads) race and must be ordered by the
+ * caller.  Nothing in it needs clearing between calls (each call writes the
+ * B entries it reads).  SIM_EINVAL when B > SIM_NOALLOC_MAX_B. */
+SIMNET_API int sim_loss_noalloc(sim_ctx* ctx, const float* logits, const int32_t* labels,
+                                int64_t B, float* loss, float* dlogits);
+
 /* Backward of predictor_fwd (training head; the predictor of Sec. 2.3 trained
  * on the hybrid loss as Sec. 4 sets up), the chain rule through the
  * head, the hidden layer, the three convolutions and their ReLUs: x and save

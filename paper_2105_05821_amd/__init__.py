@@ -21,6 +21,7 @@ SIM_FP32, SIM_BF16, SIM_FP8E4M3 = 0, 1, 2
 SIM_LAT_PREDICT, SIM_LAT_INJECT, SIM_LAT_SHADOW = 0, 1, 2
 SIM_FEAT_F32, SIM_FEAT_CODE32 = 0, 1
 CONV, FC = 0, 1
+NOALLOC_MAX_B = 65536  # SIM_NOALLOC_MAX_B: largest batch of sim_loss_noalloc
 
 STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVICE",
                 -4: "SIM_ESTATE", -5: "SIM_ENONFINITE", -6: "SIM_EUNSUPPORTED"}
@@ -29,7 +30,8 @@ EXPORTED = ("sim_validate_config", "sim_partition", "sim_init", "sim_load_weight
             "sim_run",
             "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
             "sim_autotune", "sim_set_tuning",
-            "predictor_fwd", "predictor_save_bytes", "sim_loss", "predictor_bwd", "sim_adam",
+            "predictor_fwd", "predictor_save_bytes", "sim_loss", "sim_loss_noalloc",
+            "predictor_bwd", "sim_adam",
             "sim_destroy", "sim_last_error")
 
 
@@ -94,6 +96,7 @@ def lib():
         L.sim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, C.POINTER(sim_tuning)]
         L.sim_set_tuning.argtypes = [P, C.c_int32, C.c_int32]
         L.sim_loss.argtypes = [P, P, P, C.c_int64, P, P]
+        L.sim_loss_noalloc.argtypes = [P, P, P, C.c_int64, P, P]
         L.predictor_bwd.argtypes = [P, P, P, P, C.c_int64, P, P, C.c_int32]
         L.sim_adam.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float,
                                C.c_float, C.c_int32]
@@ -371,15 +374,20 @@ class Predictor:
                                                          logits.data_ptr(), save.data_ptr()))
         return logits, save
 
-    def loss(self, logits, labels):
-        """Mean hybrid loss (device scalar) and its gradient w.r.t. logits."""
+    def loss(self, logits, labels, out=None, noalloc: bool = False):
+        """Mean hybrid loss (device scalar) and its gradient w.r.t. logits.
+        out = (loss, dlogits) device tensors to write into; noalloc selects
+        sim_loss_noalloc (the library's static scratch, no allocation)."""
         import torch
         if labels.dtype != torch.int32 or not labels.is_contiguous():
             raise ValueError("labels must be contiguous int32 [B][2]")
         B = logits.shape[0]
-        loss = torch.empty((), dtype=torch.float32, device=logits.device)
-        dz = torch.empty_like(logits)
-        self._check("sim_loss", lib().sim_loss(self.ctx, logits.data_ptr(), labels.data_ptr(), B,
+        if out is None:
+            out = (torch.empty((), dtype=torch.float32, device=logits.device),
+                   torch.empty_like(logits))
+        loss, dz = out
+        name = "sim_loss_noalloc" if noalloc else "sim_loss"
+        self._check(name, getattr(lib(), name)(self.ctx, logits.data_ptr(), labels.data_ptr(), B,
                                                loss.data_ptr(), dz.data_ptr()))
         return loss, dz
 

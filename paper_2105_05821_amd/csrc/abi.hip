@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -80,9 +81,39 @@ struct sim_ctx {
   DevState st{};
   DevWeights w{};
   std::string err;
+  float* scratch = nullptr;  // this device's address of `scratch` (sim_loss_noalloc)
 };
 
+// Device scratch of sim_loss_noalloc: the per-window losses before their
+// fixed-order mean.  One copy per GPU the library runs on, held until the
+// process ends.  Host code never passes this name to a kernel or a copy (on
+// the host it is only a stand-in for the symbol): it uses the address that
+// hipGetSymbolAddress returns for the device.
+static __device__ __align__(256) float scratch[SIM_NOALLOC_MAX_B];
+
 namespace {
+
+constexpr int SCRATCH_DEVICES = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[SCRATCH_DEVICES] = {};  // per device id, once resolved
+
+// The address of `scratch` on the current device (resolved once per device,
+// with that device current).
+hipError_t scratch_address(float** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= SCRATCH_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[dev] = static_cast<float*>(ptr);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
 
 int fail(sim_ctx* c, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 int fail(sim_ctx* c, int code, const char* fmt, ...) {
@@ -768,6 +799,14 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   c->cfg = *cfg;
   c->C = cfg->n_slot - 1;
   c->stream = static_cast<hipStream_t>(cfg->stream);
+  {
+    const hipError_t e = scratch_address(&c->scratch);
+    if (e != hipSuccess) {
+      fprintf(stderr, "sim_init: device scratch: %s\n", hipGetErrorString(e));
+      delete c;
+      return SIM_EDEVICE;
+    }
+  }
   if (tr->n_sub == 0) {  // predictor-only: forward/backward on explicit windows
     c->has_trace = false;
     *out = c;
@@ -1382,6 +1421,22 @@ int sim_loss(sim_ctx* c, const float* logits, const int32_t* labels, int64_t B, 
   int rc = ensure_train_work(c, B);
   if (rc != SIM_OK) return rc;
   hipError_t e = launch_loss(logits, labels, B, TRAIN_BINS, c->tr.work, loss, dlogits, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "loss");
+  return SIM_OK;
+}
+
+int sim_loss_noalloc(sim_ctx* c, const float* logits, const int32_t* labels, int64_t B,
+                     float* loss, float* dlogits) {
+  if (!c) return SIM_EINVAL;
+  if (c->net != 2) return fail(c, SIM_EUNSUPPORTED, "the loss needs the training head");
+  if (B < 1 || !logits || !labels || !loss || !dlogits) return fail(c, SIM_EINVAL, "bad arguments");
+  if (B > SIM_NOALLOC_MAX_B)
+    return fail(c, SIM_EINVAL, "B = %lld exceeds the scratch's %d windows", (long long)B,
+                SIM_NOALLOC_MAX_B);
+  if (!c->scratch) return fail(c, SIM_ESTATE, "no device scratch");
+  // the same kernels as sim_loss, the per-window losses in this device's
+  // static scratch instead of the context's training workspace
+  hipError_t e = launch_loss(logits, labels, B, TRAIN_BINS, c->scratch, loss, dlogits, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "loss");
   return SIM_OK;
 }

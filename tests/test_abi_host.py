@@ -125,3 +125,9 @@ def test_validate_dependency_flag_config():
     assert sn.sim_validate_config(cfg, tr2) == sn.SIM_EINVAL
     cfg.col_dep = 44                                     # 44..48 covers residence (47)
     assert sn.sim_validate_config(cfg, tr2) == sn.SIM_EINVAL
+
+
+def test_noalloc_limit_matches_header():
+    text = open(os.path.join(ROOT, "include", "simnet.h")).read()
+    m = re.search(r"#define\s+SIM_NOALLOC_MAX_B\s+(\d+)", text)
+    assert m and int(m.group(1)) == sn.NOALLOC_MAX_B
