@@ -478,6 +478,95 @@ __global__ void __launch_bounds__(256) strided_reduce(const float* __restrict__ 
   }
 }
 
+// The same sums for long lists (cnt >= 64 partials): L lanes per output
+// (16 or 64, one wave), lane l summing partials c = l, l + L, ... in order,
+// then the L lane sums combined by a fixed butterfly (xor L/2, ..., 1), so
+// the order is fixed and the latency is that of cnt / L loads, not cnt / 4.
+template <bool GEMM>
+__global__ void __launch_bounds__(256) strided_reduce_tree(const float* __restrict__ src,
+                                                           int64_t cnt, int64_t stride, int64_t N,
+                                                           int L, GemmArgs g,
+                                                           float* __restrict__ out, int beta) {
+  const int per_wg = 256 / L, sub = threadIdx.x % L;
+  const int64_t n = (int64_t)blockIdx.x * per_wg + threadIdx.x / L;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  if (n < N) {
+    int64_t c = sub;
+    for (; c + 3 * L < cnt; c += 4 * L) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += src[(c + u * L) * stride + n];
+    }
+    for (; c < cnt; c += L) acc[0] += src[c * stride + n];
+  }
+  float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int off = L / 2; off >= 1; off /= 2) v += __shfl_xor(v, off);
+  if (sub == 0 && n < N) {
+    if constexpr (GEMM) {
+      gemm_store(g, n / g.N, n % g.N, v);
+    } else {
+      out[n] = beta ? out[n] + v : v;
+    }
+  }
+}
+
+// 16 waves per 64 outputs (coalesced: a wave reads 64 adjacent outputs of
+// one partial), wave w summing partials c = w, w + 16, ... in order, the 16
+// wave sums then combined in LDS by a fixed pairwise tree: for long lists
+// of partials of many outputs (the split-K weight gradients).
+template <bool GEMM>
+__global__ void __launch_bounds__(1024) strided_reduce_wide(const float* __restrict__ src,
+                                                            int64_t cnt, int64_t stride, int64_t N,
+                                                            GemmArgs g, float* __restrict__ out,
+                                                            int beta) {
+  __shared__ float red[16][64];
+  const int col = threadIdx.x % 64, w = threadIdx.x / 64;
+  const int64_t n = (int64_t)blockIdx.x * 64 + col;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  if (n < N) {
+    int64_t c = w;
+    for (; c + 48 < cnt; c += 64) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += src[(c + 16 * u) * stride + n];
+    }
+    for (; c < cnt; c += 16) acc[0] += src[c * stride + n];
+  }
+  red[w][col] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  __syncthreads();
+  for (int h = 8; h >= 1; h /= 2) {
+    if (w < h) red[w][col] += red[w + h][col];
+    __syncthreads();
+  }
+  if (w == 0 && n < N) {
+    const float v = red[0][col];
+    if constexpr (GEMM) {
+      gemm_store(g, n / g.N, n % g.N, v);
+    } else {
+      out[n] = beta ? out[n] + v : v;
+    }
+  }
+}
+
+// Reduce cnt partials of N outputs (see strided_reduce) with the kernel
+// that suits the shape: few outputs and a long list (the bias sums): many
+// lanes per output; many outputs and a long list: 16 waves per 64 outputs;
+// otherwise 4.
+template <bool GEMM>
+static void launch_reduce(const float* src, int64_t cnt, int64_t stride, int64_t N,
+                          const GemmArgs& g, float* out, int beta, hipStream_t stream) {
+  if (cnt >= 64 && N <= 1024) {
+    const int L = cnt >= 256 ? 64 : 16;
+    const int64_t per_wg = 256 / L;
+    hipLaunchKernelGGL(strided_reduce_tree<GEMM>, dim3((unsigned)((N + per_wg - 1) / per_wg)),
+                       dim3(256), 0, stream, src, cnt, stride, N, L, g, out, beta);
+  } else if (cnt >= 64) {
+    hipLaunchKernelGGL(strided_reduce_wide<GEMM>, dim3((unsigned)((N + 63) / 64)), dim3(1024), 0,
+                       stream, src, cnt, stride, N, g, out, beta);
+  } else {
+    hipLaunchKernelGGL(strided_reduce<GEMM>, dim3((unsigned)((N + 63) / 64)), dim3(256), 0,
+                       stream, src, cnt, stride, N, g, out, beta);
+  }
+}
+
 // Operand access mode for the BF16 kernel (see gemm_bf16_kernel) and the
 // vector reads a run of 16 elements allows: 2 = 16-byte, 1 = 8-byte (rows
 // of an odd multiple of 8 bytes apart, e.g. windows of 111 x 50 FP32
@@ -545,8 +634,7 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, stream, g);
   if (ks > 1) {
     const int64_t MN = g.M * g.N;
-    hipLaunchKernelGGL(strided_reduce<true>, dim3((unsigned)((MN + 63) / 64)), dim3(256), 0, stream,
-                       part, ks, MN, MN, g, nullptr, 0);
+    launch_reduce<true>(part, ks, MN, MN, g, nullptr, 0, stream);
   }
   return hipGetLastError();
 }
@@ -654,8 +742,7 @@ hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float
   hipLaunchKernelGGL(colsum_partial, dim3(nb, (unsigned)chunks), dim3(256), 0, stream, y, M, N, ld,
                      per, work);
   GemmArgs none{};
-  hipLaunchKernelGGL(strided_reduce<false>, dim3(nb), dim3(256), 0, stream, work, chunks, N, N,
-                     none, out, beta);
+  launch_reduce<false>(work, chunks, N, N, none, out, beta, stream);
   return hipGetLastError();
 }
 
