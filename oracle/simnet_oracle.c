@@ -824,10 +824,12 @@ static void* train_worker(void* arg) {
       for (int i = 0; i < ci * li; ++i) g[l][i] = 0.0;
       for (int o = 0; o < co; ++o)
         for (int p = 0; p < lo; ++p) {
-          /* BF16 form: the output gradient enters the weight and input
-           * products rounded to bfloat16, the bias gradient unrounded */
+          /* BF16 form: the output gradient of a hidden layer is kept in
+           * bfloat16 (it enters the weight, input and bias gradients
+           * rounded); the head's, the loss gradient, enters the weight and
+           * input products rounded and its bias gradient unrounded */
           const double dy = qform(m, g[l + 1][o * lo + p]);
-          gb[o] += g[l + 1][o * lo + p];
+          gb[o] += l < NL - 1 ? dy : g[l + 1][o * lo + p];
           if (kind == OL_CONV) {
             for (int c = 0; c < ci; ++c)
               for (int t = 0; t < 2; ++t) {
@@ -860,8 +862,9 @@ static void* train_worker(void* arg) {
  * input.  The network's last layer must have 2 * (n_bins + 1) outputs.
  * A BF16-form model (prec 1) evaluates the forward as ol_forward's BF16
  * form and, in the backward, rounds each layer's output gradient to
- * bfloat16 where it multiplies weights or activations (the bias gradient
- * sums it unrounded); sums stay exact FP64. */
+ * bfloat16: a hidden layer's everywhere it is used (weight, input and bias
+ * gradients), the head's where it multiplies weights or activations (the
+ * head's bias gradient sums it unrounded); sums stay exact FP64. */
 int ol_train(const void* p, int64_t B, const double* x, const int32_t* lat, int32_t n_bins,
              double* loss, double* dparams, double* dlogits, double* dx, int32_t n_threads) {
   const ol_model* m = (const ol_model*)p;

@@ -1466,14 +1466,18 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   auto run = [&](const GemmArgs& g) {
     if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
   };
-  auto colsum = [&](const float* y, int64_t M, int64_t N, float* out) {
-    if (e == hipSuccess) e = launch_colsum(y, M, N, N, out, beta, csw, c->stream);
+  auto colsum = [&](const void* y, int y_bf16, int64_t M, int64_t N, float* out) {
+    if (e == hipSuccess) e = launch_colsum(y, y_bf16, M, N, N, out, beta, csw, c->stream);
   };
   auto scatter = [&](int l, float* dst) {
     if (e == hipSuccess)
       e = launch_map_scatter(dWt, T.maps + T.map_perm[l], (int64_t)T.n_perm[l], dst, beta,
                              c->stream);
   };
+  // The output gradients of the hidden layer and the convolutions (dH, dY3,
+  // dY2, dY1, masked by their layer's ReLU) are written in the form's
+  // precision: BF16 in the BF16 form, where every product and the bias sum
+  // take them rounded; FP32 in the FP32 form.
   // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H.
   // dZ is read from a copy with rows padded to TRAIN_LD (dY1's space, free
   // until conv2's input gradient), so both products read it in vectors.
@@ -1482,43 +1486,47 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   GemmArgs g = gemm(opnd(dZp, 0, TRAIN_LD, 1), opnd(P + T.woff[4], 0, 512, 1), dH, 512, B,
                     512, TRAIN_OUT, 0);
   g.mask = opnd(sb.h, bf, 512, 1);
+  g.c_bf16 = bf;
   run(g);
   run(gemm(opnd(dZp, 0, 1, TRAIN_LD), opnd(sb.h, bf, 512, 1), dparams + T.woff[4], 512,
            TRAIN_OUT, 512, B, beta));
-  colsum(dlogits, B, TRAIN_OUT, dparams + T.boff[4]);
+  colsum(dlogits, 0, B, TRAIN_OUT, dparams + T.boff[4]);
   // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU
-  g = gemm(opnd(dH, 0, 512, 1), opnd(T.perm + T.perm_off[3], 0, 3328, 1), dY3, 3328, B, 3328,
+  g = gemm(opnd(dH, bf, 512, 1), opnd(T.perm + T.perm_off[3], 0, 3328, 1), dY3, 3328, B, 3328,
            512, 0);
   g.mask = opnd(sb.a3, bf, 3328, 1);
+  g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dH, 0, 1, 512), opnd(sb.a3, bf, 3328, 1), dWt, 3328, 512, 3328, B, 0));
+  run(gemm(opnd(dH, bf, 1, 512), opnd(sb.a3, bf, 3328, 1), dWt, 3328, 512, 3328, B, 0));
   scatter(3, dparams);
-  colsum(dH, B, 512, dparams + T.boff[3]);
+  colsum(dH, bf, B, 512, dparams + T.boff[3]);
   // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
-  g = gemm(opnd(dY3, 0, 256, 1), opnd(T.perm + T.perm_off[2], 0, 256, 1), dY2, 256, B * 13, 256,
+  g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], 0, 256, 1), dY2, 256, B * 13, 256,
            256, 0);
   g.mask = opnd(sb.a2, bf, 256, 1);
+  g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dY3, 0, 1, 256), opnd(sb.a2, bf, 256, 1), dWt, 256, 256, 256, B * 13, 0));
+  run(gemm(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), dWt, 256, 256, 256, B * 13, 0));
   scatter(2, dparams);
-  colsum(dY3, B * 13, 256, dparams + T.boff[2]);
+  colsum(dY3, bf, B * 13, 256, dparams + T.boff[2]);
   // conv2: rows (b, p), 26 per window
-  g = gemm(opnd(dY2, 0, 128, 1), opnd(T.perm + T.perm_off[1], 0, 128, 1), dY1, 128, B * 26, 128,
+  g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], 0, 128, 1), dY1, 128, B * 26, 128,
            128, 0);
   g.mask = opnd(sb.a1, bf, 128, 1);
+  g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dY2, 0, 1, 128), opnd(sb.a1, bf, 128, 1), dWt, 128, 128, 128, B * 26, 0));
+  run(gemm(opnd(dY2, bf, 1, 128), opnd(sb.a1, bf, 128, 1), dWt, 128, 128, 128, B * 26, 0));
   scatter(1, dparams);
-  colsum(dY2, B * 26, 128, dparams + T.boff[1]);
+  colsum(dY2, bf, B * 26, 128, dparams + T.boff[1]);
   // conv1: rows (b, p), 52 per window; input pairs of window slots, rows of
   // window b at x + b*111*50 (the last 7 slots feed no output)
   const int64_t win = (int64_t)c->cfg.n_slot * c->cfg.n_feat;
-  run(gemm(opnd(dY1, 0, 1, 64), opnd(x, 0, 100, 1, 52, win), dWt, 100, 64, 100, B * 52, 0));
+  run(gemm(opnd(dY1, bf, 1, 64), opnd(x, 0, 100, 1, 52, win), dWt, 100, 64, 100, B * 52, 0));
   scatter(0, dparams);
-  colsum(dY1, B * 52, 64, dparams + T.boff[0]);
+  colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
   if (dx) {
     if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);
-    g = gemm(opnd(dY1, 0, 64, 1), opnd(T.perm + T.perm_off[0], 0, 100, 1), dx, 100, B * 52, 100,
+    g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], 0, 100, 1), dx, 100, B * 52, 100,
              64, 0);
     g.cgrp = 52;
     g.cgs = win;

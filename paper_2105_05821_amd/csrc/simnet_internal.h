@@ -225,7 +225,9 @@ struct GemmOperand {
   int64_t rs, cs, grp, gs;
 };
 // C[M][N] (+)= A(m, k) B(k, n) [+ bias[n]], then zeroed where mask(m, n) <= 0;
-// C(m, n) at C + (m / cgrp) * cgs + (m % cgrp) * ldc + n.
+// C(m, n) at C + (m / cgrp) * cgs + (m % cgrp) * ldc + n, FP32, or (c_bf16)
+// rounded to BF16 (nearest even) at the same element offsets of a uint16_t
+// array (no accumulation then).
 struct GemmArgs {
   GemmOperand A, B, mask;
   float* C;
@@ -233,6 +235,7 @@ struct GemmArgs {
   int64_t M, N, K;
   const float* bias;
   int32_t beta;
+  int32_t c_bf16;
   // set by launch_gemm
   int32_t ksplit, amode, avec, bmode, bvec, evec;
   float* part;
@@ -244,8 +247,9 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
 hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
                        float* loss_b, float* loss, float* dz, hipStream_t stream);
 size_t colsum_workspace(int64_t N);
-hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float* out, int beta,
-                         float* work, hipStream_t stream);
+// Column sums of y [M][ld] (FP32, or BF16 with y_bf16) into out[N] (+= with beta).
+hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
+                         int beta, float* work, hipStream_t stream);
 hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
                            hipStream_t stream);
 // dst[i] = src[map[i]] (0 where map[i] < 0) for i < n, in FP32 or rounded

@@ -42,12 +42,23 @@ __device__ __forceinline__ int64_t op_index(const GemmOperand& o, int64_t r, int
   return grouped_row(r, o.grp, o.gs, o.rs) + c * o.cs;
 }
 
+// Nearest-even BF16 bits of a finite float.
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  const uint32_t u = __float_as_uint(x);
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
 // C(m, n) epilogue shared by every GEMM path: bias, ReLU mask, accumulate,
-// grouped row addressing.
+// grouped row addressing, BF16 output.
 __device__ __forceinline__ void gemm_store(const GemmArgs& g, int64_t m, int64_t n, float v) {
   if (g.bias) v += g.bias[n];
   if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, op_index(g.mask, m, n)) > 0.f)) v = 0.f;
-  float* c = g.C + grouped_row(m, g.cgrp, g.cgs, g.ldc) + n;
+  const int64_t at = grouped_row(m, g.cgrp, g.cgs, g.ldc) + n;
+  if (g.c_bf16) {
+    reinterpret_cast<uint16_t*>(g.C)[at] = to_bf16(v);
+    return;
+  }
+  float* c = g.C + at;
   *c = g.beta ? *c + v : v;
 }
 
@@ -55,7 +66,7 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, int64_t m, int64_t
 // row's addresses computed once.
 __device__ __forceinline__ void gemm_store_row4(const GemmArgs& g, int64_t m, int64_t n0,
                                                 const float (&v)[4]) {
-  float* crow = g.C + grouped_row(m, g.cgrp, g.cgs, g.ldc);
+  const int64_t crow = grouped_row(m, g.cgrp, g.cgs, g.ldc);
   const int64_t mrow = g.mask.p ? grouped_row(m, g.mask.grp, g.mask.gs, g.mask.rs) : 0;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
@@ -64,7 +75,12 @@ __device__ __forceinline__ void gemm_store_row4(const GemmArgs& g, int64_t m, in
     float x = v[j];
     if (g.bias) x += g.bias[n];
     if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, mrow + n * g.mask.cs) > 0.f)) x = 0.f;
-    crow[n] = g.beta ? crow[n] + x : x;
+    if (g.c_bf16) {
+      reinterpret_cast<uint16_t*>(g.C)[crow + n] = to_bf16(x);
+    } else {
+      float* c = g.C + crow + n;
+      *c = g.beta ? *c + x : x;
+    }
   }
 }
 
@@ -183,10 +199,6 @@ constexpr int HB = 128, HK = 32, HLD = HK + 8;
 
 typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 
-__device__ __forceinline__ uint16_t bf16_rne(float x) {
-  const uint32_t u = __float_as_uint(x);
-  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
 
 struct Stage {
   float v[16];
@@ -285,13 +297,13 @@ __device__ __forceinline__ void stage_store(uint16_t (*S)[HLD], int mode, int ti
     const int k = tid / 8, outer = (tid % 8) * 16;
 #pragma unroll
     for (int e = 0; e < 16; ++e)
-      S[outer + e][8 * chunk_at(outer + e, k >> 3) + (k & 7)] = bf16_rne(st.v[e]);
+      S[outer + e][8 * chunk_at(outer + e, k >> 3) + (k & 7)] = to_bf16(st.v[e]);
   } else {
     const int outer = tid / 2, c0 = (tid % 2) * 2;
     uint32_t w[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      w[q] = (uint32_t)bf16_rne(st.v[2 * q]) | ((uint32_t)bf16_rne(st.v[2 * q + 1]) << 16);
+      w[q] = (uint32_t)to_bf16(st.v[2 * q]) | ((uint32_t)to_bf16(st.v[2 * q + 1]) << 16);
     *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0)]) = uint4{w[0], w[1], w[2], w[3]};
     *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0 + 1)]) =
         uint4{w[4], w[5], w[6], w[7]};
@@ -410,15 +422,29 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
           for (int e = 0; e < 16; ++e)
             if (!(mk[e] > 0.f)) v[e] = 0.f;
         }
-        float4* cp = reinterpret_cast<float4*>(g.C + grouped_row(mi, g.cgrp, g.cgs, g.ldc) + n);
+        const int64_t at = grouped_row(mi, g.cgrp, g.cgs, g.ldc) + n;
+        if (g.c_bf16) {
+          uint4* cp = reinterpret_cast<uint4*>(reinterpret_cast<uint16_t*>(g.C) + at);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          float4 o = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
-          if (g.beta) {
-            const float4 c = cp[q];
-            o = make_float4(c.x + o.x, c.y + o.y, c.z + o.z, c.w + o.w);
+          for (int h = 0; h < 2; ++h) {
+            uint32_t w[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              w[q] = (uint32_t)to_bf16(v[8 * h + 2 * q]) |
+                     ((uint32_t)to_bf16(v[8 * h + 2 * q + 1]) << 16);
+            cp[h] = uint4{w[0], w[1], w[2], w[3]};
           }
-          cp[q] = o;
+        } else {
+          float4* cp = reinterpret_cast<float4*>(g.C + at);
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            float4 o = make_float4(v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]);
+            if (g.beta) {
+              const float4 c = cp[q];
+              o = make_float4(c.x + o.x, c.y + o.y, c.z + o.z, c.w + o.w);
+            }
+            cp[q] = o;
+          }
         }
       }
       __syncthreads();
@@ -619,8 +645,9 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   // runs, C and the mask in 16-byte aligned rows contiguous along n
   {
     const int64_t mq = g.mask.bf16 ? 8 : 4;
-    const bool c_ok = reinterpret_cast<uintptr_t>(g.C) % 16 == 0 && g.ldc % 4 == 0 &&
-                      (g.cgrp >= NO_GROUP || g.cgs % 4 == 0);
+    const int64_t cq = g.c_bf16 ? 8 : 4;  // elements per 16 bytes of C
+    const bool c_ok = reinterpret_cast<uintptr_t>(g.C) % 16 == 0 && g.ldc % cq == 0 &&
+                      (g.cgrp >= NO_GROUP || g.cgs % cq == 0);
     const bool m_ok = !g.mask.p || (g.mask.cs == 1 &&
                                     reinterpret_cast<uintptr_t>(g.mask.p) % 16 == 0 &&
                                     g.mask.rs % mq == 0 &&
@@ -707,40 +734,72 @@ hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_
 // summed by 4 row lanes x 64 columns per workgroup, then the chunk partials
 // through strided_reduce.
 constexpr int CS_MAX_CHUNKS = 1024;
-__global__ void __launch_bounds__(256) colsum_partial(const float* __restrict__ y, int64_t M,
+// Partial column sums: workgroup (x, c) sums rows [c*per, (c+1)*per) of
+// columns [x*64*V, (x+1)*64*V), V adjacent columns per lane (V = 2 for BF16
+// input, read as one 32-bit word), 4 row lanes per column, in a fixed order.
+template <bool BF>
+__global__ void __launch_bounds__(256) colsum_partial(const void* __restrict__ yv, int64_t M,
                                                       int64_t N, int64_t ld, int64_t per,
                                                       float* __restrict__ part) {
-  __shared__ float red[4][64];
+  constexpr int V = BF ? 2 : 1;
+  __shared__ float red[4][64 * V];
   const int col = threadIdx.x % 64, lane4 = threadIdx.x / 64;
-  const int64_t n = (int64_t)blockIdx.x * 64 + col;
+  const int64_t n = ((int64_t)blockIdx.x * 64 + col) * V;
   const int64_t c = blockIdx.y, lo = c * per, hi = lo + per < M ? lo + per : M;
-  float acc[2] = {0.f, 0.f};
+  float acc[2][V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[0][v] = acc[1][v] = 0.f;
+  auto add = [&](int slot, int64_t m) {
+    if constexpr (BF) {
+      const uint16_t* y = static_cast<const uint16_t*>(yv) + m * ld + n;
+      if (n + 1 < N) {  // (ld and n even: 4-byte aligned)
+        const uint32_t w = *reinterpret_cast<const uint32_t*>(y);
+        acc[slot][0] += __uint_as_float(w << 16);
+        acc[slot][1] += __uint_as_float(w & 0xffff0000u);
+      } else {
+        acc[slot][0] += __uint_as_float((uint32_t)y[0] << 16);
+      }
+    } else {
+      acc[slot][0] += static_cast<const float*>(yv)[m * ld + n];
+    }
+  };
   if (n < N) {
     int64_t m = lo + lane4;
     for (; m + 4 < hi; m += 8) {
-      acc[0] += y[m * ld + n];
-      acc[1] += y[(m + 4) * ld + n];
+      add(0, m);
+      add(1, m + 4);
     }
-    for (; m < hi; m += 4) acc[0] += y[m * ld + n];
+    for (; m < hi; m += 4) add(0, m);
   }
-  red[lane4][col] = acc[0] + acc[1];
+#pragma unroll
+  for (int v = 0; v < V; ++v) red[lane4][col * V + v] = acc[0][v] + acc[1][v];
   __syncthreads();
-  if (lane4 == 0 && n < N)
-    part[c * N + n] = (red[0][col] + red[1][col]) + (red[2][col] + red[3][col]);
+  if (lane4 == 0)
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (n + v < N)
+        part[c * N + n + v] = (red[0][col * V + v] + red[1][col * V + v]) +
+                              (red[2][col * V + v] + red[3][col * V + v]);
 }
 
 size_t colsum_workspace(int64_t N) { return sizeof(float) * CS_MAX_CHUNKS * (size_t)N; }
 
-hipError_t launch_colsum(const float* y, int64_t M, int64_t N, int64_t ld, float* out, int beta,
-                         float* work, hipStream_t stream) {
+hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
+                         int beta, float* work, hipStream_t stream) {
   if (N <= 0) return hipSuccess;
   int64_t chunks = (M + 63) / 64;
   if (chunks > CS_MAX_CHUNKS) chunks = CS_MAX_CHUNKS;
   if (chunks < 1) chunks = 1;
   const int64_t per = (M + chunks - 1) / chunks;
-  const unsigned nb = (unsigned)((N + 63) / 64);
-  hipLaunchKernelGGL(colsum_partial, dim3(nb, (unsigned)chunks), dim3(256), 0, stream, y, M, N, ld,
-                     per, work);
+  // (BF16: two adjacent columns per lane, which needs even N and ld)
+  if (y_bf16 && N % 2 == 0 && ld % 2 == 0)
+    hipLaunchKernelGGL(colsum_partial<true>, dim3((unsigned)((N + 127) / 128), (unsigned)chunks),
+                       dim3(256), 0, stream, y, M, N, ld, per, work);
+  else if (y_bf16)
+    return hipErrorInvalidValue;
+  else
+    hipLaunchKernelGGL(colsum_partial<false>, dim3((unsigned)((N + 63) / 64), (unsigned)chunks),
+                       dim3(256), 0, stream, y, M, N, ld, per, work);
   GemmArgs none{};
   launch_reduce<false>(work, chunks, N, N, none, out, beta, stream);
   return hipGetLastError();

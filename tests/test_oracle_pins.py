@@ -644,8 +644,10 @@ class _RoundValue(torch.autograd.Function):
 def test_training_bf16_form_matches_torch_autograd(oracle_lib, net):
     """The BF16 training form against torch autograd over the same
     roundings: input, weights and hidden outputs rounded to bfloat16 in the
-    forward; each layer's output gradient rounded where it multiplies
-    (RoundGrad before the bias-free product), the bias gradient unrounded."""
+    forward; a hidden layer's output gradient rounded before it reaches the
+    weights, the input and the bias (RoundGrad around the biased sum); the
+    head's rounded where it multiplies (RoundGrad before the bias-free
+    product), its bias gradient unrounded."""
     layers = small_hybrid_net() if net == "small" else synth.net_c3_hybrid()
     D, L = (32, 16) if net == "small" else (50, 111)
     B = 5
@@ -661,12 +663,14 @@ def test_training_bf16_form_matches_torch_autograd(oracle_lib, net):
     for i, ly in enumerate(layers):
         w = _RoundValue.apply(params[2 * i])  # the gradient w.r.t. w stays unrounded
         b = params[2 * i + 1]
+        last = i == len(layers) - 1
         if ly.kind == synth.CONV:
             z = torch.nn.functional.conv1d(h, w, None, stride=2)
-            h = _RoundGrad.apply(z) + b[None, :, None]
+            bb = b[None, :, None]
         else:
             z = torch.nn.functional.linear(h.reshape(h.shape[0], -1), w, None)
-            h = _RoundGrad.apply(z) + b
+            bb = b
+        h = _RoundGrad.apply(z) + bb if last else _RoundGrad.apply(z + bb)
         if ly.relu:
             h = torch.relu(h)
         if i < len(layers) - 1:
