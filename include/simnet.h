@@ -222,7 +222,10 @@ SIMNET_API int sim_set_graph(sim_ctx* ctx, int32_t enable);
 
 /* Launch shape of the step kernel as chosen by sim_autotune. */
 typedef struct {
-  int32_t variant;            /* kernel variant (hidden-FC weight prefetch depth) */
+  int32_t variant;            /* kernel variant: C3 network, the hidden-FC weight
+                                 prefetch depth (0, 1, 2: 8, 16, 4 fragments); small
+                                 network in FP32, 0 = a workgroup per 16 slots, 1 = one
+                                 wavefront per slot */
   int32_t n_wg;               /* persistent workgroups (16 sub-trace slots each) */
   float ms;                   /* its time per million positions advanced in the trial */
   int32_t n_tried;            /* candidates timed (at most 16 listed) */
@@ -232,11 +235,14 @@ typedef struct {
 
 /* Time n_steps steps (lat_mode/lat_table as in sim_step) from the reset
  * state under each candidate launch shape: every kernel variant (the C3
- * network with the predictor running) x 4/4, 3/4 and 1/2 of the slots
- * sim_init allocated; keep the one with the least time per position
- * advanced and reset the simulation.  The
- * variants differ only in how far ahead weights are fetched, so results do
- * not depend on the choice.  Synchronises.  *out receives the choice and
+ * network with the predictor running, or the small network in FP32) x 4/4,
+ * 3/4 and 1/2 of the slots sim_init allocated; keep the one with the least
+ * time per position advanced and reset the simulation.  The C3 variants
+ * differ only in how far ahead weights are fetched, so results do not
+ * depend on the choice; the small network's two sum the same products in a
+ * different order (both within the FP32 bar of the FP64 oracle).  The small
+ * network's FP32 step starts as one wavefront per slot when the trace has
+ * at most 1,024 sub-traces.  Synchronises.  *out receives the choice and
  * the trials. */
 SIMNET_API int sim_autotune(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
                             const int32_t* lat_table, sim_tuning* out);

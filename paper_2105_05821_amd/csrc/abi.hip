@@ -752,6 +752,10 @@ static GemmArgs gemm(GemmOperand A, GemmOperand B, float* C, int64_t ldc, int64_
   return g;
 }
 
+// Sub-traces up to which the small network's FP32 step defaults to one
+// wavefront per sub-trace (sim_set_tuning / sim_autotune can change it).
+constexpr int32_t WAVE_MAX_SUB = 1024;
+
 extern "C" {
 
 int sim_validate_config(const sim_config* cfg, const sim_trace* trace) {
@@ -867,6 +871,9 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   const int per_cu = c->net == 0 ? 4 : 1;
   c->n_wg = (int32_t)std::min<int64_t>((K + MT - 1) / MT, (int64_t)n_cu * per_cu);
   c->n_wg_max = c->n_wg;
+  // the small network's FP32 step runs one wavefront per sub-trace when
+  // there are few (a step's latency bounds such runs)
+  if (c->net == 0 && cfg->prec == SIM_FP32 && K <= WAVE_MAX_SUB) c->variant = WAVE_VARIANT;
   const int32_t n_slots = c->n_wg * MT;
 
   // one device block: table + state + results + counters + total
@@ -1356,7 +1363,10 @@ int sim_autotune(sim_ctx* c, int32_t n_steps, int32_t lat_mode, const int32_t* l
   if (n_steps < 1 || !out) return fail(c, SIM_EINVAL, "bad arguments");
   // candidates: every kernel variant (C3 with the predictor running) x
   // 4/4, 3/4 and 1/2 of the slots
-  const int nv = (c->net == 1 && lat_mode != SIM_LAT_INJECT && c->cfg.col_dep < 0) ? N_VARIANTS : 1;
+  // (the small network's FP32 step: the workgroup tile or one wave per slot)
+  const int nv = (c->net == 1 && lat_mode != SIM_LAT_INJECT && c->cfg.col_dep < 0) ? N_VARIANTS
+                 : (c->net == 0 && c->cfg.prec == SIM_FP32)                       ? 2
+                                                                                  : 1;
   std::vector<int32_t> shapes;
   for (int q : {4, 3, 2}) {
     const int32_t n = std::max<int32_t>(1, c->n_wg_max * q / 4);

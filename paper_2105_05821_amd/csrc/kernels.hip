@@ -1281,6 +1281,318 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   }
 }
 
+// ------------------------------------------ one wavefront per sub-trace ---
+// The small network (16-slot windows of 32 features, conv 32 -> 32 -> 64,
+// FC 256 -> 2) when a run has few sub-traces, so that the time of one step,
+// not the throughput of many, bounds it: one wavefront (a workgroup of 64
+// threads, one sub-trace slot) per sub-trace, no barrier between waves.
+// The weights a lane needs stay in its registers for the whole launch; the
+// window and the conv1 output pass through 3 KB of LDS; the products are
+// VALU FMAs (a prediction is 33 k multiply-adds, ~520 cycles of one SIMD);
+// the final FC is a lane reduction, so every lane holds the logits, and the
+// clock and queue update runs on wave-uniform values, the retired prefix of
+// the queue counted by one ballot over its entries (their retire times are
+// non-decreasing along the queue).  FP32 form, row or packed-code traces.
+// Same state, work queue and results as step_kernel.
+constexpr int WV_D = NetSmall::D, WV_C = NetSmall::C, WV_L = NetSmall::L;
+constexpr int WV_C1 = NetSmall::CH1, WV_C2 = NetSmall::CH2, WV_NB = NetSmall::NB;
+
+// Element B[k][n] of a weight matrix packed by the FP32 form (k-groups of
+// 16, n-tiles of 16, lane = 16 * ((k % 16) / 4) + n % 16, 4 k per lane).
+__device__ __forceinline__ float packed_f32(const float* Bp, int N, int k, int n) {
+  const int kg = k >> 4, w = k & 15;
+  return Bp[((((size_t)kg * (N >> 4) + (n >> 4)) * 64 + ((w >> 2) << 4) + (n & 15)) << 2) +
+            (w & 3)];
+}
+
+template <bool RUN_NET>
+__global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t relu_mask,
+                                                       DevState st, StepParams p) {
+  __shared__ __attribute__((aligned(16))) float x[WV_L][WV_D];        // the window
+  __shared__ __attribute__((aligned(16))) float a1[WV_L / 2][WV_C1];  // conv1 output
+  __shared__ int32_t q_e[WV_C];               // the queue ring
+  __shared__ int64_t q_t[WV_C], q_r[WV_C];
+  __shared__ int64_t rw[WMAX];                // retire times of the last W instructions
+  __shared__ int claimed;
+  const int lane = threadIdx.x, slot = blockIdx.x;
+  constexpr int D = WV_D, C = WV_C;
+  const int W = p.W;
+
+  // weights this lane uses, kept in registers: conv1 output channel lane % 32
+  // (its positions: lane / 32, +2, +4, +6), conv2 output channel lane, the
+  // final FC's weights of conv2 channel lane at the 4 positions
+  float w1[2][D], w2[2][WV_C1], wf[WV_NB][2];
+  float b1 = 0.f, b2 = 0.f;
+  const int c1 = lane & (WV_C1 - 1), half = lane >> 5;
+  if (RUN_NET) {
+    const float* W1 = static_cast<const float*>(wt.conv_w[0]);
+    const float* W2 = static_cast<const float*>(wt.conv_w[1]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < D; ++c) w1[t][c] = packed_f32(W1, WV_C1, t * D + c, c1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < WV_C1; ++c) w2[t][c] = packed_f32(W2, WV_C2, t * WV_C1 + c, lane);
+#pragma unroll
+    for (int j = 0; j < WV_NB; ++j)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) wf[j][o] = wt.last_w[((size_t)j * 2 + o) * WV_C2 + lane];
+    b1 = wt.conv_b[0][c1];
+    b2 = wt.conv_b[1][lane];
+  }
+
+  // the slot's sub-trace (a finished or empty slot claims the next one)
+  int k = st.slot_kid[slot];
+  if (k < 0) {
+    if (lane == 0) claimed = claim_subtrace(st, p.n_sub);
+    __syncthreads();
+    k = claimed;
+  }
+  int64_t cur = 0, t_w = 0, r_prev = 0, pos = 0, first = 0, n_pos = 0, pred_off = 0;
+  int32_t head = 0, count = 0, warm = 0;
+  auto load_state = [&]() {
+    if (k < 0) return;
+    cur = st.cur[k];
+    t_w = st.t_w[k];
+    r_prev = st.r_prev[k];
+    pos = st.pos[k];
+    first = st.first[k];
+    n_pos = st.n_pos[k];
+    pred_off = st.pred_off[k];
+    head = st.head[k];
+    count = st.count[k];
+    warm = st.warm[k];
+    if (lane < C) {
+      const size_t g = (size_t)k * C + lane;
+      q_e[lane] = st.q_e[g];
+      q_t[lane] = st.q_t[g];
+      q_r[lane] = st.q_r[g];
+    }
+    if (lane < W) rw[lane] = st.rw[(size_t)k * WMAX + lane];
+    __syncthreads();
+  };
+  // the window's static rows stay in registers: lane (slot w, 8 features)
+  // holds trace row i - w; a step shifts them one slot (4 lanes) and takes
+  // the next instruction's row, requested a step ahead, into slot 0
+  const int ws = lane >> 2, wc = (lane & 3) * 8;
+  float rowv[8];
+  auto row_of = [&](int64_t row, float (&v)[8]) {
+    if (p.codes) {
+      const uint32_t code = p.codes[row];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = code_feature(code, wc + e);
+    } else {
+      const float4* src = reinterpret_cast<const float4*>(p.feat + row * D + wc);
+      const float4 lo = src[0], hi = src[1];
+      v[0] = lo.x; v[1] = lo.y; v[2] = lo.z; v[3] = lo.w;
+      v[4] = hi.x; v[5] = hi.y; v[6] = hi.z; v[7] = hi.w;
+    }
+  };
+  auto load_rows = [&]() {  // rows i - w that belong to the sub-trace
+#pragma unroll
+    for (int e = 0; e < 8; ++e) rowv[e] = 0.f;
+    if (RUN_NET && k >= 0 && pos < n_pos && ws <= pos) row_of(first + pos - ws, rowv);
+  };
+  load_state();
+  load_rows();
+  uint32_t n_clamped = 0, n_nonfinite = 0, n_mismatch = 0, n_pred = 0;
+
+  for (int it = 0; it < p.n_steps && k >= 0 && pos < n_pos; ++it) {
+    const int64_t i = first + pos, g = pred_off + pos;
+    float z[2] = {0.f, 0.f};
+    float nxt[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // row i + 1 (slot 0), next step
+    if (RUN_NET && ws == 0 && pos + 1 < n_pos) row_of(i + 1, nxt);
+    if (RUN_NET) {
+      // window: lane = (slot w, 8 features): the current instruction with
+      // zero dynamic columns, then the queue newest first (instructions
+      // i-1, i-2, ...: the queue holds consecutive ones), zeros past it
+      {
+        const int w = ws, c0 = wc;
+        float res = 0.f, ex = 0.f;
+        bool valid = w == 0;
+        if (w >= 1 && w <= count) {
+          int e = head + count - w;
+          e = e >= C ? e - C : e;
+          res = (float)(cur - q_t[e]);
+          ex = (float)q_e[e];
+          valid = true;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int c = c0 + e;
+          float v = valid ? rowv[e] : 0.f;
+          if (c == p.col_res) v = res;
+          if (c == p.col_exe) v = ex;
+          if (c == p.col_sto) v = 0.f;
+          x[w][c] = v;
+        }
+      }
+      __syncthreads();
+      // conv1 (kernel 2, stride 2): channel c1 at positions half, half+2, ...
+#pragma unroll
+      for (int j = 0; j < WV_L / 4; ++j) {
+        const int q = half + 2 * j;
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int c = 0; c < D; c += 4) {
+            const float4 xv = *reinterpret_cast<const float4*>(&x[2 * q + t][c]);
+            acc[0] = fmaf(w1[t][c], xv.x, acc[0]);
+            acc[1] = fmaf(w1[t][c + 1], xv.y, acc[1]);
+            acc[2] = fmaf(w1[t][c + 2], xv.z, acc[2]);
+            acc[3] = fmaf(w1[t][c + 3], xv.w, acc[3]);
+          }
+        float v = b1 + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        if (relu_mask & 1u) v = fmaxf(v, 0.f);
+        a1[q][c1] = v;
+      }
+      __syncthreads();
+      // conv2: channel lane at positions 0..3, then the final FC's share
+      float part[2] = {0.f, 0.f};
+#pragma unroll
+      for (int q = 0; q < WV_NB; ++q) {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int c = 0; c < WV_C1; c += 4) {
+            const float4 av = *reinterpret_cast<const float4*>(&a1[2 * q + t][c]);
+            acc[0] = fmaf(w2[t][c], av.x, acc[0]);
+            acc[1] = fmaf(w2[t][c + 1], av.y, acc[1]);
+            acc[2] = fmaf(w2[t][c + 2], av.z, acc[2]);
+            acc[3] = fmaf(w2[t][c + 3], av.w, acc[3]);
+          }
+        float v = b2 + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        if (relu_mask & 2u) v = fmaxf(v, 0.f);
+        part[0] = fmaf(wf[q][0], v, part[0]);
+        part[1] = fmaf(wf[q][1], v, part[1]);
+      }
+      // the final FC: sum over the 64 channels (a fixed butterfly)
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        float v = part[o];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
+        v += wt.last_b[o];
+        if (relu_mask & 4u) v = fmaxf(v, 0.f);
+        z[o] = v;
+      }
+    }
+    // round, or take the injected latencies
+    int32_t lat[2];
+    if (RUN_NET) {
+      if (p.logits_out && lane == 0)
+        for (int o = 0; o < 2; ++o) p.logits_out[g * 2 + o] = z[o];
+#pragma unroll
+      for (int o = 0; o < 2; ++o) lat[o] = round_latency(z[o], p.lat_max, n_clamped, n_nonfinite);
+    }
+    ++n_pred;
+    if (p.lat_mode != 0) {
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int32_t inj = p.lat_table[g * 2 + o];
+        if (RUN_NET && inj != lat[o]) ++n_mismatch;
+        lat[o] = inj;
+      }
+    }
+    // clock and queue (Sec. 3.2): T = cur + F; the queue's retired prefix
+    // (r <= T) leaves; r = max(T + E + 1, r_prev, r_{i-W} + 1); push
+    const int64_t Tn = cur + lat[0];
+    {
+      bool gone = false;
+      if (lane < count) {
+        int e = head + lane;
+        e = e >= C ? e - C : e;
+        gone = q_r[e] <= Tn;
+      }
+      const int n_gone = __popcll(__ballot(gone));
+      head += n_gone;
+      head = head >= C ? head - C : head;
+      count -= n_gone;
+    }
+    int64_t r = Tn + lat[1] + 1;
+    r = r > r_prev ? r : r_prev;
+    const int wi = (int)(pos % W);
+    if (pos >= W) {
+      const int64_t rb = rw[wi] + 1;
+      r = r > rb ? r : rb;
+    }
+    int sl = head + count;
+    sl = sl >= C ? sl - C : sl;
+    if (count == C) {
+      head = head + 1 == C ? 0 : head + 1;  // only the newest C stay visible
+    } else {
+      ++count;
+    }
+    __syncthreads();  // every lane has read the ring and rw for this step
+    if (lane == 0) {
+      rw[wi] = r;
+      q_e[sl] = lat[1];
+      q_t[sl] = Tn;
+      q_r[sl] = r;
+    }
+    r_prev = r;
+    cur = Tn;
+    ++pos;
+    if (pos == warm) t_w = Tn;
+    if (pos == n_pos) {  // the drain ends (Eq. 1); the slot takes the next sub-trace
+      if (lane == 0) {
+        st.fetch[k] = Tn - t_w;
+        st.drain[k] = r - Tn;
+        st.final_tick[k] = r;
+        st.warm_tick[k] = t_w;
+        st.pos[k] = pos;
+        st.cur[k] = Tn;
+        claimed = claim_subtrace(st, p.n_sub);
+      }
+      __syncthreads();
+      k = claimed;
+      load_state();
+      load_rows();
+    } else {
+      if (RUN_NET) {
+        // slot w takes slot w-1's row; slot 0 the prefetched one
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const float up = __shfl(rowv[e], lane >= 4 ? lane - 4 : lane);
+          rowv[e] = ws == 0 ? nxt[e] : up;
+        }
+      }
+      __syncthreads();
+    }
+  }
+
+  // the slot's state back to memory
+  if (lane == 0) {
+    st.slot_kid[slot] = k;
+    if (k >= 0) {
+      st.cur[k] = cur;
+      st.t_w[k] = t_w;
+      st.r_prev[k] = r_prev;
+      st.pos[k] = pos;
+      st.head[k] = head;
+      st.count[k] = count;
+    }
+    if (n_clamped) atomicAdd(&st.counters[0], (unsigned long long)n_clamped);
+    if (n_nonfinite) atomicAdd(&st.counters[1], (unsigned long long)n_nonfinite);
+    if (n_mismatch) atomicAdd(&st.counters[2], (unsigned long long)n_mismatch);
+    if (n_pred) atomicAdd(&st.counters[3], (unsigned long long)n_pred);
+  }
+  if (k >= 0) {
+    if (lane < C) {
+      const size_t gq = (size_t)k * C + lane;
+      st.q_idx[gq] = 0;
+      st.q_e[gq] = q_e[lane];
+      st.q_t[gq] = q_t[lane];
+      st.q_r[gq] = q_r[lane];
+    }
+    if (lane < W) st.rw[(size_t)k * WMAX + lane] = rw[lane];
+  }
+}
+
 // Predictor over explicit windows x [B][L][D] -> logits [B][NOUT]; TRUNK:
 // the convolutions only, the last conv's output to trunk_out [B][NB][CH3].
 template <class Net, class P, bool TRUNK = false>
@@ -1754,6 +2066,15 @@ hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint
     if (prec == 1) return launch_step_t<NetC3Hyb, PBF16>(w, relu, s, p, stream);
     return hipErrorInvalidValue;
   }
+  if (net == 0 && prec == 0 && variant == WAVE_VARIANT) {
+    // one wavefront per slot
+    const dim3 grid((unsigned)(p.n_wg * MT)), block(64);
+    if (p.lat_mode == 1)
+      hipLaunchKernelGGL(wave_step_kernel<false>, grid, block, 0, stream, w, relu, s, p);
+    else
+      hipLaunchKernelGGL(wave_step_kernel<true>, grid, block, 0, stream, w, relu, s, p);
+    return hipGetLastError();
+  }
   return net == 0 ? launch_step_n<NetSmall>(prec, w, relu, s, p, stream)
                   : launch_step_n<NetC3>(prec, w, relu, s, p, stream);
 }
@@ -1845,6 +2166,7 @@ hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, 
   const bool run_net = p.lat_mode != 1;
   void* fn;
   int nt;
+  int grid_x = p.n_wg;
   if (net == 1 && run_net && variant == 1) {
     fn = prec == 0 ? step_fn<NetC3V1, PF32>(run_net)
          : prec == 1 ? step_fn<NetC3V1, PBF16>(run_net) : step_fn<NetC3V1, PFP8>(run_net);
@@ -1853,6 +2175,11 @@ hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, 
     fn = prec == 0 ? step_fn<NetC3V2, PF32>(run_net)
          : prec == 1 ? step_fn<NetC3V2, PBF16>(run_net) : step_fn<NetC3V2, PFP8>(run_net);
     nt = Geo<NetC3V2, PF32>::NT;
+  } else if (net == 0 && prec == 0 && variant == WAVE_VARIANT) {
+    fn = run_net ? reinterpret_cast<void*>(&wave_step_kernel<true>)
+                 : reinterpret_cast<void*>(&wave_step_kernel<false>);
+    nt = 64;
+    grid_x = p.n_wg * MT;
   } else if (net == 0) {
     fn = prec == 0 ? step_fn<NetSmall, PF32>(run_net)
          : prec == 1 ? step_fn<NetSmall, PBF16>(run_net) : step_fn<NetSmall, PFP8>(run_net);
@@ -1881,7 +2208,7 @@ hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, 
   void* step_args[] = {&wa, &ra, &sa, &pa};
   hipKernelNodeParams kp{};
   kp.func = fn;
-  kp.gridDim = dim3(p.n_wg);
+  kp.gridDim = dim3(grid_x);
   kp.blockDim = dim3(nt);
   kp.sharedMemBytes = 0;
   kp.kernelParams = step_args;

@@ -51,6 +51,9 @@ struct NetC3Hyb : NetC3 {  // C3 trunk -> FC 512 -> 2 x 11
 struct NetC3V1 : NetC3 { static constexpr int FC1_FRAGS = 16; };
 struct NetC3V2 : NetC3 { static constexpr int FC1_FRAGS = 4; };
 constexpr int N_VARIANTS = 3;
+// The small network's FP32 step as one wavefront per sub-trace slot
+// (wave_step_kernel): the launch variant for runs of few sub-traces.
+constexpr int WAVE_VARIANT = 1;
 // Store latency (Sec. 3.2): three outputs (fetch, execution, store) and the
 // memory write queue that stores enter on leaving the processor queue.
 struct NetC3S : NetC3 {  // C3 trunk -> FC 512 -> 3
@@ -191,7 +194,8 @@ struct StepParams {
 // Launchers (kernels.hip).  net: 0 = NetSmall, 1 = NetC3; prec: 0 FP32,
 // 1 BF16, 2 FP8 (e4m3).  relu: bit l = ReLU after layer l.
 // variant (0 .. N_VARIANTS-1) selects a tuning variant of the C3 network
-// (net 1) when the predictor runs; other networks ignore it.
+// (net 1) when the predictor runs, or (net 0, FP32, WAVE_VARIANT) the small
+// network's one-wavefront-per-slot step; other networks ignore it.
 hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
                        const DevState& s,
                        const StepParams& p, hipStream_t stream);

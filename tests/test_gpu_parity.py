@@ -331,3 +331,34 @@ def test_error_paths(torch, sn, oracle_lib):
     S.sim.reset()
     b = S.sim.run()
     assert_same_results(a, b, 2)
+
+
+@pytest.mark.parametrize("variant,n_wg", [(0, None), (1, None), (1, 1)])
+def test_small_network_step_forms(torch, sn, oracle_lib, variant, n_wg):
+    """The small network's FP32 step as a workgroup per 16 slots (variant 0)
+    and as one wavefront per slot (variant 1, the default for few
+    sub-traces), the latter also with 16 slots for 40 sub-traces (slots
+    refilled from the work queue): injected latencies bit-exact; free runs
+    replayed by the oracle from the GPU's own latencies; shadow mode on the
+    oracle's own latencies reproduces its rounded outputs away from ties."""
+    S = Setup(torch, sn, oracle_lib, "small", 5000, 40, 64)
+    S.sim.set_tuning(variant, n_wg or (40 + 15) // 16)  # (all slots: 16 per workgroup)
+    table = synth.latency_table(29, S.n_pred, 2, heavy=0.1)
+    g = S.sim.run(sn.SIM_LAT_INJECT, dev(torch, table))
+    assert_same_results(g, S.oracle(oracle_lib, mode=oracle_lib.INJECT, lat_table=table), 40)
+    S.sim.reset()
+    logits = torch.zeros((S.n_pred, 2), dtype=torch.float32, device="cuda")
+    S.sim.record_logits(logits)
+    g = S.sim.run()
+    check_free_run(torch, sn, oracle_lib, S, g, logits.cpu().numpy())
+    o = S.oracle(oracle_lib, want_lat=True, want_logits=True, want_scale=True)
+    S.sim.reset()
+    logits.zero_()
+    sh = S.sim.run(sn.SIM_LAT_SHADOW, dev(torch, o["lat"]))
+    assert_same_results(sh, o, 40)
+    gl = logits.cpu().numpy()
+    assert rel_err(gl, o["logits"], o["scale"]).max() <= TIGHT
+    ties = near_half(o["logits"], o["scale"], TIE_TOL)
+    own = np.clip(np.rint(gl.astype(np.float64)), 0, 65535).astype(np.int32)
+    assert not np.any((own != o["lat"]) & ~ties)
+    assert sh["n_shadow_mismatch"] == int(((own != o["lat"])).sum())
