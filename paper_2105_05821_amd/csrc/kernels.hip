@@ -193,6 +193,22 @@ __device__ __forceinline__ typename P::T to_storage(float v, int col, const floa
   if constexpr (P::SCALED) v *= ai[col];
   return P::cvt(v);
 }
+// The same two with the column's bias b, weight scale s and input scale a
+// already in registers.
+template <class P>
+__device__ __forceinline__ float activation_v(float acc, float b, float s, bool relu) {
+  float v;
+  if constexpr (P::SCALED)
+    v = fmaf(acc, s, b);
+  else
+    v = acc + b;
+  return relu ? fmaxf(v, 0.f) : v;
+}
+template <class P>
+__device__ __forceinline__ typename P::T to_storage_v(float v, float a) {
+  if constexpr (P::SCALED) v *= a;
+  return P::cvt(v);
+}
 // Calibration: running per-channel max of |activation| (LDS, as ordered bits).
 __device__ __forceinline__ void cal_max(unsigned* cal, int i, float v) {
   atomicMax(cal + i, __float_as_uint(fabsf(v)));
@@ -405,6 +421,20 @@ __device__ __forceinline__ void conv_stage(
   for (int i = 0; i < MPW; ++i)
 #pragma unroll
     for (int j = 0; j < NPW; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  // the epilogue's operands for this lane's 4 columns of each tile, requested
+  // before the products: after them, the wait for these loads would also
+  // wait for every weight request in flight behind them
+  constexpr int NS = P::SCALED ? NPW : 1;
+  v4f eb[NPW], es[NS] = {}, ea[NS] = {};
+#pragma unroll
+  for (int j = 0; j < NPW; ++j) {
+    const int col0 = (nt0 + j) * 16 + 4 * (lane >> 4);
+    eb[j] = *reinterpret_cast<const v4f*>(bias + col0);
+    if constexpr (P::SCALED) {
+      es[j] = *reinterpret_cast<const v4f*>(ws + col0);
+      ea[j] = *reinterpret_cast<const v4f*>(ai + col0);
+    }
+  }
   mma_stream<P, KGS, NTILES, NPW, MPW, S::FRAGS, HEAD>(acc, ap, Bp, nt0, lane, head);
 #pragma unroll
   for (int i = 0; i < MPW; ++i) {
@@ -419,10 +449,10 @@ __device__ __forceinline__ void conv_stage(
       T e[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const float v = activation<P>(acc[i][j][q], col0 + q, bias, ws, relu);
+        const float v = activation_v<P>(acc[i][j][q], eb[j][q], es[P::SCALED ? j : 0][q], relu);
         if constexpr (CAL)
           if (live) cal_max(cal, col0 + q, v);
-        e[q] = to_storage<P>(v, col0 + q, ai);
+        e[q] = to_storage_v<P>(v, ea[P::SCALED ? j : 0][q]);
       }
       store_run<4 * sizeof(T)>(orow + col0, e);
       if constexpr (SAVE)
@@ -553,8 +583,9 @@ __device__ __forceinline__ void run_group(
       // as the packed per-block matrices are consecutive)
       auto hf = fc_head<Net, P, NBG>(wt, j0, wave, lane);
       lds_barrier();
-      finish(next_rows);
+      if constexpr (!Net::LATE_COMMIT) finish(next_rows);
       hidden_fc<Net, P, NBG, true>(wt, sm.a3(), j0, hacc, wave, lane, &hf);
+      if constexpr (Net::LATE_COMMIT) finish(next_rows);
       return;
     }
     lds_barrier();
@@ -1071,6 +1102,59 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   auto commit = [&](int j0, int nb, const RowRegs<CPT, H16>& r, T* X) {
     (void)j0;
     if (gt >= nb * BS) return;  // slots past a short group's blocks are never read
+    T* dst = X + gs * G::SX + (gt >> 1) * G::RX + (gt & 1) * DP + part * CPT;
+    // the row's column c, when this thread's share holds it, set to v
+    auto put = [&](int c, float v) {
+      if (c >= part * CPT && c < part * CPT + CPT) {
+        if constexpr (P::SCALED) v *= sm.net.x_inv[c < D ? c : 0];
+        dst[c - part * CPT] = P::cvt(v);
+      }
+    };
+    if constexpr (!CAL && !DEP) {
+      // The share written whole, then the few columns that are not copied
+      // features overwritten one by one: the same values as the per-feature
+      // conversion below at a fraction of its VALU work.  The BF16 form's
+      // rows are stored as loaded (its BF16 copy of the trace holds exactly
+      // the values the conversion would produce).
+      if constexpr (H16) {
+        if (!p.codes) {
+#pragma unroll
+          for (int q = 0; q < CPT / 8; ++q) {
+            const uint4 w = r.valid ? uint4{r.v[4 * q], r.v[4 * q + 1], r.v[4 * q + 2],
+                                            r.v[4 * q + 3]}
+                                    : uint4{0u, 0u, 0u, 0u};
+            *reinterpret_cast<uint4*>(dst + 8 * q) = w;
+          }
+          put(p.col_res, r.res);
+          put(p.col_exe, r.ex);
+          put(p.col_sto, r.sto);
+          return;
+        }
+      }
+      // packed codes: zeros, then the one-hot features of code_feature
+      static_assert(D >= 30, "the code's features are columns 0 .. 29");
+      if constexpr ((CPT * sizeof(T)) % 16 == 0) {
+        if (p.codes) {
+#pragma unroll
+          for (int q = 0; q < CPT * (int)sizeof(T) / 16; ++q)
+            *reinterpret_cast<uint4*>(reinterpret_cast<char*>(dst) + 16 * q) =
+                uint4{0u, 0u, 0u, 0u};
+          if (r.valid) {
+            const uint32_t code = r.code;
+            if ((code & 7u) < 5u) put((int)(code & 7u), 1.f);
+#pragma unroll
+            for (int g = 0; g < 3; ++g)
+              put(5 + 7 * g + (((int)((code >> (3 + 5 * g)) & 31u) * 7) >> 5), 1.f);
+            if (((code >> 18) & 3u) < 3u) put(26 + (int)((code >> 18) & 3u), 1.f);
+            if ((code >> 20) & 1u) put(29, 1.f);
+          }
+          put(p.col_res, r.res);
+          put(p.col_exe, r.ex);
+          put(p.col_sto, r.sto);
+          return;
+        }
+      }
+    }
     float v[CPT];
 #pragma unroll
     for (int cc = 0; cc < CPT; ++cc) {
@@ -1096,8 +1180,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     }
     T e[CPT];
     window_elems<P, CPT, D>(v, sm.net.x_inv, part * CPT, e);
-    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(
-        X + gs * G::SX + (gt >> 1) * G::RX + (gt & 1) * DP + part * CPT, e);
+    store_run<(CPT * sizeof(T)) % 16 == 0 ? 16 : 8>(dst, e);
   };
 
   if constexpr (STAGE == 1)

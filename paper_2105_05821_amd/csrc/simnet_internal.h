@@ -24,6 +24,7 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr bool MWQ = false;         // store latency and memory write queue
   static constexpr int FC1_FRAGS = 8;
   static constexpr int WAVES = 4;
+  static constexpr bool LATE_COMMIT = false; // (no hidden FC)
   static constexpr int CHL = CH2;            // channels of the last conv
   static constexpr int NRES = 0, EXPAND = 0; // residual blocks after the convs
 };
@@ -36,6 +37,10 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
   static constexpr bool MWQ = false;
   static constexpr int FC1_FRAGS = 8;        // hidden-FC weight fragments per prefetch chunk
   static constexpr int WAVES = 8;
+  // the next group's window rows written after the hidden FC, their latency
+  // passing under its weight stream (else before it, leaving the stream the
+  // registers)
+  static constexpr bool LATE_COMMIT = true;
   static constexpr int CHL = CH3;
   static constexpr int NRES = 0, EXPAND = 0;
 };
@@ -48,7 +53,10 @@ struct NetC3Hyb : NetC3 {  // C3 trunk -> FC 512 -> 2 x 11
 // Tuning variants of the C3 step kernel (chosen by sim_autotune): a deeper
 // or a shallower hidden-FC weight prefetch.  The products and their
 // summation order are the same in every variant, so results are identical.
-struct NetC3V1 : NetC3 { static constexpr int FC1_FRAGS = 16; };
+struct NetC3V1 : NetC3 {
+  static constexpr int FC1_FRAGS = 16;
+  static constexpr bool LATE_COMMIT = false;
+};
 struct NetC3V2 : NetC3 { static constexpr int FC1_FRAGS = 4; };
 constexpr int N_VARIANTS = 3;
 // The small network's FP32 step as one wavefront per sub-trace slot
