@@ -223,7 +223,9 @@ SIMNET_API int sim_set_graph(sim_ctx* ctx, int32_t enable);
 /* Launch shape of the step kernel as chosen by sim_autotune. */
 typedef struct {
   int32_t variant;            /* kernel variant: C3 network, the hidden-FC weight
-                                 prefetch depth (0, 1, 2: 8, 16, 4 fragments); small
+                                 prefetch depth (0, 1, 2: chunks of 8, 16, 4 fragments
+                                 requested one chunk ahead; 3: chunks of 8 fragments
+                                 requested two ahead); small
                                  network in FP32, 0 = a workgroup per 16 slots, 1 = one
                                  wavefront per slot */
   int32_t n_wg;               /* persistent workgroups (16 sub-trace slots each) */
@@ -247,7 +249,7 @@ typedef struct {
 SIMNET_API int sim_autotune(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
                             const int32_t* lat_table, sim_tuning* out);
 
-/* Apply a launch shape (a cached sim_autotune result): variant in [0, 3),
+/* Apply a launch shape (a cached sim_autotune result): variant in [0, 4),
  * n_wg in [1, slots allocated / 16].  Resets the simulation. */
 SIMNET_API int sim_set_tuning(sim_ctx* ctx, int32_t variant, int32_t n_wg);
 

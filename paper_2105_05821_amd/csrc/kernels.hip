@@ -166,6 +166,30 @@ struct NetSmem {
   alignas(16) typename P::T a2own[G::NA2];  // conv2's output when it does not alias X
   float logit[MT][Net::NOUT];
   float x_inv[Net::D];  // FP8: reciprocal input scale of each window feature
+  // The final FC on the VALU after the hidden layer (regression head): its
+  // operands copied here once per launch (stage_head), so the end of every
+  // prediction reads no global memory.  hb: hidden bias; FP8 hws, hai: the
+  // hidden layer's weight and output scales; lw: final weights [NOUT][HID];
+  // lb: final bias.
+  static constexpr bool HL = Net::HID > 0 && Net::HEAD == 0;
+  static constexpr int HLN = HL ? Net::HID : 1, HLS = HL && P::SCALED ? Net::HID : 1;
+  float hb[HLN], hws[HLS], hai[HLS], lw[HL ? Net::NOUT * Net::HID : 1], lb[Net::NOUT];
+  __device__ void stage_head(const DevWeights& wt, int tid, int nt) {
+    if constexpr (HL) {
+      // (weights without a final FC, as the training form's trunk has, leave
+      // it unstaged: kernels that run the final FC are never given them)
+      if (!wt.last_w || !wt.last_b || !wt.hid_b) return;
+      for (int i = tid; i < Net::HID; i += nt) {
+        hb[i] = wt.hid_b[i];
+        if constexpr (P::SCALED) {
+          hws[i] = wt.hid_ws[i];
+          hai[i] = wt.hid_ai[i];
+        }
+      }
+      for (int i = tid; i < Net::NOUT * Net::HID; i += nt) lw[i] = wt.last_w[i];
+      for (int i = tid; i < Net::NOUT; i += nt) lb[i] = wt.last_b[i];
+    }
+  }
   __device__ typename P::T* x() { return xa2; }
   __device__ typename P::T* a1() { return a1a3; }
   __device__ typename P::T* a2() { return G::ALIAS ? xa2 : a2own; }
@@ -272,11 +296,12 @@ __device__ __forceinline__ StreamHead<stream_chunk(KGS, NPW, FRAGS), NPW> stream
 // The weight fragment is the MFMA's first operand, so lane l ends up
 // holding row l % 16 of the activations and output columns 4*(l/16) .. +3
 // of the tile: consecutive columns, stored with one vector write.  Each
-// weight fragment serves MPW m-tiles.  Weight fragments are requested one
-// chunk ahead of their use (double buffering) and the scheduler is kept
-// from sinking the requests.  HEAD: the first chunk was requested by
+// weight fragment serves MPW m-tiles.  Weight fragments are requested
+// DEPTH - 1 chunks ahead of their use (DEPTH buffers) and the scheduler is
+// kept from sinking the requests.  HEAD: the first chunk was requested by
 // stream_head (same KGS, NTILES, NPW, FRAGS, Bp and nt0) and is passed in.
-template <class P, int KGS, int NTILES, int NPW, int MPW, int FRAGS = 8, bool HEAD = false>
+template <class P, int KGS, int NTILES, int NPW, int MPW, int FRAGS = 8, bool HEAD = false,
+          int DEPTH = 2>
 __device__ __forceinline__ void mma_stream(
     typename P::Acc (&acc)[MPW][NPW], const typename P::T* const (&ap)[MPW],
     const uint4* __restrict__ Bp, int nt0, int lane,
@@ -285,25 +310,27 @@ __device__ __forceinline__ void mma_stream(
   const __amdgpu_buffer_rsrc_t rs = frag_rsrc(Bp, KGS * NTILES * 1024);
   const int lo = lane * 16;
   const int wn = __builtin_amdgcn_readfirstlane(nt0) * 1024;
-  uint4 b[2][CH][NPW];
+  uint4 b[DEPTH][CH][NPW];
+  auto request = [&](int c) {
 #pragma unroll
-  for (int kg = 0; kg < CH; ++kg)
+    for (int kg = 0; kg < CH; ++kg)
 #pragma unroll
-    for (int j = 0; j < NPW; ++j) {
-      if constexpr (HEAD)
-        b[0][kg][j] = head->b[kg][j];
-      else
-        b[0][kg][j] = load_frag(rs, lo, wn + (kg * NTILES + j) * 1024);
-    }
+      for (int j = 0; j < NPW; ++j)
+        b[c % DEPTH][kg][j] = load_frag(rs, lo, wn + ((c * CH + kg) * NTILES + j) * 1024);
+  };
+  if constexpr (HEAD) {
+#pragma unroll
+    for (int kg = 0; kg < CH; ++kg)
+#pragma unroll
+      for (int j = 0; j < NPW; ++j) b[0][kg][j] = head->b[kg][j];
+  } else {
+    request(0);
+  }
+#pragma unroll
+  for (int c = 1; c < DEPTH - 1 && c < NCH; ++c) request(c);
 #pragma unroll
   for (int c = 0; c < NCH; ++c) {
-    if (c + 1 < NCH) {
-#pragma unroll
-      for (int kg = 0; kg < CH; ++kg)
-#pragma unroll
-        for (int j = 0; j < NPW; ++j)
-          b[(c + 1) & 1][kg][j] = load_frag(rs, lo, wn + (((c + 1) * CH + kg) * NTILES + j) * 1024);
-    }
+    if (c + DEPTH - 1 < NCH) request(c + DEPTH - 1);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int kg = 0; kg < CH; ++kg) {
@@ -311,7 +338,7 @@ __device__ __forceinline__ void mma_stream(
       for (int i = 0; i < MPW; ++i) {
         const uint4 a = *reinterpret_cast<const uint4*>(ap[i] + (c * CH + kg) * P::KG);
 #pragma unroll
-        for (int j = 0; j < NPW; ++j) acc[i][j] = P::mma(acc[i][j], b[c & 1][kg][j], a);
+        for (int j = 0; j < NPW; ++j) acc[i][j] = P::mma(acc[i][j], b[c % DEPTH][kg][j], a);
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -519,7 +546,7 @@ __device__ __forceinline__ void hidden_fc(const DevWeights& wt, const typename P
   v4f bacc[1][HT];
 #pragma unroll
   for (int jj = 0; jj < HT; ++jj) bacc[0][jj] = v4f{0.f, 0.f, 0.f, 0.f};
-  mma_stream<P, S::KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS, HEAD>(
+  mma_stream<P, S::KGS, Net::HID / 16, HT, 1, Net::FC1_FRAGS, HEAD, Net::FC1_DEPTH>(
       bacc, ap, S::weights(wt, j0), wave * HT, lane, head);
 #pragma unroll
   for (int jj = 0; jj < HT; ++jj) hacc[jj] += bacc[0][jj];
@@ -757,12 +784,12 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int col = (wave * HT + jj) * 16 + 4 * (lane >> 4) + i;
-        const float hv = activation<P>(hacc[jj][i], col, wt.hid_b, wt.hid_ws, hrelu);
+        const float hv = activation<P>(hacc[jj][i], col, sm.hb, sm.hws, hrelu);
         if constexpr (CAL)
           if (live) cal_max(cal, Net::D + Net::CH1 + Net::CH2 + Net::CH3 + col, hv);
-        const float h = P::val(to_storage<P>(hv, col, wt.hid_ai));
+        const float h = P::val(to_storage<P>(hv, col, sm.hai));
 #pragma unroll
-        for (int o = 0; o < Net::NOUT; ++o) p[o] = fmaf(h, wt.last_w[o * Net::HID + col], p[o]);
+        for (int o = 0; o < Net::NOUT; ++o) p[o] = fmaf(h, sm.lw[o * Net::HID + col], p[o]);
       }
     }
 #pragma unroll
@@ -778,7 +805,7 @@ __device__ __forceinline__ void predict_tile(const DevWeights& wt, uint32_t relu
       float v = 0.f;
 #pragma unroll
       for (int w = 0; w < Net::WAVES; ++w) v += sm.red()[(w * MT + s) * Net::NOUT + o];
-      v += wt.last_b[o];
+      v += sm.lb[o];
       if (relu_mask & (1u << (hidden_layer<Net>() + 1))) v = fmaxf(v, 0.f);
       sm.logit[s][o] = v;
     }
@@ -999,6 +1026,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
     if (k < 0) k = claim_subtrace(st, p.n_sub);
     load_slot(sm, tid, k, st, p.W);
   }
+  if constexpr (RUN_NET) sm.net.stage_head(wt, tid, NT);
   __syncthreads();
   for (int i = tid; i < MT * C; i += NT) {
     const int s = i / C, e = i % C, k = sm.kid[s];
@@ -1693,10 +1721,10 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   const int row = tid / TPR, part = tid % TPR;
   const int s = row / GSL, t = row % GSL;
   static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
-  if constexpr (P::SCALED) {
+  if constexpr (P::SCALED)
     for (int c = tid; c < D; c += NT) sm.x_inv[c] = wt.x_inv[c];
-    __syncthreads();
-  }
+  sm.stage_head(wt, tid, NT);
+  __syncthreads();
   const int64_t b = b0 + s;
   auto load = [&](int j0, int nb) {
     RowRegs<CPT> r;
@@ -2008,10 +2036,9 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   const int row = tid / TPR, part = tid % TPR;
   const int s = row / GSL, t = row % GSL;
   static_assert(NT % ROWS == 0 && DP % TPR == 0 && CPT % 2 == 0 && D % 2 == 0, "gather split");
-  if constexpr (P::SCALED) {
+  if constexpr (P::SCALED)
     for (int c = tid; c < D; c += NT) sm.x_inv[c] = wt.x_inv[c];
-    __syncthreads();
-  }
+  __syncthreads();
   const int64_t b = b0 + s;
   auto load = [&](int j0, int nb) {
     RowRegs<CPT> r;
@@ -2139,6 +2166,8 @@ hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint
     return launch_step_n<NetC3V1>(prec, w, relu, s, p, stream);
   if (net == 1 && p.lat_mode != 1 && variant == 2)
     return launch_step_n<NetC3V2>(prec, w, relu, s, p, stream);
+  if (net == 1 && p.lat_mode != 1 && variant == 3)
+    return launch_step_n<NetC3V3>(prec, w, relu, s, p, stream);
   if (net == 4) {  // store latencies: FP32 and BF16 forms
     if (prec == 0) return launch_step_t<NetC3S, PF32>(w, relu, s, p, stream);
     if (prec == 1) return launch_step_t<NetC3S, PBF16>(w, relu, s, p, stream);
@@ -2258,6 +2287,10 @@ hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, 
     fn = prec == 0 ? step_fn<NetC3V2, PF32>(run_net)
          : prec == 1 ? step_fn<NetC3V2, PBF16>(run_net) : step_fn<NetC3V2, PFP8>(run_net);
     nt = Geo<NetC3V2, PF32>::NT;
+  } else if (net == 1 && run_net && variant == 3) {
+    fn = prec == 0 ? step_fn<NetC3V3, PF32>(run_net)
+         : prec == 1 ? step_fn<NetC3V3, PBF16>(run_net) : step_fn<NetC3V3, PFP8>(run_net);
+    nt = Geo<NetC3V3, PF32>::NT;
   } else if (net == 0 && prec == 0 && variant == WAVE_VARIANT) {
     fn = run_net ? reinterpret_cast<void*>(&wave_step_kernel<true>)
                  : reinterpret_cast<void*>(&wave_step_kernel<false>);

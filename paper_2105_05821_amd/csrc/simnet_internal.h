@@ -23,6 +23,7 @@ struct NetSmall {  // [16 slots x 32 feat] -> conv 32 -> conv 64 -> FC 2
   static constexpr int NLAT = 2, HEAD = 0;   // latencies per instruction; regression head
   static constexpr bool MWQ = false;         // store latency and memory write queue
   static constexpr int FC1_FRAGS = 8;
+  static constexpr int FC1_DEPTH = 2;
   static constexpr int WAVES = 4;
   static constexpr bool LATE_COMMIT = false; // (no hidden FC)
   static constexpr int CHL = CH2;            // channels of the last conv
@@ -36,6 +37,7 @@ struct NetC3 {     // [111 slots x 50 feat] -> conv 64 -> conv 128 -> conv 256 -
   static constexpr int NLAT = 2, HEAD = 0;
   static constexpr bool MWQ = false;
   static constexpr int FC1_FRAGS = 8;        // hidden-FC weight fragments per prefetch chunk
+  static constexpr int FC1_DEPTH = 2;        // chunks in registers (DEPTH - 1 requested ahead)
   static constexpr int WAVES = 8;
   // the next group's window rows written after the hidden FC, their latency
   // passing under its weight stream (else before it, leaving the stream the
@@ -51,14 +53,19 @@ struct NetC3Hyb : NetC3 {  // C3 trunk -> FC 512 -> 2 x 11
   static constexpr int NOUT = 2 * HYB_PER_TYPE, HEAD = 1;
 };
 // Tuning variants of the C3 step kernel (chosen by sim_autotune): a deeper
-// or a shallower hidden-FC weight prefetch.  The products and their
-// summation order are the same in every variant, so results are identical.
+// or a shallower hidden-FC weight prefetch (chunks of 16 or 4 fragments, or
+// 8-fragment chunks requested two ahead).  The products and their summation
+// order are the same in every variant, so results are identical.
 struct NetC3V1 : NetC3 {
   static constexpr int FC1_FRAGS = 16;
   static constexpr bool LATE_COMMIT = false;
 };
 struct NetC3V2 : NetC3 { static constexpr int FC1_FRAGS = 4; };
-constexpr int N_VARIANTS = 3;
+struct NetC3V3 : NetC3 {
+  static constexpr int FC1_DEPTH = 3;
+  static constexpr bool LATE_COMMIT = false;
+};
+constexpr int N_VARIANTS = 4;
 // The small network's FP32 step as one wavefront per sub-trace slot
 // (wave_step_kernel): the launch variant for runs of few sub-traces.
 constexpr int WAVE_VARIANT = 1;

@@ -198,7 +198,7 @@ def test_autotune_choice_does_not_change_results(torch, sn, tmp_path):
     assert t2["cached"] and (t2["variant"], t2["n_wg"]) == (t["variant"], t["n_wg"])
     assert_same(sim.run(), ref)
     with pytest.raises(sn.SimError):
-        sim.set_tuning(3, 1)
+        sim.set_tuning(4, 1)
     sim.close()
 
 
