@@ -1138,7 +1138,14 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
         dst[c - part * CPT] = P::cvt(v);
       }
     };
-    if constexpr (!CAL && !DEP) {
+    // the memory dependency flags (after the other columns, as below)
+    auto put_dep = [&]() {
+      if constexpr (DEP)
+#pragma unroll
+        for (int f = 0; f < 5; ++f)
+          put(p.col_dep + f, r.valid == 1 ? dep_flag(r.mem, r.cur_mem, f) : 0.f);
+    };
+    if constexpr (!CAL) {
       // The share written whole, then the few columns that are not copied
       // features overwritten one by one: the same values as the per-feature
       // conversion below at a fraction of its VALU work.  The BF16 form's
@@ -1156,6 +1163,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
           put(p.col_res, r.res);
           put(p.col_exe, r.ex);
           put(p.col_sto, r.sto);
+          put_dep();
           return;
         }
       }
@@ -1179,6 +1187,7 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
           put(p.col_res, r.res);
           put(p.col_exe, r.ex);
           put(p.col_sto, r.sto);
+          put_dep();
           return;
         }
       }
