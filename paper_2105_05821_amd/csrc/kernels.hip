@@ -1412,7 +1412,9 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
 // the final FC is a lane reduction, so every lane holds the logits, and the
 // clock and queue update runs on wave-uniform values, the retired prefix of
 // the queue counted by one ballot over its entries (their retire times are
-// non-decreasing along the queue).  FP32 form, row or packed-code traces.
+// non-decreasing along the queue).  The barriers order LDS only, so the next
+// instruction's row, requested at the top of a step, stays in flight
+// across them.  FP32 form, row or packed-code traces.
 // Same state, work queue and results as step_kernel.
 constexpr int WV_D = NetSmall::D, WV_C = NetSmall::C, WV_L = NetSmall::L;
 constexpr int WV_C1 = NetSmall::CH1, WV_C2 = NetSmall::CH2, WV_NB = NetSmall::NB;
@@ -1442,7 +1444,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
   // (its positions: lane / 32, +2, +4, +6), conv2 output channel lane, the
   // final FC's weights of conv2 channel lane at the 4 positions
   float w1[2][D], w2[2][WV_C1], wf[WV_NB][2];
-  float b1 = 0.f, b2 = 0.f;
+  float b1 = 0.f, b2 = 0.f, bl[2] = {0.f, 0.f};
   const int c1 = lane & (WV_C1 - 1), half = lane >> 5;
   if (RUN_NET) {
     const float* W1 = static_cast<const float*>(wt.conv_w[0]);
@@ -1461,6 +1463,8 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
       for (int o = 0; o < 2; ++o) wf[j][o] = wt.last_w[((size_t)j * 2 + o) * WV_C2 + lane];
     b1 = wt.conv_b[0][c1];
     b2 = wt.conv_b[1][lane];
+    bl[0] = wt.last_b[0];
+    bl[1] = wt.last_b[1];
   }
 
   // the slot's sub-trace (a finished or empty slot claims the next one)
@@ -1491,7 +1495,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
       q_r[lane] = st.q_r[g];
     }
     if (lane < W) rw[lane] = st.rw[(size_t)k * WMAX + lane];
-    __syncthreads();
+    lds_barrier();
   };
   // the window's static rows stay in registers: lane (slot w, 8 features)
   // holds trace row i - w; a step shifts them one slot (4 lanes) and takes
@@ -1549,7 +1553,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
           x[w][c] = v;
         }
       }
-      __syncthreads();
+      lds_barrier();
       // conv1 (kernel 2, stride 2): channel c1 at positions half, half+2, ...
 #pragma unroll
       for (int j = 0; j < WV_L / 4; ++j) {
@@ -1569,7 +1573,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
         if (relu_mask & 1u) v = fmaxf(v, 0.f);
         a1[q][c1] = v;
       }
-      __syncthreads();
+      lds_barrier();
       // conv2: channel lane at positions 0..3, then the final FC's share
       float part[2] = {0.f, 0.f};
 #pragma unroll
@@ -1596,7 +1600,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
         float v = part[o];
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m);
-        v += wt.last_b[o];
+        v += bl[o];
         if (relu_mask & 4u) v = fmaxf(v, 0.f);
         z[o] = v;
       }
@@ -1647,7 +1651,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
     } else {
       ++count;
     }
-    __syncthreads();  // every lane has read the ring and rw for this step
+    lds_barrier();  // every lane has read the ring and rw for this step
     if (lane == 0) {
       rw[wi] = r;
       q_e[sl] = lat[1];
@@ -1668,7 +1672,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
         st.cur[k] = Tn;
         claimed = claim_subtrace(st, p.n_sub);
       }
-      __syncthreads();
+      lds_barrier();
       k = claimed;
       load_state();
       load_rows();
@@ -1681,7 +1685,7 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
           rowv[e] = ws == 0 ? nxt[e] : up;
         }
       }
-      __syncthreads();
+      lds_barrier();
     }
   }
 
