@@ -227,7 +227,8 @@ typedef struct {
                                  requested one chunk ahead; 3: chunks of 8 fragments
                                  requested two ahead); small
                                  network in FP32, 0 = a workgroup per 16 slots, 1 = one
-                                 wavefront per slot */
+                                 wavefront per slot, 2 = four wavefronts per slot (one
+                                 per block of the conv tree) */
   int32_t n_wg;               /* persistent workgroups (16 sub-trace slots each) */
   float ms;                   /* its time per million positions advanced in the trial */
   int32_t n_tried;            /* candidates timed (at most 16 listed) */
@@ -241,9 +242,9 @@ typedef struct {
  * 3/4 and 1/2 of the slots sim_init allocated; keep the one with the least
  * time per position advanced and reset the simulation.  The C3 variants
  * differ only in how far ahead weights are fetched, so results do not
- * depend on the choice; the small network's two sum the same products in a
- * different order (both within the FP32 bar of the FP64 oracle).  The small
- * network's FP32 step starts as one wavefront per slot when the trace has
+ * depend on the choice; the small network's three sum the same products in
+ * different orders (all within the FP32 bar of the FP64 oracle).  The small
+ * network's FP32 step starts as four wavefronts per slot when the trace has
  * at most 1,024 sub-traces.  Synchronises.  *out receives the choice and
  * the trials. */
 SIMNET_API int sim_autotune(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,

@@ -873,7 +873,7 @@ int sim_init(const sim_config* cfg, const sim_trace* tr, sim_ctx** out) {
   c->n_wg_max = c->n_wg;
   // the small network's FP32 step runs one wavefront per sub-trace when
   // there are few (a step's latency bounds such runs)
-  if (c->net == 0 && cfg->prec == SIM_FP32 && K <= WAVE_MAX_SUB) c->variant = WAVE_VARIANT;
+  if (c->net == 0 && cfg->prec == SIM_FP32 && K <= WAVE_MAX_SUB) c->variant = QUAD_VARIANT;
   const int32_t n_slots = c->n_wg * MT;
 
   // one device block: table + state + results + counters + total
@@ -1365,7 +1365,7 @@ int sim_autotune(sim_ctx* c, int32_t n_steps, int32_t lat_mode, const int32_t* l
   // 4/4, 3/4 and 1/2 of the slots
   // (the small network's FP32 step: the workgroup tile or one wave per slot)
   const int nv = (c->net == 1 && lat_mode != SIM_LAT_INJECT && c->cfg.col_dep < 0) ? N_VARIANTS
-                 : (c->net == 0 && c->cfg.prec == SIM_FP32)                       ? 2
+                 : (c->net == 0 && c->cfg.prec == SIM_FP32)                       ? 3
                                                                                   : 1;
   std::vector<int32_t> shapes;
   for (int q : {4, 3, 2}) {

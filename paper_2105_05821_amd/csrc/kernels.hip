@@ -1717,6 +1717,309 @@ __global__ void __launch_bounds__(64) wave_step_kernel(DevWeights wt, uint32_t r
   }
 }
 
+// ------------------------------------------ four wavefronts per sub-trace ---
+// The small network's FP32 step split over the four blocks of its kernel-2
+// stride-2 tree: conv2's position j depends on window slots 4j .. 4j+3 only,
+// so wave j builds those four slots, runs conv1 at positions 2j and 2j+1 and
+// conv2 at position j (each wave reading only what it wrote), and multiplies
+// its share of the final FC; the four partial sums meet in LDS, and every
+// wave runs the same clock and queue update on the same values (wave 0
+// alone writes the ring, the results and the state).  Per lane that is
+// 64 + 64 multiply-adds per prediction instead of the single wave's 768.
+// The ring has QR = 16 entries for the C = 15 visible ones, so a push never
+// lands on an entry read in the same step and two barriers per step
+// suffice: one after the partial sums, one after the push.  Each wave keeps
+// the retire times of the last W instructions in a register spread over its
+// lanes (lane l: the instruction with pos % W == l).  Same state, work queue
+// and results as step_kernel (the ring is written back with head 0).
+constexpr int QW = 4, QR = 16;
+static_assert(WV_NB == QW && WV_L == 16 && WV_C < QR, "four blocks of four slots");
+
+// LDS written by this wave and read by other lanes of it: the wave's LDS
+// requests complete in order, so a compiler fence and a wait suffice
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+template <bool RUN_NET>
+__global__ void __launch_bounds__(QW * 64) quad_step_kernel(DevWeights wt, uint32_t relu_mask,
+                                                           DevState st, StepParams p) {
+  constexpr int D = WV_D, C = WV_C;
+  __shared__ __attribute__((aligned(16))) float x[QW][4][D];   // each wave's four slots
+  __shared__ __attribute__((aligned(16))) float a1[QW][2][WV_C1];  // its conv1 output
+  __shared__ float red[QW][2];                                   // partial sums of the final FC
+  __shared__ int32_t q_e[QR];
+  __shared__ int64_t q_t[QR], q_r[QR];
+  __shared__ int claimed;
+  const int tid = threadIdx.x, v = tid >> 6, lane = tid & 63, slot = blockIdx.x;
+  const int W = p.W;
+
+  // this lane's weights: conv1 channel lane % 32 (position 2v + lane / 32),
+  // conv2 channel lane (position v), the final FC's weights of that channel
+  // at position v
+  const int c1 = lane & (WV_C1 - 1), pl = lane >> 5;
+  float w1[2][D], w2[2][WV_C1], wf[2];
+  float b1 = 0.f, b2 = 0.f, bl[2] = {0.f, 0.f};
+  if (RUN_NET) {
+    const float* W1 = static_cast<const float*>(wt.conv_w[0]);
+    const float* W2 = static_cast<const float*>(wt.conv_w[1]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < D; ++c) w1[t][c] = packed_f32(W1, WV_C1, t * D + c, c1);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int c = 0; c < WV_C1; ++c) w2[t][c] = packed_f32(W2, WV_C2, t * WV_C1 + c, lane);
+#pragma unroll
+    for (int o = 0; o < 2; ++o) wf[o] = wt.last_w[((size_t)v * 2 + o) * WV_C2 + lane];
+    b1 = wt.conv_b[0][c1];
+    b2 = wt.conv_b[1][lane];
+    bl[0] = wt.last_b[0];
+    bl[1] = wt.last_b[1];
+  }
+
+  int k = st.slot_kid[slot];
+  if (k < 0) {
+    if (tid == 0) claimed = claim_subtrace(st, p.n_sub);
+    __syncthreads();
+    k = claimed;
+  }
+  int64_t cur = 0, t_w = 0, r_prev = 0, pos = 0, first = 0, n_pos = 0, pred_off = 0;
+  int32_t head = 0, count = 0, warm = 0;
+  int64_t rwv = 0;  // lane l < W: retire time of the last instruction with pos % W == l
+  // the sub-trace's state; the ring into LDS from entry 0 (head 0)
+  auto load_state = [&]() {
+    if (k >= 0) {
+      cur = st.cur[k];
+      t_w = st.t_w[k];
+      r_prev = st.r_prev[k];
+      pos = st.pos[k];
+      first = st.first[k];
+      n_pos = st.n_pos[k];
+      pred_off = st.pred_off[k];
+      const int h = st.head[k];
+      count = st.count[k];
+      warm = st.warm[k];
+      head = 0;
+      if (v == 0 && lane < count) {
+        int e = h + lane;
+        e = e >= C ? e - C : e;
+        const size_t g = (size_t)k * C + e;
+        q_e[lane] = st.q_e[g];
+        q_t[lane] = st.q_t[g];
+        q_r[lane] = st.q_r[g];
+      }
+      rwv = lane < W ? st.rw[(size_t)k * WMAX + lane] : 0;
+    }
+    __syncthreads();
+  };
+  // this lane's window element pair: slot w = 4v + lane / 16, features
+  // f0, f0 + 1; its trace row is instruction (first + pos) - w
+  const int ls = lane >> 4, w = 4 * v + ls, f0 = (lane & 15) * 2;
+  auto row_of = [&](int64_t row, float (&r)[2]) {
+    if (p.codes) {
+      const uint32_t code = p.codes[row];
+      r[0] = code_feature(code, f0);
+      r[1] = code_feature(code, f0 + 1);
+    } else {
+      const float2 t = *reinterpret_cast<const float2*>(p.feat + row * D + f0);
+      r[0] = t.x;
+      r[1] = t.y;
+    }
+  };
+  float rowv[2] = {0.f, 0.f};
+  auto load_row = [&]() {
+    rowv[0] = rowv[1] = 0.f;
+    if (RUN_NET && k >= 0 && pos < n_pos && w <= pos) row_of(first + pos - w, rowv);
+  };
+  load_state();
+  load_row();
+  uint32_t n_clamped = 0, n_nonfinite = 0, n_mismatch = 0, n_pred = 0;
+
+  for (int it = 0; it < p.n_steps && k >= 0 && pos < n_pos; ++it) {
+    const int64_t g = pred_off + pos;
+    float nxt[2] = {0.f, 0.f};  // the next step's row for this lane
+    if (RUN_NET && pos + 1 < n_pos && w <= pos + 1) row_of(first + pos + 1 - w, nxt);
+    float z[2] = {0.f, 0.f};
+    if (RUN_NET) {
+      // window: slot 0 the current instruction with zero dynamic columns,
+      // slot w >= 1 the w-th newest queued one (queue entry count - w)
+      {
+        float res = 0.f, ex = 0.f;
+        bool valid = w == 0;
+        if (w >= 1 && w <= count) {
+          const int e = (head + count - w) & (QR - 1);
+          res = (float)(cur - q_t[e]);
+          ex = (float)q_e[e];
+          valid = true;
+        }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          const int c = f0 + e;
+          float val = valid ? rowv[e] : 0.f;
+          if (c == p.col_res) val = res;
+          if (c == p.col_exe) val = ex;
+          if (c == p.col_sto) val = 0.f;
+          x[v][ls][c] = val;
+        }
+      }
+      wave_lds_sync();
+      // conv1: channel c1 at position 2v + pl (slots 2 pl, 2 pl + 1 of the wave)
+      {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int c = 0; c < D; c += 4) {
+            const float4 xv = *reinterpret_cast<const float4*>(&x[v][2 * pl + t][c]);
+            acc[0] = fmaf(w1[t][c], xv.x, acc[0]);
+            acc[1] = fmaf(w1[t][c + 1], xv.y, acc[1]);
+            acc[2] = fmaf(w1[t][c + 2], xv.z, acc[2]);
+            acc[3] = fmaf(w1[t][c + 3], xv.w, acc[3]);
+          }
+        float val = b1 + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        if (relu_mask & 1u) val = fmaxf(val, 0.f);
+        a1[v][pl][c1] = val;
+      }
+      wave_lds_sync();
+      // conv2: channel lane at position v, then its share of the final FC
+      float part[2];
+      {
+        float acc[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+          for (int c = 0; c < WV_C1; c += 4) {
+            const float4 av = *reinterpret_cast<const float4*>(&a1[v][t][c]);
+            acc[0] = fmaf(w2[t][c], av.x, acc[0]);
+            acc[1] = fmaf(w2[t][c + 1], av.y, acc[1]);
+            acc[2] = fmaf(w2[t][c + 2], av.z, acc[2]);
+            acc[3] = fmaf(w2[t][c + 3], av.w, acc[3]);
+          }
+        float val = b2 + ((acc[0] + acc[1]) + (acc[2] + acc[3]));
+        if (relu_mask & 2u) val = fmaxf(val, 0.f);
+        part[0] = wf[0] * val;
+        part[1] = wf[1] * val;
+      }
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        float s = part[o];
+#pragma unroll
+        for (int m = 32; m >= 1; m >>= 1) s += __shfl_xor(s, m);
+        if (lane == 0) red[v][o] = s;
+      }
+      lds_barrier();
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        float s = ((red[0][o] + red[1][o]) + red[2][o]) + red[3][o];
+        s += bl[o];
+        if (relu_mask & 4u) s = fmaxf(s, 0.f);
+        z[o] = s;
+      }
+    }
+    // round, or take the injected latencies (every wave alike)
+    int32_t lat[2];
+    if (RUN_NET) {
+      if (p.logits_out && tid == 0)
+        for (int o = 0; o < 2; ++o) p.logits_out[g * 2 + o] = z[o];
+#pragma unroll
+      for (int o = 0; o < 2; ++o) lat[o] = round_latency(z[o], p.lat_max, n_clamped, n_nonfinite);
+    }
+    ++n_pred;
+    if (p.lat_mode != 0) {
+#pragma unroll
+      for (int o = 0; o < 2; ++o) {
+        const int32_t inj = p.lat_table[g * 2 + o];
+        if (RUN_NET && inj != lat[o]) ++n_mismatch;
+        lat[o] = inj;
+      }
+    }
+    // clock and queue (Sec. 3.2): T = cur + F; the retired prefix (r <= T)
+    // leaves; r = max(T + E + 1, r_prev, r_{i-W} + 1); push
+    const int64_t Tn = cur + lat[0];
+    {
+      bool gone = false;
+      if (lane < count) gone = q_r[(head + lane) & (QR - 1)] <= Tn;
+      const int n_gone = __popcll(__ballot(gone));
+      head = (head + n_gone) & (QR - 1);
+      count -= n_gone;
+    }
+    int64_t r = Tn + lat[1] + 1;
+    r = r > r_prev ? r : r_prev;
+    const int wi = (int)(pos % W);
+    if (pos >= W) {
+      const int64_t rb = __shfl(rwv, wi) + 1;
+      r = r > rb ? r : rb;
+    }
+    if (lane == wi) rwv = r;
+    const int sl = (head + count) & (QR - 1);
+    if (count == C) {
+      head = (head + 1) & (QR - 1);  // only the newest C stay visible
+    } else {
+      ++count;
+    }
+    if (tid == 0) {
+      q_e[sl] = lat[1];
+      q_t[sl] = Tn;
+      q_r[sl] = r;
+    }
+    r_prev = r;
+    cur = Tn;
+    ++pos;
+    if (pos == warm) t_w = Tn;
+    if (pos == n_pos) {  // the drain ends (Eq. 1); the slot takes the next sub-trace
+      if (tid == 0) {
+        st.fetch[k] = Tn - t_w;
+        st.drain[k] = r - Tn;
+        st.final_tick[k] = r;
+        st.warm_tick[k] = t_w;
+        st.pos[k] = pos;
+        st.cur[k] = Tn;
+        claimed = claim_subtrace(st, p.n_sub);
+      }
+      __syncthreads();
+      k = claimed;
+      load_state();
+      load_row();
+    } else {
+      rowv[0] = nxt[0];
+      rowv[1] = nxt[1];
+      lds_barrier();  // the push is visible to the next step's window
+    }
+  }
+
+  // the slot's state back to memory, the ring from entry 0 (head 0)
+  if (tid == 0) {
+    st.slot_kid[slot] = k;
+    if (k >= 0) {
+      st.cur[k] = cur;
+      st.t_w[k] = t_w;
+      st.r_prev[k] = r_prev;
+      st.pos[k] = pos;
+      st.head[k] = 0;
+      st.count[k] = count;
+    }
+    if (n_clamped) atomicAdd(&st.counters[0], (unsigned long long)n_clamped);
+    if (n_nonfinite) atomicAdd(&st.counters[1], (unsigned long long)n_nonfinite);
+    if (n_mismatch) atomicAdd(&st.counters[2], (unsigned long long)n_mismatch);
+    if (n_pred) atomicAdd(&st.counters[3], (unsigned long long)n_pred);
+  }
+  if (k >= 0 && v == 0) {
+    if (lane < count) {
+      const int e = (head + lane) & (QR - 1);
+      const size_t gq = (size_t)k * C + lane;
+      st.q_idx[gq] = (int32_t)(first + pos - count + lane);
+      st.q_e[gq] = q_e[e];
+      st.q_t[gq] = q_t[e];
+      st.q_r[gq] = q_r[e];
+    }
+    if (lane < W) st.rw[(size_t)k * WMAX + lane] = rwv;
+  }
+}
+
 // Predictor over explicit windows x [B][L][D] -> logits [B][NOUT]; TRUNK:
 // the convolutions only, the last conv's output to trunk_out [B][NB][CH3].
 template <class Net, class P, bool TRUNK = false>
@@ -2200,6 +2503,15 @@ hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint
       hipLaunchKernelGGL(wave_step_kernel<true>, grid, block, 0, stream, w, relu, s, p);
     return hipGetLastError();
   }
+  if (net == 0 && prec == 0 && variant == QUAD_VARIANT) {
+    // four wavefronts per slot
+    const dim3 grid((unsigned)(p.n_wg * MT)), block(QW * 64);
+    if (p.lat_mode == 1)
+      hipLaunchKernelGGL(quad_step_kernel<false>, grid, block, 0, stream, w, relu, s, p);
+    else
+      hipLaunchKernelGGL(quad_step_kernel<true>, grid, block, 0, stream, w, relu, s, p);
+    return hipGetLastError();
+  }
   return net == 0 ? launch_step_n<NetSmall>(prec, w, relu, s, p, stream)
                   : launch_step_n<NetC3>(prec, w, relu, s, p, stream);
 }
@@ -2308,6 +2620,11 @@ hipError_t build_run_graph(int net, int prec, int variant, const DevWeights& w, 
     fn = run_net ? reinterpret_cast<void*>(&wave_step_kernel<true>)
                  : reinterpret_cast<void*>(&wave_step_kernel<false>);
     nt = 64;
+    grid_x = p.n_wg * MT;
+  } else if (net == 0 && prec == 0 && variant == QUAD_VARIANT) {
+    fn = run_net ? reinterpret_cast<void*>(&quad_step_kernel<true>)
+                 : reinterpret_cast<void*>(&quad_step_kernel<false>);
+    nt = QW * 64;
     grid_x = p.n_wg * MT;
   } else if (net == 0) {
     fn = prec == 0 ? step_fn<NetSmall, PF32>(run_net)

@@ -69,6 +69,9 @@ constexpr int N_VARIANTS = 4;
 // The small network's FP32 step as one wavefront per sub-trace slot
 // (wave_step_kernel): the launch variant for runs of few sub-traces.
 constexpr int WAVE_VARIANT = 1;
+// ... or as four wavefronts per slot, one per block of its conv tree
+// (quad_step_kernel).
+constexpr int QUAD_VARIANT = 2;
 // Store latency (Sec. 3.2): three outputs (fetch, execution, store) and the
 // memory write queue that stores enter on leaving the processor queue.
 struct NetC3S : NetC3 {  // C3 trunk -> FC 512 -> 3

@@ -333,14 +333,15 @@ def test_error_paths(torch, sn, oracle_lib):
     assert_same_results(a, b, 2)
 
 
-@pytest.mark.parametrize("variant,n_wg", [(0, None), (1, None), (1, 1)])
+@pytest.mark.parametrize("variant,n_wg", [(0, None), (1, None), (1, 1), (2, None), (2, 1)])
 def test_small_network_step_forms(torch, sn, oracle_lib, variant, n_wg):
-    """The small network's FP32 step as a workgroup per 16 slots (variant 0)
-    and as one wavefront per slot (variant 1, the default for few
-    sub-traces), the latter also with 16 slots for 40 sub-traces (slots
-    refilled from the work queue): injected latencies bit-exact; free runs
-    replayed by the oracle from the GPU's own latencies; shadow mode on the
-    oracle's own latencies reproduces its rounded outputs away from ties."""
+    """The small network's FP32 step as a workgroup per 16 slots (variant 0),
+    as one wavefront per slot (variant 1) and as four wavefronts per slot,
+    one per block of the conv tree (variant 2), the latter two also with 16
+    slots for 40 sub-traces (slots refilled from the work queue): injected
+    latencies bit-exact; free runs replayed by the oracle from the GPU's own
+    latencies; shadow mode on the oracle's own latencies reproduces its
+    rounded outputs away from ties."""
     S = Setup(torch, sn, oracle_lib, "small", 5000, 40, 64)
     S.sim.set_tuning(variant, n_wg or (40 + 15) // 16)  # (all slots: 16 per workgroup)
     table = synth.latency_table(29, S.n_pred, 2, heavy=0.1)
@@ -362,3 +363,31 @@ def test_small_network_step_forms(torch, sn, oracle_lib, variant, n_wg):
     own = np.clip(np.rint(gl.astype(np.float64)), 0, 65535).astype(np.int32)
     assert not np.any((own != o["lat"]) & ~ties)
     assert sh["n_shadow_mismatch"] == int(((own != o["lat"])).sum())
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2])
+def test_small_network_steps_in_pieces(torch, sn, oracle_lib, variant):
+    """A run in pieces of 7 steps (each launch writes the sub-traces' state,
+    queue ring included, back to memory and the next reads it) equals one
+    run, in each of the small network's step forms."""
+    S = Setup(torch, sn, oracle_lib, "small", 3000, 9, 64)
+    table = synth.latency_table(31, S.n_pred, 2, heavy=0.1)
+    S.sim.set_tuning(variant, 1)
+    a = S.sim.run(sn.SIM_LAT_INJECT, dev(torch, table))
+    S.sim.reset()
+    for _ in range(40):
+        S.sim.step(7, sn.SIM_LAT_INJECT, dev(torch, table))
+    b = S.sim.run(sn.SIM_LAT_INJECT, dev(torch, table))
+    assert_same_results(a, b, 9)
+    S.sim.reset()
+    logits = torch.zeros((S.n_pred, 2), dtype=torch.float32, device="cuda")
+    S.sim.record_logits(logits)
+    c = S.sim.run()
+    d_logits = logits.clone()
+    S.sim.reset()
+    logits.zero_()
+    for _ in range(40):
+        S.sim.step(7)
+    d = S.sim.run()
+    assert_same_results(c, d, 9)
+    assert torch.equal(logits, d_logits)
