@@ -621,11 +621,13 @@ static int relayout_train(sim_ctx* c) {
   for (int l = 0; l < 4; ++l)
     segs.seg[segs.count++] = GatherSeg{T.maps + T.map_pack[l], (int64_t)T.n_pack[l],
                                        static_cast<char*>(T.packed) + T.pack_off[l], bf16};
-  // the head's transposed copy is the forward's operand: in the form's
-  // precision; the others serve the backward products in FP32
+  // the transposed copies (the head's is the forward's operand, the others
+  // serve the backward products) in the form's precision: the BF16 form's
+  // products round their operands to BF16 (nearest even, as here) anyway,
+  // and BF16 operands are staged without conversion
   for (int l = 0; l < 5; ++l)
     segs.seg[segs.count++] = GatherSeg{T.maps + T.map_perm[l], (int64_t)T.n_perm[l],
-                                       T.perm + T.perm_off[l], l == 4 ? bf16 : 0};
+                                       T.perm + T.perm_off[l], bf16};
   const hipError_t e = launch_map_gather_multi(T.master, segs, c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "training re-layout");
   DevWeights& w = c->w;
@@ -1502,7 +1504,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
            TRAIN_OUT, 512, B, beta));
   colsum(dlogits, 0, B, TRAIN_OUT, dparams + T.boff[4]);
   // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU
-  g = gemm(opnd(dH, bf, 512, 1), opnd(T.perm + T.perm_off[3], 0, 3328, 1), dY3, 3328, B, 3328,
+  g = gemm(opnd(dH, bf, 512, 1), opnd(T.perm + T.perm_off[3], bf, 3328, 1), dY3, 3328, B, 3328,
            512, 0);
   g.mask = opnd(sb.a3, bf, 3328, 1);
   g.c_bf16 = bf;
@@ -1511,7 +1513,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   scatter(3, dparams);
   colsum(dH, bf, B, 512, dparams + T.boff[3]);
   // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
-  g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], 0, 256, 1), dY2, 256, B * 13, 256,
+  g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], bf, 256, 1), dY2, 256, B * 13, 256,
            256, 0);
   g.mask = opnd(sb.a2, bf, 256, 1);
   g.c_bf16 = bf;
@@ -1520,7 +1522,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   scatter(2, dparams);
   colsum(dY3, bf, B * 13, 256, dparams + T.boff[2]);
   // conv2: rows (b, p), 26 per window
-  g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], 0, 128, 1), dY1, 128, B * 26, 128,
+  g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 128, 1), dY1, 128, B * 26, 128,
            128, 0);
   g.mask = opnd(sb.a1, bf, 128, 1);
   g.c_bf16 = bf;
@@ -1536,7 +1538,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
   if (dx) {
     if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);
-    g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], 0, 100, 1), dx, 100, B * 52, 100,
+    g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], bf, 100, 1), dx, 100, B * 52, 100,
              64, 0);
     g.cgrp = 52;
     g.cgs = win;

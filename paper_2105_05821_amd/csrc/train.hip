@@ -200,8 +200,15 @@ constexpr int HB = 128, HK = 32, HLD = HK + 8;
 typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 
 
+// One thread's 16 staged elements of an operand: as floats (converted to
+// BF16 when stored), or, raw, the 16 BF16 values as loaded (an operand
+// already in BF16 needs no conversion: its values round to themselves).
 struct Stage {
-  float v[16];
+  union {
+    float v[16];
+    uint32_t w[8];  // raw: element 2q in the low half of w[q], 2q + 1 in the high
+  };
+  int raw;
 };
 
 // Element (outer, k) of an operand: A is (m, k), B is (k, n).
@@ -226,6 +233,7 @@ __device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int 
     const int64_t left = k_lim - k;
     cnt = outer < outer_lim ? (left > 16 ? 16 : (left > 0 ? (int)left : 0)) : 0;
   }
+  st.raw = 0;
   if (mode != 0 && vec == 1 && cnt == 16) {  // 8-byte vectors
     const int64_t a = elem_addr(o, is_b, outer, k);
     if (o.bf16) {
@@ -233,11 +241,10 @@ __device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int 
 #pragma unroll
       for (int h = 0; h < 4; ++h) {
         const uint2 w = p[h];
-        st.v[4 * h] = __uint_as_float(w.x << 16);
-        st.v[4 * h + 1] = __uint_as_float(w.x & 0xffff0000u);
-        st.v[4 * h + 2] = __uint_as_float(w.y << 16);
-        st.v[4 * h + 3] = __uint_as_float(w.y & 0xffff0000u);
+        st.w[2 * h] = w.x;
+        st.w[2 * h + 1] = w.y;
       }
+      st.raw = 1;
     } else {
       const float2* p = reinterpret_cast<const float2*>(static_cast<const float*>(o.p) + a);
 #pragma unroll
@@ -256,13 +263,12 @@ __device__ __forceinline__ void stage_load(const GemmOperand& o, bool is_b, int 
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const uint4 w = p[h];
-        const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          st.v[h * 8 + 2 * q] = __uint_as_float(ws[q] << 16);
-          st.v[h * 8 + 2 * q + 1] = __uint_as_float(ws[q] & 0xffff0000u);
-        }
+        st.w[4 * h] = w.x;
+        st.w[4 * h + 1] = w.y;
+        st.w[4 * h + 2] = w.z;
+        st.w[4 * h + 3] = w.w;
       }
+      st.raw = 1;
     } else {
       const float4* p = reinterpret_cast<const float4*>(static_cast<const float*>(o.p) + a);
 #pragma unroll
@@ -295,6 +301,13 @@ __device__ __forceinline__ void stage_store(uint16_t (*S)[HLD], int mode, int ti
                                             const Stage& st) {
   if (mode == 2) {
     const int k = tid / 8, outer = (tid % 8) * 16;
+    if (st.raw) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        S[outer + e][8 * chunk_at(outer + e, k >> 3) + (k & 7)] =
+            (uint16_t)(e & 1 ? st.w[e / 2] >> 16 : st.w[e / 2] & 0xffffu);
+      return;
+    }
 #pragma unroll
     for (int e = 0; e < 16; ++e)
       S[outer + e][8 * chunk_at(outer + e, k >> 3) + (k & 7)] = to_bf16(st.v[e]);
@@ -303,7 +316,8 @@ __device__ __forceinline__ void stage_store(uint16_t (*S)[HLD], int mode, int ti
     uint32_t w[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q)
-      w[q] = (uint32_t)to_bf16(st.v[2 * q]) | ((uint32_t)to_bf16(st.v[2 * q + 1]) << 16);
+      w[q] = st.raw ? st.w[q]
+                    : (uint32_t)to_bf16(st.v[2 * q]) | ((uint32_t)to_bf16(st.v[2 * q + 1]) << 16);
     *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0)]) = uint4{w[0], w[1], w[2], w[3]};
     *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0 + 1)]) =
         uint4{w[4], w[5], w[6], w[7]};
