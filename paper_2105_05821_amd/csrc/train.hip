@@ -17,6 +17,8 @@
 //   map kernels      weight re-layouts and gradient scatters by index maps.
 //   pad_rows         a row-major matrix copied with its rows padded.
 //   adam_kernel      Adam on FP32 master weights.
+#include <type_traits>
+
 #include "simnet_internal.h"
 
 namespace simnet {
@@ -196,6 +198,8 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs g) {
 // runs), mode 2 = along the outer dimension (written as 16 scalars, a
 // transpose), mode 0 = no unit stride (scalar reads, k-major mapping).
 constexpr int HB = 128, HK = 32, HLD = HK + 8;
+static_assert(32 * (HB + 4) * sizeof(float) <= 2 * HB * HLD * sizeof(uint16_t),
+              "the epilogue's staging fits one operand's LDS tiles");
 
 typedef __bf16 v8bf_t __attribute__((ext_vector_type(8)));
 
@@ -324,65 +328,19 @@ __device__ __forceinline__ void stage_store(uint16_t (*S)[HLD], int mode, int ti
   }
 }
 
-__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[2][HB][HLD];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HB][HLD];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t m0 = (int64_t)blockIdx.y * HB, n0 = (int64_t)blockIdx.x * HB;
-  const int wm = wave >> 1, wn = wave & 1;
-  int64_t kb, ke;
-  k_range(g, HK, &kb, &ke);
-  v4f acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  Stage sa, sb;
-  stage_load(g.A, false, g.amode, g.avec, m0, kb, g.M, ke, tid, sa);
-  stage_load(g.B, true, g.bmode, g.bvec, n0, kb, g.N, ke, tid, sb);
-  stage_store(As[0], g.amode, tid, sa);
-  stage_store(Bs[0], g.bmode, tid, sb);
-  __syncthreads();
-  int cur = 0;
-  for (int64_t k0 = kb; k0 < ke; k0 += HK) {
-    const bool more = k0 + HK < ke;
-    if (more) {  // next k-step's operands in flight during this one's MFMAs
-      stage_load(g.A, false, g.amode, g.avec, m0, k0 + HK, g.M, ke, tid, sa);
-      stage_load(g.B, true, g.bmode, g.bvec, n0, k0 + HK, g.N, ke, tid, sb);
-    }
-    uint4 af[4], bfr[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int row = wm * 64 + i * 16 + (lane & 15);
-      af[i] = *reinterpret_cast<const uint4*>(&As[cur][row][8 * chunk_at(row, lane >> 4)]);
-    }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int row = wn * 64 + j * 16 + (lane & 15);
-      bfr[j] = *reinterpret_cast<const uint4*>(&Bs[cur][row][8 * chunk_at(row, lane >> 4)]);
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf_t, af[i]),
-                                                           __builtin_bit_cast(v8bf_t, bfr[j]),
-                                                           acc[i][j], 0, 0, 0);
-    if (more) {
-      stage_store(As[cur ^ 1], g.amode, tid, sa);
-      stage_store(Bs[cur ^ 1], g.bmode, tid, sb);
-    }
-    __syncthreads();
-    cur ^= 1;
-  }
+// The BF16 kernels' output: the tile's accumulators (wave (wm, wn) holds
+// rows wm*64 .., columns wn*64 ..) to C through the epilogue (bias, ReLU
+// mask, accumulate, BF16 output), or to the split-K partials.  E: LDS
+// scratch of at least 32 x (HB + 4) floats, free once the products end.
+__device__ __forceinline__ void gemm_bf16_epilogue(const GemmArgs& g, v4f (&acc)[4][4], float* E,
+                                                   int64_t m0, int64_t n0, int wm, int wn, int tid,
+                                                   int lane) {
   if (g.evec) {
     // whole 16-byte rows: the tile goes through LDS a quarter at a time (32
     // rows x 128 columns), and each thread finishes 16 consecutive columns
     // of one row with vector reads of the mask and previous C and vector
     // stores (full cache lines per row instead of 64-byte pieces)
     constexpr int ES = HB + 4;  // row stride of the staged quarter, in floats
-    static_assert(32 * ES * sizeof(float) <= sizeof(As), "epilogue staging");
-    float* E = reinterpret_cast<float*>(&As[0][0][0]);
     const int er = tid / 8, ec = (tid % 8) * 16;
     const int64_t m = m0 + (er / 16) * 64 + (er % 16);  // + i * 16
 #pragma unroll
@@ -482,6 +440,60 @@ __global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
         gemm_store_row4(g, m, nb, v);
       }
     }
+}
+
+__global__ void __launch_bounds__(256) gemm_bf16_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][HB][HLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HB][HLD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.y * HB, n0 = (int64_t)blockIdx.x * HB;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t kb, ke;
+  k_range(g, HK, &kb, &ke);
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  Stage sa, sb;
+  stage_load(g.A, false, g.amode, g.avec, m0, kb, g.M, ke, tid, sa);
+  stage_load(g.B, true, g.bmode, g.bvec, n0, kb, g.N, ke, tid, sb);
+  stage_store(As[0], g.amode, tid, sa);
+  stage_store(Bs[0], g.bmode, tid, sb);
+  __syncthreads();
+  int cur = 0;
+  for (int64_t k0 = kb; k0 < ke; k0 += HK) {
+    const bool more = k0 + HK < ke;
+    if (more) {  // next k-step's operands in flight during this one's MFMAs
+      stage_load(g.A, false, g.amode, g.avec, m0, k0 + HK, g.M, ke, tid, sa);
+      stage_load(g.B, true, g.bmode, g.bvec, n0, k0 + HK, g.N, ke, tid, sb);
+    }
+    uint4 af[4], bfr[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = wm * 64 + i * 16 + (lane & 15);
+      af[i] = *reinterpret_cast<const uint4*>(&As[cur][row][8 * chunk_at(row, lane >> 4)]);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int row = wn * 64 + j * 16 + (lane & 15);
+      bfr[j] = *reinterpret_cast<const uint4*>(&Bs[cur][row][8 * chunk_at(row, lane >> 4)]);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf_t, af[i]),
+                                                           __builtin_bit_cast(v8bf_t, bfr[j]),
+                                                           acc[i][j], 0, 0, 0);
+    if (more) {
+      stage_store(As[cur ^ 1], g.amode, tid, sa);
+      stage_store(Bs[cur ^ 1], g.bmode, tid, sb);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  gemm_bf16_epilogue(g, acc, reinterpret_cast<float*>(&As[0][0][0]), m0, n0, wm, wn, tid, lane);
 }
 
 // out[n] = sum_{c < cnt} src[c * stride + n] for n < N, in a fixed order:
@@ -607,6 +619,153 @@ static void launch_reduce(const float* src, int64_t cnt, int64_t stride, int64_t
   }
 }
 
+// The BF16 kernel for operands that need no edge handling: both in BF16
+// with 16-byte runs along their contiguous dimension, rows not grouped,
+// every dimension a multiple of the tile (M and N of HB, each split-K
+// range of HK).  A thread's requests are then the same two 16-byte vectors
+// per operand in every k-step, at addresses a fixed stride apart, so they
+// run NS k-steps ahead of their use in a ring of NS register stages (past
+// the end they repeat the last k-step's addresses: a uniform count of
+// requests keeps every wait exact; the general kernel's per-thread paths
+// force a wait for all of them), and the values go to LDS as loaded.
+// AM, BM: the operands' modes (1 = contiguous along k, 2 = along the outer
+// dimension), as in gemm_bf16_kernel.  Same products in the same order as
+// gemm_bf16_kernel, so the same results.  (NS = 3 here.)
+// This thread's first vector of an operand at k-step 0, and the uint4s
+// between consecutive k-steps.
+template <int MODE>
+__device__ __forceinline__ const uint4* fast_base(const GemmOperand& o, bool is_b, int64_t outer0,
+                                                  int64_t kb, int tid, int64_t* step) {
+  const int64_t outer = MODE == 2 ? outer0 + (tid % 8) * 16 : outer0 + tid / 2;
+  const int64_t k = MODE == 2 ? kb + tid / 8 : kb + (tid % 2) * 16;
+  *step = HK * (is_b ? o.rs : o.cs) / 8;
+  return reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(o.p) +
+                                        elem_addr(o, is_b, outer, k));
+}
+
+__device__ __forceinline__ void fast_load(const uint4* p, int64_t step, int64_t i,
+                                          uint32_t (&w)[8]) {
+  const uint4* q = p + i * step;
+  const uint4 a = q[0], b = q[1];
+  w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+  w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+}
+
+template <int MODE>
+__device__ __forceinline__ void fast_store(uint16_t (*S)[HLD], int tid, const uint32_t (&w)[8]) {
+  if constexpr (MODE == 2) {
+    const int k = tid / 8, outer = (tid % 8) * 16;
+#pragma unroll
+    for (int e = 0; e < 16; ++e)
+      S[outer + e][8 * chunk_at(outer + e, k >> 3) + (k & 7)] =
+          (uint16_t)(e & 1 ? w[e / 2] >> 16 : w[e / 2] & 0xffffu);
+  } else {
+    const int outer = tid / 2, c0 = (tid % 2) * 2;
+    *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0)]) = uint4{w[0], w[1], w[2], w[3]};
+    *reinterpret_cast<uint4*>(&S[outer][8 * chunk_at(outer, c0 + 1)]) =
+        uint4{w[4], w[5], w[6], w[7]};
+  }
+}
+
+// k-step i of gemm_bf16_fast_kernel: request step i + 3 into the stage (la,
+// lb) that held step i's operands, multiply LDS buffer CUR, store step i +
+// 1's stage (sa, sb), requested two steps ago, into the other buffer.
+template <int AM, int BM, int CUR>
+__device__ __forceinline__ void fast_step(int64_t i, int64_t n_steps, v4f (&acc)[4][4],
+                                          uint16_t (*As)[HB][HLD], uint16_t (*Bs)[HB][HLD],
+                                          const uint4* pa, int64_t sta, const uint4* pb,
+                                          int64_t stb, uint32_t (&la)[8], uint32_t (&lb)[8],
+                                          const uint32_t (&sa)[8], const uint32_t (&sb)[8],
+                                          int wm, int wn, int lane, int tid) {
+  const int64_t r = i + 3 < n_steps ? i + 3 : n_steps - 1;  // past the end: the last again
+  fast_load(pa, sta, r, la);
+  fast_load(pb, stb, r, lb);
+  uint4 af[4], bfr[4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int row = wm * 64 + a * 16 + (lane & 15);
+    af[a] = *reinterpret_cast<const uint4*>(&As[CUR][row][8 * chunk_at(row, lane >> 4)]);
+  }
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int row = wn * 64 + b * 16 + (lane & 15);
+    bfr[b] = *reinterpret_cast<const uint4*>(&Bs[CUR][row][8 * chunk_at(row, lane >> 4)]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf_t, af[a]),
+                                                         __builtin_bit_cast(v8bf_t, bfr[b]),
+                                                         acc[a][b], 0, 0, 0);
+  if (i + 1 < n_steps) {
+    fast_store<AM>(As[CUR ^ 1], tid, sa);
+    fast_store<BM>(Bs[CUR ^ 1], tid, sb);
+  }
+  __syncthreads();
+}
+
+template <int AM, int BM>
+__global__ void __launch_bounds__(256) gemm_bf16_fast_kernel(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][HB][HLD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HB][HLD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int64_t m0 = (int64_t)blockIdx.y * HB, n0 = (int64_t)blockIdx.x * HB;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t kb, ke;
+  k_range(g, HK, &kb, &ke);
+  v4f acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int64_t n = (ke - kb) / HK;
+  if (n > 0) {
+    int64_t sta, stb;
+    const uint4* pa = fast_base<AM>(g.A, false, m0, kb, tid, &sta);
+    const uint4* pb = fast_base<BM>(g.B, true, n0, kb, tid, &stb);
+    // three register stages; k-step i's operands are requested into stage
+    // i % 3 at the start of step i - 3 (the first three here)
+    uint32_t a0[8], b0[8], a1[8], b1[8], a2[8], b2[8];
+    fast_load(pa, sta, 0, a0);
+    fast_load(pb, stb, 0, b0);
+    fast_load(pa, sta, n > 1 ? 1 : 0, a1);
+    fast_load(pb, stb, n > 1 ? 1 : 0, b1);
+    fast_load(pa, sta, n > 2 ? 2 : n - 1, a2);
+    fast_load(pb, stb, n > 2 ? 2 : n - 1, b2);
+    fast_store<AM>(As[0], tid, a0);
+    fast_store<BM>(Bs[0], tid, b0);
+    __syncthreads();
+    // six steps per iteration, so that stages (i % 3) and LDS buffers (i % 2)
+    // are fixed registers and fixed addresses
+    // (the guards are nested: a step runs only after the one before it, so
+    // the compiler counts the requests in flight exactly)
+    for (int64_t i = 0; i < n; i += 6) {
+      fast_step<AM, BM, 0>(i, n, acc, As, Bs, pa, sta, pb, stb, a0, b0, a1, b1, wm, wn, lane, tid);
+      if (i + 1 < n) {
+        fast_step<AM, BM, 1>(i + 1, n, acc, As, Bs, pa, sta, pb, stb, a1, b1, a2, b2, wm, wn, lane,
+                             tid);
+        if (i + 2 < n) {
+          fast_step<AM, BM, 0>(i + 2, n, acc, As, Bs, pa, sta, pb, stb, a2, b2, a0, b0, wm, wn,
+                               lane, tid);
+          if (i + 3 < n) {
+            fast_step<AM, BM, 1>(i + 3, n, acc, As, Bs, pa, sta, pb, stb, a0, b0, a1, b1, wm, wn,
+                                 lane, tid);
+            if (i + 4 < n) {
+              fast_step<AM, BM, 0>(i + 4, n, acc, As, Bs, pa, sta, pb, stb, a1, b1, a2, b2, wm, wn,
+                                   lane, tid);
+              if (i + 5 < n)
+                fast_step<AM, BM, 1>(i + 5, n, acc, As, Bs, pa, sta, pb, stb, a2, b2, a0, b0, wm,
+                                     wn, lane, tid);
+            }
+          }
+        }
+      }
+    }
+  }
+  gemm_bf16_epilogue(g, acc, reinterpret_cast<float*>(&As[0][0][0]), m0, n0, wm, wn, tid, lane);
+}
+
 // Operand access mode for the BF16 kernel (see gemm_bf16_kernel) and the
 // vector reads a run of 16 elements allows: 2 = 16-byte, 1 = 8-byte (rows
 // of an odd multiple of 8 bytes apart, e.g. windows of 111 x 50 FP32
@@ -669,10 +828,24 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
     g.evec = bf16_mma && ks == 1 && !g.bias && g.N % 16 == 0 && c_ok && m_ok;
   }
   const dim3 grid((unsigned)((g.N + TB - 1) / TB), (unsigned)((g.M + TB - 1) / TB), (unsigned)ks);
-  if (bf16_mma)
+  // operands with nothing to guard: the pipelined kernel
+  const bool fast = bf16_mma && g.A.bf16 && g.B.bf16 && g.avec == 2 && g.bvec == 2 &&
+                    g.amode != 0 && g.bmode != 0 && g.A.grp >= NO_GROUP && g.B.grp >= NO_GROUP &&
+                    g.M % HB == 0 && g.N % HB == 0 && g.K % HK == 0;
+  if (fast) {
+    if (g.amode == 1 && g.bmode == 1)
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<1, 1>), grid, dim3(256), 0, stream, g);
+    else if (g.amode == 1)
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<1, 2>), grid, dim3(256), 0, stream, g);
+    else if (g.bmode == 1)
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<2, 1>), grid, dim3(256), 0, stream, g);
+    else
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<2, 2>), grid, dim3(256), 0, stream, g);
+  } else if (bf16_mma) {
     hipLaunchKernelGGL(gemm_bf16_kernel, grid, dim3(256), 0, stream, g);
-  else
+  } else {
     hipLaunchKernelGGL(gemm_kernel, grid, dim3(256), 0, stream, g);
+  }
   if (ks > 1) {
     const int64_t MN = g.M * g.N;
     launch_reduce<true>(part, ks, MN, MN, g, nullptr, 0, stream);
