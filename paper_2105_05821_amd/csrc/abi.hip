@@ -18,13 +18,16 @@ using namespace simnet;
 
 // Training form (net 2: C3 trunk, hidden layer kept, head FC 512 -> 802):
 // FP32 master parameters, index maps for the device-side re-layouts, the
-// packed trunk weights in the form's precision, FP32 permuted copies used by
-// the backward products, and the backward workspace.
+// packed trunk weights in the form's precision, permuted copies in the
+// form's precision used by the forward head and the backward products, the
+// maps that scatter a weight-gradient staging matrix ([c_out][input column])
+// to the parameters, and the backward workspace.
 struct TrainState {
   float* master = nullptr;
   int32_t* maps = nullptr;
   size_t map_pack[4] = {0}, n_pack[4] = {0};
-  size_t map_perm[5] = {0}, n_perm[5] = {0};  // w1c, w2c, w3, w1, w2t
+  size_t map_perm[5] = {0}, n_perm[5] = {0};  // w1c, w2c, w3, w1, w2
+  size_t map_scat[4] = {0};                   // w1c, w2c, w3, w1 (n_perm entries each)
   void* packed = nullptr;
   size_t pack_off[4] = {0};
   float* perm = nullptr;
@@ -536,7 +539,9 @@ static int upload_weights(sim_ctx* c, int prec, const float* params,
 
 constexpr int TRAIN_BINS = 400, TRAIN_OUT = 2 * (TRAIN_BINS + 1);
 // the head's operand rows padded to whole 16-byte vectors (BF16 and FP32)
-constexpr int TRAIN_LD = (TRAIN_OUT + 7) / 8 * 8;
+// the head's outputs padded to whole 32-deep k-steps (its input-gradient
+// product runs over them, the padding zero)
+constexpr int TRAIN_LD = (TRAIN_OUT + 31) / 32 * 32;
 
 static bool train_layers_match(const sim_layer* l, int32_t n) {
   const int32_t want[5][4] = {{0, 50, 64, 1}, {0, 64, 128, 1}, {0, 128, 256, 1},
@@ -588,25 +593,38 @@ static void build_train_maps(sim_ctx* c, std::vector<int32_t>* maps) {
   for (int j = 0; j < 13; ++j)
     packed(256, 512, [&](int ch, int n) { return (int32_t)(T.woff[3] + (size_t)n * 3328 + ch * 13 + j); });
   T.n_pack[3] = maps->size() - T.map_pack[3];
-  // FP32 row-major copies for the backward: conv l as [c_out][2*c_in] with
-  // column t*c_in + c, the hidden layer with column p*256 + c, the head
-  // transposed [512][802] with rows padded to TRAIN_LD
+  // row-major copies, each contiguous along the dimension its products sum
+  // over: conv l as [2*c_in][c_out] (input column t*c_in + c) and the hidden
+  // layer as [3328][512] (input column p*256 + c), the input-gradient
+  // products' right operands; the head as [TRAIN_LD][512] (the FP32 layout,
+  // rows past 802 zero), the forward's right operand and the head's
+  // input-gradient one
   for (int l = 0; l < 3; ++l) {
     T.map_perm[l] = maps->size();
     const int ci = chs[l], co = chs[l + 1];
-    for (int o = 0; o < co; ++o)
-      for (int k = 0; k < 2 * ci; ++k)
+    for (int k = 0; k < 2 * ci; ++k)
+      for (int o = 0; o < co; ++o)
         maps->push_back((int32_t)(T.woff[l] + ((size_t)o * ci + k % ci) * 2 + k / ci));
     T.n_perm[l] = maps->size() - T.map_perm[l];
   }
   T.map_perm[3] = maps->size();
-  for (int o = 0; o < 512; ++o)
-    for (int k = 0; k < 3328; ++k)
+  for (int k = 0; k < 3328; ++k)
+    for (int o = 0; o < 512; ++o)
       maps->push_back((int32_t)(T.woff[3] + (size_t)o * 3328 + (k % 256) * 13 + k / 256));
   T.n_perm[3] = maps->size() - T.map_perm[3];
+  // the trunk's weight gradients are staged as [c_out][input column]
+  for (int l = 0; l < 4; ++l) {
+    T.map_scat[l] = maps->size();
+    const int ci = l < 3 ? 2 * chs[l] : 3328, co = l < 3 ? chs[l + 1] : 512;
+    for (int o = 0; o < co; ++o)
+      for (int k = 0; k < ci; ++k) {
+        const int32_t src = (*maps)[T.map_perm[l] + (size_t)k * co + o];
+        maps->push_back(src);
+      }
+  }
   T.map_perm[4] = maps->size();
-  for (int j = 0; j < 512; ++j)
-    for (int o = 0; o < TRAIN_LD; ++o)
+  for (int o = 0; o < TRAIN_LD; ++o)
+    for (int j = 0; j < 512; ++j)
       maps->push_back(o < TRAIN_OUT ? (int32_t)(T.woff[4] + (size_t)o * 512 + j) : -1);
   T.n_perm[4] = maps->size() - T.map_perm[4];
 }
@@ -733,6 +751,14 @@ static GemmOperand opnd(const void* p, int bf16, int64_t rs, int64_t cs,
   o.cs = cs;
   o.grp = grp;
   o.gs = gs;
+  o.ext = 0;
+  return o;
+}
+
+// The operand with `ext` elements readable along its contiguous outer
+// dimension (a copy whose rows are padded past M or N).
+static GemmOperand padded(GemmOperand o, int64_t ext) {
+  o.ext = ext;
   return o;
 }
 
@@ -1307,7 +1333,7 @@ int predictor_fwd(sim_ctx* c, const void* x, int64_t B, float* logits, void* sav
                                        B, sb, c->stream);
     TrainState& T = c->tr;
     const int bf = c->cfg.prec == SIM_BF16;
-    GemmArgs g = gemm(opnd(sb.h, bf, 512, 1), opnd(T.perm + T.perm_off[4], bf, TRAIN_LD, 1),
+    GemmArgs g = gemm(opnd(sb.h, bf, 512, 1), opnd(T.perm + T.perm_off[4], bf, 1, 512),
                       logits, TRAIN_OUT, B, TRAIN_OUT, 512, 0);
     g.bias = T.master + T.boff[4];
     if (e == hipSuccess) e = launch_gemm(g, bf, nullptr, 0, c->stream);
@@ -1473,7 +1499,6 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   float* dWt = W + train_work_off(B, 5);
   float* csw = W + train_work_off(B, 6);
   float* part = W + train_work_off(B, 7);
-  const float* P = T.master;
   hipError_t e = hipSuccess;
   auto run = [&](const GemmArgs& g) {
     if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
@@ -1483,7 +1508,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   };
   auto scatter = [&](int l, float* dst) {
     if (e == hipSuccess)
-      e = launch_map_scatter(dWt, T.maps + T.map_perm[l], (int64_t)T.n_perm[l], dst, beta,
+      e = launch_map_scatter(dWt, T.maps + T.map_scat[l], (int64_t)T.n_perm[l], dst, beta,
                              c->stream);
   };
   // The output gradients of the hidden layer and the convolutions (dH, dY3,
@@ -1491,20 +1516,23 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   // precision: BF16 in the BF16 form, where every product and the bias sum
   // take them rounded; FP32 in the FP32 form.
   // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H.
-  // dZ is read from a copy with rows padded to TRAIN_LD (dY1's space, free
-  // until conv2's input gradient), so both products read it in vectors.
-  float* dZp = dY1;
-  e = launch_pad_rows(dlogits, B, TRAIN_OUT, TRAIN_LD, dZp, c->stream);
-  GemmArgs g = gemm(opnd(dZp, 0, TRAIN_LD, 1), opnd(P + T.woff[4], 0, 512, 1), dH, 512, B,
-                    512, TRAIN_OUT, 0);
+  // dZ is read from a copy with rows padded to TRAIN_LD with zeros (dY1's
+  // space, free until conv2's input gradient), in the form's precision (the
+  // BF16 products round it to BF16 anyway), so both products read it in
+  // vectors and dH's runs over whole k-steps (the head copy's padding rows
+  // are zero too).
+  void* dZp = dY1;
+  e = launch_pad_rows(dlogits, B, TRAIN_OUT, TRAIN_LD, dZp, bf, c->stream);
+  GemmArgs g = gemm(opnd(dZp, bf, TRAIN_LD, 1), opnd(T.perm + T.perm_off[4], bf, 512, 1), dH,
+                    512, B, 512, TRAIN_LD, 0);
   g.mask = opnd(sb.h, bf, 512, 1);
   g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dZp, 0, 1, TRAIN_LD), opnd(sb.h, bf, 512, 1), dparams + T.woff[4], 512,
-           TRAIN_OUT, 512, B, beta));
+  run(gemm(padded(opnd(dZp, bf, 1, TRAIN_LD), TRAIN_LD), opnd(sb.h, bf, 512, 1),
+           dparams + T.woff[4], 512, TRAIN_OUT, 512, B, beta));
   colsum(dlogits, 0, B, TRAIN_OUT, dparams + T.boff[4]);
   // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU
-  g = gemm(opnd(dH, bf, 512, 1), opnd(T.perm + T.perm_off[3], bf, 3328, 1), dY3, 3328, B, 3328,
+  g = gemm(opnd(dH, bf, 512, 1), opnd(T.perm + T.perm_off[3], bf, 1, 512), dY3, 3328, B, 3328,
            512, 0);
   g.mask = opnd(sb.a3, bf, 3328, 1);
   g.c_bf16 = bf;
@@ -1513,7 +1541,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   scatter(3, dparams);
   colsum(dH, bf, B, 512, dparams + T.boff[3]);
   // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
-  g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], bf, 256, 1), dY2, 256, B * 13, 256,
+  g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], bf, 1, 256), dY2, 256, B * 13, 256,
            256, 0);
   g.mask = opnd(sb.a2, bf, 256, 1);
   g.c_bf16 = bf;
@@ -1522,7 +1550,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   scatter(2, dparams);
   colsum(dY3, bf, B * 13, 256, dparams + T.boff[2]);
   // conv2: rows (b, p), 26 per window
-  g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 128, 1), dY1, 128, B * 26, 128,
+  g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 1, 128), dY1, 128, B * 26, 128,
            128, 0);
   g.mask = opnd(sb.a1, bf, 128, 1);
   g.c_bf16 = bf;
@@ -1538,7 +1566,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
   if (dx) {
     if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);
-    g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], bf, 100, 1), dx, 100, B * 52, 100,
+    g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], bf, 1, 64), dx, 100, B * 52, 100,
              64, 0);
     g.cgrp = 52;
     g.cgs = win;

@@ -241,10 +241,15 @@ hipError_t launch_forward_save(int prec, const DevWeights& w, uint32_t relu, con
 // (grp splits the rows into groups with their own stride, e.g. the window
 // rows of a batch of 111-slot windows), FP32 or BF16.
 constexpr int64_t NO_GROUP = (int64_t)1 << 62;  // GemmOperand.grp of an ungrouped operand
+// ext: elements readable along the outer dimension (m of A, n of B) when
+// that dimension is the contiguous one (rows of a padded copy), 0 = the
+// matrix's own M or N; the pipelined BF16 kernel reads whole 16-element runs
+// up to it and keeps what lies past M or N out of the output.
 struct GemmOperand {
   const void* p;
   int32_t bf16;
   int64_t rs, cs, grp, gs;
+  int64_t ext;
 };
 // C[M][N] (+)= A(m, k) B(k, n) [+ bias[n]], then zeroed where mask(m, n) <= 0;
 // C(m, n) at C + (m / cgrp) * cgs + (m % cgrp) * ldc + n, FP32, or (c_bf16)
@@ -272,8 +277,8 @@ size_t colsum_workspace(int64_t N);
 // Column sums of y [M][ld] (FP32, or BF16 with y_bf16) into out[N] (+= with beta).
 hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
                          int beta, float* work, hipStream_t stream);
-hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
-                           hipStream_t stream);
+hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, void* dst,
+                           int32_t dst_bf16, hipStream_t stream);
 // dst[i] = src[map[i]] (0 where map[i] < 0) for i < n, in FP32 or rounded
 // to BF16, for up to MAX (map, n, dst) segments in one launch.
 struct GatherSeg {

@@ -632,11 +632,23 @@ static void launch_reduce(const float* src, int64_t cnt, int64_t stride, int64_t
 // dimension), as in gemm_bf16_kernel.  Same products in the same order as
 // gemm_bf16_kernel, so the same results.  (NS = 3 here.)
 // This thread's first vector of an operand at k-step 0, and the uint4s
-// between consecutive k-steps.
+// between consecutive k-steps.  Past the matrix's outer size `dim` the tile
+// is filled from rows (mode 1) or runs (mode 2) that exist, the last row or
+// the last whole run below the readable extent: they only reach outputs
+// past M or N, which the epilogue does not store.
 template <int MODE>
 __device__ __forceinline__ const uint4* fast_base(const GemmOperand& o, bool is_b, int64_t outer0,
-                                                  int64_t kb, int tid, int64_t* step) {
-  const int64_t outer = MODE == 2 ? outer0 + (tid % 8) * 16 : outer0 + tid / 2;
+                                                  int64_t dim, int64_t kb, int tid,
+                                                  int64_t* step) {
+  int64_t outer;
+  if constexpr (MODE == 2) {
+    const int64_t cap = o.ext ? o.ext : dim;  // a multiple of 16, at least dim
+    outer = outer0 + (tid % 8) * 16;
+    if (outer > cap - 16) outer = cap - 16;
+  } else {
+    outer = outer0 + tid / 2;
+    if (outer > dim - 1) outer = dim - 1;
+  }
   const int64_t k = MODE == 2 ? kb + tid / 8 : kb + (tid % 2) * 16;
   *step = HK * (is_b ? o.rs : o.cs) / 8;
   return reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(o.p) +
@@ -722,8 +734,8 @@ __global__ void __launch_bounds__(256) gemm_bf16_fast_kernel(GemmArgs g) {
   const int64_t n = (ke - kb) / HK;
   if (n > 0) {
     int64_t sta, stb;
-    const uint4* pa = fast_base<AM>(g.A, false, m0, kb, tid, &sta);
-    const uint4* pb = fast_base<BM>(g.B, true, n0, kb, tid, &stb);
+    const uint4* pa = fast_base<AM>(g.A, false, m0, g.M, kb, tid, &sta);
+    const uint4* pb = fast_base<BM>(g.B, true, n0, g.N, kb, tid, &stb);
     // three register stages; k-step i's operands are requested into stage
     // i % 3 at the start of step i - 3 (the first three here)
     uint32_t a0[8], b0[8], a1[8], b1[8], a2[8], b2[8];
@@ -828,10 +840,17 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
     g.evec = bf16_mma && ks == 1 && !g.bias && g.N % 16 == 0 && c_ok && m_ok;
   }
   const dim3 grid((unsigned)((g.N + TB - 1) / TB), (unsigned)((g.M + TB - 1) / TB), (unsigned)ks);
-  // operands with nothing to guard: the pipelined kernel
+  // operands with nothing to guard along k: the pipelined kernel (rows
+  // along the outer dimension are clamped; runs of 16 along it need a
+  // readable extent of whole runs)
+  auto whole_runs = [](const GemmOperand& o, int32_t mode, int64_t dim) {
+    const int64_t cap = o.ext ? o.ext : dim;
+    return mode == 1 || (cap % 16 == 0 && cap >= dim);
+  };
   const bool fast = bf16_mma && g.A.bf16 && g.B.bf16 && g.avec == 2 && g.bvec == 2 &&
                     g.amode != 0 && g.bmode != 0 && g.A.grp >= NO_GROUP && g.B.grp >= NO_GROUP &&
-                    g.M % HB == 0 && g.N % HB == 0 && g.K % HK == 0;
+                    whole_runs(g.A, g.amode, g.M) && whole_runs(g.B, g.bmode, g.N) &&
+                    g.K % HK == 0;
   if (fast) {
     if (g.amode == 1 && g.bmode == 1)
       hipLaunchKernelGGL((gemm_bf16_fast_kernel<1, 1>), grid, dim3(256), 0, stream, g);
@@ -1006,18 +1025,22 @@ __global__ void map_scatter(const float* __restrict__ src, const int32_t* __rest
 // One workgroup row per matrix row (grid x), 256 columns per workgroup
 // (grid y).
 __global__ void pad_rows(const float* __restrict__ src, int64_t cols, int64_t ld,
-                         float* __restrict__ dst) {
+                         void* __restrict__ dst, int32_t dst_bf16) {
   const int64_t r = blockIdx.x, c = (int64_t)blockIdx.y * 256 + threadIdx.x;
   if (c >= ld) return;
-  dst[r * ld + c] = c < cols ? src[r * cols + c] : 0.f;
+  const float v = c < cols ? src[r * cols + c] : 0.f;
+  if (dst_bf16)
+    static_cast<uint16_t*>(dst)[r * ld + c] = to_bf16(v);
+  else
+    static_cast<float*>(dst)[r * ld + c] = v;
 }
 
-hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, float* dst,
-                           hipStream_t stream) {
+hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, void* dst,
+                           int32_t dst_bf16, hipStream_t stream) {
   if (rows <= 0) return hipSuccess;
   if (rows > INT32_MAX || (ld + 255) / 256 > 65535) return hipErrorInvalidValue;
   hipLaunchKernelGGL(pad_rows, dim3((unsigned)rows, (unsigned)((ld + 255) / 256)), dim3(256), 0,
-                     stream, src, cols, ld, dst);
+                     stream, src, cols, ld, dst, dst_bf16);
   return hipGetLastError();
 }
 
