@@ -1561,7 +1561,10 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   // conv1: rows (b, p), 52 per window; input pairs of window slots, rows of
   // window b at x + b*111*50 (the last 7 slots feed no output)
   const int64_t win = (int64_t)c->cfg.n_slot * c->cfg.n_feat;
-  run(gemm(opnd(dY1, bf, 1, 64), opnd(x, 0, 100, 1, 52, win), dWt, 100, 64, 100, B * 52, 0));
+  // (x read in runs of 16 along the 100 columns of a pair: up to column 111
+  // of the last pair, slot 104, still inside its window)
+  run(gemm(opnd(dY1, bf, 1, 64), padded(opnd(x, 0, 100, 1, 52, win), 112), dWt, 100, 64, 100,
+           B * 52, 0));
   scatter(0, dparams);
   colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
   if (dx) {

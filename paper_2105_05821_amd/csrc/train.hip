@@ -631,17 +631,49 @@ static void launch_reduce(const float* src, int64_t cnt, int64_t stride, int64_t
 // AM, BM: the operands' modes (1 = contiguous along k, 2 = along the outer
 // dimension), as in gemm_bf16_kernel.  Same products in the same order as
 // gemm_bf16_kernel, so the same results.  (NS = 3 here.)
-// This thread's first vector of an operand at k-step 0, and the uint4s
-// between consecutive k-steps.  Past the matrix's outer size `dim` the tile
-// is filled from rows (mode 1) or runs (mode 2) that exist, the last row or
-// the last whole run below the readable extent: they only reach outputs
-// past M or N, which the epilogue does not store.
+// One thread's share of an operand, 16 elements per k-step.  Modes 1 and 2:
+// BF16 in 16-byte runs, rows a fixed distance apart (the uint4s between
+// consecutive k-steps in `step`).  Mode 3 (the right operand only): FP32
+// runs along n in 8-byte pieces, rows (k) possibly grouped, rounded to BF16
+// (nearest even, as gemm_bf16_kernel does) on their way to LDS, which then
+// takes them as mode 2.  Past the matrix's outer size `dim` the tile is
+// filled from rows (mode 1) or runs (modes 2, 3) that exist, the last row or
+// the last whole run below the readable extent: they only reach outputs past
+// M or N, which the epilogue does not store.
 template <int MODE>
-__device__ __forceinline__ const uint4* fast_base(const GemmOperand& o, bool is_b, int64_t outer0,
-                                                  int64_t dim, int64_t kb, int tid,
-                                                  int64_t* step) {
+struct FastOp {
+  static constexpr int W = 8;  // 32-bit words staged per k-step
+  const uint4* p;
+  int64_t step;
+  __device__ __forceinline__ void load(int64_t i, uint32_t (&w)[W]) const {
+    const uint4* q = p + i * step;
+    const uint4 a = q[0], b = q[1];
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+    w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+  }
+};
+
+template <>
+struct FastOp<3> {
+  static constexpr int W = 16;
+  const float* p;  // the run's first column, row offset 0
+  int64_t k0, grp, gs, rs;
+  __device__ __forceinline__ void load(int64_t i, uint32_t (&w)[W]) const {
+    const uint2* q = reinterpret_cast<const uint2*>(p + grouped_row(k0 + i * HK, grp, gs, rs));
+#pragma unroll
+    for (int h = 0; h < 8; ++h) {
+      const uint2 v = q[h];
+      w[2 * h] = v.x;
+      w[2 * h + 1] = v.y;
+    }
+  }
+};
+
+template <int MODE>
+__device__ __forceinline__ FastOp<MODE> fast_op(const GemmOperand& o, bool is_b, int64_t outer0,
+                                                int64_t dim, int64_t kb, int tid) {
   int64_t outer;
-  if constexpr (MODE == 2) {
+  if constexpr (MODE >= 2) {
     const int64_t cap = o.ext ? o.ext : dim;  // a multiple of 16, at least dim
     outer = outer0 + (tid % 8) * 16;
     if (outer > cap - 16) outer = cap - 16;
@@ -649,23 +681,33 @@ __device__ __forceinline__ const uint4* fast_base(const GemmOperand& o, bool is_
     outer = outer0 + tid / 2;
     if (outer > dim - 1) outer = dim - 1;
   }
-  const int64_t k = MODE == 2 ? kb + tid / 8 : kb + (tid % 2) * 16;
-  *step = HK * (is_b ? o.rs : o.cs) / 8;
-  return reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(o.p) +
-                                        elem_addr(o, is_b, outer, k));
-}
-
-__device__ __forceinline__ void fast_load(const uint4* p, int64_t step, int64_t i,
-                                          uint32_t (&w)[8]) {
-  const uint4* q = p + i * step;
-  const uint4 a = q[0], b = q[1];
-  w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
-  w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+  const int64_t k = MODE >= 2 ? kb + tid / 8 : kb + (tid % 2) * 16;
+  FastOp<MODE> f;
+  if constexpr (MODE == 3) {
+    f.p = static_cast<const float*>(o.p) + outer;
+    f.k0 = k;
+    f.grp = o.grp;
+    f.gs = o.gs;
+    f.rs = o.rs;
+  } else {
+    f.step = HK * (is_b ? o.rs : o.cs) / 8;
+    f.p = reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(o.p) +
+                                         elem_addr(o, is_b, outer, k));
+  }
+  return f;
 }
 
 template <int MODE>
-__device__ __forceinline__ void fast_store(uint16_t (*S)[HLD], int tid, const uint32_t (&w)[8]) {
-  if constexpr (MODE == 2) {
+__device__ __forceinline__ void fast_store(uint16_t (*S)[HLD], int tid,
+                                           const uint32_t (&w)[FastOp<MODE>::W]) {
+  if constexpr (MODE == 3) {
+    uint32_t h[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      h[e] = (uint32_t)to_bf16(__uint_as_float(w[2 * e])) |
+             ((uint32_t)to_bf16(__uint_as_float(w[2 * e + 1])) << 16);
+    fast_store<2>(S, tid, h);
+  } else if constexpr (MODE == 2) {
     const int k = tid / 8, outer = (tid % 8) * 16;
 #pragma unroll
     for (int e = 0; e < 16; ++e)
@@ -685,13 +727,15 @@ __device__ __forceinline__ void fast_store(uint16_t (*S)[HLD], int tid, const ui
 template <int AM, int BM, int CUR>
 __device__ __forceinline__ void fast_step(int64_t i, int64_t n_steps, v4f (&acc)[4][4],
                                           uint16_t (*As)[HB][HLD], uint16_t (*Bs)[HB][HLD],
-                                          const uint4* pa, int64_t sta, const uint4* pb,
-                                          int64_t stb, uint32_t (&la)[8], uint32_t (&lb)[8],
-                                          const uint32_t (&sa)[8], const uint32_t (&sb)[8],
-                                          int wm, int wn, int lane, int tid) {
+                                          const FastOp<AM>& pa, const FastOp<BM>& pb,
+                                          uint32_t (&la)[FastOp<AM>::W],
+                                          uint32_t (&lb)[FastOp<BM>::W],
+                                          const uint32_t (&sa)[FastOp<AM>::W],
+                                          const uint32_t (&sb)[FastOp<BM>::W], int wm, int wn,
+                                          int lane, int tid) {
   const int64_t r = i + 3 < n_steps ? i + 3 : n_steps - 1;  // past the end: the last again
-  fast_load(pa, sta, r, la);
-  fast_load(pb, stb, r, lb);
+  pa.load(r, la);
+  pb.load(r, lb);
   uint4 af[4], bfr[4];
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
@@ -718,7 +762,7 @@ __device__ __forceinline__ void fast_step(int64_t i, int64_t n_steps, v4f (&acc)
 }
 
 template <int AM, int BM>
-__global__ void __launch_bounds__(256) gemm_bf16_fast_kernel(GemmArgs g) {
+__global__ void __launch_bounds__(256, 2) gemm_bf16_fast_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][HB][HLD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HB][HLD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -733,18 +777,18 @@ __global__ void __launch_bounds__(256) gemm_bf16_fast_kernel(GemmArgs g) {
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int64_t n = (ke - kb) / HK;
   if (n > 0) {
-    int64_t sta, stb;
-    const uint4* pa = fast_base<AM>(g.A, false, m0, g.M, kb, tid, &sta);
-    const uint4* pb = fast_base<BM>(g.B, true, n0, g.N, kb, tid, &stb);
+    const FastOp<AM> pa = fast_op<AM>(g.A, false, m0, g.M, kb, tid);
+    const FastOp<BM> pb = fast_op<BM>(g.B, true, n0, g.N, kb, tid);
     // three register stages; k-step i's operands are requested into stage
     // i % 3 at the start of step i - 3 (the first three here)
-    uint32_t a0[8], b0[8], a1[8], b1[8], a2[8], b2[8];
-    fast_load(pa, sta, 0, a0);
-    fast_load(pb, stb, 0, b0);
-    fast_load(pa, sta, n > 1 ? 1 : 0, a1);
-    fast_load(pb, stb, n > 1 ? 1 : 0, b1);
-    fast_load(pa, sta, n > 2 ? 2 : n - 1, a2);
-    fast_load(pb, stb, n > 2 ? 2 : n - 1, b2);
+    uint32_t a0[FastOp<AM>::W], a1[FastOp<AM>::W], a2[FastOp<AM>::W];
+    uint32_t b0[FastOp<BM>::W], b1[FastOp<BM>::W], b2[FastOp<BM>::W];
+    pa.load(0, a0);
+    pb.load(0, b0);
+    pa.load(n > 1 ? 1 : 0, a1);
+    pb.load(n > 1 ? 1 : 0, b1);
+    pa.load(n > 2 ? 2 : n - 1, a2);
+    pb.load(n > 2 ? 2 : n - 1, b2);
     fast_store<AM>(As[0], tid, a0);
     fast_store<BM>(Bs[0], tid, b0);
     __syncthreads();
@@ -753,21 +797,21 @@ __global__ void __launch_bounds__(256) gemm_bf16_fast_kernel(GemmArgs g) {
     // (the guards are nested: a step runs only after the one before it, so
     // the compiler counts the requests in flight exactly)
     for (int64_t i = 0; i < n; i += 6) {
-      fast_step<AM, BM, 0>(i, n, acc, As, Bs, pa, sta, pb, stb, a0, b0, a1, b1, wm, wn, lane, tid);
+      fast_step<AM, BM, 0>(i, n, acc, As, Bs, pa, pb, a0, b0, a1, b1, wm, wn, lane, tid);
       if (i + 1 < n) {
-        fast_step<AM, BM, 1>(i + 1, n, acc, As, Bs, pa, sta, pb, stb, a1, b1, a2, b2, wm, wn, lane,
+        fast_step<AM, BM, 1>(i + 1, n, acc, As, Bs, pa, pb, a1, b1, a2, b2, wm, wn, lane,
                              tid);
         if (i + 2 < n) {
-          fast_step<AM, BM, 0>(i + 2, n, acc, As, Bs, pa, sta, pb, stb, a2, b2, a0, b0, wm, wn,
+          fast_step<AM, BM, 0>(i + 2, n, acc, As, Bs, pa, pb, a2, b2, a0, b0, wm, wn,
                                lane, tid);
           if (i + 3 < n) {
-            fast_step<AM, BM, 1>(i + 3, n, acc, As, Bs, pa, sta, pb, stb, a0, b0, a1, b1, wm, wn,
+            fast_step<AM, BM, 1>(i + 3, n, acc, As, Bs, pa, pb, a0, b0, a1, b1, wm, wn,
                                  lane, tid);
             if (i + 4 < n) {
-              fast_step<AM, BM, 0>(i + 4, n, acc, As, Bs, pa, sta, pb, stb, a1, b1, a2, b2, wm, wn,
+              fast_step<AM, BM, 0>(i + 4, n, acc, As, Bs, pa, pb, a1, b1, a2, b2, wm, wn,
                                    lane, tid);
               if (i + 5 < n)
-                fast_step<AM, BM, 1>(i + 5, n, acc, As, Bs, pa, sta, pb, stb, a2, b2, a0, b0, wm,
+                fast_step<AM, BM, 1>(i + 5, n, acc, As, Bs, pa, pb, a2, b2, a0, b0, wm,
                                      wn, lane, tid);
             }
           }
@@ -847,11 +891,18 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
     const int64_t cap = o.ext ? o.ext : dim;
     return mode == 1 || (cap % 16 == 0 && cap >= dim);
   };
-  const bool fast = bf16_mma && g.A.bf16 && g.B.bf16 && g.avec == 2 && g.bvec == 2 &&
-                    g.amode != 0 && g.bmode != 0 && g.A.grp >= NO_GROUP && g.B.grp >= NO_GROUP &&
-                    whole_runs(g.A, g.amode, g.M) && whole_runs(g.B, g.bmode, g.N) &&
-                    g.K % HK == 0;
-  if (fast) {
+  const bool fast_a = bf16_mma && g.A.bf16 && g.avec == 2 && g.amode != 0 &&
+                      g.A.grp >= NO_GROUP && whole_runs(g.A, g.amode, g.M) && g.K % HK == 0;
+  const bool fast_b = g.B.bf16 && g.bvec == 2 && g.bmode != 0 && g.B.grp >= NO_GROUP &&
+                      whole_runs(g.B, g.bmode, g.N);
+  // FP32 along n in 8-byte pieces, rows possibly grouped (e.g. the windows)
+  const bool fast_b32 = !g.B.bf16 && g.bvec >= 1 && g.bmode == 2 && whole_runs(g.B, 2, g.N);
+  if (fast_a && fast_b32) {
+    if (g.amode == 1)
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<1, 3>), grid, dim3(256), 0, stream, g);
+    else
+      hipLaunchKernelGGL((gemm_bf16_fast_kernel<2, 3>), grid, dim3(256), 0, stream, g);
+  } else if (fast_a && fast_b) {
     if (g.amode == 1 && g.bmode == 1)
       hipLaunchKernelGGL((gemm_bf16_fast_kernel<1, 1>), grid, dim3(256), 0, stream, g);
     else if (g.amode == 1)
