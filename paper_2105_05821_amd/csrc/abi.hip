@@ -19,15 +19,13 @@ using namespace simnet;
 // Training form (net 2: C3 trunk, hidden layer kept, head FC 512 -> 802):
 // FP32 master parameters, index maps for the device-side re-layouts, the
 // packed trunk weights in the form's precision, permuted copies in the
-// form's precision used by the forward head and the backward products, the
-// maps that scatter a weight-gradient staging matrix ([c_out][input column])
-// to the parameters, and the backward workspace.
+// form's precision used by the forward head and the backward products, and
+// the backward workspace.
 struct TrainState {
   float* master = nullptr;
   int32_t* maps = nullptr;
   size_t map_pack[4] = {0}, n_pack[4] = {0};
   size_t map_perm[5] = {0}, n_perm[5] = {0};  // w1c, w2c, w3, w1, w2
-  size_t map_scat[4] = {0};                   // w1c, w2c, w3, w1 (n_perm entries each)
   void* packed = nullptr;
   size_t pack_off[4] = {0};
   float* perm = nullptr;
@@ -612,16 +610,6 @@ static void build_train_maps(sim_ctx* c, std::vector<int32_t>* maps) {
     for (int o = 0; o < 512; ++o)
       maps->push_back((int32_t)(T.woff[3] + (size_t)o * 3328 + (k % 256) * 13 + k / 256));
   T.n_perm[3] = maps->size() - T.map_perm[3];
-  // the trunk's weight gradients are staged as [c_out][input column]
-  for (int l = 0; l < 4; ++l) {
-    T.map_scat[l] = maps->size();
-    const int ci = l < 3 ? 2 * chs[l] : 3328, co = l < 3 ? chs[l + 1] : 512;
-    for (int o = 0; o < co; ++o)
-      for (int k = 0; k < ci; ++k) {
-        const int32_t src = (*maps)[T.map_perm[l] + (size_t)k * co + o];
-        maps->push_back(src);
-      }
-  }
   T.map_perm[4] = maps->size();
   for (int o = 0; o < TRAIN_LD; ++o)
     for (int j = 0; j < 512; ++j)
@@ -699,14 +687,12 @@ static int load_train_weights(sim_ctx* c, const sim_layer* layers, int32_t n_lay
 }
 
 // Backward workspace (floats): [0] per-window losses, [1] dH [B][512],
-// [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] a
-// weight-gradient staging matrix (largest [512][3328]), [6] column sums,
-// [7] split-K partial products.
+// [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] column
+// sums, [6] split-K partial products.
 constexpr size_t SPLITK_CAP = (size_t)8 << 20;
 static size_t train_work_off(int64_t B, int part) {
-  const size_t sizes[8] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
-                           (size_t)B * 3328, (size_t)512 * 3328, colsum_workspace(TRAIN_OUT) / 4,
-                           SPLITK_CAP};
+  const size_t sizes[7] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
+                           (size_t)B * 3328, colsum_workspace(TRAIN_OUT) / 4, SPLITK_CAP};
   size_t off = 0;
   for (int i = 0; i < part; ++i) off += (sizes[i] + 63) / 64 * 64;
   return off;
@@ -720,7 +706,7 @@ static int ensure_train_work(sim_ctx* c, int64_t B) {
     (void)hipFree(T.work);
     T.work = nullptr;
   }
-  hipError_t e = hipMalloc(&T.work, train_work_off(B, 8) * 4);
+  hipError_t e = hipMalloc(&T.work, train_work_off(B, 7) * 4);
   if (e != hipSuccess) return hip_fail(c, e, "training workspace");
   T.work_B = B;
   return SIM_OK;
@@ -772,6 +758,8 @@ static GemmArgs gemm(GemmOperand A, GemmOperand B, float* C, int64_t ldc, int64_
   g.ldc = ldc;
   g.cgrp = NO_GROUP;
   g.cgs = 0;
+  g.ccg = 0;
+  g.ccm = 0;
   g.M = M;
   g.N = N;
   g.K = K;
@@ -1496,9 +1484,8 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   float* dY3 = W + train_work_off(B, 2);
   float* dY2 = W + train_work_off(B, 3);
   float* dY1 = W + train_work_off(B, 4);
-  float* dWt = W + train_work_off(B, 5);
-  float* csw = W + train_work_off(B, 6);
-  float* part = W + train_work_off(B, 7);
+  float* csw = W + train_work_off(B, 5);
+  float* part = W + train_work_off(B, 6);
   hipError_t e = hipSuccess;
   auto run = [&](const GemmArgs& g) {
     if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
@@ -1506,10 +1493,15 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   auto colsum = [&](const void* y, int y_bf16, int64_t M, int64_t N, float* out) {
     if (e == hipSuccess) e = launch_colsum(y, y_bf16, M, N, N, out, beta, csw, c->stream);
   };
-  auto scatter = [&](int l, float* dst) {
-    if (e == hipSuccess)
-      e = launch_map_scatter(dWt, T.maps + T.map_scat[l], (int64_t)T.n_perm[l], dst, beta,
-                             c->stream);
+  // trunk layer l's weight gradient, [c_out][input column] with input
+  // column t*c_in + c (p*256 + c for the hidden layer), stored straight
+  // into the parameters' layout ([c_out][c_in][2], [512][256][13])
+  auto wgrad = [&](const GemmOperand& dy, const GemmOperand& act, int l, int64_t c_out,
+                   int64_t cols, int64_t c_in, int64_t taps, int64_t rows) {
+    GemmArgs g = gemm(dy, act, dparams + T.woff[l], cols, c_out, cols, rows, beta);
+    g.ccg = c_in;
+    g.ccm = taps;
+    run(g);
   };
   // The output gradients of the hidden layer and the convolutions (dH, dY3,
   // dY2, dY1, masked by their layer's ReLU) are written in the form's
@@ -1537,8 +1529,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   g.mask = opnd(sb.a3, bf, 3328, 1);
   g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dH, bf, 1, 512), opnd(sb.a3, bf, 3328, 1), dWt, 3328, 512, 3328, B, 0));
-  scatter(3, dparams);
+  wgrad(opnd(dH, bf, 1, 512), opnd(sb.a3, bf, 3328, 1), 3, 512, 3328, 256, 13, B);
   colsum(dH, bf, B, 512, dparams + T.boff[3]);
   // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
   g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], bf, 1, 256), dY2, 256, B * 13, 256,
@@ -1546,8 +1537,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   g.mask = opnd(sb.a2, bf, 256, 1);
   g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), dWt, 256, 256, 256, B * 13, 0));
-  scatter(2, dparams);
+  wgrad(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), 2, 256, 256, 128, 2, B * 13);
   colsum(dY3, bf, B * 13, 256, dparams + T.boff[2]);
   // conv2: rows (b, p), 26 per window
   g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 1, 128), dY1, 128, B * 26, 128,
@@ -1555,17 +1545,15 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   g.mask = opnd(sb.a1, bf, 128, 1);
   g.c_bf16 = bf;
   run(g);
-  run(gemm(opnd(dY2, bf, 1, 128), opnd(sb.a1, bf, 128, 1), dWt, 128, 128, 128, B * 26, 0));
-  scatter(1, dparams);
+  wgrad(opnd(dY2, bf, 1, 128), opnd(sb.a1, bf, 128, 1), 1, 128, 128, 64, 2, B * 26);
   colsum(dY2, bf, B * 26, 128, dparams + T.boff[1]);
   // conv1: rows (b, p), 52 per window; input pairs of window slots, rows of
   // window b at x + b*111*50 (the last 7 slots feed no output)
   const int64_t win = (int64_t)c->cfg.n_slot * c->cfg.n_feat;
   // (x read in runs of 16 along the 100 columns of a pair: up to column 111
   // of the last pair, slot 104, still inside its window)
-  run(gemm(opnd(dY1, bf, 1, 64), padded(opnd(x, 0, 100, 1, 52, win), 112), dWt, 100, 64, 100,
-           B * 52, 0));
-  scatter(0, dparams);
+  wgrad(opnd(dY1, bf, 1, 64), padded(opnd(x, 0, 100, 1, 52, win), 112), 0, 64, 100, 50, 2,
+        B * 52);
   colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
   if (dx) {
     if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);

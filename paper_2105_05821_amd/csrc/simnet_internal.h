@@ -252,13 +252,16 @@ struct GemmOperand {
   int64_t ext;
 };
 // C[M][N] (+)= A(m, k) B(k, n) [+ bias[n]], then zeroed where mask(m, n) <= 0;
-// C(m, n) at C + (m / cgrp) * cgs + (m % cgrp) * ldc + n, FP32, or (c_bf16)
-// rounded to BF16 (nearest even) at the same element offsets of a uint16_t
-// array (no accumulation then).
+// C(m, n) at C + (m / cgrp) * cgs + (m % cgrp) * ldc + col(n), FP32, or
+// (c_bf16) rounded to BF16 (nearest even) at the same element offsets of a
+// uint16_t array (no accumulation then); col(n) = n, or with ccg > 0
+// (n % ccg) * ccm + n / ccg (a weight gradient stored straight into a
+// parameter layout whose input columns interleave).
 struct GemmArgs {
   GemmOperand A, B, mask;
   float* C;
   int64_t ldc, cgrp, cgs;
+  int64_t ccg, ccm;
   int64_t M, N, K;
   const float* bias;
   int32_t beta;
@@ -293,8 +296,6 @@ struct GatherSegs {
   int32_t count;
 };
 hipError_t launch_map_gather_multi(const float* src, const GatherSegs& segs, hipStream_t stream);
-hipError_t launch_map_scatter(const float* src, const int32_t* map, int64_t n, float* dst,
-                              int beta, hipStream_t stream);
 hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int32_t t, hipStream_t stream);

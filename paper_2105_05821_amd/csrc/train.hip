@@ -6,15 +6,17 @@
 //                    rounded to BF16 in LDS); operands in FP32 or BF16 with
 //                    arbitrary strides; split-K with an ordered reduction
 //                    when the output is small; epilogue with bias, ReLU mask
-//                    (a saved activation > 0) and accumulation.  Used for the head and for every
-//                    input-gradient and weight-gradient product of the
+//                    (a saved activation > 0), accumulation and a column
+//                    permutation of C (weight gradients stored in the
+//                    parameters' own layout).  Used for the head and for
+//                    every input-gradient and weight-gradient product of the
 //                    backward pass (a kernel-2 stride-2 convolution is a
 //                    GEMM over position pairs).
 //   loss_kernel      hybrid loss per window (400-bin cross-entropy + L1 on
 //                    log1p(latency) per latency type) and its gradient
 //                    w.r.t. the head outputs.
 //   colsum kernels   bias gradients, summed in a fixed order.
-//   map kernels      weight re-layouts and gradient scatters by index maps.
+//   map_gather_multi weight re-layouts by index maps.
 //   pad_rows         a row-major matrix copied with its rows padded.
 //   adam_kernel      Adam on FP32 master weights.
 #include <type_traits>
@@ -50,12 +52,20 @@ __device__ __forceinline__ uint16_t to_bf16(float x) {
   return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// Column n's offset in a row of C (N below 2^32 when permuted: the host
+// checks).
+__device__ __forceinline__ int64_t c_col(const GemmArgs& g, int64_t n) {
+  if (g.ccg == 0) return n;
+  const uint32_t q = (uint32_t)n / (uint32_t)g.ccg;
+  return (int64_t)((uint32_t)n - q * (uint32_t)g.ccg) * g.ccm + q;
+}
+
 // C(m, n) epilogue shared by every GEMM path: bias, ReLU mask, accumulate,
-// grouped row addressing, BF16 output.
+// grouped row and permuted column addressing, BF16 output.
 __device__ __forceinline__ void gemm_store(const GemmArgs& g, int64_t m, int64_t n, float v) {
   if (g.bias) v += g.bias[n];
   if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, op_index(g.mask, m, n)) > 0.f)) v = 0.f;
-  const int64_t at = grouped_row(m, g.cgrp, g.cgs, g.ldc) + n;
+  const int64_t at = grouped_row(m, g.cgrp, g.cgs, g.ldc) + c_col(g, n);
   if (g.c_bf16) {
     reinterpret_cast<uint16_t*>(g.C)[at] = to_bf16(v);
     return;
@@ -77,10 +87,11 @@ __device__ __forceinline__ void gemm_store_row4(const GemmArgs& g, int64_t m, in
     float x = v[j];
     if (g.bias) x += g.bias[n];
     if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, mrow + n * g.mask.cs) > 0.f)) x = 0.f;
+    const int64_t at = crow + c_col(g, n);
     if (g.c_bf16) {
-      reinterpret_cast<uint16_t*>(g.C)[crow + n] = to_bf16(x);
+      reinterpret_cast<uint16_t*>(g.C)[at] = to_bf16(x);
     } else {
-      float* c = g.C + crow + n;
+      float* c = g.C + at;
       *c = g.beta ? *c + x : x;
     }
   }
@@ -619,18 +630,20 @@ static void launch_reduce(const float* src, int64_t cnt, int64_t stride, int64_t
   }
 }
 
-// The BF16 kernel for operands that need no edge handling: both in BF16
-// with 16-byte runs along their contiguous dimension, rows not grouped,
-// every dimension a multiple of the tile (M and N of HB, each split-K
-// range of HK).  A thread's requests are then the same two 16-byte vectors
-// per operand in every k-step, at addresses a fixed stride apart, so they
-// run NS k-steps ahead of their use in a ring of NS register stages (past
+// The BF16 kernel for operands that need no edge handling along k: the
+// left one in BF16 with 16-byte runs along its contiguous dimension, the
+// right one so too or FP32 along n (mode 3 below), rows not grouped (but
+// mode 3's), each split-K range a whole number of HK-deep steps, tails of M
+// and N filled as fast_op describes.  A thread's requests are then the same
+// vectors per operand in every k-step, at addresses that step uniformly, so
+// they run NS k-steps ahead of their use in a ring of NS register stages (past
 // the end they repeat the last k-step's addresses: a uniform count of
 // requests keeps every wait exact; the general kernel's per-thread paths
 // force a wait for all of them), and the values go to LDS as loaded.
 // AM, BM: the operands' modes (1 = contiguous along k, 2 = along the outer
-// dimension), as in gemm_bf16_kernel.  Same products in the same order as
-// gemm_bf16_kernel, so the same results.  (NS = 3 here.)
+// dimension, as in gemm_bf16_kernel; 3 = FP32 along n).  Same products in
+// the same order as gemm_bf16_kernel, so the same results.  (NS = 3 here.)
+
 // One thread's share of an operand, 16 elements per k-step.  Modes 1 and 2:
 // BF16 in 16-byte runs, rows a fixed distance apart (the uint4s between
 // consecutive k-steps in `step`).  Mode 3 (the right operand only): FP32
@@ -864,7 +877,8 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   // grouped rows are divided in 32 bits
   const int64_t big = (int64_t)1 << 32;
   if ((g.A.grp < NO_GROUP && g.M >= big) || (g.B.grp < NO_GROUP && g.K >= big) ||
-      (g.mask.p && g.mask.grp < NO_GROUP && g.M >= big) || (g.cgrp < NO_GROUP && g.M >= big))
+      (g.mask.p && g.mask.grp < NO_GROUP && g.M >= big) || (g.cgrp < NO_GROUP && g.M >= big) ||
+      (g.ccg != 0 && (g.ccg < 0 || g.N >= big)))
     return hipErrorInvalidValue;
   g.ksplit = (int32_t)ks;
   g.part = part;
@@ -881,7 +895,7 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
                                     reinterpret_cast<uintptr_t>(g.mask.p) % 16 == 0 &&
                                     g.mask.rs % mq == 0 &&
                                     (g.mask.grp >= NO_GROUP || g.mask.gs % mq == 0));
-    g.evec = bf16_mma && ks == 1 && !g.bias && g.N % 16 == 0 && c_ok && m_ok;
+    g.evec = bf16_mma && ks == 1 && !g.bias && g.ccg == 0 && g.N % 16 == 0 && c_ok && m_ok;
   }
   const dim3 grid((unsigned)((g.N + TB - 1) / TB), (unsigned)((g.M + TB - 1) / TB), (unsigned)ks);
   // operands with nothing to guard along k: the pipelined kernel (rows
@@ -1062,15 +1076,6 @@ hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_
   return hipGetLastError();
 }
 
-// dst[map[i]] (=|+=) src[i] for map[i] >= 0 (the map is one-to-one).
-__global__ void map_scatter(const float* __restrict__ src, const int32_t* __restrict__ map,
-                            int64_t n, float* __restrict__ dst, int beta) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
-  const int32_t k = map[i];
-  if (k >= 0) dst[k] = beta ? dst[k] + src[i] : src[i];
-}
-
 // dst[r][c] = src[r][c] for c < cols, 0 for cols <= c < ld: rows padded to
 // a stride whose 16-byte vectors the GEMM operand reads can use.
 // One workgroup row per matrix row (grid x), 256 columns per workgroup
@@ -1125,13 +1130,6 @@ hipError_t launch_map_gather_multi(const float* src, const GatherSegs& segs, hip
   for (int s = 0; s < segs.count; ++s) blocks += (segs.seg[s].n + 255) / 256;
   if (blocks == 0) return hipSuccess;
   hipLaunchKernelGGL(map_gather_multi, dim3((unsigned)blocks), dim3(256), 0, stream, src, segs);
-  return hipGetLastError();
-}
-
-hipError_t launch_map_scatter(const float* src, const int32_t* map, int64_t n, float* dst,
-                              int beta, hipStream_t stream) {
-  hipLaunchKernelGGL(map_scatter, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, src,
-                     map, n, dst, beta);
   return hipGetLastError();
 }
 
