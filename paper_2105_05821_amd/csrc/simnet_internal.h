@@ -277,7 +277,8 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
 hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
                        float* loss_b, float* loss, float* dz, hipStream_t stream);
 size_t colsum_workspace(int64_t N);
-// Column sums of y [M][ld] (FP32, or BF16 with y_bf16) into out[N] (+= with beta).
+// Column sums of y [M][ld] (FP32, or BF16 with y_bf16) into out[N] (+= with
+// beta), in a fixed order; work: colsum_workspace(N) bytes.
 hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
                          int beta, float* work, hipStream_t stream);
 hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, void* dst,

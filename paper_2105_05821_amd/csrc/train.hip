@@ -1053,11 +1053,126 @@ __global__ void __launch_bounds__(256) colsum_partial(const void* __restrict__ y
                               (red[2][col * V + v] + red[3][col * V + v]);
 }
 
+// Partial column sums for rows whose columns come in whole VB-byte vectors
+// (VW columns each).  Workgroup (x, c) takes column block x (TPR vectors side
+// by side) and rows [c*per, min(M, (c+1)*per)): RP = 256 / TPR row lanes,
+// lane r summing rows lo + r, lo + r + RP, ... in order, four requests in
+// flight; the RP lane sums are combined by a fixed pairwise tree in LDS into
+// part[c][n], which strided_reduce then sums over c.  (A single launch in
+// which the last workgroup of a block adds the partials was slower: the
+// device-scope release each workgroup needs before counting writes back its
+// XCD's whole L2.)
+template <bool BF, int VB>
+struct ColVec {
+  static constexpr int VW = VB / (BF ? 2 : 4);
+  using T = typename std::conditional<VB == 16, uint4, uint2>::type;
+  __device__ static __forceinline__ T load(const void* y, int64_t at) {
+    return *reinterpret_cast<const T*>(static_cast<const char*>(y) + at * (BF ? 2 : 4));
+  }
+  __device__ static __forceinline__ void add(float (&a)[VW], const T& t) {
+    const uint32_t* w = reinterpret_cast<const uint32_t*>(&t);
+#pragma unroll
+    for (int q = 0; q < VB / 4; ++q) {
+      if constexpr (BF) {
+        a[2 * q] += __uint_as_float(w[q] << 16);
+        a[2 * q + 1] += __uint_as_float(w[q] & 0xffff0000u);
+      } else {
+        a[q] += __uint_as_float(w[q]);
+      }
+    }
+  }
+};
+
+template <int VW>
+__device__ __forceinline__ void lane_tree(float (&a)[VW], float* red, int r, int j, int tpr,
+                                          int rp) {
+#pragma unroll
+  for (int v = 0; v < VW; ++v) red[(r * tpr + j) * VW + v] = a[v];
+  __syncthreads();
+  for (int h = rp / 2; h >= 1; h /= 2) {
+    if (r < h)
+#pragma unroll
+      for (int v = 0; v < VW; ++v)
+        red[(r * tpr + j) * VW + v] += red[((r + h) * tpr + j) * VW + v];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int v = 0; v < VW; ++v) a[v] = red[j * VW + v];
+}
+
+template <bool BF, int VB>
+__global__ void __launch_bounds__(256) colsum_vec(const void* __restrict__ y, int64_t M, int64_t N,
+                                                  int64_t ld, int64_t per, int tpr,
+                                                  float* __restrict__ part) {
+  using V = ColVec<BF, VB>;
+  constexpr int VW = V::VW;
+  __shared__ float red[256 * VW];
+  const int tid = threadIdx.x, j = tid % tpr, r = tid / tpr, rp = 256 / tpr;
+  const int64_t n = (int64_t)blockIdx.x * tpr * VW + j * VW;
+  const int64_t c = blockIdx.y, lo = c * per, hi = lo + per < M ? lo + per : M;
+  const bool on = n < N;
+  float a[VW];
+#pragma unroll
+  for (int v = 0; v < VW; ++v) a[v] = 0.f;
+  if (on) {
+    int64_t m = lo + r;
+    for (; m + 3 * rp < hi; m += 4 * rp) {
+      const typename V::T t0 = V::load(y, m * ld + n), t1 = V::load(y, (m + rp) * ld + n),
+                          t2 = V::load(y, (m + 2 * rp) * ld + n),
+                          t3 = V::load(y, (m + 3 * rp) * ld + n);
+      V::add(a, t0);
+      V::add(a, t1);
+      V::add(a, t2);
+      V::add(a, t3);
+    }
+    for (; m < hi; m += rp) V::add(a, V::load(y, m * ld + n));
+  }
+  lane_tree<VW>(a, red, r, j, tpr, rp);
+  if (r == 0 && on)
+#pragma unroll
+    for (int v = 0; v < VW; ++v) part[c * N + n + v] = a[v];
+}
+
 size_t colsum_workspace(int64_t N) { return sizeof(float) * CS_MAX_CHUNKS * (size_t)N; }
 
 hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
                          int beta, float* work, hipStream_t stream) {
   if (N <= 0) return hipSuccess;
+  GemmArgs none{};
+  {
+    // whole vectors along the rows: 16 bytes, else 8
+    const int es = y_bf16 ? 2 : 4;
+    const uintptr_t a = reinterpret_cast<uintptr_t>(y);
+    auto fits = [&](int vb) {
+      const int64_t vw = vb / es;
+      return a % vb == 0 && N % vw == 0 && ld % vw == 0;
+    };
+    const int vb = fits(16) ? 16 : fits(8) ? 8 : 0;
+    if (vb && M > 0) {
+      const int vw = vb / es;
+      int tpr = 1;
+      while (tpr < 64 && (int64_t)tpr * vw < N) tpr *= 2;
+      const int rp = 256 / tpr;
+      const int64_t blocks = (N + (int64_t)tpr * vw - 1) / ((int64_t)tpr * vw);
+      if (blocks <= 65535) {
+        int64_t chunks = (M + rp * 8 - 1) / (rp * 8);  // about 8 rows per lane
+        if (chunks > CS_MAX_CHUNKS) chunks = CS_MAX_CHUNKS;
+        const int64_t per = (M + chunks - 1) / chunks;
+        chunks = (M + per - 1) / per;
+        const dim3 grid((unsigned)blocks, (unsigned)chunks);
+#define SIMNET_COLSUM(BF, VB)                                                                   \
+  hipLaunchKernelGGL((colsum_vec<BF, VB>), grid, dim3(256), 0, stream, y, M, N, ld, per, tpr, \
+                     work)
+        if (y_bf16 && vb == 16) SIMNET_COLSUM(true, 16);
+        else if (y_bf16) SIMNET_COLSUM(true, 8);
+        else if (vb == 16) SIMNET_COLSUM(false, 16);
+        else SIMNET_COLSUM(false, 8);
+#undef SIMNET_COLSUM
+        launch_reduce<false>(work, chunks, N, N, none, out, beta, stream);
+        return hipGetLastError();
+      }
+    }
+  }
   int64_t chunks = (M + 63) / 64;
   if (chunks > CS_MAX_CHUNKS) chunks = CS_MAX_CHUNKS;
   if (chunks < 1) chunks = 1;
@@ -1071,7 +1186,6 @@ hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_
   else
     hipLaunchKernelGGL(colsum_partial<false>, dim3((unsigned)((N + 63) / 64), (unsigned)chunks),
                        dim3(256), 0, stream, y, M, N, ld, per, work);
-  GemmArgs none{};
   launch_reduce<false>(work, chunks, N, N, none, out, beta, stream);
   return hipGetLastError();
 }
