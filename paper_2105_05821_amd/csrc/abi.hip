@@ -687,12 +687,15 @@ static int load_train_weights(sim_ctx* c, const sim_layer* layers, int32_t n_lay
 }
 
 // Backward workspace (floats): [0] per-window losses, [1] dH [B][512],
-// [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] column
-// sums, [6] split-K partial products.
+// [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] the
+// five bias sums' chunk partials, [6] split-K partial products.
 constexpr size_t SPLITK_CAP = (size_t)8 << 20;
+// floats for the chunk partials of the bias sums (head, hidden, conv3..1),
+// each list starting on a 64-float boundary
+constexpr size_t BIAS_PART = colsum_workspace_floats(TRAIN_OUT + 512 + 256 + 128 + 64) + 5 * 64;
 static size_t train_work_off(int64_t B, int part) {
   const size_t sizes[7] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
-                           (size_t)B * 3328, colsum_workspace(TRAIN_OUT) / 4, SPLITK_CAP};
+                           (size_t)B * 3328, BIAS_PART, SPLITK_CAP};
   size_t off = 0;
   for (int i = 0; i < part; ++i) off += (sizes[i] + 63) / 64 * 64;
   return off;
@@ -1490,8 +1493,17 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   auto run = [&](const GemmArgs& g) {
     if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
   };
+  // the bias sums: chunk partials now, all five added in one launch at the end
+  SumSegs bias{};
+  bias.beta = beta;
+  float* csw_next = csw;
   auto colsum = [&](const void* y, int y_bf16, int64_t M, int64_t N, float* out) {
-    if (e == hipSuccess) e = launch_colsum(y, y_bf16, M, N, N, out, beta, csw, c->stream);
+    int64_t chunks = 0;
+    if (e == hipSuccess) e = launch_colsum_partial(y, y_bf16, M, N, N, csw_next, &chunks, c->stream);
+    if (e == hipSuccess && chunks > 0) {
+      bias.seg[bias.count++] = SumSeg{csw_next, chunks, N, out, 0, 0};
+      csw_next += (chunks * N + 63) / 64 * 64;
+    }
   };
   // trunk layer l's weight gradient, [c_out][input column] with input
   // column t*c_in + c (p*256 + c for the hidden layer), stored straight
@@ -1555,6 +1567,7 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   wgrad(opnd(dY1, bf, 1, 64), padded(opnd(x, 0, 100, 1, 52, win), 112), 0, 64, 100, 50, 2,
         B * 52);
   colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
+  if (e == hipSuccess && bias.count > 0) e = launch_sum_partials(bias, c->stream);
   if (dx) {
     if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);
     g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], bf, 1, 64), dx, 100, B * 52, 100,

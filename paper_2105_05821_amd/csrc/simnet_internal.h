@@ -276,11 +276,30 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
                        hipStream_t stream);
 hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
                        float* loss_b, float* loss, float* dz, hipStream_t stream);
-size_t colsum_workspace(int64_t N);
-// Column sums of y [M][ld] (FP32, or BF16 with y_bf16) into out[N] (+= with
-// beta), in a fixed order; work: colsum_workspace(N) bytes.
-hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
-                         int beta, float* work, hipStream_t stream);
+// at most this many chunk partials per column
+constexpr int64_t COLSUM_MAX_CHUNKS = 1024;
+constexpr size_t colsum_workspace_floats(int64_t N) { return (size_t)(COLSUM_MAX_CHUNKS * N); }
+// Column sums of y [M][ld] (FP32, or BF16 with y_bf16) in two phases, each
+// sum in a fixed order: launch_colsum_partial leaves *chunks partial sums
+// [*chunks][N] in work (colsum_workspace_floats(N)); launch_sum_partials
+// adds several such lists (cnt partials of N outputs at src) into their
+// outputs (= or, with beta, +=) in one launch.
+hipError_t launch_colsum_partial(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld,
+                                 float* work, int64_t* chunks, hipStream_t stream);
+struct SumSeg {
+  const float* src;
+  int64_t cnt, N;
+  float* out;
+  int32_t lanes;   // set by launch_sum_partials
+  int64_t blocks;  // set by launch_sum_partials
+};
+struct SumSegs {
+  static constexpr int MAX = 8;
+  SumSeg seg[MAX];
+  int32_t count;
+  int32_t beta;
+};
+hipError_t launch_sum_partials(SumSegs segs, hipStream_t stream);
 hipError_t launch_pad_rows(const float* src, int64_t rows, int64_t cols, int64_t ld, void* dst,
                            int32_t dst_bf16, hipStream_t stream);
 // dst[i] = src[map[i]] (0 where map[i] < 0) for i < n, in FP32 or rounded

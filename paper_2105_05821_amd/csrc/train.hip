@@ -1002,10 +1002,8 @@ hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_
 }
 
 // Column sums of Y [M][ld] over rows in a fixed order: chunks of rows
-// summed by 4 row lanes x 64 columns per workgroup, then the chunk partials
-// through strided_reduce.
-constexpr int CS_MAX_CHUNKS = 1024;
-// Partial column sums: workgroup (x, c) sums rows [c*per, (c+1)*per) of
+// summed per workgroup, then the chunk partials through sum_partials.
+// Partial column sums (rows without whole vectors): workgroup (x, c) sums rows [c*per, (c+1)*per) of
 // columns [x*64*V, (x+1)*64*V), V adjacent columns per lane (V = 2 for BF16
 // input, read as one 32-bit word), 4 row lanes per column, in a fixed order.
 template <bool BF>
@@ -1058,7 +1056,7 @@ __global__ void __launch_bounds__(256) colsum_partial(const void* __restrict__ y
 // by side) and rows [c*per, min(M, (c+1)*per)): RP = 256 / TPR row lanes,
 // lane r summing rows lo + r, lo + r + RP, ... in order, four requests in
 // flight; the RP lane sums are combined by a fixed pairwise tree in LDS into
-// part[c][n], which strided_reduce then sums over c.  (A single launch in
+// part[c][n], which sum_partials then adds over c.  (A single launch in
 // which the last workgroup of a block adds the partials was slower: the
 // device-scope release each workgroup needs before counting writes back its
 // XCD's whole L2.)
@@ -1133,12 +1131,10 @@ __global__ void __launch_bounds__(256) colsum_vec(const void* __restrict__ y, in
     for (int v = 0; v < VW; ++v) part[c * N + n + v] = a[v];
 }
 
-size_t colsum_workspace(int64_t N) { return sizeof(float) * CS_MAX_CHUNKS * (size_t)N; }
-
-hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld, float* out,
-                         int beta, float* work, hipStream_t stream) {
+hipError_t launch_colsum_partial(const void* y, int y_bf16, int64_t M, int64_t N, int64_t ld,
+                                 float* work, int64_t* chunks_out, hipStream_t stream) {
+  *chunks_out = 0;
   if (N <= 0) return hipSuccess;
-  GemmArgs none{};
   {
     // whole vectors along the rows: 16 bytes, else 8
     const int es = y_bf16 ? 2 : 4;
@@ -1156,7 +1152,7 @@ hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_
       const int64_t blocks = (N + (int64_t)tpr * vw - 1) / ((int64_t)tpr * vw);
       if (blocks <= 65535) {
         int64_t chunks = (M + rp * 8 - 1) / (rp * 8);  // about 8 rows per lane
-        if (chunks > CS_MAX_CHUNKS) chunks = CS_MAX_CHUNKS;
+        if (chunks > COLSUM_MAX_CHUNKS) chunks = COLSUM_MAX_CHUNKS;
         const int64_t per = (M + chunks - 1) / chunks;
         chunks = (M + per - 1) / per;
         const dim3 grid((unsigned)blocks, (unsigned)chunks);
@@ -1168,13 +1164,13 @@ hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_
         else if (vb == 16) SIMNET_COLSUM(false, 16);
         else SIMNET_COLSUM(false, 8);
 #undef SIMNET_COLSUM
-        launch_reduce<false>(work, chunks, N, N, none, out, beta, stream);
+        *chunks_out = chunks;
         return hipGetLastError();
       }
     }
   }
   int64_t chunks = (M + 63) / 64;
-  if (chunks > CS_MAX_CHUNKS) chunks = CS_MAX_CHUNKS;
+  if (chunks > COLSUM_MAX_CHUNKS) chunks = COLSUM_MAX_CHUNKS;
   if (chunks < 1) chunks = 1;
   const int64_t per = (M + chunks - 1) / chunks;
   // (BF16: two adjacent columns per lane, which needs even N and ld)
@@ -1186,7 +1182,49 @@ hipError_t launch_colsum(const void* y, int y_bf16, int64_t M, int64_t N, int64_
   else
     hipLaunchKernelGGL(colsum_partial<false>, dim3((unsigned)((N + 63) / 64), (unsigned)chunks),
                        dim3(256), 0, stream, y, M, N, ld, per, work);
-  launch_reduce<false>(work, chunks, N, N, none, out, beta, stream);
+  *chunks_out = chunks;
+  return hipGetLastError();
+}
+
+// Several lists of partials summed in one launch: workgroup b serves the
+// segment whose block range holds b; per segment L lanes per output (16 or
+// 64, or 4 for short lists), lane l summing partials c = l, l + L, ... in
+// order, then the L lane sums combined by a fixed butterfly.
+__global__ void __launch_bounds__(256) sum_partials(SumSegs segs) {
+  int s = 0;
+  int64_t b = blockIdx.x;
+  while (s + 1 < segs.count && b >= segs.seg[s].blocks) {
+    b -= segs.seg[s].blocks;
+    ++s;
+  }
+  const SumSeg& q = segs.seg[s];
+  const int L = q.lanes, sub = threadIdx.x % L;
+  const int64_t n = b * (256 / L) + threadIdx.x / L;
+  float acc[4] = {0.f, 0.f, 0.f, 0.f};
+  if (n < q.N) {
+    int64_t c = sub;
+    for (; c + 3 * L < q.cnt; c += 4 * L) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += q.src[(c + u * L) * q.N + n];
+    }
+    for (; c < q.cnt; c += L) acc[0] += q.src[c * q.N + n];
+  }
+  float v = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  for (int off = L / 2; off >= 1; off /= 2) v += __shfl_xor(v, off);
+  if (sub == 0 && n < q.N) q.out[n] = segs.beta ? q.out[n] + v : v;
+}
+
+hipError_t launch_sum_partials(SumSegs segs, hipStream_t stream) {
+  if (segs.count < 1 || segs.count > SumSegs::MAX) return hipErrorInvalidValue;
+  int64_t blocks = 0;
+  for (int s = 0; s < segs.count; ++s) {
+    SumSeg& q = segs.seg[s];
+    q.lanes = q.cnt >= 256 ? 64 : q.cnt >= 32 ? 16 : 4;
+    q.blocks = (q.N + 256 / q.lanes - 1) / (256 / q.lanes);
+    blocks += q.blocks;
+  }
+  if (blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(sum_partials, dim3((unsigned)blocks), dim3(256), 0, stream, segs);
   return hipGetLastError();
 }
 
