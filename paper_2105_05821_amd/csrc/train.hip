@@ -609,6 +609,29 @@ __global__ void __launch_bounds__(1024) strided_reduce_wide(const float* __restr
   }
 }
 
+// Split-K partials of a GEMM with few parts (cnt < 64) and N a multiple of
+// 4: each thread finishes four adjacent outputs of one row, its partials
+// read as 16-byte vectors and added in part order, then the epilogue.
+__global__ void __launch_bounds__(256) reduce_gemm_vec4(const float* __restrict__ src, int64_t cnt,
+                                                        int64_t MN, GemmArgs g) {
+  const int64_t q = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (q >= MN) return;
+  float4 a = *reinterpret_cast<const float4*>(src + q);
+#pragma unroll 4
+  for (int64_t c = 1; c < cnt; ++c) {
+    const float4 t = *reinterpret_cast<const float4*>(src + c * MN + q);
+    a.x += t.x;
+    a.y += t.y;
+    a.z += t.z;
+    a.w += t.w;
+  }
+  const int64_t m = q / g.N, n = q - m * g.N;
+  gemm_store(g, m, n, a.x);
+  gemm_store(g, m, n + 1, a.y);
+  gemm_store(g, m, n + 2, a.z);
+  gemm_store(g, m, n + 3, a.w);
+}
+
 // Reduce cnt partials of N outputs (see strided_reduce) with the kernel
 // that suits the shape: few outputs and a long list (the bias sums): many
 // lanes per output; many outputs and a long list: 16 waves per 64 outputs;
@@ -774,12 +797,35 @@ __device__ __forceinline__ void fast_step(int64_t i, int64_t n_steps, v4f (&acc)
   __syncthreads();
 }
 
+// The tile of this workgroup.  Workgroups go to the 8 XCDs in turn (id %
+// 8), each XCD with its own L2: when the tiles of a k-split divide evenly,
+// XCD x takes the x-th eighth of them in row-major order along the longer
+// tile dimension, a band that shares the shorter operand whole and holds an
+// eighth of the other, instead of tiles from everywhere.
+__device__ __forceinline__ void xcd_tile(int64_t* tm, int64_t* tn) {
+  const int64_t nx = gridDim.x, ny = gridDim.y, tiles = nx * ny;
+  *tm = blockIdx.y;
+  *tn = blockIdx.x;
+  if (tiles % 8 != 0 || tiles < 64) return;
+  const int64_t id = (int64_t)blockIdx.y * nx + blockIdx.x;
+  const int64_t t = (id % 8) * (tiles / 8) + id / 8;
+  if (ny >= nx) {
+    *tm = t / nx;
+    *tn = t % nx;
+  } else {
+    *tn = t / ny;
+    *tm = t % ny;
+  }
+}
+
 template <int AM, int BM>
 __global__ void __launch_bounds__(256, 2) gemm_bf16_fast_kernel(GemmArgs g) {
   __shared__ __attribute__((aligned(16))) uint16_t As[2][HB][HLD];
   __shared__ __attribute__((aligned(16))) uint16_t Bs[2][HB][HLD];
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int64_t m0 = (int64_t)blockIdx.y * HB, n0 = (int64_t)blockIdx.x * HB;
+  int64_t tm, tn;
+  xcd_tile(&tm, &tn);
+  const int64_t m0 = tm * HB, n0 = tn * HB;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t kb, ke;
   k_range(g, HK, &kb, &ke);
@@ -932,7 +978,11 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   }
   if (ks > 1) {
     const int64_t MN = g.M * g.N;
-    launch_reduce<true>(part, ks, MN, MN, g, nullptr, 0, stream);
+    if (ks < 64 && g.N % 4 == 0)
+      hipLaunchKernelGGL(reduce_gemm_vec4, dim3((unsigned)((MN / 4 + 255) / 256)), dim3(256), 0,
+                         stream, part, ks, MN, g);
+    else
+      launch_reduce<true>(part, ks, MN, MN, g, nullptr, 0, stream);
   }
   return hipGetLastError();
 }
