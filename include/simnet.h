@@ -245,10 +245,18 @@ typedef struct {
  * depend on the choice; the small network's three sum the same products in
  * different orders (all within the FP32 bar of the FP64 oracle).  The small
  * network's FP32 step starts as four wavefronts per slot when the trace has
- * at most 1,024 sub-traces.  Synchronises.  *out receives the choice and
- * the trials. */
+ * at most 1,024 sub-traces.  C3 variants whose kernel needs scratch memory
+ * (register spills, see sim_variant_scratch) are left out when another
+ * variant needs none.  Synchronises.  *out receives the choice and the
+ * trials. */
 SIMNET_API int sim_autotune(sim_ctx* ctx, int32_t n_steps, int32_t lat_mode,
                             const int32_t* lat_table, sim_tuning* out);
+
+/* Private (scratch) memory per lane, in bytes, that the C3 network's step
+ * kernel of `variant` (in [0, 4), predictor running) uses in this context's
+ * precision form: nonzero means the compiler spilled registers to memory.
+ * SIM_EUNSUPPORTED for other networks. */
+SIMNET_API int sim_variant_scratch(sim_ctx* ctx, int32_t variant, int64_t* bytes);
 
 /* Apply a launch shape (a cached sim_autotune result): variant in [0, 4),
  * n_wg in [1, slots allocated / 16].  Resets the simulation. */

@@ -29,7 +29,7 @@ STATUS_NAMES = {0: "SIM_OK", -1: "SIM_EINVAL", -2: "SIM_ENOMEM", -3: "SIM_EDEVIC
 EXPORTED = ("sim_validate_config", "sim_partition", "sim_init", "sim_load_weights", "sim_step",
             "sim_run",
             "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
-            "sim_autotune", "sim_set_tuning",
+            "sim_autotune", "sim_set_tuning", "sim_variant_scratch",
             "predictor_fwd", "predictor_save_bytes", "sim_loss", "sim_loss_noalloc",
             "predictor_bwd", "sim_adam",
             "sim_destroy", "sim_last_error")
@@ -95,6 +95,7 @@ def lib():
         L.predictor_save_bytes.argtypes = [P, C.c_int64]
         L.sim_autotune.argtypes = [P, C.c_int32, C.c_int32, P, C.POINTER(sim_tuning)]
         L.sim_set_tuning.argtypes = [P, C.c_int32, C.c_int32]
+        L.sim_variant_scratch.argtypes = [P, C.c_int32, C.POINTER(C.c_int64)]
         L.sim_loss.argtypes = [P, P, P, C.c_int64, P, P]
         L.sim_loss_noalloc.argtypes = [P, P, P, C.c_int64, P, P]
         L.predictor_bwd.argtypes = [P, P, P, P, C.c_int64, P, P, C.c_int32]
@@ -275,6 +276,13 @@ class Simulator:
 
     def set_tuning(self, variant: int, n_wg: int) -> None:
         self._check("sim_set_tuning", lib().sim_set_tuning(self.ctx, variant, n_wg))
+
+    def variant_scratch(self, variant: int) -> int:
+        """Scratch bytes per lane of the C3 step kernel of `variant` in this
+        form (nonzero: register spills)."""
+        b = C.c_int64(0)
+        self._check("sim_variant_scratch", lib().sim_variant_scratch(self.ctx, variant, C.byref(b)))
+        return int(b.value)
 
     def calibrate(self, n_steps: int = 64, lat_mode: int = SIM_LAT_PREDICT, lat_table=None):
         self._check("sim_calibrate",

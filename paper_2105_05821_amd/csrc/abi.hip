@@ -1391,6 +1391,19 @@ int sim_autotune(sim_ctx* c, int32_t n_steps, int32_t lat_mode, const int32_t* l
     const int32_t n = std::max<int32_t>(1, c->n_wg_max * q / 4);
     if (std::find(shapes.begin(), shapes.end(), n) == shapes.end()) shapes.push_back(n);
   }
+  // kernels that need scratch memory (register spills) are tried only when
+  // every candidate does
+  bool skip[N_VARIANTS] = {};
+  if (nv == N_VARIANTS) {
+    size_t sc[N_VARIANTS];
+    bool any_free = false;
+    for (int v = 0; v < nv; ++v) {
+      const hipError_t e = c3_step_scratch(c->cfg.prec, v, &sc[v]);
+      if (e != hipSuccess) return hip_fail(c, e, "kernel attributes");
+      any_free = any_free || sc[v] == 0;
+    }
+    for (int v = 0; v < nv; ++v) skip[v] = any_free && sc[v] > 0;
+  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   hipError_t e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
@@ -1400,6 +1413,7 @@ int sim_autotune(sim_ctx* c, int32_t n_steps, int32_t lat_mode, const int32_t* l
   int rc = SIM_OK;
   for (int v = 0; v < nv && rc == SIM_OK; ++v)
     for (int32_t nw : shapes) {
+      if (v < N_VARIANTS && skip[v]) break;
       if ((rc = sim_set_tuning(c, v, nw)) != SIM_OK) break;
       // one untimed launch (first use of a kernel), then the timed one
       if ((rc = step_launch(c, n_steps, lat_mode, lat_table)) != SIM_OK) break;
@@ -1435,6 +1449,17 @@ int sim_autotune(sim_ctx* c, int32_t n_steps, int32_t lat_mode, const int32_t* l
   (void)hipEventDestroy(e1);
   if (rc != SIM_OK) return rc;
   return sim_set_tuning(c, out->variant, out->n_wg);
+}
+
+int sim_variant_scratch(sim_ctx* c, int32_t variant, int64_t* bytes) {
+  if (!c || !bytes) return SIM_EINVAL;
+  if (c->net != 1) return fail(c, SIM_EUNSUPPORTED, "scratch query: C3 step variants only");
+  if (variant < 0 || variant >= N_VARIANTS) return fail(c, SIM_EINVAL, "variant out of range");
+  size_t b = 0;
+  const hipError_t e = c3_step_scratch(c->cfg.prec, variant, &b);
+  if (e != hipSuccess) return hip_fail(c, e, "kernel attributes");
+  *bytes = (int64_t)b;
+  return SIM_OK;
 }
 
 int64_t predictor_save_bytes(const sim_ctx* c, int64_t B) {

@@ -2476,6 +2476,24 @@ static hipError_t launch_step_n(int prec, const DevWeights& w, uint32_t relu, co
   return launch_step_t<Net, PFP8>(w, relu, s, p, stream);
 }
 
+template <class Net>
+static const void* c3_step_fn(int prec) {
+  if (prec == 0) return reinterpret_cast<const void*>(&step_kernel<Net, PF32, true>);
+  if (prec == 1) return reinterpret_cast<const void*>(&step_kernel<Net, PBF16, true>);
+  return reinterpret_cast<const void*>(&step_kernel<Net, PFP8, true>);
+}
+
+hipError_t c3_step_scratch(int prec, int variant, size_t* bytes) {
+  const void* f = variant == 1   ? c3_step_fn<NetC3V1>(prec)
+                  : variant == 2 ? c3_step_fn<NetC3V2>(prec)
+                  : variant == 3 ? c3_step_fn<NetC3V3>(prec)
+                                 : c3_step_fn<NetC3>(prec);
+  hipFuncAttributes a{};
+  const hipError_t e = hipFuncGetAttributes(&a, f);
+  *bytes = e == hipSuccess ? a.localSizeBytes : 0;
+  return e;
+}
+
 hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
                        const DevState& s, const StepParams& p, hipStream_t stream) {
   if (net == 1 && p.lat_mode != 1 && variant == 1)

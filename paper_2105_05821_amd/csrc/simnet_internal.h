@@ -217,6 +217,9 @@ struct StepParams {
 hipError_t launch_step(int net, int prec, int variant, const DevWeights& w, uint32_t relu,
                        const DevState& s,
                        const StepParams& p, hipStream_t stream);
+// Private (scratch) bytes per lane of the C3 step kernel of `variant` with
+// the predictor running, the kernels sim_autotune chooses among.
+hipError_t c3_step_scratch(int prec, int variant, size_t* bytes);
 hipError_t launch_forward(int net, int prec, const DevWeights& w, uint32_t relu, const float* x,
                           int64_t B, float* logits, hipStream_t stream);
 // FP32 step launch that also records per-channel max |input| of every layer

@@ -75,7 +75,7 @@ __device__ __forceinline__ void gemm_store(const GemmArgs& g, int64_t m, int64_t
 }
 
 // The same for the four columns n0 + 16*j (j < 4) of one row m, with the
-// row's addresses computed once.
+// row's addresses computed once; the caller has added the bias.
 __device__ __forceinline__ void gemm_store_row4(const GemmArgs& g, int64_t m, int64_t n0,
                                                 const float (&v)[4]) {
   const int64_t crow = grouped_row(m, g.cgrp, g.cgs, g.ldc);
@@ -85,7 +85,6 @@ __device__ __forceinline__ void gemm_store_row4(const GemmArgs& g, int64_t m, in
     const int64_t n = n0 + 16 * j;
     if (n >= g.N) continue;
     float x = v[j];
-    if (g.bias) x += g.bias[n];
     if (g.mask.p && !(ld_elem(g.mask.p, g.mask.bf16, mrow + n * g.mask.cs) > 0.f)) x = 0.f;
     const int64_t at = crow + c_col(g, n);
     if (g.c_bf16) {
@@ -435,13 +434,21 @@ __device__ __forceinline__ void gemm_bf16_epilogue(const GemmArgs& g, v4f (&acc)
     return;
   }
   const int64_t nb = n0 + wn * 64 + (lane & 15);
+  // the bias of this lane's four columns, read once (per row the compiler
+  // would read it again after every store to C)
+  float bj[4] = {0.f, 0.f, 0.f, 0.f};
+  if (g.ksplit <= 1 && g.bias)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (nb + 16 * j < g.N) bj[j] = g.bias[nb + 16 * j];
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int64_t m = m0 + wm * 64 + i * 16 + 4 * (lane >> 4) + r;
       if (m >= g.M) continue;
-      const float v[4] = {acc[i][0][r], acc[i][1][r], acc[i][2][r], acc[i][3][r]};
+      const float v[4] = {acc[i][0][r] + bj[0], acc[i][1][r] + bj[1], acc[i][2][r] + bj[2],
+                          acc[i][3][r] + bj[3]};
       if (g.ksplit > 1) {
         float* prow = g.part + ((int64_t)blockIdx.z * g.M + m) * g.N;
 #pragma unroll

@@ -176,8 +176,10 @@ def test_graph_replay_equals_direct_run(torch, sn):
 
 
 def test_autotune_choice_does_not_change_results(torch, sn, tmp_path):
-    """sim_autotune tries every kernel variant and slot count; the chosen
-    shape, any other shape and the cached choice all give the same cycles."""
+    """sim_autotune tries every kernel variant that needs no scratch memory
+    (every variant when all need some) and slot count; the chosen shape,
+    every variant including those left out, and the cached choice all give
+    the same cycles."""
     layers = synth.net_c3()
     ws, bs = synth.init_weights(2, layers)
     start, length, warm, N = independent_streams(600, 20, 900)
@@ -190,9 +192,15 @@ def test_autotune_choice_does_not_change_results(torch, sn, tmp_path):
     t = sim.autotune(50, cache=cache)
     assert not t["cached"] and len(t["trials"]) >= 3
     assert (t["variant"], t["n_wg"]) in [(v, n) for v, n, _ in t["trials"]]
+    scratch = [sim.variant_scratch(v) for v in range(4)]
+    free = {v for v in range(4) if scratch[v] == 0}
+    assert {v for v, _, _ in t["trials"]} == (free or set(range(4))), scratch
     assert_same(sim.run(), ref)
     for v, n, _ in t["trials"]:
         sim.set_tuning(v, n)
+        assert_same(sim.run(), ref)
+    for v in range(4):
+        sim.set_tuning(v, t["n_wg"])
         assert_same(sim.run(), ref)
     t2 = sim.autotune(50, cache=cache)
     assert t2["cached"] and (t2["variant"], t2["n_wg"]) == (t["variant"], t["n_wg"])
