@@ -994,45 +994,57 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   return hipGetLastError();
 }
 
-// One window per workgroup: per latency type t the head outputs are 400
-// class logits and one regression output; loss = CE(class min(lat, 399)) +
-// |reg - log1p(lat)|; dz = (softmax - onehot) / B, dreg = sign / B.
+// Per latency type t the head outputs are n_bins class logits and one
+// regression output; loss = CE(class min(lat, n_bins - 1)) + |reg -
+// log1p(lat)| summed over t; dz = (softmax - onehot) / B, dreg = sign / B.
+// One wavefront per (window, t), its logits held in registers (LOSS_PER per
+// lane, lane l taking bins l, l + 64, ...), max and sum of exponentials
+// reduced across the wave by a fixed butterfly; four waves (two windows) per
+// workgroup, each window's two terms added in t order.
+constexpr int LOSS_PER = 8;  // bins per lane: n_bins <= 64 * LOSS_PER
 __global__ void __launch_bounds__(256)
     loss_kernel(const float* __restrict__ z, const int32_t* __restrict__ lat, int64_t B,
                 int32_t n_bins, float* __restrict__ loss_b, float* __restrict__ dz) {
-  __shared__ float red[4];
-  const int64_t b = blockIdx.x;
-  const int tid = threadIdx.x;
+  __shared__ float part[4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t b = (int64_t)blockIdx.x * 2 + (w >> 1);
+  const int t = w & 1;
   const int per = n_bins + 1;
-  float total = 0.f;
-  for (int t = 0; t < 2; ++t) {
+  float term = 0.f;
+  if (b < B) {
     const float* zt = z + (b * 2 + t) * per;
     const int l = lat[b * 2 + t];
     const int bin = l < n_bins - 1 ? l : n_bins - 1;
+    float v[LOSS_PER];
     float m = -INFINITY;
-    for (int i = tid; i < n_bins; i += 256) m = fmaxf(m, zt[i]);
+#pragma unroll
+    for (int q = 0; q < LOSS_PER; ++q) {
+      const int i = lane + 64 * q;
+      v[q] = i < n_bins ? zt[i] : -INFINITY;
+      m = fmaxf(m, v[q]);
+    }
     for (int o = 32; o >= 1; o >>= 1) m = fmaxf(m, __shfl_xor(m, o));
-    if ((tid & 63) == 0) red[tid >> 6] = m;
-    __syncthreads();
-    m = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-    __syncthreads();
     float se = 0.f;
-    for (int i = tid; i < n_bins; i += 256) se += expf(zt[i] - m);
+#pragma unroll
+    for (int q = 0; q < LOSS_PER; ++q)
+      if (lane + 64 * q < n_bins) se += expf(v[q] - m);
     for (int o = 32; o >= 1; o >>= 1) se += __shfl_xor(se, o);
-    if ((tid & 63) == 0) red[tid >> 6] = se;
-    __syncthreads();
-    se = red[0] + red[1] + red[2] + red[3];
-    __syncthreads();
     const float lse = m + logf(se);
-    const float r = zt[n_bins] - log1pf((float)l);
+    const float zr = zt[n_bins], zb = zt[bin];
+    const float r = zr - log1pf((float)l);
     const float inv = 1.f / (float)B;
     float* dzt = dz + (b * 2 + t) * per;
-    for (int i = tid; i < n_bins; i += 256)
-      dzt[i] = inv * (expf(zt[i] - lse) - (i == bin ? 1.f : 0.f));
-    if (tid == 0) dzt[n_bins] = inv * (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f));
-    total += lse - zt[bin] + fabsf(r);
+#pragma unroll
+    for (int q = 0; q < LOSS_PER; ++q) {
+      const int i = lane + 64 * q;
+      if (i < n_bins) dzt[i] = inv * (expf(v[q] - lse) - (i == bin ? 1.f : 0.f));
+    }
+    if (lane == 0) dzt[n_bins] = inv * (r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f));
+    term = lse - zb + fabsf(r);
   }
-  if (tid == 0) loss_b[b] = total;
+  if (lane == 0) part[w] = term;
+  __syncthreads();
+  if ((threadIdx.x & 127) == 0 && b < B) loss_b[b] = part[w] + part[w + 1];
 }
 
 // loss = mean of per-window losses, summed in a fixed order (one workgroup).
@@ -1052,8 +1064,9 @@ __global__ void __launch_bounds__(256) mean_kernel(const float* __restrict__ v, 
 
 hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
                        float* loss_b, float* loss, float* dz, hipStream_t stream) {
-  hipLaunchKernelGGL(loss_kernel, dim3((unsigned)B), dim3(256), 0, stream, z, lat, B, n_bins,
-                     loss_b, dz);
+  if (n_bins < 1 || n_bins > 64 * LOSS_PER) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(loss_kernel, dim3((unsigned)((B + 1) / 2)), dim3(256), 0, stream, z, lat, B,
+                     n_bins, loss_b, dz);
   hipLaunchKernelGGL(mean_kernel, dim3(1), dim3(256), 0, stream, loss_b, B, loss);
   return hipGetLastError();
 }
