@@ -360,6 +360,18 @@ SIMNET_API int predictor_bwd(sim_ctx* ctx, const void* x, const void* save, cons
 SIMNET_API int sim_adam(sim_ctx* ctx, float* params, const float* grads, float* m, float* v,
                         int64_t n, float lr, float beta1, float beta2, float eps, int32_t step);
 
+/* sim_adam on the n = all parameters of a training context's predictor,
+ * after which the context's weights are the updated parameters, exactly as
+ * after sim_load_weights(..., params, on_device = 1) with the layers it was
+ * loaded with, in one launch: each updated weight is also written to the
+ * context's master copy and, in the form's precision, to its places in the
+ * kernels' re-laid-out copies (no copy, no gather).  Needs weights loaded;
+ * n must equal the network's parameter count (SIM_EINVAL otherwise).
+ * Asynchronous on the context's stream. */
+SIMNET_API int sim_adam_load(sim_ctx* ctx, float* params, const float* grads, float* m,
+                             float* v, int64_t n, float lr, float beta1, float beta2, float eps,
+                             int32_t step);
+
 SIMNET_API void sim_destroy(sim_ctx* ctx);
 SIMNET_API const char* sim_last_error(const sim_ctx* ctx);
 

@@ -31,7 +31,7 @@ EXPORTED = ("sim_validate_config", "sim_partition", "sim_init", "sim_load_weight
             "sim_reset", "sim_record_logits", "sim_calibrate", "sim_act_scales", "sim_set_graph",
             "sim_autotune", "sim_set_tuning", "sim_variant_scratch",
             "predictor_fwd", "predictor_save_bytes", "sim_loss", "sim_loss_noalloc",
-            "predictor_bwd", "sim_adam",
+            "predictor_bwd", "sim_adam", "sim_adam_load",
             "sim_destroy", "sim_last_error")
 
 
@@ -101,6 +101,8 @@ def lib():
         L.predictor_bwd.argtypes = [P, P, P, P, C.c_int64, P, P, C.c_int32]
         L.sim_adam.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float, C.c_float,
                                C.c_float, C.c_int32]
+        L.sim_adam_load.argtypes = [P, P, P, P, P, C.c_int64, C.c_float, C.c_float,
+                                    C.c_float, C.c_float, C.c_int32]
         L.sim_destroy.argtypes = [P]
         L.sim_destroy.restype = None
         L.sim_last_error.argtypes = [P]
@@ -417,6 +419,15 @@ class Predictor:
                                                m.data_ptr(), v.data_ptr(), params.numel(), lr,
                                                betas[0], betas[1], eps, step))
 
+    def adam_load(self, params, grads, m, v, step: int, lr: float = 1e-3, betas=(0.9, 0.999),
+                  eps: float = 1e-8):
+        """adam(), then the predictor's weights are the updated parameters
+        (as load_weights would make them), in one launch."""
+        self._check("sim_adam_load",
+                    lib().sim_adam_load(self.ctx, params.data_ptr(), grads.data_ptr(),
+                                        m.data_ptr(), v.data_ptr(), params.numel(), lr, betas[0],
+                                        betas[1], eps, step))
+
 
 def _check_windows(x, n_slot, n_feat):
     import torch
@@ -489,9 +500,8 @@ class Trainer:
         loss, dz = self.pred.loss(logits, labels)
         self.pred.backward(x, save, dz, self.grads)
         self.t += 1
-        self.pred.adam(self.params, self.grads, self.m, self.v, self.t, self.lr, self.betas,
-                       self.eps)
-        self.pred.load_weights(self.pred.layers, self.params)
+        self.pred.adam_load(self.params, self.grads, self.m, self.v, self.t, self.lr, self.betas,
+                            self.eps)
         return loss
 
     def close(self):

@@ -32,6 +32,7 @@ struct TrainState {
   size_t perm_off[5] = {0};
   float* work = nullptr;
   int64_t work_B = 0;
+  int2* inv = nullptr;  // per parameter: byte offsets in packed and perm (-1: none)
   size_t woff[5] = {0}, boff[5] = {0};
   size_t n_params = 0;
 };
@@ -670,6 +671,32 @@ static int load_train_weights(sim_ctx* c, const sim_layer* layers, int32_t n_lay
     }
     if (e == hipSuccess) e = hipMalloc(&T.perm, qf * 4);
     if (e != hipSuccess) return hip_fail(c, e, "training buffers");
+    // per master parameter its byte offsets in the packed and permuted
+    // copies (-1: none), for sim_adam_load's re-layout in the update pass
+    // (left off if a parameter appeared twice in one copy)
+    const size_t es = c->cfg.prec == SIM_BF16 ? 2 : 4;
+    std::vector<int2> inv(T.n_params, int2{-1, -1});
+    bool once = true;
+    for (int l = 0; l < 4; ++l)
+      for (size_t q = 0; q < T.n_pack[l]; ++q) {
+        const int32_t k = maps[T.map_pack[l] + q];
+        if (k < 0) continue;
+        once = once && inv[k].x < 0;
+        inv[k].x = (int32_t)(T.pack_off[l] + q * es);
+      }
+    for (int l = 0; l < 5; ++l)
+      for (size_t q = 0; q < T.n_perm[l]; ++q) {
+        const int32_t k = maps[T.map_perm[l] + q];
+        if (k < 0) continue;
+        once = once && inv[k].y < 0;
+        inv[k].y = (int32_t)(T.perm_off[l] * 4 + q * es);
+      }
+    if (once) {
+      e = hipMalloc(&T.inv, inv.size() * sizeof(int2));
+      if (e == hipSuccess)
+        e = hipMemcpy(T.inv, inv.data(), inv.size() * sizeof(int2), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return hip_fail(c, e, "re-layout offsets");
+    }
   }
   e = hipMemcpyAsync(T.master, params, T.n_params * 4,
                      on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream);
@@ -1605,6 +1632,24 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   return SIM_OK;
 }
 
+int sim_adam_load(sim_ctx* c, float* params, const float* grads, float* m, float* v, int64_t n,
+                  float lr, float beta1, float beta2, float eps, int32_t step) {
+  if (!c) return SIM_EINVAL;
+  if (!params || !grads || !m || !v || step < 1) return fail(c, SIM_EINVAL, "bad arguments");
+  if (c->net != 2) return fail(c, SIM_EUNSUPPORTED, "sim_adam_load needs the training head");
+  if (!c->weights) return fail(c, SIM_ESTATE, "weights not loaded");
+  TrainState& T = c->tr;
+  if (n != (int64_t)T.n_params)
+    return fail(c, SIM_EINVAL, "n = %lld but the network has %lld parameters", (long long)n,
+                (long long)T.n_params);
+  if (!T.inv) return fail(c, SIM_EUNSUPPORTED, "no one-to-one re-layout for this network");
+  hipError_t e = launch_adam_relayout(params, grads, m, v, n, lr, beta1, beta2, eps, step,
+                                      T.master, T.inv, T.packed, T.perm,
+                                      c->cfg.prec == SIM_BF16, c->stream);
+  if (e != hipSuccess) return hip_fail(c, e, "adam");
+  return SIM_OK;
+}
+
 int sim_adam(sim_ctx* c, float* params, const float* grads, float* m, float* v, int64_t n,
              float lr, float beta1, float beta2, float eps, int32_t step) {
   if (!c) return SIM_EINVAL;
@@ -1624,6 +1669,7 @@ void sim_destroy(sim_ctx* c) {
   if (c->tr.maps) (void)hipFree(c->tr.maps);
   if (c->tr.packed) (void)hipFree(c->tr.packed);
   if (c->tr.perm) (void)hipFree(c->tr.perm);
+  if (c->tr.inv) (void)hipFree(c->tr.inv);
   if (c->tr.work) (void)hipFree(c->tr.work);
   if (c->dev_block) (void)hipFree(c->dev_block);
   if (c->rb_trunk) (void)hipFree(c->rb_trunk);

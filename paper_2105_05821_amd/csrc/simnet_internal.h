@@ -322,6 +322,12 @@ hipError_t launch_map_gather_multi(const float* src, const GatherSegs& segs, hip
 hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int32_t t, hipStream_t stream);
+// Adam, then master[i] = w[i] and, for inv[i] = (packed byte offset, perm
+// byte offset) >= 0, the copies in the form's precision.
+hipError_t launch_adam_relayout(float* w, const float* g, float* m, float* v, int64_t n, float lr,
+                                float b1, float b2, float eps, int32_t t, float* master,
+                                const int2* inv, void* packed, void* perm, int32_t bf16,
+                                hipStream_t stream);
 
 // RB7, one step in three parts (n_steps = 1 each): stage 1 = gather and
 // convolutions into p.trunk_out; then launch_resblocks and launch_rb_head

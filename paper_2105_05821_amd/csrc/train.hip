@@ -18,7 +18,8 @@
 //   colsum kernels   bias gradients, summed in a fixed order.
 //   map_gather_multi weight re-layouts by index maps.
 //   pad_rows         a row-major matrix copied with its rows padded.
-//   adam_kernel      Adam on FP32 master weights.
+//   adam kernels     Adam on FP32 master weights (and, fused, the re-layout
+//                    of the updated weights).
 #include <type_traits>
 
 #include "simnet_internal.h"
@@ -1378,6 +1379,48 @@ __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
   m[i] = mi;
   v[i] = vi;
   w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Adam as adam_kernel, the updated weight also written to a context's
+// master copy and, where inv gives byte offsets (-1: none), to its packed and
+// permuted copies in the form's precision (BF16 rounded to nearest even, as
+// map_gather_multi writes them): the update and the re-layout in one pass.
+__global__ void adam_relayout_kernel(float* __restrict__ w, const float* __restrict__ g,
+                                     float* __restrict__ m, float* __restrict__ v, int64_t n,
+                                     float lr, float b1, float b2, float eps, float c1, float c2,
+                                     float* __restrict__ master, const int2* __restrict__ inv,
+                                     char* __restrict__ packed, char* __restrict__ perm,
+                                     int32_t bf16) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+  master[i] = wi;
+  const int2 d = inv[i];
+  if (bf16) {
+    const uint16_t h = to_bf16(wi);
+    if (d.x >= 0) *reinterpret_cast<uint16_t*>(packed + d.x) = h;
+    if (d.y >= 0) *reinterpret_cast<uint16_t*>(perm + d.y) = h;
+  } else {
+    if (d.x >= 0) *reinterpret_cast<float*>(packed + d.x) = wi;
+    if (d.y >= 0) *reinterpret_cast<float*>(perm + d.y) = wi;
+  }
+}
+
+hipError_t launch_adam_relayout(float* w, const float* g, float* m, float* v, int64_t n, float lr,
+                                float b1, float b2, float eps, int32_t t, float* master,
+                                const int2* inv, void* packed, void* perm, int32_t bf16,
+                                hipStream_t stream) {
+  const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+  hipLaunchKernelGGL(adam_relayout_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                     stream, w, g, m, v, n, lr, b1, b2, eps, c1, c2, master, inv,
+                     static_cast<char*>(packed), static_cast<char*>(perm), bf16);
+  return hipGetLastError();
 }
 
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,

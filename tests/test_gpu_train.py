@@ -298,6 +298,49 @@ def test_train_accumulate_and_autograd(torch, sn):
     pred.close()
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_adam_load_equals_adam_then_load_weights(torch, sn, prec):
+    """sim_adam_load (the update and the re-layout in one pass) leaves the
+    same parameters and moments as sim_adam and the same kernel weights as
+    a following sim_load_weights: bit-identical parameters, forward outputs
+    and gradients over three steps; a wrong parameter count is refused."""
+    B = 40
+    layers, ws, bs, x, lat = inputs(B, 43)
+    flat = sn.flat_params(ws, bs)
+    form = sn.SIM_FP32 if prec == "f32" else sn.SIM_BF16
+    p1, p2 = sn.Predictor(layers, form), sn.Predictor(layers, form)
+    w1, w2 = dev(torch, flat), dev(torch, flat)
+    p1.load_weights(layers, w1)
+    p2.load_weights(layers, w2)
+    m1, v1 = torch.zeros_like(w1), torch.zeros_like(w1)
+    m2, v2 = torch.zeros_like(w1), torch.zeros_like(w1)
+    xd = dev(torch, x)
+    gen = torch.Generator(device="cpu").manual_seed(5)
+    for t in range(1, 4):
+        g = (torch.randn(flat.size, generator=gen) * 0.1).cuda()
+        p1.adam(w1, g, m1, v1, t, lr=1e-2)
+        p1.load_weights(layers, w1)
+        p2.adam_load(w2, g, m2, v2, t, lr=1e-2)
+        torch.cuda.synchronize()
+        for a, b in ((w1, w2), (m1, m2), (v1, v2)):
+            np.testing.assert_array_equal(a.cpu().numpy(), b.cpu().numpy())
+        z1, s1 = p1.forward(xd)
+        z2, s2 = p2.forward(xd)
+        np.testing.assert_array_equal(z1.cpu().numpy(), z2.cpu().numpy())
+        up = torch.randn(z1.shape, generator=gen).cuda()
+        g1 = torch.empty_like(w1)
+        g2 = torch.empty_like(w1)
+        d1 = p1.backward(xd, s1, up, g1, want_dx=True)
+        d2 = p2.backward(xd, s2, up, g2, want_dx=True)
+        np.testing.assert_array_equal(g1.cpu().numpy(), g2.cpu().numpy())
+        np.testing.assert_array_equal(d1.cpu().numpy(), d2.cpu().numpy())
+    with pytest.raises(sn.SimError) as e:
+        p2.adam_load(w2[:-1], g[:-1], m2[:-1], v2[:-1], 4)
+    assert e.value.code == sn.SIM_EINVAL
+    p1.close()
+    p2.close()
+
+
 def analytic_batch(B, seed):
     """Windows ending at trace row i with the analytic model's latencies of
     row i as labels."""
