@@ -917,11 +917,12 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int TB = bf16_mma ? HB : GB;
   const int64_t tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);
-  // split K when the output is too small to fill the chip: aim at ~1024
-  // workgroups, at least 8 k-steps each, within the partial buffer
+  // split K when the output is too small to fill the chip: aim at one round
+  // of workgroups (512: two per CU), at least 8 k-steps each, within the
+  // partial buffer
   int64_t ks = 1;
   if (part && tiles < 512) {
-    ks = (1024 + tiles - 1) / tiles;
+    ks = 512 / tiles;
     const int64_t steps = g.K / ((bf16_mma ? HK : GK) * 8);
     if (ks > steps) ks = steps;
     if (ks > part_cap / (g.M * g.N)) ks = part_cap / (g.M * g.N);
