@@ -921,7 +921,7 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   // of workgroups (512: two per CU), at least 8 k-steps each, within the
   // partial buffer
   int64_t ks = 1;
-  if (part && tiles < 512) {
+  if (part && tiles < 128) {
     ks = 512 / tiles;
     const int64_t steps = g.K / ((bf16_mma ? HK : GK) * 8);
     if (ks > steps) ks = steps;
