@@ -640,6 +640,38 @@ __global__ void __launch_bounds__(256) reduce_gemm_vec4(const float* __restrict_
   gemm_store(g, m, n + 3, a.w);
 }
 
+// The same for a permuted C (ccg > 0, N = ccg * ccm, no bias, mask or BF16
+// output, 16-byte aligned rows): each thread finishes four adjacent outputs
+// of one row in C's own order, d -> GEMM column (d % ccm) * ccg + d / ccm,
+// so the stores are 16-byte vectors and the permutation falls on the reads
+// (a wave's 256 outputs read about two cache lines per part and tap).
+__global__ void __launch_bounds__(256) reduce_gemm_perm4(const float* __restrict__ src,
+                                                         int64_t cnt, int64_t MN, GemmArgs g) {
+  const int64_t q = ((int64_t)blockIdx.x * 256 + threadIdx.x) * 4;
+  if (q >= MN) return;
+  const int64_t m = q / g.N, d0 = q - m * g.N;
+  int64_t col[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t d = d0 + e, t = d / g.ccm;
+    col[e] = m * g.N + (d - t * g.ccm) * g.ccg + t;
+  }
+  float a[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) a[e] = src[col[e]];
+#pragma unroll 4
+  for (int64_t c = 1; c < cnt; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] += src[c * MN + col[e]];
+  float4* cp = reinterpret_cast<float4*>(g.C + m * g.ldc + d0);
+  float4 o = make_float4(a[0], a[1], a[2], a[3]);
+  if (g.beta) {
+    const float4 p = *cp;
+    o = make_float4(p.x + o.x, p.y + o.y, p.z + o.z, p.w + o.w);
+  }
+  *cp = o;
+}
+
 // Reduce cnt partials of N outputs (see strided_reduce) with the kernel
 // that suits the shape: few outputs and a long list (the bias sums): many
 // lanes per output; many outputs and a long list: 16 waves per 64 outputs;
@@ -987,7 +1019,13 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
   }
   if (ks > 1) {
     const int64_t MN = g.M * g.N;
-    if (ks < 64 && g.N % 4 == 0)
+    const bool perm4 = g.ccg > 0 && g.N == g.ccg * g.ccm && !g.bias && !g.mask.p && !g.c_bf16 &&
+                       g.cgrp >= NO_GROUP && g.ldc % 4 == 0 &&
+                       reinterpret_cast<uintptr_t>(g.C) % 16 == 0;
+    if (ks < 64 && g.N % 4 == 0 && perm4)
+      hipLaunchKernelGGL(reduce_gemm_perm4, dim3((unsigned)((MN / 4 + 255) / 256)), dim3(256), 0,
+                         stream, part, ks, MN, g);
+    else if (ks < 64 && g.N % 4 == 0)
       hipLaunchKernelGGL(reduce_gemm_vec4, dim3((unsigned)((MN / 4 + 255) / 256)), dim3(256), 0,
                          stream, part, ks, MN, g);
     else
