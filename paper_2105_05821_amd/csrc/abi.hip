@@ -1545,7 +1545,8 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   auto run = [&](const GemmArgs& g) {
     if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
   };
-  // the bias sums: chunk partials now, all five added in one launch at the end
+  // the bias sums: lists of partials now (column-sum chunks or a weight
+  // gradient's per-split row sums), all five added in one launch at the end
   SumSegs bias{};
   bias.beta = beta;
   float* csw_next = csw;
@@ -1559,13 +1560,26 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   };
   // trunk layer l's weight gradient, [c_out][input column] with input
   // column t*c_in + c (p*256 + c for the hidden layer), stored straight
-  // into the parameters' layout ([c_out][c_in][2], [512][256][13])
-  auto wgrad = [&](const GemmOperand& dy, const GemmOperand& act, int l, int64_t c_out,
-                   int64_t cols, int64_t c_in, int64_t taps, int64_t rows) {
-    GemmArgs g = gemm(dy, act, dparams + T.woff[l], cols, c_out, cols, rows, beta);
+  // into the parameters' layout ([c_out][c_in][2], [512][256][13]); its
+  // bias gradient (the column sums of dy, y [rows][c_out]) from the same
+  // product's row sums of dy^T where the pipelined kernel runs it (one list
+  // of partials per k-split for the final sum), else as a column sum
+  auto wgrad = [&](const GemmOperand& dyt, const GemmOperand& act, int l, int64_t c_out,
+                   int64_t cols, int64_t c_in, int64_t taps, int64_t rows, const void* y) {
+    GemmArgs g = gemm(dyt, act, dparams + T.woff[l], cols, c_out, cols, rows, beta);
     g.ccg = c_in;
     g.ccm = taps;
-    run(g);
+    g.rowsum = csw_next;
+    int64_t parts = 0;
+    if (e == hipSuccess)
+      e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream, &parts);
+    if (e != hipSuccess) return;
+    if (parts > 0) {
+      bias.seg[bias.count++] = SumSeg{csw_next, parts, c_out, dparams + T.boff[l], 0, 0};
+      csw_next += (parts * c_out + 63) / 64 * 64;
+    } else {
+      colsum(y, bf, rows, c_out, dparams + T.boff[l]);
+    }
   };
   // The output gradients of the hidden layer and the convolutions (dH, dY3,
   // dY2, dY1, masked by their layer's ReLU) are written in the form's
@@ -1593,32 +1607,28 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   g.mask = opnd(sb.a3, bf, 3328, 1);
   g.c_bf16 = bf;
   run(g);
-  wgrad(opnd(dH, bf, 1, 512), opnd(sb.a3, bf, 3328, 1), 3, 512, 3328, 256, 13, B);
-  colsum(dH, bf, B, 512, dparams + T.boff[3]);
+  wgrad(opnd(dH, bf, 1, 512), opnd(sb.a3, bf, 3328, 1), 3, 512, 3328, 256, 13, B, dH);
   // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
   g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], bf, 1, 256), dY2, 256, B * 13, 256,
            256, 0);
   g.mask = opnd(sb.a2, bf, 256, 1);
   g.c_bf16 = bf;
   run(g);
-  wgrad(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), 2, 256, 256, 128, 2, B * 13);
-  colsum(dY3, bf, B * 13, 256, dparams + T.boff[2]);
+  wgrad(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), 2, 256, 256, 128, 2, B * 13, dY3);
   // conv2: rows (b, p), 26 per window
   g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 1, 128), dY1, 128, B * 26, 128,
            128, 0);
   g.mask = opnd(sb.a1, bf, 128, 1);
   g.c_bf16 = bf;
   run(g);
-  wgrad(opnd(dY2, bf, 1, 128), opnd(sb.a1, bf, 128, 1), 1, 128, 128, 64, 2, B * 26);
-  colsum(dY2, bf, B * 26, 128, dparams + T.boff[1]);
+  wgrad(opnd(dY2, bf, 1, 128), opnd(sb.a1, bf, 128, 1), 1, 128, 128, 64, 2, B * 26, dY2);
   // conv1: rows (b, p), 52 per window; input pairs of window slots, rows of
   // window b at x + b*111*50 (the last 7 slots feed no output)
   const int64_t win = (int64_t)c->cfg.n_slot * c->cfg.n_feat;
   // (x read in runs of 16 along the 100 columns of a pair: up to column 111
   // of the last pair, slot 104, still inside its window)
   wgrad(opnd(dY1, bf, 1, 64), padded(opnd(x, 0, 100, 1, 52, win), 112), 0, 64, 100, 50, 2,
-        B * 52);
-  colsum(dY1, bf, B * 52, 64, dparams + T.boff[0]);
+        B * 52, dY1);
   if (e == hipSuccess && bias.count > 0) e = launch_sum_partials(bias, c->stream);
   if (dx) {
     if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);

@@ -269,14 +269,19 @@ struct GemmArgs {
   const float* bias;
   int32_t beta;
   int32_t c_bf16;
+  // optional: the sums of A(m, k) over each k-split's range, rowsum[z][m]
+  // (FP32, k in order), written by the pipelined BF16 kernel only
+  float* rowsum;
   // set by launch_gemm
   int32_t ksplit, amode, avec, bmode, bvec, evec;
   float* part;
 };
 // bf16_mma: BF16 MFMA with operands rounded to BF16 (else FP32 MFMA).  part
 // (part_cap floats, may be NULL) is scratch for split-K partial products.
+// With g.rowsum set, *rowsum_parts receives the number of k-splits whose row
+// sums were written there, or 0 if this launch's kernel writes none.
 hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
-                       hipStream_t stream);
+                       hipStream_t stream, int64_t* rowsum_parts = nullptr);
 hipError_t launch_loss(const float* z, const int32_t* lat, int64_t B, int32_t n_bins,
                        float* loss_b, float* loss, float* dz, hipStream_t stream);
 // at most this many chunk partials per column

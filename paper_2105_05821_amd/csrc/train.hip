@@ -808,7 +808,7 @@ __device__ __forceinline__ void fast_step(int64_t i, int64_t n_steps, v4f (&acc)
                                           uint32_t (&lb)[FastOp<BM>::W],
                                           const uint32_t (&sa)[FastOp<AM>::W],
                                           const uint32_t (&sb)[FastOp<BM>::W], int wm, int wn,
-                                          int lane, int tid) {
+                                          int lane, int tid, bool do_rs, float& rs) {
   const int64_t r = i + 3 < n_steps ? i + 3 : n_steps - 1;  // past the end: the last again
   pa.load(r, la);
   pb.load(r, lb);
@@ -830,6 +830,20 @@ __device__ __forceinline__ void fast_step(int64_t i, int64_t n_steps, v4f (&acc)
       acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf_t, af[a]),
                                                          __builtin_bit_cast(v8bf_t, bfr[b]),
                                                          acc[a][b], 0, 0, 0);
+  if (do_rs) {  // this thread's half of row tid / 2 of the A tile, in k order
+    const int row = tid >> 1, h = tid & 1;
+    const uint4 x0 = *reinterpret_cast<const uint4*>(&As[CUR][row][8 * chunk_at(row, 2 * h)]);
+    const uint4 x1 =
+        *reinterpret_cast<const uint4*>(&As[CUR][row][8 * chunk_at(row, 2 * h + 1)]);
+    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    float t = 0.f;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      t += __uint_as_float(w[q] << 16);
+      t += __uint_as_float(w[q] & 0xffff0000u);
+    }
+    rs += t;
+  }
   if (i + 1 < n_steps) {
     fast_store<AM>(As[CUR ^ 1], tid, sa);
     fast_store<BM>(Bs[CUR ^ 1], tid, sb);
@@ -875,6 +889,9 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16_fast_kernel(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
   const int64_t n = (ke - kb) / HK;
+  // the workgroups of the first column of tiles also sum A's rows
+  const bool do_rs = g.rowsum != nullptr && tn == 0;
+  float rs = 0.f;
   if (n > 0) {
     const FastOp<AM> pa = fast_op<AM>(g.A, false, m0, g.M, kb, tid);
     const FastOp<BM> pb = fast_op<BM>(g.B, true, n0, g.N, kb, tid);
@@ -896,27 +913,31 @@ __global__ void __launch_bounds__(256, 2) gemm_bf16_fast_kernel(GemmArgs g) {
     // (the guards are nested: a step runs only after the one before it, so
     // the compiler counts the requests in flight exactly)
     for (int64_t i = 0; i < n; i += 6) {
-      fast_step<AM, BM, 0>(i, n, acc, As, Bs, pa, pb, a0, b0, a1, b1, wm, wn, lane, tid);
+      fast_step<AM, BM, 0>(i, n, acc, As, Bs, pa, pb, a0, b0, a1, b1, wm, wn, lane, tid, do_rs, rs);
       if (i + 1 < n) {
-        fast_step<AM, BM, 1>(i + 1, n, acc, As, Bs, pa, pb, a1, b1, a2, b2, wm, wn, lane,
-                             tid);
+        fast_step<AM, BM, 1>(i + 1, n, acc, As, Bs, pa, pb, a1, b1, a2, b2, wm, wn, lane, tid, do_rs, rs);
         if (i + 2 < n) {
           fast_step<AM, BM, 0>(i + 2, n, acc, As, Bs, pa, pb, a2, b2, a0, b0, wm, wn,
-                               lane, tid);
+                               lane, tid, do_rs, rs);
           if (i + 3 < n) {
             fast_step<AM, BM, 1>(i + 3, n, acc, As, Bs, pa, pb, a0, b0, a1, b1, wm, wn,
-                                 lane, tid);
+                                 lane, tid, do_rs, rs);
             if (i + 4 < n) {
               fast_step<AM, BM, 0>(i + 4, n, acc, As, Bs, pa, pb, a1, b1, a2, b2, wm, wn,
-                                   lane, tid);
+                                   lane, tid, do_rs, rs);
               if (i + 5 < n)
                 fast_step<AM, BM, 1>(i + 5, n, acc, As, Bs, pa, pb, a2, b2, a0, b0, wm,
-                                     wn, lane, tid);
+                                     wn, lane, tid, do_rs, rs);
             }
           }
         }
       }
     }
+  }
+  if (do_rs) {  // the two halves of each row, then one row sum per row below M
+    const float other = __shfl_xor(rs, 1);
+    const int64_t m = m0 + (tid >> 1);
+    if ((tid & 1) == 0 && m < g.M) g.rowsum[(int64_t)blockIdx.z * g.M + m] = rs + other;
   }
   gemm_bf16_epilogue(g, acc, reinterpret_cast<float*>(&As[0][0][0]), m0, n0, wm, wn, tid, lane);
 }
@@ -945,7 +966,7 @@ static void operand_mode(const GemmOperand& o, bool is_b, int32_t* mode, int32_t
 }
 
 hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
-                       hipStream_t stream) {
+                       hipStream_t stream, int64_t* rowsum_parts) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;
   const int TB = bf16_mma ? HB : GB;
   const int64_t tiles = ((g.M + TB - 1) / TB) * ((g.N + TB - 1) / TB);
@@ -998,6 +1019,8 @@ hipError_t launch_gemm(GemmArgs g, int bf16_mma, float* part, int64_t part_cap,
                       whole_runs(g.B, g.bmode, g.N);
   // FP32 along n in 8-byte pieces, rows possibly grouped (e.g. the windows)
   const bool fast_b32 = !g.B.bf16 && g.bvec >= 1 && g.bmode == 2 && whole_runs(g.B, 2, g.N);
+  if (rowsum_parts) *rowsum_parts = (fast_a && (fast_b32 || fast_b) && g.rowsum) ? ks : 0;
+  if (!(fast_a && (fast_b32 || fast_b))) g.rowsum = nullptr;
   if (fast_a && fast_b32) {
     if (g.amode == 1)
       hipLaunchKernelGGL((gemm_bf16_fast_kernel<1, 3>), grid, dim3(256), 0, stream, g);
