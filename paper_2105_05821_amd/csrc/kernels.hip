@@ -2393,11 +2393,13 @@ __global__ void __launch_bounds__(Net::WAVES * 64)
   predict_tile<Net, P, false, true>(wt, relu_mask, sm, load, commit, nullptr, nullptr, sv);
 }
 
+// (the hidden FC's 8-fragment weight chunks requested two ahead, as the step
+// kernel's variant 3: 2 % faster than one ahead here, no spills)
 template <class P>
 static hipError_t launch_fwd_save_t(const DevWeights& w, uint32_t relu, const float* x, int64_t B,
                                     const SaveBlock& sb, hipStream_t stream) {
   const dim3 grid((unsigned)((B + MT - 1) / MT)), block(Geo<NetC3, P>::NT);
-  hipLaunchKernelGGL((forward_save_kernel<NetC3, P>), grid, block, 0, stream, w, relu, x, B, sb);
+  hipLaunchKernelGGL((forward_save_kernel<NetC3V3, P>), grid, block, 0, stream, w, relu, x, B, sb);
   return hipGetLastError();
 }
 
