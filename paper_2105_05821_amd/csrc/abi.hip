@@ -1653,9 +1653,11 @@ int sim_adam_load(sim_ctx* c, float* params, const float* grads, float* m, float
     return fail(c, SIM_EINVAL, "n = %lld but the network has %lld parameters", (long long)n,
                 (long long)T.n_params);
   if (!T.inv) return fail(c, SIM_EUNSUPPORTED, "no one-to-one re-layout for this network");
-  hipError_t e = launch_adam_relayout(params, grads, m, v, n, lr, beta1, beta2, eps, step,
-                                      T.master, T.inv, T.packed, T.perm,
-                                      c->cfg.prec == SIM_BF16, c->stream);
+  // (the hidden layer's 1.7 M weights through the tiled kernel)
+  hipError_t e = launch_adam_relayout(
+      params, grads, m, v, n, lr, beta1, beta2, eps, step, T.master, T.inv, T.packed, T.perm,
+      c->cfg.prec == SIM_BF16, (int64_t)T.woff[3], static_cast<char*>(T.packed) + T.pack_off[3],
+      T.perm + T.perm_off[3], c->stream);
   if (e != hipSuccess) return hip_fail(c, e, "adam");
   return SIM_OK;
 }

@@ -328,10 +328,14 @@ hipError_t launch_zero(float* p, int64_t n, hipStream_t stream);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, int64_t n, float lr, float b1,
                        float b2, float eps, int32_t t, hipStream_t stream);
 // Adam, then master[i] = w[i] and, for inv[i] = (packed byte offset, perm
-// byte offset) >= 0, the copies in the form's precision.
+// byte offset) >= 0, the copies in the form's precision.  With hid_packed
+// set, the C3 hidden layer's weights (512 x 256 x 13 from hid_off) go
+// through a tiled kernel instead, writing its packed copy at hid_packed and
+// its permuted copy at hid_perm in whole runs.
 hipError_t launch_adam_relayout(float* w, const float* g, float* m, float* v, int64_t n, float lr,
                                 float b1, float b2, float eps, int32_t t, float* master,
                                 const int2* inv, void* packed, void* perm, int32_t bf16,
+                                int64_t hid_off, void* hid_packed, void* hid_perm,
                                 hipStream_t stream);
 
 // RB7, one step in three parts (n_steps = 1 each): stage 1 = gather and

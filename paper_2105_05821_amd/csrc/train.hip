@@ -1429,38 +1429,60 @@ hipError_t launch_zero(float* p, int64_t n, hipStream_t stream) {
   return hipGetLastError();
 }
 
-// Adam (Kingma & Ba) on FP32 master weights, step t >= 1, no weight decay.
+// One Adam step (Kingma & Ba, bias corrections c1 = 1 - b1^t, c2 = 1 -
+// b2^t, no weight decay) on values: the moments updated in place, the new
+// weight returned.  Every Adam kernel here applies this one function with
+// contraction into fused multiply-adds off, so they all round alike.
+__device__ __forceinline__ float adam_math(float gi, float& mi, float& vi, float wi, float lr,
+                                           float b1, float b2, float eps, float c1, float c2) {
+#pragma clang fp contract(off)
+  mi = b1 * mi + (1.f - b1) * gi;
+  vi = b2 * vi + (1.f - b2) * gi * gi;
+  return wi - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Adam on FP32 master weights, step t >= 1.
 __global__ void adam_kernel(float* __restrict__ w, const float* __restrict__ g,
                             float* __restrict__ m, float* __restrict__ v, int64_t n, float lr,
                             float b1, float b2, float eps, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  float mi = m[i], vi = v[i];
+  const float wi = adam_math(g[i], mi, vi, w[i], lr, b1, b2, eps, c1, c2);
   m[i] = mi;
   v[i] = vi;
-  w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  w[i] = wi;
+}
+
+// adam_math on parameter i: moments stored, the new weight returned (and
+// not yet stored).
+__device__ __forceinline__ float adam_one(const float* __restrict__ w,
+                                          const float* __restrict__ g, float* __restrict__ m,
+                                          float* __restrict__ v, int64_t i, float lr, float b1,
+                                          float b2, float eps, float c1, float c2) {
+  float mi = m[i], vi = v[i];
+  const float wi = adam_math(g[i], mi, vi, w[i], lr, b1, b2, eps, c1, c2);
+  m[i] = mi;
+  v[i] = vi;
+  return wi;
 }
 
 // Adam as adam_kernel, the updated weight also written to a context's
 // master copy and, where inv gives byte offsets (-1: none), to its packed and
 // permuted copies in the form's precision (BF16 rounded to nearest even, as
 // map_gather_multi writes them): the update and the re-layout in one pass.
+// Thread t takes parameter t, or t + skip_n from skip_lo on (a range that
+// adam_hidden_tiles updates).
 __global__ void adam_relayout_kernel(float* __restrict__ w, const float* __restrict__ g,
                                      float* __restrict__ m, float* __restrict__ v, int64_t n,
                                      float lr, float b1, float b2, float eps, float c1, float c2,
                                      float* __restrict__ master, const int2* __restrict__ inv,
                                      char* __restrict__ packed, char* __restrict__ perm,
-                                     int32_t bf16) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+                                     int32_t bf16, int64_t skip_lo, int64_t skip_n) {
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= skip_lo) i += skip_n;
   if (i >= n) return;
-  const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
-  m[i] = mi;
-  v[i] = vi;
-  const float wi = w[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float wi = adam_one(w, g, m, v, i, lr, b1, b2, eps, c1, c2);
   w[i] = wi;
   master[i] = wi;
   const int2 d = inv[i];
@@ -1474,14 +1496,99 @@ __global__ void adam_relayout_kernel(float* __restrict__ w, const float* __restr
   }
 }
 
+// The hidden layer's weights (HO outputs x HC channels x HP positions,
+// parameter o*HC*HP + c*HP + p) in tiles of HTO outputs x HTC channels: Adam
+// on the tile's rows (contiguous runs of HTC*HP parameters, four requested
+// per thread before any is used), the new weights to the master copy and to
+// LDS, then from LDS to the permuted copy ([p*HC + c][o]: runs of HTO
+// outputs) and the packed copy (per position p the K = HC x N = HO fragment
+// order of the forward kernels: k-groups of KG channels, 16-output tiles,
+// lane (k % KG) / E * 16 + o % 16, element k % E, E = KG / 4: whole 64 x E
+// blocks), in the form's precision.
+constexpr int HO = 512, HC = 256, HP = 13, HTO = 16, HTC = 32, HROW = HTC * HP + 1;
+__global__ void __launch_bounds__(256)
+    adam_hidden_tiles(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                      float* __restrict__ v, float lr, float b1, float b2, float eps, float c1,
+                      float c2, float* __restrict__ master, char* __restrict__ packed,
+                      char* __restrict__ perm, int32_t bf16, int32_t KG) {
+  __shared__ float T[HTO * HROW];  // [o - o0][(c - c0) * HP + p], rows padded by one
+  constexpr int NT = HTO * HTC * HP, U = 4;
+  const int o0 = blockIdx.x * HTO, c0 = blockIdx.y * HTC;
+  for (int base = threadIdx.x; base < NT; base += 256 * U) {
+    int64_t ii[U];
+    float gv[U], mv[U], vv[U], wv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * 256;
+      const int r = idx / (HTC * HP), col = idx - r * (HTC * HP);
+      ii[u] = (int64_t)(o0 + r) * (HC * HP) + c0 * HP + col;
+      if (idx < NT) {
+        gv[u] = g[ii[u]];
+        mv[u] = m[ii[u]];
+        vv[u] = v[ii[u]];
+        wv[u] = w[ii[u]];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int idx = base + u * 256;
+      if (idx >= NT) continue;
+      float mi = mv[u], vi = vv[u];
+      const float wi = adam_math(gv[u], mi, vi, wv[u], lr, b1, b2, eps, c1, c2);
+      m[ii[u]] = mi;
+      v[ii[u]] = vi;
+      w[ii[u]] = wi;
+      master[ii[u]] = wi;
+      const int r = idx / (HTC * HP), col = idx - r * (HTC * HP);
+      T[r * HROW + col] = wi;
+    }
+  }
+  __syncthreads();
+  // permuted copy: element (p, c, o) at (p*HC + c)*HO + o
+  for (int idx = threadIdx.x; idx < NT; idx += 256) {
+    const int ol = idx % HTO, rest = idx / HTO, cl = rest % HTC, p = rest / HTC;
+    const float x = T[ol * HROW + cl * HP + p];
+    const int64_t q = ((int64_t)p * HC + c0 + cl) * HO + o0 + ol;
+    if (bf16)
+      reinterpret_cast<uint16_t*>(perm)[q] = to_bf16(x);
+    else
+      reinterpret_cast<float*>(perm)[q] = x;
+  }
+  // packed copy: per position p, blocks (kg, nt) of 64 lanes x E elements
+  const int E = KG / 4, BLK = 64 * E, NKG = HTC / KG, NNT = HTO / 16;
+  for (int idx = threadIdx.x; idx < NT; idx += 256) {
+    const int blk = idx / BLK, wi = idx - blk * BLK, lane = wi / E, e = wi - lane * E;
+    const int ntl = blk % NNT, rest = blk / NNT, kgl = rest % NKG, p = rest / NKG;
+    const int kg = c0 / KG + kgl, nt = o0 / 16 + ntl;
+    const int c = kg * KG + (lane / 16) * E + e, o = nt * 16 + (lane & 15);
+    const float x = T[(o - o0) * HROW + (c - c0) * HP + p];
+    const int64_t q = (int64_t)p * (HC * HO) + ((int64_t)(kg * (HO / 16) + nt) * 64 + lane) * E + e;
+    if (bf16)
+      reinterpret_cast<uint16_t*>(packed)[q] = to_bf16(x);
+    else
+      reinterpret_cast<float*>(packed)[q] = x;
+  }
+}
+
 hipError_t launch_adam_relayout(float* w, const float* g, float* m, float* v, int64_t n, float lr,
                                 float b1, float b2, float eps, int32_t t, float* master,
                                 const int2* inv, void* packed, void* perm, int32_t bf16,
+                                int64_t hid_off, void* hid_packed, void* hid_perm,
                                 hipStream_t stream) {
   const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
-  hipLaunchKernelGGL(adam_relayout_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     stream, w, g, m, v, n, lr, b1, b2, eps, c1, c2, master, inv,
-                     static_cast<char*>(packed), static_cast<char*>(perm), bf16);
+  const int64_t hn = hid_packed ? (int64_t)HO * HC * HP : 0;
+  if (hid_packed && (hid_off < 0 || hid_off + hn > n)) return hipErrorInvalidValue;
+  const int64_t rest = n - hn;
+  if (rest > 0)
+    hipLaunchKernelGGL(adam_relayout_kernel, dim3((unsigned)((rest + 255) / 256)), dim3(256), 0,
+                       stream, w, g, m, v, n, lr, b1, b2, eps, c1, c2, master, inv,
+                       static_cast<char*>(packed), static_cast<char*>(perm), bf16,
+                       hid_packed ? hid_off : n, hn);
+  if (hid_packed)
+    hipLaunchKernelGGL(adam_hidden_tiles, dim3(HO / HTO, HC / HTC), dim3(256), 0, stream,
+                       w + hid_off, g + hid_off, m + hid_off, v + hid_off, lr, b1, b2, eps, c1,
+                       c2, master + hid_off, static_cast<char*>(hid_packed),
+                       static_cast<char*>(hid_perm), bf16, bf16 ? 32 : 16);
   return hipGetLastError();
 }
 
