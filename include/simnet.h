@@ -356,7 +356,8 @@ SIMNET_API int predictor_bwd(sim_ctx* ctx, const void* x, const void* save, cons
  * parameters, in place, with moments m and v (DEVICE, n floats each, zero
  * before step 1); step counts from 1.  To train a context's predictor: keep
  * the master parameters in a device buffer, update them here, then
- * sim_load_weights(..., on_device = 1) to re-lay them out for the kernels. */
+ * sim_load_weights(..., on_device = 1) to re-lay them out for the kernels
+ * (sim_adam_load does both in one launch, with the same results). */
 SIMNET_API int sim_adam(sim_ctx* ctx, float* params, const float* grads, float* m, float* v,
                         int64_t n, float lr, float beta1, float beta2, float eps, int32_t step);
 
