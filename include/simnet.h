@@ -352,7 +352,8 @@ SIMNET_API int sim_loss_noalloc(sim_ctx* ctx, const float* logits, const int32_t
 SIMNET_API int predictor_bwd(sim_ctx* ctx, const void* x, const void* save, const float* dlogits,
                              int64_t B, float* dx, float* dparams, int32_t accumulate);
 
-/* One Adam step (Kingma and Ba, bias-corrected) on n DEVICE float32
+/* One Adam step (Sec. 2.4 trains the predictor with Adam, without weight
+ * decay; Kingma and Ba's bias-corrected update) on n DEVICE float32
  * parameters, in place, with moments m and v (DEVICE, n floats each, zero
  * before step 1); step counts from 1.  To train a context's predictor: keep
  * the master parameters in a device buffer, update them here, then
@@ -361,8 +362,9 @@ SIMNET_API int predictor_bwd(sim_ctx* ctx, const void* x, const void* save, cons
 SIMNET_API int sim_adam(sim_ctx* ctx, float* params, const float* grads, float* m, float* v,
                         int64_t n, float lr, float beta1, float beta2, float eps, int32_t step);
 
-/* sim_adam on the n = all parameters of a training context's predictor,
- * after which the context's weights are the updated parameters, exactly as
+/* sim_adam (Sec. 2.4) on the n = all parameters of a training context's
+ * predictor, after which the context's weights are the updated parameters,
+ * exactly as
  * after sim_load_weights(..., params, on_device = 1) with the layers it was
  * loaded with, in one launch: each updated weight is also written to the
  * context's master copy and, in the form's precision, to its places in the
