@@ -33,6 +33,10 @@ struct TrainState {
   float* work = nullptr;
   int64_t work_B = 0;
   int2* inv = nullptr;  // per parameter: byte offsets in packed and perm (-1: none)
+  // the backward pass's second stream (the weight gradients) and its
+  // fork/join events
+  hipStream_t side = nullptr;
+  hipEvent_t ev[7] = {nullptr};
   size_t woff[5] = {0}, boff[5] = {0};
   size_t n_params = 0;
 };
@@ -730,6 +734,12 @@ static size_t train_work_off(int64_t B, int part) {
 
 static int ensure_train_work(sim_ctx* c, int64_t B) {
   TrainState& T = c->tr;
+  if (!T.side) {
+    hipError_t e = hipStreamCreateWithFlags(&T.side, hipStreamNonBlocking);
+    for (int k = 0; k < 7 && e == hipSuccess; ++k)
+      e = hipEventCreateWithFlags(&T.ev[k], hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(c, e, "backward stream");
+  }
   if (T.work && T.work_B >= B) return SIM_OK;
   if (T.work) {
     (void)hipStreamSynchronize(c->stream);
@@ -1542,26 +1552,43 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   float* csw = W + train_work_off(B, 5);
   float* part = W + train_work_off(B, 6);
   hipError_t e = hipSuccess;
-  auto run = [&](const GemmArgs& g) {
-    if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream);
+  // Two streams: the input-gradient chain on the context's stream s1, the
+  // weight gradients (and their split-K partials, which only they use) on
+  // the side stream s2, each starting when its output gradient is ready
+  // (event k recorded on one stream, awaited on the other); s1 joins s2
+  // before the bias sums.
+  hipStream_t s1 = c->stream, s2 = T.side;
+  auto signal = [&](int k, hipStream_t from) {
+    if (e == hipSuccess) e = hipEventRecord(T.ev[k], from);
+  };
+  auto await = [&](int k, hipStream_t to) {
+    if (e == hipSuccess) e = hipStreamWaitEvent(to, T.ev[k], 0);
+  };
+  // (s1's products are never split: no partial buffer)
+  auto run1 = [&](const GemmArgs& g) {
+    if (e == hipSuccess) e = launch_gemm(g, bf, nullptr, 0, s1);
+  };
+  auto run2 = [&](const GemmArgs& g) {
+    if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, s2);
   };
   // the bias sums: lists of partials now (column-sum chunks or a weight
   // gradient's per-split row sums), all five added in one launch at the end
   SumSegs bias{};
   bias.beta = beta;
   float* csw_next = csw;
-  auto colsum = [&](const void* y, int y_bf16, int64_t M, int64_t N, float* out) {
+  auto colsum = [&](const void* y, int y_bf16, int64_t M, int64_t N, float* out,
+                    hipStream_t st) {
     int64_t chunks = 0;
-    if (e == hipSuccess) e = launch_colsum_partial(y, y_bf16, M, N, N, csw_next, &chunks, c->stream);
+    if (e == hipSuccess) e = launch_colsum_partial(y, y_bf16, M, N, N, csw_next, &chunks, st);
     if (e == hipSuccess && chunks > 0) {
       bias.seg[bias.count++] = SumSeg{csw_next, chunks, N, out, 0, 0};
       csw_next += (chunks * N + 63) / 64 * 64;
     }
   };
-  // trunk layer l's weight gradient, [c_out][input column] with input
-  // column t*c_in + c (p*256 + c for the hidden layer), stored straight
-  // into the parameters' layout ([c_out][c_in][2], [512][256][13]); its
-  // bias gradient (the column sums of dy, y [rows][c_out]) from the same
+  // trunk layer l's weight gradient (on s2), [c_out][input column] with
+  // input column t*c_in + c (p*256 + c for the hidden layer), stored
+  // straight into the parameters' layout ([c_out][c_in][2], [512][256][13]);
+  // its bias gradient (the column sums of dy, y [rows][c_out]) from the same
   // product's row sums of dy^T where the pipelined kernel runs it (one list
   // of partials per k-split for the final sum), else as a column sum
   auto wgrad = [&](const GemmOperand& dyt, const GemmOperand& act, int l, int64_t c_out,
@@ -1571,14 +1598,13 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
     g.ccm = taps;
     g.rowsum = csw_next;
     int64_t parts = 0;
-    if (e == hipSuccess)
-      e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, c->stream, &parts);
+    if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, s2, &parts);
     if (e != hipSuccess) return;
     if (parts > 0) {
       bias.seg[bias.count++] = SumSeg{csw_next, parts, c_out, dparams + T.boff[l], 0, 0};
       csw_next += (parts * c_out + 63) / 64 * 64;
     } else {
-      colsum(y, bf, rows, c_out, dparams + T.boff[l]);
+      colsum(y, bf, rows, c_out, dparams + T.boff[l], s2);
     }
   };
   // The output gradients of the hidden layer and the convolutions (dH, dY3,
@@ -1587,41 +1613,53 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   // take them rounded; FP32 in the FP32 form.
   // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H.
   // dZ is read from a copy with rows padded to TRAIN_LD with zeros (dY1's
-  // space, free until conv2's input gradient), in the form's precision (the
-  // BF16 products round it to BF16 anyway), so both products read it in
-  // vectors and dH's runs over whole k-steps (the head copy's padding rows
-  // are zero too).
+  // space, free until conv2's input gradient, which waits for dW2), in the
+  // form's precision (the BF16 products round it to BF16 anyway), so both
+  // products read it in vectors and dH's runs over whole k-steps (the head
+  // copy's padding rows are zero too).
   void* dZp = dY1;
-  e = launch_pad_rows(dlogits, B, TRAIN_OUT, TRAIN_LD, dZp, bf, c->stream);
+  e = launch_pad_rows(dlogits, B, TRAIN_OUT, TRAIN_LD, dZp, bf, s1);
+  signal(0, s1);  // everything before, and the padded copy
+  await(0, s2);
+  run2(gemm(padded(opnd(dZp, bf, 1, TRAIN_LD), TRAIN_LD), opnd(sb.h, bf, 512, 1),
+            dparams + T.woff[4], 512, TRAIN_OUT, 512, B, beta));
+  signal(1, s2);  // dZ's copy read for the last time
   GemmArgs g = gemm(opnd(dZp, bf, TRAIN_LD, 1), opnd(T.perm + T.perm_off[4], bf, 512, 1), dH,
                     512, B, 512, TRAIN_LD, 0);
   g.mask = opnd(sb.h, bf, 512, 1);
   g.c_bf16 = bf;
-  run(g);
-  run(gemm(padded(opnd(dZp, bf, 1, TRAIN_LD), TRAIN_LD), opnd(sb.h, bf, 512, 1),
-           dparams + T.woff[4], 512, TRAIN_OUT, 512, B, beta));
-  colsum(dlogits, 0, B, TRAIN_OUT, dparams + T.boff[4]);
+  run1(g);
+  signal(2, s1);  // dH
+  await(2, s2);
+  colsum(dlogits, 0, B, TRAIN_OUT, dparams + T.boff[4], s1);
   // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU
   g = gemm(opnd(dH, bf, 512, 1), opnd(T.perm + T.perm_off[3], bf, 1, 512), dY3, 3328, B, 3328,
            512, 0);
   g.mask = opnd(sb.a3, bf, 3328, 1);
   g.c_bf16 = bf;
-  run(g);
+  run1(g);
   wgrad(opnd(dH, bf, 1, 512), opnd(sb.a3, bf, 3328, 1), 3, 512, 3328, 256, 13, B, dH);
+  signal(3, s1);  // dY3
+  await(3, s2);
   // conv3: rows (b, p), 13 per window; input pairs of conv2 positions
   g = gemm(opnd(dY3, bf, 256, 1), opnd(T.perm + T.perm_off[2], bf, 1, 256), dY2, 256, B * 13, 256,
            256, 0);
   g.mask = opnd(sb.a2, bf, 256, 1);
   g.c_bf16 = bf;
-  run(g);
+  run1(g);
   wgrad(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), 2, 256, 256, 128, 2, B * 13, dY3);
-  // conv2: rows (b, p), 26 per window
+  signal(4, s1);  // dY2
+  await(4, s2);
+  // conv2: rows (b, p), 26 per window (dY1 overwrites dZ's copy: after dW2)
+  await(1, s1);
   g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 1, 128), dY1, 128, B * 26, 128,
            128, 0);
   g.mask = opnd(sb.a1, bf, 128, 1);
   g.c_bf16 = bf;
-  run(g);
+  run1(g);
   wgrad(opnd(dY2, bf, 1, 128), opnd(sb.a1, bf, 128, 1), 1, 128, 128, 64, 2, B * 26, dY2);
+  signal(5, s1);  // dY1
+  await(5, s2);
   // conv1: rows (b, p), 52 per window; input pairs of window slots, rows of
   // window b at x + b*111*50 (the last 7 slots feed no output)
   const int64_t win = (int64_t)c->cfg.n_slot * c->cfg.n_feat;
@@ -1629,15 +1667,17 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   // of the last pair, slot 104, still inside its window)
   wgrad(opnd(dY1, bf, 1, 64), padded(opnd(x, 0, 100, 1, 52, win), 112), 0, 64, 100, 50, 2,
         B * 52, dY1);
-  if (e == hipSuccess && bias.count > 0) e = launch_sum_partials(bias, c->stream);
   if (dx) {
-    if (e == hipSuccess) e = launch_zero(dx, B * win, c->stream);
+    if (e == hipSuccess) e = launch_zero(dx, B * win, s1);
     g = gemm(opnd(dY1, bf, 64, 1), opnd(T.perm + T.perm_off[0], bf, 1, 64), dx, 100, B * 52, 100,
              64, 0);
     g.cgrp = 52;
     g.cgs = win;
-    run(g);
+    run1(g);
   }
+  signal(6, s2);  // join
+  await(6, s1);
+  if (e == hipSuccess && bias.count > 0) e = launch_sum_partials(bias, s1);
   if (e != hipSuccess) return hip_fail(c, e, "backward");
   return SIM_OK;
 }
@@ -1682,6 +1722,9 @@ void sim_destroy(sim_ctx* c) {
   if (c->tr.packed) (void)hipFree(c->tr.packed);
   if (c->tr.perm) (void)hipFree(c->tr.perm);
   if (c->tr.inv) (void)hipFree(c->tr.inv);
+  for (hipEvent_t ev : c->tr.ev)
+    if (ev) (void)hipEventDestroy(ev);
+  if (c->tr.side) (void)hipStreamDestroy(c->tr.side);
   if (c->tr.work) (void)hipFree(c->tr.work);
   if (c->dev_block) (void)hipFree(c->dev_block);
   if (c->rb_trunk) (void)hipFree(c->rb_trunk);
