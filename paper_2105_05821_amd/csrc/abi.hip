@@ -719,14 +719,15 @@ static int load_train_weights(sim_ctx* c, const sim_layer* layers, int32_t n_lay
 
 // Backward workspace (floats): [0] per-window losses, [1] dH [B][512],
 // [2] dY3 [B*13][256], [3] dY2 [B*26][128], [4] dY1 [B*52][64], [5] the
-// five bias sums' chunk partials, [6] split-K partial products.
+// five bias sums' chunk partials, [6] and [7] split-K partial products of
+// the two streams' products.
 constexpr size_t SPLITK_CAP = (size_t)8 << 20;
 // floats for the chunk partials of the bias sums (head, hidden, conv3..1),
 // each list starting on a 64-float boundary
 constexpr size_t BIAS_PART = colsum_workspace_floats(TRAIN_OUT + 512 + 256 + 128 + 64) + 5 * 64;
 static size_t train_work_off(int64_t B, int part) {
-  const size_t sizes[7] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
-                           (size_t)B * 3328, BIAS_PART, SPLITK_CAP};
+  const size_t sizes[8] = {(size_t)B, (size_t)B * 512, (size_t)B * 3328, (size_t)B * 3328,
+                           (size_t)B * 3328, BIAS_PART, SPLITK_CAP, SPLITK_CAP};
   size_t off = 0;
   for (int i = 0; i < part; ++i) off += (sizes[i] + 63) / 64 * 64;
   return off;
@@ -746,7 +747,7 @@ static int ensure_train_work(sim_ctx* c, int64_t B) {
     (void)hipFree(T.work);
     T.work = nullptr;
   }
-  hipError_t e = hipMalloc(&T.work, train_work_off(B, 7) * 4);
+  hipError_t e = hipMalloc(&T.work, train_work_off(B, 8) * 4);
   if (e != hipSuccess) return hip_fail(c, e, "training workspace");
   T.work_B = B;
   return SIM_OK;
@@ -1551,12 +1552,13 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   float* dY1 = W + train_work_off(B, 4);
   float* csw = W + train_work_off(B, 5);
   float* part = W + train_work_off(B, 6);
+  float* part1 = W + train_work_off(B, 7);
   hipError_t e = hipSuccess;
-  // Two streams: the input-gradient chain on the context's stream s1, the
-  // weight gradients (and their split-K partials, which only they use) on
-  // the side stream s2, each starting when its output gradient is ready
-  // (event k recorded on one stream, awaited on the other); s1 joins s2
-  // before the bias sums.
+  // Two streams: the input-gradient chain and the head's weight gradient on
+  // the context's stream s1, the trunk's weight gradients on the side
+  // stream s2, each starting when its output gradient is ready (event k
+  // recorded on one stream, awaited on the other), each stream with split-K
+  // partials of its own; s1 joins s2 before the bias sums.
   hipStream_t s1 = c->stream, s2 = T.side;
   auto signal = [&](int k, hipStream_t from) {
     if (e == hipSuccess) e = hipEventRecord(T.ev[k], from);
@@ -1564,12 +1566,8 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   auto await = [&](int k, hipStream_t to) {
     if (e == hipSuccess) e = hipStreamWaitEvent(to, T.ev[k], 0);
   };
-  // (s1's products are never split: no partial buffer)
   auto run1 = [&](const GemmArgs& g) {
-    if (e == hipSuccess) e = launch_gemm(g, bf, nullptr, 0, s1);
-  };
-  auto run2 = [&](const GemmArgs& g) {
-    if (e == hipSuccess) e = launch_gemm(g, bf, part, (int64_t)SPLITK_CAP, s2);
+    if (e == hipSuccess) e = launch_gemm(g, bf, part1, (int64_t)SPLITK_CAP, s1);
   };
   // the bias sums: lists of partials now (column-sum chunks or a weight
   // gradient's per-split row sums), all five added in one launch at the end
@@ -1611,25 +1609,20 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   // dY2, dY1, masked by their layer's ReLU) are written in the form's
   // precision: BF16 in the BF16 form, where every product and the bias sum
   // take them rounded; FP32 in the FP32 form.
-  // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H.
-  // dZ is read from a copy with rows padded to TRAIN_LD with zeros (dY1's
-  // space, free until conv2's input gradient, which waits for dW2), in the
-  // form's precision (the BF16 products round it to BF16 anyway), so both
-  // products read it in vectors and dH's runs over whole k-steps (the head
-  // copy's padding rows are zero too).
+  // head: dH = dZ W2 through the ReLU of the hidden layer; dW2 = dZ^T H
+  // (later on s1, beside s2's trunk weight gradients). dZ is read from a
+  // copy with rows padded to TRAIN_LD with zeros (dY1's space, free until
+  // conv2's input gradient), in the form's precision (the BF16 products
+  // round it to BF16 anyway), so both products read it in vectors and dH's
+  // runs over whole k-steps (the head copy's padding rows are zero too).
   void* dZp = dY1;
   e = launch_pad_rows(dlogits, B, TRAIN_OUT, TRAIN_LD, dZp, bf, s1);
-  signal(0, s1);  // everything before, and the padded copy
-  await(0, s2);
-  run2(gemm(padded(opnd(dZp, bf, 1, TRAIN_LD), TRAIN_LD), opnd(sb.h, bf, 512, 1),
-            dparams + T.woff[4], 512, TRAIN_OUT, 512, B, beta));
-  signal(1, s2);  // dZ's copy read for the last time
   GemmArgs g = gemm(opnd(dZp, bf, TRAIN_LD, 1), opnd(T.perm + T.perm_off[4], bf, 512, 1), dH,
                     512, B, 512, TRAIN_LD, 0);
   g.mask = opnd(sb.h, bf, 512, 1);
   g.c_bf16 = bf;
   run1(g);
-  signal(2, s1);  // dH
+  signal(2, s1);  // dH, and everything before it on s1
   await(2, s2);
   colsum(dlogits, 0, B, TRAIN_OUT, dparams + T.boff[4], s1);
   // hidden layer: dA3 = dH W1 (columns p*256 + c) through conv3's ReLU
@@ -1650,8 +1643,10 @@ int predictor_bwd(sim_ctx* c, const void* x, const void* save, const float* dlog
   wgrad(opnd(dY3, bf, 1, 256), opnd(sb.a2, bf, 256, 1), 2, 256, 256, 128, 2, B * 13, dY3);
   signal(4, s1);  // dY2
   await(4, s2);
-  // conv2: rows (b, p), 26 per window (dY1 overwrites dZ's copy: after dW2)
-  await(1, s1);
+  run1(gemm(padded(opnd(dZp, bf, 1, TRAIN_LD), TRAIN_LD), opnd(sb.h, bf, 512, 1),
+            dparams + T.woff[4], 512, TRAIN_OUT, 512, B, beta));
+  // conv2: rows (b, p), 26 per window (dY1 overwrites dZ's copy, after dW2
+  // on the same stream)
   g = gemm(opnd(dY2, bf, 128, 1), opnd(T.perm + T.perm_off[1], bf, 1, 128), dY1, 128, B * 26, 128,
            128, 0);
   g.mask = opnd(sb.a1, bf, 128, 1);
