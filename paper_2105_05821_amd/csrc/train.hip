@@ -11,11 +11,15 @@
 //                    parameters' own layout).  Used for the head and for
 //                    every input-gradient and weight-gradient product of the
 //                    backward pass (a kernel-2 stride-2 convolution is a
-//                    GEMM over position pairs).
+//                    GEMM over position pairs); the pipelined BF16 kernel
+//                    also sums its left operand's rows (the trunk's bias
+//                    gradients).
+//   reductions       split-K partials summed in order with the epilogue.
 //   loss_kernel      hybrid loss per window (400-bin cross-entropy + L1 on
 //                    log1p(latency) per latency type) and its gradient
 //                    w.r.t. the head outputs.
-//   colsum kernels   bias gradients, summed in a fixed order.
+//   colsum kernels   bias gradients as chunk partials; sum_partials adds
+//                    several lists of partials, each in a fixed order.
 //   map_gather_multi weight re-layouts by index maps.
 //   pad_rows         a row-major matrix copied with its rows padded.
 //   adam kernels     Adam on FP32 master weights (and, fused, the re-layout
